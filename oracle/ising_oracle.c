@@ -1,0 +1,234 @@
+/*
+ * ising_oracle.c — plain CPU oracle (TEST INFRASTRUCTURE ONLY; see ising_oracle.h).
+ *
+ * Paper: Yang, Chen, Roumpos, Colby, Anderson, "High Performance Monte Carlo
+ * Simulation of Ising Model on TPU Clusters" (arXiv 1903.11714).
+ *   Sec. 3          Hamiltonian H = -J sum_<ij> s_i s_j - mu sum_i s_i, J = 1, mu = 0,
+ *                   periodic (torus) lattice.
+ *   Sec. 3.1, eq. 1 checkerboard: with one colour fixed, every site of the other colour
+ *                   is offered a Metropolis flip independently; white first, then black.
+ *   Sec. 3.2, Alg. 1 nn = sum of the four neighbours; accept where a uniform in [0, 1) is
+ *                   below exp(-2 beta nn sigma); flip sigma -> -sigma.
+ *   Sec. 4.1        m = (1/N) sum_i sigma_i.
+ *   Sec. 4.2        a sweep = one update of all black plus all white sites.
+ */
+#include "ising_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- Philox4x32-10 (Salmon et al., SC'11, "Parallel random numbers: as easy as 1, 2, 3").
+ * One round: the two 32x32 -> 64-bit products M0 * x0 and M1 * x2; the new state is
+ * (hi(M1 x2) ^ x1 ^ k0, lo(M1 x2), hi(M0 x0) ^ x3 ^ k1, lo(M0 x0)); the key is bumped by the
+ * Weyl constants between rounds, the first round uses the key as given. */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static void seed_to_key(uint64_t seed, uint32_t key[2]) {
+    key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
+    key[1] = (uint32_t)(seed >> 32);
+}
+
+/* ---- The site's uniform (Sec. 3.2, Alg. 1 "probs"; Sec. 5.1 random_uniform).
+ * All 32 bits are assembled from the eight Philox blocks of the site's group, then used
+ * as one unsigned integer. */
+uint32_t oracle_uniform(uint64_t seed, uint32_t r, uint32_t c, uint32_t t, int q) {
+    uint32_t key[2];
+    seed_to_key(seed, key);
+    uint32_t j = c >> 1;          /* index among this row's colour-q sites */
+    uint32_t g = j >> 5;          /* group of 32 such sites                 */
+    uint32_t i = j & 31u;         /* position inside the group              */
+    uint32_t pos = 8u * (i & 3u) + (i >> 2); /* bit of each word that belongs to the site */
+    uint32_t x = 0;
+    for (uint32_t m = 0; m < 8; ++m) {
+        uint32_t ctr[4] = {g, r, t, 2u * m + (uint32_t)q};
+        uint32_t blk[4];
+        oracle_philox4x32_10(ctr, key, blk);
+        for (uint32_t w = 0; w < 4; ++w) {
+            uint32_t k = 4u * m + w;               /* k = 0 is the most significant bit */
+            uint32_t bit = (blk[w] >> pos) & 1u;
+            x |= bit << (31u - k);
+        }
+    }
+    return x;
+}
+
+/* ---- Thresholds.  u = x / 2^32 < p  <=>  x < ceil(p 2^32) for integer x, so the test
+ * "uniform < acceptance ratio" of Alg. 1 becomes an exact integer compare. */
+void oracle_thresholds(double beta, uint64_t T[2]) {
+    for (int k = 0; k < 2; ++k) {
+        double s = (k == 0) ? 2.0 : 4.0;
+        double p = exp(-2.0 * beta * s);     /* Metropolis ratio for energy change 2 s */
+        double y = ceil(ldexp(p, 32));
+        if (y > 4294967296.0) y = 4294967296.0;
+        if (!(y >= 0.0)) y = 0.0;
+        T[k] = (uint64_t)y;
+    }
+}
+
+/* ---- Hot start. */
+int oracle_init_site(uint64_t seed, uint32_t r, uint32_t c) {
+    uint32_t key[2];
+    seed_to_key(seed, key);
+    uint32_t ctr[4] = {c >> 7, r, 0u, 0x80000000u};
+    uint32_t blk[4];
+    oracle_philox4x32_10(ctr, key, blk);
+    uint32_t bit = (blk[(c >> 5) & 3u] >> (c & 31u)) & 1u;
+    return bit ? -1 : +1;
+}
+
+void oracle_init(int8_t* spins, int64_t L, uint64_t seed) {
+    for (int64_t r = 0; r < L; ++r)
+        for (int64_t c = 0; c < L; ++c)
+            spins[r * L + c] = (int8_t)oracle_init_site(seed, (uint32_t)r, (uint32_t)c);
+}
+
+/* ---- Neighbour sum on the torus. */
+static int64_t wrap(int64_t a, int64_t L) {
+    a %= L;
+    return a < 0 ? a + L : a;
+}
+
+static int neighbour_sum(const int8_t* s, int64_t L, int64_t r, int64_t c) {
+    int64_t up = wrap(r - 1, L), down = wrap(r + 1, L);
+    int64_t left = wrap(c - 1, L), right = wrap(c + 1, L);
+    return s[up * L + c] + s[down * L + c] + s[r * L + left] + s[r * L + right];
+}
+
+void oracle_local_field(const int8_t* spins, int64_t L, int8_t* nn) {
+    for (int64_t r = 0; r < L; ++r)
+        for (int64_t c = 0; c < L; ++c)
+            nn[r * L + c] = (int8_t)neighbour_sum(spins, L, r, c);
+}
+
+/* Metropolis decision for one site: s = sigma * nn is half the energy change of a flip. */
+static int accept_flip(int sigma, int nn, const uint64_t T[2], uint64_t seed, uint32_t r,
+                       uint32_t c, uint32_t t, int q) {
+    int s = sigma * nn;
+    if (s <= 0) return 1;                  /* min{1, exp(-2 beta s)} = 1 */
+    uint64_t thr = (s == 2) ? T[0] : T[1];
+    uint64_t x = oracle_uniform(seed, r, c, t, q);
+    return x < thr;
+}
+
+void oracle_half_sweep(int8_t* spins, int64_t L, const uint64_t T[2], uint64_t seed,
+                       uint32_t t, int q) {
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < L; ++r) {
+        for (int64_t c = 0; c < L; ++c) {
+            if (((r + c) & 1) != q) continue;
+            int sigma = spins[r * L + c];
+            int nn = neighbour_sum(spins, L, r, c);
+            if (accept_flip(sigma, nn, T, seed, (uint32_t)r, (uint32_t)c, t, q))
+                spins[r * L + c] = (int8_t)(-sigma);
+        }
+    }
+}
+
+void oracle_observables(const int8_t* spins, int64_t L, int64_t out[2]) {
+    int64_t M = 0, E = 0;
+    for (int64_t r = 0; r < L; ++r) {
+        for (int64_t c = 0; c < L; ++c) {
+            int sigma = spins[r * L + c];
+            M += sigma;
+            /* each bond once: the right and the lower neighbour of every site */
+            E -= sigma * (spins[r * L + wrap(c + 1, L)] + spins[wrap(r + 1, L) * L + c]);
+        }
+    }
+    out[0] = M;
+    out[1] = E;
+}
+
+void oracle_sweep(int8_t* spins, int64_t L, double beta, int64_t n, uint64_t seed,
+                  uint64_t offset, int64_t* trace) {
+    uint64_t T[2];
+    oracle_thresholds(beta, T);
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t t = (uint32_t)(offset + (uint64_t)i);
+        oracle_half_sweep(spins, L, T, seed, t, 1);   /* white */
+        oracle_half_sweep(spins, L, T, seed, t, 0);   /* black */
+        if (trace) oracle_observables(spins, L, trace + 2 * i);
+    }
+}
+
+/* ---- Light-cone crop.  One half-sweep moves information by one lattice step, so after
+ * 2 n half-sweeps a site depends only on sites within distance 2 n.  The window is the crop
+ * grown by R = 2 n on every side; half-sweep k updates only the part of the window that is
+ * still exact afterwards (the crop grown by R - k - 1). */
+void oracle_crop(int64_t L, uint64_t seed, double beta, int64_t n, uint64_t offset,
+                 int64_t r0, int64_t c0, int64_t h, int64_t w, int8_t* out) {
+    int64_t R = 2 * n;
+    if (h + 2 * R >= L || w + 2 * R >= L) {
+        int8_t* full = (int8_t*)malloc((size_t)(L * L));
+        oracle_init(full, L, seed);
+        oracle_sweep(full, L, beta, n, seed, offset, NULL);
+        for (int64_t a = 0; a < h; ++a)
+            for (int64_t b = 0; b < w; ++b)
+                out[a * w + b] = full[wrap(r0 + a, L) * L + wrap(c0 + b, L)];
+        free(full);
+        return;
+    }
+    int64_t H = h + 2 * R, W = w + 2 * R;
+    int8_t* win = (int8_t*)malloc((size_t)(H * W));
+    for (int64_t a = 0; a < H; ++a)
+        for (int64_t b = 0; b < W; ++b)
+            win[a * W + b] = (int8_t)oracle_init_site(seed, (uint32_t)wrap(r0 - R + a, L),
+                                                      (uint32_t)wrap(c0 - R + b, L));
+    uint64_t T[2];
+    oracle_thresholds(beta, T);
+    for (int64_t k = 0; k < 2 * n; ++k) {
+        uint32_t t = (uint32_t)(offset + (uint64_t)(k / 2));
+        int q = (k % 2 == 0) ? 1 : 0;
+        int64_t lo = k + 1;
+#pragma omp parallel for schedule(static)
+        for (int64_t a = lo; a < H - lo; ++a) {
+            int64_t r = wrap(r0 - R + a, L);
+            for (int64_t b = lo; b < W - lo; ++b) {
+                int64_t c = wrap(c0 - R + b, L);
+                if (((r + c) & 1) != q) continue;
+                int sigma = win[a * W + b];
+                int nn = win[(a - 1) * W + b] + win[(a + 1) * W + b] + win[a * W + b - 1] +
+                         win[a * W + b + 1];
+                if (accept_flip(sigma, nn, T, seed, (uint32_t)r, (uint32_t)c, t, q))
+                    win[a * W + b] = (int8_t)(-sigma);
+            }
+        }
+    }
+    for (int64_t a = 0; a < h; ++a)
+        memcpy(out + a * w, win + (a + R) * W + R, (size_t)w);
+    free(win);
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
