@@ -64,7 +64,9 @@ uint32_t oracle_uniform(uint64_t seed, uint32_t r, uint32_t c, uint32_t t, int q
     uint32_t j = c >> 1;          /* index among this row's colour-q sites */
     uint32_t g = j >> 5;          /* group of 32 such sites                 */
     uint32_t i = j & 31u;         /* position inside the group              */
-    uint32_t pos = 8u * (i & 3u) + (i >> 2); /* bit of each word that belongs to the site */
+    /* bit of each Philox word that belongs to the site: byte (0, 2, 1, 3)[i mod 4], bit i div 4 */
+    static const uint32_t byte_of[4] = {0u, 2u, 1u, 3u};
+    uint32_t pos = 8u * byte_of[i & 3u] + (i >> 2);
     uint32_t x = 0;
     for (uint32_t m = 0; m < 8; ++m) {
         uint32_t ctr[4] = {g, r, t, 2u * m + (uint32_t)q};

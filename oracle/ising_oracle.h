@@ -21,7 +21,7 @@
  *              alternating sub-routines, white updated first).
  *   uniform    x(r, c, t) is a 32-bit unsigned integer, u = x / 2^32 in [0, 1).
  *              With j = c >> 1 (index of the site among its row's colour-q sites),
- *              g = j >> 5, i = j & 31 and p(i) = 8 * (i & 3) + (i >> 2):
+ *              g = j >> 5, i = j & 31 and p(i) = 8 * b(i & 3) + (i >> 2), b = (0, 2, 1, 3):
  *              bit (31 - k) of x, k = 0..31, is bit p(i) of word (k & 3) of
  *              Philox4x32-10(key = (seed mod 2^32, seed >> 32),
  *                            counter = (g, r, t, 2 * (k >> 2) + q)).
