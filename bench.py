@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark of the checkerboard Metropolis sweep on one MI355X.
+
+Workload (the paper's single-lattice measurement, Sec. 4.2: time per sweep of all black and
+all white sites, flips/ns = L^2 / sweep time): a periodic 16384 x 16384 int8 lattice, hot
+start from seed 1, beta = beta_c = ln(1 + sqrt 2) / 2, exact-threshold acceptance, with the
+(M, E) trace recorded after every sweep.  One "step" is one sweep.  The lattice is resident in
+HBM before the timed region starts.
+
+Prints one JSON line with the throughput (spin-flip attempts per ns), the roofline of the
+dominant kernel (the half-sweep kernel; algorithmic bytes = one read and one write of the
+L^2-byte lattice per launch, measured with HIP events on the launch stream) and the CPU
+oracle's throughput on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+BETA_C = 0.5 * math.log1p(math.sqrt(2.0))
+HBM_PEAK_GBS = 8000.0
+METRIC = "spin-flip attempts/ns (L=16384², T_c) + % HBM peak, exact vs bf16 accept"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_11714_amd", "csrc", f) for f in ("ising.hip", "philox.hpp")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(layout: str, L: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
+    kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    entry = rec.get(f"{layout}_L{L}")
+    if not entry or entry.get("source_hash") != kernel_source_hash():
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(L: int, beta: float, seed: int, sweeps: int):
+    import oracle
+    spins = oracle.init(L, seed)
+    t0 = time.perf_counter()
+    oracle.sweep(spins, beta, sweeps, seed, 0)
+    dt = time.perf_counter() - t0
+    return {
+        "value": L * L * sweeps / (dt * 1e9),
+        "unit": "attempts/ns",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{sweeps} sweeps of the full {L}x{L} lattice at T_c from the seed-{seed} hot start "
+                  f"({dt:.1f} s; plain C oracle, OpenMP over the rows of each half-sweep)",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000, help="timed sweeps")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed sweeps first")
+    ap.add_argument("--L", type=int, default=16384)
+    ap.add_argument("--beta", type=float, default=BETA_C)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--kernel-sweeps", type=int, default=50, help="sweeps timed launch by launch")
+    ap.add_argument("--cpu-sweeps", type=int, default=2, help="sweeps in the CPU-oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(one periodic lattice per GPU, no sharding).", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1903_11714_amd import ising
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    L, beta, seed, K, W = args.L, args.beta, args.seed, args.steps, args.warmup
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+
+    spins = torch.empty((L, L), dtype=torch.int8, device=dev)
+    ising.ising_init(spins, L, seed, stream)
+    warm_trace = torch.empty((max(W, 1), 2), dtype=torch.int64, device=dev)
+    trace = torch.empty((max(K, 1), 2), dtype=torch.int64, device=dev)
+    if W:
+        ising.ising_sweep(spins, L, beta, W, seed, 0, warm_trace, stream)
+    torch.cuda.synchronize()
+    print(f"bench: L={L} warmup={W} done", file=sys.stderr, flush=True)
+
+    # ---- timed region: K sweeps with the (M, E) trace
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    ising.ising_sweep(spins, L, beta, K, seed, W, trace, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    print(f"bench: timed {K} sweeps in {wall:.3f} s wall, {gpu_ms:.1f} ms events", file=sys.stderr, flush=True)
+    attempts = float(L) * L * K
+    value = attempts / (wall * 1e9)
+
+    # ---- dominant kernel: each half-sweep launch bracketed by events on the same stream
+    nk = args.kernel_sweeps
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nk + 1)]
+    t = W + K
+    evs[0].record(stream)
+    for i in range(nk):
+        ising.ising_half_sweep(spins, L, beta, seed, t + i, 1, stream)
+        evs[2 * i + 1].record(stream)
+        ising.ising_half_sweep(spins, L, beta, seed, t + i, 0, stream)
+        evs[2 * i + 2].record(stream)
+    torch.cuda.synchronize()
+    durs = [evs[k].elapsed_time(evs[k + 1]) for k in range(2 * nk)]
+    avg_ms = sum(durs) / len(durs)
+    alg_bytes = 2.0 * L * L          # read + write of the L^2-byte lattice per launch
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic("int8", L)
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "attempts/ns",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": wall * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic: Philox hot start from the seed (no dataset)",
+        "config": {
+            "workload": f"single periodic {L}x{L} lattice, T=T_c, hot start seed {seed}, plain exact-threshold "
+                        f"checkerboard Metropolis, int8 layout, (M,E) traced every sweep",
+            "L": L, "beta": beta, "layout": "int8", "sweeps_timed": K,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_sweep_int8 (one colour per launch)",
+            "avg_launch_us": avg_ms * 1e3,
+            "alg_bytes_per_launch": alg_bytes,
+        },
+        "gpu_event_ms": gpu_ms,
+        "final_ME": trace[K - 1].tolist() if K else None,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(L, beta, seed, args.cpu_sweeps)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,108 @@
+/*
+ * ising.h — C ABI of the MI355X (gfx950) checkerboard Metropolis library for the periodic
+ * 2D Ising model (Yang et al., "High Performance Monte Carlo Simulation of Ising Model on TPU
+ * Clusters", arXiv 1903.11714).
+ *
+ * Common rules for every entry point:
+ *   - All functions are extern "C", return an int status (ISING_OK = 0, negative on error)
+ *     and never throw.
+ *   - Device pointers are HIP device allocations owned by the caller; the library never
+ *     allocates, frees or keeps them.  Work is enqueued on `stream` (a hipStream_t, NULL for
+ *     the default stream) and the call returns without synchronising.
+ *   - Arguments are validated before anything is enqueued; ISING_EINVAL means nothing ran.
+ *     ISING_EHIP means a HIP call failed; ising_last_error() returns its text.
+ *   - Spin lattices hold +1 / -1 only (int8 layout) or the packed bit form of such a lattice.
+ *     Other byte values give unspecified (but memory-safe) results.
+ *   - L is the linear size of a square periodic lattice: L % 64 == 0, 64 <= L <= 2^20.
+ *
+ * Lattice conventions (Sec. 3, Sec. 3.1, Sec. 3.2 of the paper):
+ *   int8 layout: row-major L x L bytes, sigma[r][c] at offset r * L + c, periodic in r and c.
+ *   colour of (r, c): (r + c) & 1; 0 = black, 1 = white.  A sweep updates every white site
+ *   and then every black site (Sec. 3.1: alternate the two colours, white first).
+ *   Acceptance (Sec. 3.2, Algorithm 1): a site with s = sigma * nn <= 0 flips; otherwise it
+ *   flips iff its 32-bit uniform x is below T_s = ceil(2^32 exp(-2 beta s)), s in {2, 4}.
+ *   The uniform of site (r, c) in sweep t: j = c >> 1, g = j >> 5, i = j & 31,
+ *   p = 8 * (0, 2, 1, 3)[i & 3] + (i >> 2); bit 31 - k of x is bit p of word k & 3 of
+ *   Philox4x32-10(key = (seed & 0xffffffff, seed >> 32), counter = (g, r, t, 2 (k >> 2) + q)).
+ */
+#ifndef ISING_H
+#define ISING_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ISING_OK = 0,
+    ISING_EINVAL = -1,      /* invalid argument; nothing was enqueued        */
+    ISING_EHIP = -2,        /* a HIP runtime call or kernel launch failed      */
+    ISING_EUNSUPPORTED = -3 /* valid request this build or device cannot serve */
+};
+
+/* Hot start (the paper leaves the initial configuration open; Sec. 3.2 takes it as input):
+ * spins[r * L + c] = -1 iff bit (c & 31) of word ((c >> 5) & 3) of
+ * Philox4x32-10(key(seed), counter = (c >> 7, r, 0, 0x80000000)) is set, else +1.
+ * spins: device int8[L * L], written completely. */
+int ising_init(int8_t* spins, int64_t L, uint64_t seed, void* stream);
+
+/* Cold start: every spin set to `value` (+1 or -1).  spins: device int8[L * L]. */
+int ising_fill(int8_t* spins, int64_t L, int value, void* stream);
+
+/* n_sweeps checkerboard Metropolis sweeps in place (Sec. 3.1 eq. 1, Sec. 3.2 Algorithm 1),
+ * sweep indices t = sweep_offset .. sweep_offset + n_sweeps - 1 (the counter word of the
+ * random numbers, so runs split into chunks reproduce an unsplit run bit for bit).
+ *   spins     device int8[L * L], updated in place.
+ *   beta      inverse temperature, finite and >= 0, or +inf (zero temperature).
+ *   n_sweeps  >= 0;  sweep_offset + n_sweeps <= 2^32.
+ *   trace_ME  device int64[2 * n_sweeps] receiving (M, E) after every sweep, or NULL.
+ *             M = sum of spins, E = -sum over the 2 L^2 nearest-neighbour bonds of
+ *             sigma_i sigma_j (Sec. 3 Hamiltonian with J = 1, mu = 0; Sec. 4.1 m = M / N). */
+int ising_sweep(int8_t* spins, int64_t L, double beta, int64_t n_sweeps, uint64_t seed,
+                uint64_t sweep_offset, int64_t* trace_ME, void* stream);
+
+/* One colour update (half of a sweep) for colour q in {0, 1} with sweep index t.
+ * Same arguments as ising_sweep otherwise; t < 2^32. */
+int ising_half_sweep(int8_t* spins, int64_t L, double beta, uint64_t seed, uint64_t t, int q,
+                     void* stream);
+
+/* out_ME: device int64[2] receiving (M, E) of the lattice (definitions as above, Sec. 3 and
+ * Sec. 4.1).  Exact integer sums; the result does not depend on the launch order. */
+int ising_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* stream);
+
+/* ---- 1-bit packed layout -----------------------------------------------------------------
+ * planes: device uint32[L * L / 32], two colour planes of L rows x (L / 64) words each:
+ * word (q * L + r) * (L / 64) + g holds the colour-q sites of row r with j = c >> 1 in
+ * [32 g, 32 g + 32); site i = j & 31 sits at bit 8 * (0, 2, 1, 3)[i & 3] + (i >> 2) (the bit
+ * position its uniform uses); a set bit is spin -1. */
+int ising_pack(const int8_t* spins, int64_t L, uint32_t* planes, void* stream);
+int ising_unpack(const uint32_t* planes, int64_t L, int8_t* spins, void* stream);
+
+/* The same chain as ising_sweep on the packed layout: identical spins after every sweep. */
+int ising_sweep_packed(uint32_t* planes, int64_t L, double beta, int64_t n_sweeps,
+                       uint64_t seed, uint64_t sweep_offset, int64_t* trace_ME, void* stream);
+
+/* (M, E) of a packed lattice into device int64[2]. */
+int ising_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME, void* stream);
+
+/* ---- host helpers -------------------------------------------------------------------------- */
+
+/* The two acceptance thresholds for beta: out[0] = T_2, out[1] = T_4 (each in [0, 2^32]),
+ * T_s = ceil(2^32 exp(-2 beta s)).  Host pointer.  Sec. 3.2, Algorithm 1. */
+int ising_thresholds(double beta, uint64_t out[2]);
+
+/* Text of the most recent ISING_EHIP failure on this thread (empty if none). */
+const char* ising_last_error(void);
+
+/* Static text for a status code. */
+const char* ising_strerror(int status);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int ising_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISING_H */

@@ -106,6 +106,7 @@ int oracle_init_site(uint64_t seed, uint32_t r, uint32_t c) {
 }
 
 void oracle_init(int8_t* spins, int64_t L, uint64_t seed) {
+#pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < L; ++r)
         for (int64_t c = 0; c < L; ++c)
             spins[r * L + c] = (int8_t)oracle_init_site(seed, (uint32_t)r, (uint32_t)c);

@@ -1,0 +1,22 @@
+"""MI355X-native checkerboard Metropolis sweep of the periodic 2D Ising model.
+
+The hot path (arXiv 1903.11714, Sec. 3.1-3.2) runs in hand-written HIP kernels for gfx950
+behind the C ABI in include/ising.h; ``paper_1903_11714_amd.ising`` is its ctypes binding.
+"""
+from . import ising  # noqa: F401
+from .ising import (  # noqa: F401
+    IsingError,
+    ising_fill,
+    ising_half_sweep,
+    ising_init,
+    ising_observables,
+    ising_observables_packed,
+    ising_pack,
+    ising_sweep,
+    ising_sweep_packed,
+    ising_thresholds,
+    ising_unpack,
+    ising_version,
+    new_lattice,
+    observables,
+)

@@ -1,0 +1,538 @@
+// ising.hip — checkerboard Metropolis sweep of the periodic 2D Ising model on gfx950.
+//
+// Paper: Yang, Chen, Roumpos, Colby, Anderson, "High Performance Monte Carlo Simulation of
+// Ising Model on TPU Clusters" (arXiv 1903.11714).  The update rule is Sec. 3.1 (eq. 1: with
+// one colour fixed, all sites of the other colour are independent; white first, then black)
+// and Sec. 3.2 Algorithm 1 (neighbour sum, accept where the uniform is below the Metropolis
+// ratio, flip).  The paper computes the neighbour sum with matrix products on the TPU's MXU;
+// here it is a bit-parallel stencil on the vector ALU, because the update is a memory-bound
+// 4-point integer stencil and not a dense contraction.
+//
+// int8 half-sweep kernel, one launch per colour:
+//   * a lane owns one 64-column segment ("group": its 32 same-colour sites share Philox
+//     blocks) of a strip of R consecutive rows and streams down the strip, so every row is
+//     read from HBM once per half-sweep (plus one halo row above and below the strip);
+//   * each row's 64 bytes are reduced to two 32-bit words of sign bits, one per colour, with
+//     one byte-permute per pair of dwords; the neighbour count, the acceptance decision and
+//     the observables all work on those bit words, 32 sites per instruction;
+//   * the site's 32-bit uniform is compared with its threshold one bit plane at a time, most
+//     significant first, four planes per Philox block, stopping as soon as no site of the
+//     wave is still tied with its threshold (the result is the exact x < T);
+//   * flips go back into the bytes with a sign-extending byte permute and one xor.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "ising.h"
+#include "philox.hpp"
+
+namespace ising {
+
+// ------------------------------------------------------------------------------------------
+// Bit-word helpers.  "Site order": site i (0..31) of a group sits at bit p(i) =
+// 8 * (0, 2, 1, 3)[i & 3] + (i >> 2), the bit position its uniform uses in each Philox word.
+
+struct Row {
+    uint32_t d[16];  // 64 bytes = one group of one row; dword k holds columns 4k .. 4k + 3
+};
+
+__device__ __forceinline__ uint32_t perm(uint32_t s0, uint32_t s1, uint32_t sel) {
+    return __builtin_amdgcn_perm(s0, s1, sel);
+}
+
+__device__ __forceinline__ void load_row(Row& row, const int8_t* p) {
+    const uint4* v = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint4 x = v[i];
+        row.d[4 * i + 0] = x.x;
+        row.d[4 * i + 1] = x.y;
+        row.d[4 * i + 2] = x.z;
+        row.d[4 * i + 3] = x.w;
+    }
+}
+
+__device__ __forceinline__ void store_row(int8_t* p, const Row& row) {
+    uint4* v = reinterpret_cast<uint4*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        v[i] = make_uint4(row.d[4 * i], row.d[4 * i + 1], row.d[4 * i + 2], row.d[4 * i + 3]);
+}
+
+// Sign bits (1 = spin -1) of the 32 sites at columns of parity OFF, in site order.
+// A +-1 byte is 0x01 or 0xFF, so bits 1..7 of the byte all equal its sign.
+template <int OFF>
+__device__ __forceinline__ uint32_t site_bits(const Row& row) {
+    // bytes of the compact word: (site 4k, site 4k+2, site 4k+1, site 4k+3)
+    constexpr uint32_t sel = OFF | ((4 + OFF) << 8) | ((OFF + 2) << 16) | ((6 + OFF) << 24);
+    uint32_t acc = (perm(row.d[1], row.d[0], sel) >> 1) & 0x01010101u;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) acc |= perm(row.d[2 * k + 1], row.d[2 * k], sel) & (0x01010101u << k);
+    return acc;
+}
+
+// S[p(i)] = y[p(i + 1)] for i < 31, S[p(31)] = bit0 (site 0 of the next group).
+__device__ __forceinline__ uint32_t shift_next(uint32_t y, uint32_t bit0) {
+    const uint32_t top = ((y >> 1) & 0x7Fu) | (bit0 << 7);
+    return perm(top, y, 0x04010302u);
+}
+
+// S[p(i)] = y[p(i - 1)] for i > 0, S[p(0)] = bit31 (site 31 of the previous group).
+__device__ __forceinline__ uint32_t shift_prev(uint32_t y, uint32_t bit31) {
+    const uint32_t low = ((y >> 23) & 0xFEu) | bit31;
+    return perm(y, low, 0x05040600u);
+}
+
+// Flip the colour-OFF bytes of `row` whose site bit is set in F.  The two sites of dword
+// 2k + h sit at bits k + 8h and k + 8h + 16; shifting them to bits 15 and 31 lets the
+// sign-extending selectors 8 and 9 of v_perm produce 0xFF at exactly those bytes.
+template <int OFF>
+__device__ __forceinline__ void apply_flips(Row& row, uint32_t F) {
+    constexpr uint32_t sel = OFF == 0 ? 0x0C090C08u : 0x090C080Cu;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t m = perm(0u, F << (15 - k - 8 * h), sel);
+            row.d[2 * k + h] ^= m & 0xFEFEFEFEu;  // 0x01 <-> 0xFF
+        }
+    }
+}
+
+__device__ __forceinline__ bool wave_any(bool v) { return __builtin_amdgcn_ballot_w64(v) != 0; }
+
+// Metropolis thresholds of one launch (uniform): a site with a anti-aligned neighbours has
+// s = 4 - 2a; a >= 2 always flips, a = 1 compares with T_2, a = 0 with T_4.
+struct Thresholds {
+    uint32_t t2, t4;      // low 32 bits of T_2, T_4
+    uint32_t full2, full4;  // 1 when T_s = 2^32 (always accept)
+};
+
+// Exact x < T for every site in sel2 (threshold T_2) or sel4 (T_4), bit plane by bit plane.
+// Returns the accepted sites.  Planes come four per Philox block with counter
+// (g, r, t, 2m + q), plane k = 4m + w is bit 31 - k of each site's uniform.
+__device__ __forceinline__ uint32_t accept_mask(uint32_t sel2, uint32_t sel4, const Thresholds& th,
+                                                uint32_t g, uint32_t r, uint32_t t, uint32_t q,
+                                                uint32_t key0, uint32_t key1) {
+    uint32_t acc = 0;
+    if (th.full2) { acc |= sel2; sel2 = 0; }
+    if (th.full4) { acc |= sel4; sel4 = 0; }
+    uint32_t tied = sel2 | sel4;
+#pragma unroll 1
+    for (uint32_t m = 0; m < 8; ++m) {
+        if (!wave_any(tied != 0)) break;
+        const Words4 blk = philox4x32_10(g, r, t, 2u * m + q, key0, key1);
+        const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t k = 4u * m + (uint32_t)w;
+            const uint32_t b2 = (th.t2 >> (31u - k)) & 1u;
+            const uint32_t b4 = (th.t4 >> (31u - k)) & 1u;
+            const uint32_t tbit = (b2 ? sel2 : 0u) | (b4 ? sel4 : 0u);  // threshold bit per site
+            const uint32_t x = planes[w];
+            acc |= tied & tbit & ~x;   // first difference: x has 0 where T has 1 -> x < T
+            tied &= ~(x ^ tbit);       // still equal so far
+        }
+    }
+    return acc;
+}
+
+struct Counts {
+    uint32_t anti;  // anti-aligned bonds seen from this colour's sites after the update
+    uint32_t neg;   // spins equal to -1 in the rows processed
+};
+
+// One row of the half-sweep for colour Q.  O = column parity of the colour-Q sites of this row.
+// bprev: row r-1 sites at parity O (vertical neighbours), bcur: row r sites at parity 1-O
+// (horizontal neighbours).  Returns row r+1's sites at parity O (the next row's bcur).
+template <int Q, int O, bool OBS>
+__device__ __forceinline__ uint32_t sweep_row(Row& cur, const Row& nxt, uint32_t bprev, uint32_t bcur,
+                                              uint32_t halo, const Thresholds& th, uint32_t g,
+                                              uint32_t r, uint32_t t, uint32_t key0, uint32_t key1,
+                                              Counts& cnt) {
+    const uint32_t bnext = site_bits<O>(nxt);
+    const uint32_t a = site_bits<O>(cur);
+    // horizontal neighbour that lies in the adjacent group: byte 0 of the right halo dword
+    // (O = 1) or byte 3 of the left halo dword (O = 0); bit 1 of a byte is its sign
+    const uint32_t hs = O == 1 ? shift_next(bcur, (halo >> 1) & 1u) : shift_prev(bcur, (halo >> 25) & 1u);
+    const uint32_t x1 = a ^ bprev, x2 = a ^ bnext, x3 = a ^ bcur, x4 = a ^ hs;  // anti-aligned
+    const uint32_t o12 = x1 | x2, o34 = x3 | x4;
+    const uint32_t ge2 = (x1 & x2) | (x3 & x4) | (o12 & o34);  // >= 2 anti-aligned: s <= 0
+    const uint32_t any = o12 | o34;
+    const uint32_t sel2 = any & ~ge2;                            // exactly one: s = 2
+    const uint32_t sel4 = ~any;                                  // none: s = 4
+    const uint32_t F = ge2 | accept_mask(sel2, sel4, th, g, r, t, (uint32_t)Q, key0, key1);
+    apply_flips<O>(cur, F);
+    if (OBS) {
+        cnt.anti += __builtin_popcount(x1 ^ F) + __builtin_popcount(x2 ^ F) +
+                    __builtin_popcount(x3 ^ F) + __builtin_popcount(x4 ^ F);
+        cnt.neg += __builtin_popcount(a ^ F) + __builtin_popcount(bcur);
+    }
+    return bnext;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-level sum of (anti, neg) -> one pair of 64-bit atomics per block.
+// sites_per_lane: sites each active lane covered; bonds: 2 per site.
+__device__ __forceinline__ void block_accumulate(int64_t* out, uint32_t anti, uint32_t neg, uint32_t active,
+                                                 uint32_t sites_per_lane) {
+    __shared__ uint32_t red[3][8];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    anti = wave_sum(anti);
+    neg = wave_sum(neg);
+    active = wave_sum(active);
+    if (lane == 0) { red[0][wave] = anti; red[1][wave] = neg; red[2][wave] = active; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t A = 0, Nn = 0, act = 0;
+        for (uint32_t w = 0; w < blockDim.x / 64u; ++w) { A += red[0][w]; Nn += red[1][w]; act += red[2][w]; }
+        const int64_t sites = (int64_t)act * sites_per_lane;
+        const int64_t M = sites - 2 * (int64_t)Nn;            // sum of spins
+        const int64_t E = 2 * (int64_t)A - 2 * sites;         // #anti - #aligned over 2 bonds/site
+        atomicAdd(reinterpret_cast<unsigned long long*>(out), (unsigned long long)M);
+        atomicAdd(reinterpret_cast<unsigned long long*>(out + 1), (unsigned long long)E);
+    }
+}
+
+struct SweepArgs {
+    int8_t* spins;
+    uint32_t L, groups, rows, n_lanes;  // rows = rows per lane (even, divides L)
+    uint32_t t, key0, key1;
+    Thresholds th;
+    int64_t* obs;        // OBS: (M, E) accumulator, zeroed beforehand
+    int64_t* zero_slot;  // if non-null, block 0 zeroes these two int64 (a later launch's obs)
+};
+
+template <int Q, bool OBS>
+__global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
+    const uint32_t lane_id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a.zero_slot && lane_id == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
+    const bool active = lane_id < a.n_lanes;
+    Counts cnt{0u, 0u};
+    if (active) {
+        const uint32_t g = lane_id % a.groups;
+        const uint32_t strip = lane_id / a.groups;
+        const uint32_t L = a.L;
+        const uint32_t r0 = strip * a.rows;
+        const uint32_t gl = g == 0 ? a.groups - 1 : g - 1;
+        const uint32_t gr = g + 1 == a.groups ? 0 : g + 1;
+        int8_t* const col = a.spins + (size_t)g * 64u;
+        auto rowp = [&](uint32_t r) { return col + (size_t)r * L; };
+        auto halo_left = [&](uint32_t r) {
+            return *reinterpret_cast<const uint32_t*>(a.spins + (size_t)r * L + (size_t)gl * 64u + 60u);
+        };
+        auto halo_right = [&](uint32_t r) {
+            return *reinterpret_cast<const uint32_t*>(a.spins + (size_t)r * L + (size_t)gr * 64u);
+        };
+        // rows r0 (parity offset Q, since r0 is even) and r0 + 1 (offset 1 - Q) alternate
+        constexpr int O0 = Q, O1 = 1 - Q;
+        Row above, cur, nxt;
+        load_row(above, rowp(r0 == 0 ? L - 1 : r0 - 1));
+        load_row(cur, rowp(r0));
+        load_row(nxt, rowp(r0 + 1 == L ? 0 : r0 + 1));
+        uint32_t bprev = site_bits<O0>(above);
+        uint32_t bcur = site_bits<O1>(cur);
+#pragma unroll 1
+        for (uint32_t s = 0; s < a.rows; s += 2) {
+            const uint32_t r = r0 + s;
+            Row n2;
+            load_row(n2, rowp(r + 2 >= L ? r + 2 - L : r + 2));
+            const uint32_t h0 = O0 == 1 ? halo_right(r) : halo_left(r);
+            uint32_t bn = sweep_row<Q, O0, OBS>(cur, nxt, bprev, bcur, h0, a.th, g, r, a.t, a.key0, a.key1, cnt);
+            store_row(rowp(r), cur);
+            bprev = bcur;
+            bcur = bn;
+            // row r + 1
+            Row n3;
+            load_row(n3, rowp(r + 3 >= L ? r + 3 - L : r + 3));
+            const uint32_t h1 = O1 == 1 ? halo_right(r + 1) : halo_left(r + 1);
+            bn = sweep_row<Q, O1, OBS>(nxt, n2, bprev, bcur, h1, a.th, g, r + 1, a.t, a.key0, a.key1, cnt);
+            store_row(rowp(r + 1), nxt);
+            bprev = bcur;
+            bcur = bn;
+            cur = n2;
+            nxt = n3;
+        }
+    }
+    if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, active ? 1u : 0u, 64u * a.rows);
+}
+
+// ---- observables of an int8 lattice: M = sum of spins, E = -sum over bonds (right, down).
+struct ObsArgs {
+    const int8_t* spins;
+    uint32_t L, groups, rows, n_lanes;
+    int64_t* out;
+};
+
+__global__ __launch_bounds__(256) void k_observables_int8(ObsArgs a) {
+    const uint32_t lane_id = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = lane_id < a.n_lanes;
+    uint32_t anti = 0, neg = 0;
+    if (active) {
+        const uint32_t g = lane_id % a.groups;
+        const uint32_t strip = lane_id / a.groups;
+        const uint32_t L = a.L;
+        const uint32_t gr = g + 1 == a.groups ? 0 : g + 1;
+        const int8_t* col = a.spins + (size_t)g * 64u;
+        Row cur, dn;
+        uint32_t r = strip * a.rows;
+        load_row(cur, col + (size_t)r * L);
+#pragma unroll 1
+        for (uint32_t s = 0; s < a.rows; ++s, ++r) {
+            const uint32_t rd = r + 1 == L ? 0 : r + 1;
+            load_row(dn, col + (size_t)rd * L);
+            const uint32_t right = *reinterpret_cast<const uint32_t*>(a.spins + (size_t)r * L + (size_t)gr * 64u);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t nb = k < 15 ? cur.d[k + 1] : right;
+                const uint32_t rn = __builtin_amdgcn_alignbyte(nb, cur.d[k], 1);  // right neighbours
+                neg += __builtin_popcount(cur.d[k] & 0x80808080u);
+                anti += __builtin_popcount((cur.d[k] ^ rn) & 0x80808080u);
+                anti += __builtin_popcount((cur.d[k] ^ dn.d[k]) & 0x80808080u);
+            }
+            cur = dn;
+        }
+    }
+    // every site contributes 2 bonds; block_accumulate converts counts to (M, E)
+    block_accumulate(a.out, anti, neg, active ? 1u : 0u, 64u * a.rows);
+}
+
+__global__ void k_zero2(int64_t* p) {
+    if (threadIdx.x == 0) { p[0] = 0; p[1] = 0; }
+}
+
+// ---- hot start: bit (c & 31) of word (c >> 5) & 3 of Philox(c >> 7, r, 0, 0x80000000).
+__device__ __forceinline__ uint32_t nibble_to_bytes(uint32_t nib) {
+    const uint32_t t = (nib * 0x00204081u) & 0x01010101u;  // bit j -> byte j (no carries)
+    return 0x01010101u | (t * 0xFEu);                         // 0x01 for +1, 0xFF for -1
+}
+
+__global__ __launch_bounds__(256) void k_init_int8(int8_t* spins, uint32_t L, uint32_t chunks,
+                                                   uint64_t n_lanes, uint32_t key0, uint32_t key1) {
+    const uint64_t lane_id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane_id >= n_lanes) return;
+    const uint32_t cb = (uint32_t)(lane_id % chunks);
+    const uint32_t r = (uint32_t)(lane_id / chunks);
+    const Words4 w = philox4x32_10(cb, r, 0u, 0x80000000u, key0, key1);
+    const uint32_t words[4] = {w.w0, w.w1, w.w2, w.w3};
+    int8_t* p = spins + (size_t)r * L + (size_t)cb * 128u;
+    const uint32_t n_words = (cb * 128u + 128u <= L) ? 4u : 2u;  // L % 64 == 0
+    for (uint32_t i = 0; i < n_words; ++i) {
+        uint4* v = reinterpret_cast<uint4*>(p + 32u * i);
+        const uint32_t x = words[i];
+        v[0] = make_uint4(nibble_to_bytes(x & 15u), nibble_to_bytes((x >> 4) & 15u),
+                          nibble_to_bytes((x >> 8) & 15u), nibble_to_bytes((x >> 12) & 15u));
+        v[1] = make_uint4(nibble_to_bytes((x >> 16) & 15u), nibble_to_bytes((x >> 20) & 15u),
+                          nibble_to_bytes((x >> 24) & 15u), nibble_to_bytes(x >> 28));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_int8(int8_t* spins, uint64_t n16, uint32_t word) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        reinterpret_cast<uint4*>(spins)[i] = make_uint4(word, word, word, word);
+}
+
+}  // namespace ising
+
+// ==========================================================================================
+// Host side: validation, thresholds, launches.
+namespace {
+
+thread_local std::string g_last_error;
+
+int hip_failed(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return ISING_EHIP;
+}
+
+int check_launch(const char* what) {
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ISING_OK : hip_failed(e, what);
+}
+
+bool valid_L(int64_t L) { return L >= 64 && L % 64 == 0 && L <= (int64_t(1) << 20); }
+
+bool valid_beta(double beta) { return !std::isnan(beta) && beta >= 0.0; }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+void host_thresholds(double beta, uint64_t T[2]) {
+    for (int k = 0; k < 2; ++k) {
+        const double s = k == 0 ? 2.0 : 4.0;
+        double y = std::ceil(std::ldexp(std::exp(-2.0 * beta * s), 32));
+        if (y > 4294967296.0) y = 4294967296.0;
+        if (!(y >= 0.0)) y = 0.0;
+        T[k] = (uint64_t)y;
+    }
+}
+
+ising::Thresholds make_thresholds(double beta) {
+    uint64_t T[2];
+    host_thresholds(beta, T);
+    ising::Thresholds th;
+    th.full2 = T[0] >= (uint64_t(1) << 32);
+    th.full4 = T[1] >= (uint64_t(1) << 32);
+    th.t2 = th.full2 ? 0u : (uint32_t)T[0];
+    th.t4 = th.full4 ? 0u : (uint32_t)T[1];
+    return th;
+}
+
+// rows per lane for the streaming kernels: even, divides L (L % 64 == 0)
+uint32_t rows_per_lane(int64_t L) {
+    const uint32_t groups = (uint32_t)(L / 64);
+    // keep at least ~2048 workgroups' worth of lanes when the lattice allows it
+    uint32_t R = 32;
+    while (R > 2 && (uint64_t)groups * (uint64_t)(L / R) < 2048ull * 256ull) R >>= 1;
+    return R;
+}
+
+int launch_half_sweep(int8_t* spins, int64_t L, const ising::Thresholds& th, uint64_t seed, uint32_t t,
+                      int q, int64_t* obs, int64_t* zero_slot, hipStream_t stream) {
+    ising::SweepArgs a;
+    a.spins = spins;
+    a.L = (uint32_t)L;
+    a.groups = (uint32_t)(L / 64);
+    a.rows = rows_per_lane(L);
+    a.n_lanes = a.groups * (uint32_t)(L / a.rows);
+    a.t = t;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.th = th;
+    a.obs = obs;
+    a.zero_slot = zero_slot;
+    const dim3 grid((a.n_lanes + 255u) / 256u), block(256);
+    if (q == 1) {
+        if (obs) hipLaunchKernelGGL((ising::k_sweep_int8<1, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((ising::k_sweep_int8<1, false>), grid, block, 0, stream, a);
+    } else {
+        if (obs) hipLaunchKernelGGL((ising::k_sweep_int8<0, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((ising::k_sweep_int8<0, false>), grid, block, 0, stream, a);
+    }
+    return check_launch("k_sweep_int8");
+}
+
+}  // namespace
+
+extern "C" {
+
+int ising_thresholds(double beta, uint64_t out[2]) {
+    if (!out || !valid_beta(beta)) return ISING_EINVAL;
+    host_thresholds(beta, out);
+    return ISING_OK;
+}
+
+int ising_init(int8_t* spins, int64_t L, uint64_t seed, void* stream) {
+    if (!spins || !valid_L(L) || !aligned16(spins)) return ISING_EINVAL;
+    const uint32_t chunks = (uint32_t)((L + 127) / 128);
+    const uint64_t n_lanes = (uint64_t)chunks * (uint64_t)L;
+    const dim3 grid((unsigned)((n_lanes + 255) / 256)), block(256);
+    hipLaunchKernelGGL(ising::k_init_int8, grid, block, 0, (hipStream_t)stream, spins, (uint32_t)L, chunks,
+                       n_lanes, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return check_launch("k_init_int8");
+}
+
+int ising_fill(int8_t* spins, int64_t L, int value, void* stream) {
+    if (!spins || !valid_L(L) || !aligned16(spins) || (value != 1 && value != -1)) return ISING_EINVAL;
+    const uint64_t n16 = (uint64_t)L * (uint64_t)L / 16u;
+    const uint32_t word = value == 1 ? 0x01010101u : 0xFFFFFFFFu;
+    uint64_t blocks = (n16 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(ising::k_fill_int8, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, spins,
+                       n16, word);
+    return check_launch("k_fill_int8");
+}
+
+int ising_half_sweep(int8_t* spins, int64_t L, double beta, uint64_t seed, uint64_t t, int q, void* stream) {
+    if (!spins || !valid_L(L) || !aligned16(spins) || !valid_beta(beta) || (q != 0 && q != 1) ||
+        t >= (uint64_t(1) << 32))
+        return ISING_EINVAL;
+    return launch_half_sweep(spins, L, make_thresholds(beta), seed, (uint32_t)t, q, nullptr, nullptr,
+                             (hipStream_t)stream);
+}
+
+int ising_sweep(int8_t* spins, int64_t L, double beta, int64_t n_sweeps, uint64_t seed, uint64_t sweep_offset,
+                int64_t* trace_ME, void* stream) {
+    if (!spins || !valid_L(L) || !aligned16(spins) || !valid_beta(beta) || n_sweeps < 0 ||
+        sweep_offset > (uint64_t(1) << 32) || (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset)
+        return ISING_EINVAL;
+    const ising::Thresholds th = make_thresholds(beta);
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t i = 0; i < n_sweeps; ++i) {
+        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
+        int64_t* slot = trace_ME ? trace_ME + 2 * i : nullptr;
+        int rc = launch_half_sweep(spins, L, th, seed, t, 1, nullptr, slot, s);  // white
+        if (rc) return rc;
+        rc = launch_half_sweep(spins, L, th, seed, t, 0, slot, nullptr, s);      // black (+ M, E)
+        if (rc) return rc;
+    }
+    return ISING_OK;
+}
+
+int ising_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* stream) {
+    if (!spins || !out_ME || !valid_L(L) || !aligned16(spins)) return ISING_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(ising::k_zero2, dim3(1), dim3(64), 0, s, out_ME);
+    int rc = check_launch("k_zero2");
+    if (rc) return rc;
+    ising::ObsArgs a;
+    a.spins = spins;
+    a.L = (uint32_t)L;
+    a.groups = (uint32_t)(L / 64);
+    a.rows = rows_per_lane(L);
+    a.n_lanes = a.groups * (uint32_t)(L / a.rows);
+    a.out = out_ME;
+    hipLaunchKernelGGL(ising::k_observables_int8, dim3((a.n_lanes + 255u) / 256u), dim3(256), 0, s, a);
+    return check_launch("k_observables_int8");
+}
+
+int ising_pack(const int8_t* spins, int64_t L, uint32_t* planes, void* stream) {
+    if (!spins || !planes || !valid_L(L) || !aligned16(spins) || !aligned16(planes)) return ISING_EINVAL;
+    (void)stream;
+    return ISING_EUNSUPPORTED;
+}
+
+int ising_unpack(const uint32_t* planes, int64_t L, int8_t* spins, void* stream) {
+    if (!spins || !planes || !valid_L(L) || !aligned16(spins) || !aligned16(planes)) return ISING_EINVAL;
+    (void)stream;
+    return ISING_EUNSUPPORTED;
+}
+
+int ising_sweep_packed(uint32_t* planes, int64_t L, double beta, int64_t n_sweeps, uint64_t seed,
+                       uint64_t sweep_offset, int64_t* trace_ME, void* stream) {
+    if (!planes || !valid_L(L) || !aligned16(planes) || !valid_beta(beta) || n_sweeps < 0 ||
+        sweep_offset > (uint64_t(1) << 32) || (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset)
+        return ISING_EINVAL;
+    (void)seed; (void)trace_ME; (void)stream;
+    return ISING_EUNSUPPORTED;
+}
+
+int ising_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME, void* stream) {
+    if (!planes || !out_ME || !valid_L(L) || !aligned16(planes)) return ISING_EINVAL;
+    (void)stream;
+    return ISING_EUNSUPPORTED;
+}
+
+const char* ising_last_error(void) { return g_last_error.c_str(); }
+
+const char* ising_strerror(int status) {
+    switch (status) {
+        case ISING_OK: return "ok";
+        case ISING_EINVAL: return "invalid argument";
+        case ISING_EHIP: return "HIP runtime error";
+        case ISING_EUNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+int ising_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,182 @@
+"""Thin ctypes binding of ``libising.so`` (the C ABI declared in include/ising.h).
+
+Argument marshalling only: every step of the sweep runs in the HIP kernels of the library.
+PyTorch supplies device memory and the stream.  There is no fallback: if the library is not
+built, or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libising.so")
+
+ISING_OK = 0
+ISING_EINVAL = -1
+ISING_EHIP = -2
+ISING_EUNSUPPORTED = -3
+
+_lib = None
+
+
+class IsingError(RuntimeError):
+    def __init__(self, func: str, status: int, detail: str = ""):
+        self.status = status
+        msg = f"{func} failed with status {status}"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+_SIGNATURES = {
+    "ising_init": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p], ctypes.c_int),
+    "ising_fill": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "ising_sweep": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64,
+                     ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising_half_sweep": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                          ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "ising_observables": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising_pack": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising_unpack": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising_sweep_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64,
+                            ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising_observables_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
+                                 ctypes.c_int),
+    "ising_thresholds": ([ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "ising_last_error": ([], ctypes.c_char_p),
+    "ising_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "ising_version": ([], ctypes.c_int),
+}
+
+
+def library():
+    """Load libising.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1903_11714_amd.build.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(name: str, status: int) -> None:
+    if status != ISING_OK:
+        lib = library()
+        detail = lib.ising_strerror(status).decode()
+        if status == ISING_EHIP:
+            detail += " (" + lib.ising_last_error().decode() + ")"
+        raise IsingError(name, status, detail)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype_name: str, numel: int | None = None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if str(t.dtype) != dtype_name:
+        raise TypeError(f"expected dtype {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opt_ptr(t, dtype_name: str, numel: int):
+    return None if t is None else _dev_ptr(t, dtype_name, numel)
+
+
+# ---- same names as the C ABI -----------------------------------------------------------------
+
+def ising_init(spins, L: int, seed: int, stream=None) -> None:
+    _check("ising_init", library().ising_init(_dev_ptr(spins, "torch.int8", L * L), L, seed, _stream(stream)))
+
+
+def ising_fill(spins, L: int, value: int, stream=None) -> None:
+    _check("ising_fill", library().ising_fill(_dev_ptr(spins, "torch.int8", L * L), L, value, _stream(stream)))
+
+
+def ising_sweep(spins, L: int, beta: float, n_sweeps: int, seed: int, sweep_offset: int = 0,
+                trace_ME=None, stream=None) -> None:
+    _check("ising_sweep", library().ising_sweep(
+        _dev_ptr(spins, "torch.int8", L * L), L, float(beta), n_sweeps, seed, sweep_offset,
+        _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
+
+
+def ising_half_sweep(spins, L: int, beta: float, seed: int, t: int, q: int, stream=None) -> None:
+    _check("ising_half_sweep", library().ising_half_sweep(
+        _dev_ptr(spins, "torch.int8", L * L), L, float(beta), seed, t, q, _stream(stream)))
+
+
+def ising_observables(spins, L: int, out_ME, stream=None) -> None:
+    _check("ising_observables", library().ising_observables(
+        _dev_ptr(spins, "torch.int8", L * L), L, _dev_ptr(out_ME, "torch.int64", 2), _stream(stream)))
+
+
+def ising_pack(spins, L: int, planes, stream=None) -> None:
+    _check("ising_pack", library().ising_pack(
+        _dev_ptr(spins, "torch.int8", L * L), L, _dev_ptr(planes, "torch.int32", L * L // 32), _stream(stream)))
+
+
+def ising_unpack(planes, L: int, spins, stream=None) -> None:
+    _check("ising_unpack", library().ising_unpack(
+        _dev_ptr(planes, "torch.int32", L * L // 32), L, _dev_ptr(spins, "torch.int8", L * L), _stream(stream)))
+
+
+def ising_sweep_packed(planes, L: int, beta: float, n_sweeps: int, seed: int, sweep_offset: int = 0,
+                       trace_ME=None, stream=None) -> None:
+    _check("ising_sweep_packed", library().ising_sweep_packed(
+        _dev_ptr(planes, "torch.int32", L * L // 32), L, float(beta), n_sweeps, seed, sweep_offset,
+        _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
+
+
+def ising_observables_packed(planes, L: int, out_ME, stream=None) -> None:
+    _check("ising_observables_packed", library().ising_observables_packed(
+        _dev_ptr(planes, "torch.int32", L * L // 32), L, _dev_ptr(out_ME, "torch.int64", 2), _stream(stream)))
+
+
+def ising_thresholds(beta: float) -> tuple[int, int]:
+    out = (ctypes.c_uint64 * 2)()
+    _check("ising_thresholds", library().ising_thresholds(float(beta), out))
+    return int(out[0]), int(out[1])
+
+
+def ising_version() -> int:
+    return int(library().ising_version())
+
+
+# ---- conveniences built only from the calls above ---------------------------------------------
+
+def new_lattice(L: int, seed: int | None = None, device: str = "cuda"):
+    """Allocate an L x L int8 lattice; hot start from `seed`, or all +1 when seed is None."""
+    import torch
+    spins = torch.empty((L, L), dtype=torch.int8, device=device)
+    if seed is None:
+        ising_fill(spins, L, 1)
+    else:
+        ising_init(spins, L, seed)
+    return spins
+
+
+def observables(spins) -> tuple[int, int]:
+    """(M, E) of an int8 lattice; synchronises to read the result."""
+    import torch
+    L = spins.shape[-1]
+    out = torch.empty(2, dtype=torch.int64, device=spins.device)
+    ising_observables(spins, L, out)
+    M, E = out.tolist()
+    return int(M), int(E)

@@ -1,0 +1,87 @@
+"""The C-ABI library loads, exports every symbol include/ising.h declares, and its host-side
+logic (argument checks, thresholds) behaves as documented.  No GPU is needed: every call
+here returns before touching the HIP runtime.
+"""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ising.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1903_11714_amd import ising
+    if not os.path.exists(ising.LIB_PATH):
+        pytest.fail("libising.so is not built (run __graft_entry__.build())")
+    return ising.library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ising_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("ising_init", "ising_sweep", "ising_observables", "ising_pack", "ising_unpack",
+                     "ising_sweep_packed", "ising_observables_packed", "ising_thresholds"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_strerror(lib):
+    assert lib.ising_version() >= 100
+    assert lib.ising_strerror(0) == b"ok"
+    assert lib.ising_strerror(-1) == b"invalid argument"
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.1, 0.3, 0.44068679350977147, 0.5, 1 / 2.6, 2.0, math.inf])
+def test_library_thresholds_match_oracle(oracle_lib, beta):
+    from paper_1903_11714_amd import ising
+    assert ising.ising_thresholds(beta) == oracle_lib.thresholds(beta)
+
+
+def test_thresholds_reject_bad_beta(lib):
+    out = (ctypes.c_uint64 * 2)()
+    assert lib.ising_thresholds(float("nan"), out) == -1
+    assert lib.ising_thresholds(-0.1, out) == -1
+    assert lib.ising_thresholds(0.4, None) == -1
+
+
+def test_argument_checks_before_any_launch(lib):
+    fake = ctypes.c_void_p(4096)          # never dereferenced: validation fails first
+    null = ctypes.c_void_p(0)
+    EINVAL = -1
+    assert lib.ising_init(null, 64, 1, null) == EINVAL
+    assert lib.ising_init(fake, 60, 1, null) == EINVAL               # L % 64 != 0
+    assert lib.ising_init(fake, 0, 1, null) == EINVAL
+    assert lib.ising_init(ctypes.c_void_p(4097), 64, 1, null) == EINVAL  # misaligned
+    assert lib.ising_fill(fake, 64, 0, null) == EINVAL               # value must be +-1
+    assert lib.ising_sweep(fake, 64, float("nan"), 1, 1, 0, null, null) == EINVAL
+    assert lib.ising_sweep(fake, 64, -1.0, 1, 1, 0, null, null) == EINVAL
+    assert lib.ising_sweep(fake, 64, 0.4, -1, 1, 0, null, null) == EINVAL
+    assert lib.ising_sweep(fake, 64, 0.4, 2, 1, 2**32 - 1, null, null) == EINVAL  # t overflows
+    assert lib.ising_sweep(fake, 96, 0.4, 1, 1, 0, null, null) == EINVAL
+    assert lib.ising_half_sweep(fake, 64, 0.4, 1, 0, 2, null) == EINVAL
+    assert lib.ising_half_sweep(fake, 64, 0.4, 1, 2**32, 0, null) == EINVAL
+    assert lib.ising_observables(fake, 64, null, null) == EINVAL
+    assert lib.ising_pack(fake, 64, null, null) == EINVAL
+    assert lib.ising_unpack(null, 64, fake, null) == EINVAL
+    assert lib.ising_sweep_packed(null, 64, 0.4, 1, 1, 0, null, null) == EINVAL
+    assert lib.ising_observables_packed(fake, 32, fake, null) == EINVAL
+
+
+def test_zero_sweeps_is_a_no_op(lib):
+    # n_sweeps = 0 enqueues nothing, so it succeeds without touching the device.
+    fake = ctypes.c_void_p(4096)
+    assert lib.ising_sweep(fake, 64, 0.4, 0, 1, 0, ctypes.c_void_p(0), ctypes.c_void_p(0)) == 0
