@@ -92,6 +92,18 @@ int ising_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME,
  * T_s = ceil(2^32 exp(-2 beta s)).  Host pointer.  Sec. 3.2, Algorithm 1. */
 int ising_thresholds(double beta, uint64_t out[2]);
 
+/* Launch-shape options of the int8 kernels, process-wide; results are bit-identical for every
+ * valid setting (the random numbers depend only on site, sweep and colour).  Not thread-safe
+ * against concurrent launches.
+ *   "rows_per_lane"  rows each lane streams through: 0 = automatic, else a power of two in
+ *                    [2, 64] (ignored for lattices it does not divide).
+ *   "xcd_remap"      1 = hand each XCD one contiguous range of row strips (default), 0 = not.
+ *   "nt_store"       1 = non-temporal stores of updated rows, 0 = ordinary stores (default).
+ *   "staged"         1 = coalesced row loads and stores regrouped through LDS when L is a
+ *                    multiple of 4096 (default), 0 = every lane reads its own 64 bytes. */
+int ising_set_option(const char* name, int64_t value);
+int ising_get_option(const char* name, int64_t* value);
+
 /* Text of the most recent ISING_EHIP failure on this thread (empty if none). */
 const char* ising_last_error(void);
 

@@ -7,6 +7,8 @@ from . import ising  # noqa: F401
 from .ising import (  # noqa: F401
     IsingError,
     ising_fill,
+    ising_get_option,
+    ising_set_option,
     ising_half_sweep,
     ising_init,
     ising_observables,

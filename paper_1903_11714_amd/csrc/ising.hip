@@ -55,11 +55,93 @@ __device__ __forceinline__ void load_row(Row& row, const int8_t* p) {
     }
 }
 
-__device__ __forceinline__ void store_row(int8_t* p, const Row& row) {
-    uint4* v = reinterpret_cast<uint4*>(p);
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void store_row(int8_t* p, const Row& row, bool streaming) {
+    u32x4* v = reinterpret_cast<u32x4*>(p);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        v[i] = make_uint4(row.d[4 * i], row.d[4 * i + 1], row.d[4 * i + 2], row.d[4 * i + 3]);
+    for (int i = 0; i < 4; ++i) {
+        const u32x4 x = {row.d[4 * i], row.d[4 * i + 1], row.d[4 * i + 2], row.d[4 * i + 3]};
+        if (streaming) __builtin_nontemporal_store(x, v + i);
+        else v[i] = x;
+    }
+}
+
+// ---- Coalesced row I/O through LDS.  When a wave's 64 lanes own 64 consecutive groups of
+// one row (4 KiB), loading "64 contiguous bytes per lane" wastes most of every memory
+// instruction.  Instead lane l moves 16-byte chunks l, l + 64, l + 128, l + 192 of the wave's
+// row segment (each instruction covers 1 KiB contiguous) and the bytes are regrouped per lane
+// through a 4 KiB per-wave LDS buffer.  Chunk c belongs to lane c / 4, quarter c % 4, and is
+// kept in LDS slot 4 (c / 4) + ((c % 4 + c / 8) mod 4): any 8 consecutive lanes then touch 8
+// distinct 16-byte bank groups on both the write and the read side.
+__device__ __forceinline__ uint32_t lds_slot(uint32_t owner, uint32_t quarter) {
+    return 4u * owner + ((quarter + (owner >> 1)) & 3u);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// raw: this lane's four coalesced chunks (chunk l + 64 k in raw.d[4k .. 4k + 3]).
+__device__ __forceinline__ void load_row_coalesced(Row& raw, const int8_t* seg, uint32_t lane) {
+    const uint4* v = reinterpret_cast<const uint4*>(seg) + lane;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint4 x = v[64 * k];
+        raw.d[4 * k + 0] = x.x;
+        raw.d[4 * k + 1] = x.y;
+        raw.d[4 * k + 2] = x.z;
+        raw.d[4 * k + 3] = x.w;
+    }
+}
+
+// coalesced chunks -> this lane's own 64 bytes
+__device__ __forceinline__ void regroup_to_owner(Row& row, const Row& raw, uint4* lds, uint32_t lane) {
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t c = lane + 64u * k;
+        lds[lds_slot(c >> 2, c & 3u)] = make_uint4(raw.d[4 * k], raw.d[4 * k + 1], raw.d[4 * k + 2], raw.d[4 * k + 3]);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+        const uint4 x = lds[lds_slot(lane, q)];
+        row.d[4 * q + 0] = x.x;
+        row.d[4 * q + 1] = x.y;
+        row.d[4 * q + 2] = x.z;
+        row.d[4 * q + 3] = x.w;
+    }
+    wave_lds_sync();
+}
+
+// this lane's own 64 bytes -> coalesced stores of the wave's row segment
+__device__ __forceinline__ void store_row_coalesced(int8_t* seg, const Row& row, uint4* lds, uint32_t lane,
+                                                    bool streaming) {
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q)
+        lds[lds_slot(lane, q)] = make_uint4(row.d[4 * q], row.d[4 * q + 1], row.d[4 * q + 2], row.d[4 * q + 3]);
+    wave_lds_sync();
+    u32x4* v = reinterpret_cast<u32x4*>(seg) + lane;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t c = lane + 64u * k;
+        const uint4 x = lds[lds_slot(c >> 2, c & 3u)];
+        const u32x4 y = {x.x, x.y, x.z, x.w};
+        if (streaming) __builtin_nontemporal_store(y, v + 64 * k);
+        else v[64 * k] = y;
+    }
+    wave_lds_sync();
+}
+
+// Workgroups are dispatched to the eight XCDs round robin (block b runs on XCD b mod 8).
+// Renumbering them so that each XCD receives one contiguous range of logical blocks keeps
+// neighbouring row strips, which read each other's boundary rows, inside one L2.
+__device__ __forceinline__ uint32_t logical_block(uint32_t b, uint32_t nb, bool remap) {
+    if (!remap) return b;
+    const uint32_t x = b & 7u, i = b >> 3, per = nb >> 3, rem = nb & 7u;
+    return x * per + (x < rem ? x : rem) + i;
 }
 
 // Sign bits (1 = spin -1) of the 32 sites at columns of parity OFF, in site order.
@@ -121,6 +203,7 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t sel2, uint32_t sel4, co
     if (th.full2) { acc |= sel2; sel2 = 0; }
     if (th.full4) { acc |= sel4; sel4 = 0; }
     uint32_t tied = sel2 | sel4;
+    // sites outside sel2 are compared with T_4 below; make sure only tied ones matter
 #pragma unroll 1
     for (uint32_t m = 0; m < 8; ++m) {
         if (!wave_any(tied != 0)) break;
@@ -129,9 +212,11 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t sel2, uint32_t sel4, co
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
             const uint32_t k = 4u * m + (uint32_t)w;
-            const uint32_t b2 = (th.t2 >> (31u - k)) & 1u;
-            const uint32_t b4 = (th.t4 >> (31u - k)) & 1u;
-            const uint32_t tbit = (b2 ? sel2 : 0u) | (b4 ? sel4 : 0u);  // threshold bit per site
+            // threshold bit of every site: bit 31 - k of T_2 on sel2, of T_4 elsewhere (the
+            // value outside sel2 | sel4 is never used because those sites are not tied)
+            const uint32_t m2 = 0u - ((th.t2 >> (31u - k)) & 1u);
+            const uint32_t m4 = 0u - ((th.t4 >> (31u - k)) & 1u);
+            const uint32_t tbit = (sel2 & m2) | (~sel2 & m4);
             const uint32_t x = planes[w];
             acc |= tied & tbit & ~x;   // first difference: x has 0 where T has 1 -> x < T
             tied &= ~(x ^ tbit);       // still equal so far
@@ -209,11 +294,16 @@ struct SweepArgs {
     Thresholds th;
     int64_t* obs;        // OBS: (M, E) accumulator, zeroed beforehand
     int64_t* zero_slot;  // if non-null, block 0 zeroes these two int64 (a later launch's obs)
+    uint32_t xcd_remap;  // renumber blocks per XCD (see logical_block)
+    uint32_t nt_store;   // non-temporal stores of the updated rows
 };
 
-template <int Q, bool OBS>
+// STAGED: the wave's lanes own 64 consecutive groups of one row (groups % 64 == 0); rows move
+// through LDS with coalesced loads and stores.  Otherwise every lane reads its own 64 bytes.
+template <int Q, bool OBS, bool STAGED>
 __global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
-    const uint32_t lane_id = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint4 lds_all[4][256];
+    const uint32_t lane_id = logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * blockDim.x + threadIdx.x;
     if (a.zero_slot && lane_id == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
     const bool active = lane_id < a.n_lanes;
     Counts cnt{0u, 0u};
@@ -224,42 +314,75 @@ __global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
         const uint32_t r0 = strip * a.rows;
         const uint32_t gl = g == 0 ? a.groups - 1 : g - 1;
         const uint32_t gr = g + 1 == a.groups ? 0 : g + 1;
-        int8_t* const col = a.spins + (size_t)g * 64u;
+        const uint32_t lane = threadIdx.x & 63u;
+        uint4* const lds = lds_all[threadIdx.x >> 6];
+        // first byte of this lane's group (unstaged) or of the wave's 64 groups (staged)
+        int8_t* const col = a.spins + (size_t)(STAGED ? g - lane : g) * 64u;
         auto rowp = [&](uint32_t r) { return col + (size_t)r * L; };
+        auto fetch = [&](Row& raw, uint32_t r) {
+            if (STAGED) load_row_coalesced(raw, rowp(r), lane);
+            else load_row(raw, rowp(r));
+        };
+        auto own = [&](Row& row, const Row& raw) {
+            if (STAGED) regroup_to_owner(row, raw, lds, lane);
+            else row = raw;
+        };
+        auto put = [&](uint32_t r, const Row& row) {
+            if (STAGED) store_row_coalesced(rowp(r), row, lds, lane, a.nt_store);
+            else store_row(rowp(r), row, a.nt_store);
+        };
         auto halo_left = [&](uint32_t r) {
             return *reinterpret_cast<const uint32_t*>(a.spins + (size_t)r * L + (size_t)gl * 64u + 60u);
         };
         auto halo_right = [&](uint32_t r) {
             return *reinterpret_cast<const uint32_t*>(a.spins + (size_t)r * L + (size_t)gr * 64u);
         };
-        // rows r0 (parity offset Q, since r0 is even) and r0 + 1 (offset 1 - Q) alternate
+        auto wrapr = [&](uint32_t r) { return r >= L ? r - L : r; };
+        auto halo = [&](uint32_t r, int o) { return o == 1 ? halo_right(r) : halo_left(r); };
+        // rows r0 (parity offset Q, since r0 is even) and r0 + 1 (offset 1 - Q) alternate.
+        // Software pipeline: rows r .. r + 3 and their halo dwords are in registers while
+        // rows r + 4, r + 5 are loaded, so HBM latency overlaps two rows of work.
         constexpr int O0 = Q, O1 = 1 - Q;
-        Row above, cur, nxt;
-        load_row(above, rowp(r0 == 0 ? L - 1 : r0 - 1));
-        load_row(cur, rowp(r0));
-        load_row(nxt, rowp(r0 + 1 == L ? 0 : r0 + 1));
+        // Rows r0 - 1 .. r0 + R are needed (R = a.rows >= 2, even).  Prefetches past r0 + R
+        // are clamped to row r0 + R, which is already in cache: the loads stay unconditional
+        // so the compiler can keep counting them and never has to drain the memory queue.
+        const uint32_t R = a.rows;
+        const uint32_t last = r0 + R;
+        auto ahead = [&](uint32_t r) { return wrapr(r < last ? r : last); };
+        // Pipeline: rows r + 2, r + 3 arrive as raw (coalesced) loads during iteration s - 1 and
+        // are regrouped at the top of iteration s, a full iteration after they were requested.
+        Row above, cur, nxt, pa, pb, ra, rb;
+        fetch(ra, r0 == 0 ? L - 1 : r0 - 1);
+        own(above, ra);
+        fetch(ra, r0);
+        own(cur, ra);
+        fetch(ra, wrapr(r0 + 1));
+        own(nxt, ra);
+        fetch(ra, ahead(r0 + 2));
+        fetch(rb, ahead(r0 + 3));
+        uint32_t h0 = halo(r0, O0), h1 = halo(wrapr(r0 + 1), O1);
         uint32_t bprev = site_bits<O0>(above);
         uint32_t bcur = site_bits<O1>(cur);
 #pragma unroll 1
-        for (uint32_t s = 0; s < a.rows; s += 2) {
+        for (uint32_t s = 0; s < R; s += 2) {
             const uint32_t r = r0 + s;
-            Row n2;
-            load_row(n2, rowp(r + 2 >= L ? r + 2 - L : r + 2));
-            const uint32_t h0 = O0 == 1 ? halo_right(r) : halo_left(r);
+            own(pa, ra);
+            own(pb, rb);
+            fetch(ra, ahead(r + 4));
+            fetch(rb, ahead(r + 5));
+            const uint32_t h2 = halo(ahead(r + 2), O0), h3 = halo(ahead(r + 3), O1);
             uint32_t bn = sweep_row<Q, O0, OBS>(cur, nxt, bprev, bcur, h0, a.th, g, r, a.t, a.key0, a.key1, cnt);
-            store_row(rowp(r), cur);
+            put(r, cur);
             bprev = bcur;
             bcur = bn;
-            // row r + 1
-            Row n3;
-            load_row(n3, rowp(r + 3 >= L ? r + 3 - L : r + 3));
-            const uint32_t h1 = O1 == 1 ? halo_right(r + 1) : halo_left(r + 1);
-            bn = sweep_row<Q, O1, OBS>(nxt, n2, bprev, bcur, h1, a.th, g, r + 1, a.t, a.key0, a.key1, cnt);
-            store_row(rowp(r + 1), nxt);
+            bn = sweep_row<Q, O1, OBS>(nxt, pa, bprev, bcur, h1, a.th, g, r + 1, a.t, a.key0, a.key1, cnt);
+            put(r + 1, nxt);
             bprev = bcur;
             bcur = bn;
-            cur = n2;
-            nxt = n3;
+            cur = pa;
+            nxt = pb;
+            h0 = h2;
+            h1 = h3;
         }
     }
     if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, active ? 1u : 0u, 64u * a.rows);
@@ -349,6 +472,15 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// Launch-shape options (ising_set_option).  Every valid setting gives bit-identical results.
+struct Options {
+    int64_t rows_per_lane = 0;  // 0 = choose from L
+    int64_t xcd_remap = 1;
+    int64_t nt_store = 0;
+    int64_t staged = 1;
+};
+Options g_opt;
+
 int hip_failed(hipError_t e, const char* what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
     return ISING_EHIP;
@@ -388,6 +520,7 @@ ising::Thresholds make_thresholds(double beta) {
 
 // rows per lane for the streaming kernels: even, divides L (L % 64 == 0)
 uint32_t rows_per_lane(int64_t L) {
+    if (g_opt.rows_per_lane > 0 && L % g_opt.rows_per_lane == 0) return (uint32_t)g_opt.rows_per_lane;
     const uint32_t groups = (uint32_t)(L / 64);
     // keep at least ~2048 workgroups' worth of lanes when the lattice allows it
     uint32_t R = 32;
@@ -409,14 +542,21 @@ int launch_half_sweep(int8_t* spins, int64_t L, const ising::Thresholds& th, uin
     a.th = th;
     a.obs = obs;
     a.zero_slot = zero_slot;
+    a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
+    a.nt_store = g_opt.nt_store ? 1u : 0u;
     const dim3 grid((a.n_lanes + 255u) / 256u), block(256);
+    // coalesced LDS-staged row I/O needs whole waves on 64 consecutive groups of one row
+    const bool staged = g_opt.staged && a.groups % 64u == 0;
+#define ISING_LAUNCH_SWEEP(QQ, OO, SS) \
+    hipLaunchKernelGGL((ising::k_sweep_int8<QQ, OO, SS>), grid, block, 0, stream, a)
     if (q == 1) {
-        if (obs) hipLaunchKernelGGL((ising::k_sweep_int8<1, true>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((ising::k_sweep_int8<1, false>), grid, block, 0, stream, a);
+        if (staged) { if (obs) ISING_LAUNCH_SWEEP(1, true, true); else ISING_LAUNCH_SWEEP(1, false, true); }
+        else { if (obs) ISING_LAUNCH_SWEEP(1, true, false); else ISING_LAUNCH_SWEEP(1, false, false); }
     } else {
-        if (obs) hipLaunchKernelGGL((ising::k_sweep_int8<0, true>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((ising::k_sweep_int8<0, false>), grid, block, 0, stream, a);
+        if (staged) { if (obs) ISING_LAUNCH_SWEEP(0, true, true); else ISING_LAUNCH_SWEEP(0, false, true); }
+        else { if (obs) ISING_LAUNCH_SWEEP(0, true, false); else ISING_LAUNCH_SWEEP(0, false, false); }
     }
+#undef ISING_LAUNCH_SWEEP
     return check_launch("k_sweep_int8");
 }
 
@@ -519,6 +659,38 @@ int ising_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME,
     if (!planes || !out_ME || !valid_L(L) || !aligned16(planes)) return ISING_EINVAL;
     (void)stream;
     return ISING_EUNSUPPORTED;
+}
+
+int ising_set_option(const char* name, int64_t value) {
+    if (!name) return ISING_EINVAL;
+    const std::string n(name);
+    if (n == "rows_per_lane") {
+        if (value != 0 && (value < 2 || value > 64 || (value & (value - 1)) != 0)) return ISING_EINVAL;
+        g_opt.rows_per_lane = value;
+    } else if (n == "xcd_remap") {
+        if (value != 0 && value != 1) return ISING_EINVAL;
+        g_opt.xcd_remap = value;
+    } else if (n == "nt_store") {
+        if (value != 0 && value != 1) return ISING_EINVAL;
+        g_opt.nt_store = value;
+    } else if (n == "staged") {
+        if (value != 0 && value != 1) return ISING_EINVAL;
+        g_opt.staged = value;
+    } else {
+        return ISING_EINVAL;
+    }
+    return ISING_OK;
+}
+
+int ising_get_option(const char* name, int64_t* value) {
+    if (!name || !value) return ISING_EINVAL;
+    const std::string n(name);
+    if (n == "rows_per_lane") *value = g_opt.rows_per_lane;
+    else if (n == "xcd_remap") *value = g_opt.xcd_remap;
+    else if (n == "nt_store") *value = g_opt.nt_store;
+    else if (n == "staged") *value = g_opt.staged;
+    else return ISING_EINVAL;
+    return ISING_OK;
 }
 
 const char* ising_last_error(void) { return g_last_error.c_str(); }

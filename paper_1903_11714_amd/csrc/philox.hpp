@@ -4,7 +4,7 @@
 // as easy as 1, 2, 3"): ten rounds of two 32x32 -> 64-bit products (M0 * x0, M1 * x2) mixed
 // with the other two words and the key; the key advances by the Weyl increments (W0, W1)
 // between rounds.  The whole key schedule is uniform across a launch, so it lives in scalar
-// registers and costs no vector instructions; each round is two v_mad_u64_u32 and two xors.
+// registers and costs no vector instructions; each round is two v_mad_u64_u32 and two three-input xors.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,8 +27,9 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     for (int round = 0; round < 10; ++round) {
         const uint64_t a = (uint64_t)kPhiloxM0 * c0;
         const uint64_t b = (uint64_t)kPhiloxM1 * c2;
-        const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        // three-input xor in one gfx950 v_bitop3_b32 (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), c3, k1, 0x96);
         c1 = (uint32_t)b;
         c3 = (uint32_t)a;
         c0 = n0;

@@ -44,6 +44,8 @@ _SIGNATURES = {
     "ising_observables_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
                                  ctypes.c_int),
     "ising_thresholds": ([ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "ising_set_option": ([ctypes.c_char_p, ctypes.c_int64], ctypes.c_int),
+    "ising_get_option": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ising_last_error": ([], ctypes.c_char_p),
     "ising_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "ising_version": ([], ctypes.c_int),
@@ -153,6 +155,16 @@ def ising_thresholds(beta: float) -> tuple[int, int]:
     out = (ctypes.c_uint64 * 2)()
     _check("ising_thresholds", library().ising_thresholds(float(beta), out))
     return int(out[0]), int(out[1])
+
+
+def ising_set_option(name: str, value: int) -> None:
+    _check("ising_set_option", library().ising_set_option(name.encode(), int(value)))
+
+
+def ising_get_option(name: str) -> int:
+    v = ctypes.c_int64()
+    _check("ising_get_option", library().ising_get_option(name.encode(), ctypes.byref(v)))
+    return int(v.value)
 
 
 def ising_version() -> int:

@@ -85,3 +85,21 @@ def test_zero_sweeps_is_a_no_op(lib):
     # n_sweeps = 0 enqueues nothing, so it succeeds without touching the device.
     fake = ctypes.c_void_p(4096)
     assert lib.ising_sweep(fake, 64, 0.4, 0, 1, 0, ctypes.c_void_p(0), ctypes.c_void_p(0)) == 0
+
+
+def test_options_round_trip(lib):
+    from paper_1903_11714_amd import ising
+    for name, good, bad in (("rows_per_lane", [0, 2, 64], [1, 3, 128, -2]), ("xcd_remap", [0, 1], [2]),
+                            ("staged", [0, 1], [-1]), ("nt_store", [0, 1], [5])):
+        old = ising.ising_get_option(name)
+        try:
+            for v in good:
+                ising.ising_set_option(name, v)
+                assert ising.ising_get_option(name) == v
+            for v in bad:
+                with pytest.raises(ising.IsingError):
+                    ising.ising_set_option(name, v)
+        finally:
+            ising.ising_set_option(name, old)
+    with pytest.raises(ising.IsingError):
+        ising.ising_set_option("no_such_option", 1)

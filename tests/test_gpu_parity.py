@@ -175,3 +175,51 @@ def test_invalid_arguments_raise(dev):
     s = torch.empty((64, 64), dtype=torch.int8, device="cuda")
     with pytest.raises(dev.IsingError):
         dev.ising_sweep(s, 64, -1.0, 1, 1)
+
+
+def test_staged_path_full_lattice_matches_oracle(dev, oracle_lib):
+    # L = 4096: every wave owns 64 whole groups of a row, so rows move through LDS.
+    L, n, seed = 4096, 2, 6
+    _say("staged full lattice", L, n)
+    s = torch.empty((L, L), dtype=torch.int8, device="cuda")
+    dev.ising_init(s, L, seed)
+    trace = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising_sweep(s, L, BETA_C, n, seed, 3, trace)
+    host = oracle_lib.init(L, seed)
+    ref = oracle_lib.sweep(host, BETA_C, n, seed, 3, trace=True)
+    assert np.array_equal(_host(s), host)
+    assert np.array_equal(_host(trace), ref)
+
+
+@pytest.mark.parametrize("L", [4096, 16384])
+def test_every_launch_option_gives_identical_lattices(dev, L):
+    # Launch shapes (rows per lane, XCD renumbering, LDS staging, store kind) must not change
+    # a single spin: the random numbers depend only on (site, sweep, colour).  This also
+    # catches races between lanes that share boundary rows.
+    _say("options", L)
+    base = torch.empty((L, L), dtype=torch.int8, device="cuda")
+    dev.ising_init(base, L, 17)
+    opts = {"rows_per_lane": [0, 2, 8, 64], "xcd_remap": [1, 0], "staged": [1, 0], "nt_store": [0, 1]}
+    ref = None
+    try:
+        for rows in opts["rows_per_lane"]:
+            for remap in opts["xcd_remap"]:
+                for staged in opts["staged"]:
+                    for nt in opts["nt_store"]:
+                        if nt and (rows, remap, staged) != (0, 1, 1):
+                            continue
+                        dev.ising_set_option("rows_per_lane", rows)
+                        dev.ising_set_option("xcd_remap", remap)
+                        dev.ising_set_option("staged", staged)
+                        dev.ising_set_option("nt_store", nt)
+                        s = base.clone()
+                        trace = torch.empty((3, 2), dtype=torch.int64, device="cuda")
+                        dev.ising_sweep(s, L, BETA_C, 3, 17, 40, trace)
+                        if ref is None:
+                            ref = (s, trace)
+                        else:
+                            assert torch.equal(s, ref[0]), (rows, remap, staged, nt)
+                            assert torch.equal(trace, ref[1]), (rows, remap, staged, nt)
+    finally:
+        for k, v in (("rows_per_lane", 0), ("xcd_remap", 1), ("staged", 1), ("nt_store", 0)):
+            dev.ising_set_option(k, v)
