@@ -82,6 +82,8 @@ def main() -> int:
     ap.add_argument("--kernel-sweeps", type=int, default=50, help="sweeps timed launch by launch")
     ap.add_argument("--cpu-sweeps", type=int, default=2, help="sweeps in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run this many plain device copies of an L^2-byte buffer (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -172,6 +174,18 @@ def main() -> int:
         "gpu_event_ms": gpu_ms,
         "final_ME": trace[K - 1].tolist() if K else None,
     }
+    if args.copy_calibration:
+        # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the
+        # per-launch HBM traffic read from the same counters for the sweep kernel.
+        # (int8 -> uint8 goes through an elementwise copy kernel that reads L^2 bytes and writes
+        # L^2 bytes, like the sweep; a same-dtype copy would use the runtime's blit kernel.)
+        src = torch.empty((L, L), dtype=torch.int8, device=dev)
+        ising.ising_fill(src, L, 1, stream)
+        dst = torch.empty((L, L), dtype=torch.uint8, device=dev)
+        for _ in range(args.copy_calibration):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(L, beta, seed, args.cpu_sweeps)

@@ -79,9 +79,17 @@ int ising_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* str
 int ising_pack(const int8_t* spins, int64_t L, uint32_t* planes, void* stream);
 int ising_unpack(const uint32_t* planes, int64_t L, int8_t* spins, void* stream);
 
-/* The same chain as ising_sweep on the packed layout: identical spins after every sweep. */
+/* Hot start written directly in the packed layout (equals ising_pack of ising_init). */
+int ising_init_packed(uint32_t* planes, int64_t L, uint64_t seed, void* stream);
+
+/* The same chain as ising_sweep on the packed layout: identical spins after every sweep and
+ * the same (M, E) trace.  Arguments as for ising_sweep. */
 int ising_sweep_packed(uint32_t* planes, int64_t L, double beta, int64_t n_sweeps,
                        uint64_t seed, uint64_t sweep_offset, int64_t* trace_ME, void* stream);
+
+/* One colour update on the packed layout (as ising_half_sweep). */
+int ising_half_sweep_packed(uint32_t* planes, int64_t L, double beta, uint64_t seed, uint64_t t,
+                            int q, void* stream);
 
 /* (M, E) of a packed lattice into device int64[2]. */
 int ising_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME, void* stream);

@@ -10,6 +10,8 @@ from .ising import (  # noqa: F401
     ising_get_option,
     ising_set_option,
     ising_half_sweep,
+    ising_half_sweep_packed,
+    ising_init_packed,
     ising_init,
     ising_observables,
     ising_observables_packed,
@@ -20,5 +22,6 @@ from .ising import (  # noqa: F401
     ising_unpack,
     ising_version,
     new_lattice,
+    new_packed,
     observables,
 )

@@ -233,6 +233,33 @@ struct Counts {
 // One row of the half-sweep for colour Q.  O = column parity of the colour-Q sites of this row.
 // bprev: row r-1 sites at parity O (vertical neighbours), bcur: row r sites at parity 1-O
 // (horizontal neighbours).  Returns row r+1's sites at parity O (the next row's bcur).
+// The Metropolis decision for the 32 colour-Q sites of one group of one row, all in bit words
+// (site order): a = the sites, up/down = the vertical neighbours, side = the horizontal
+// neighbour with the same site index, hs = the other horizontal neighbour.  Returns the flip
+// mask; with OBS it also counts the anti-aligned bonds of these sites after the update and
+// the -1 spins among these sites (after) plus `others` (the other colour of the row).
+template <int Q, bool OBS>
+__device__ __forceinline__ uint32_t decide(uint32_t a, uint32_t up, uint32_t down, uint32_t side, uint32_t hs,
+                                           uint32_t others, const Thresholds& th, uint32_t g, uint32_t r,
+                                           uint32_t t, uint32_t key0, uint32_t key1, Counts& cnt) {
+    const uint32_t x1 = a ^ up, x2 = a ^ down, x3 = a ^ side, x4 = a ^ hs;  // anti-aligned
+    const uint32_t o12 = x1 | x2, o34 = x3 | x4;
+    const uint32_t ge2 = (x1 & x2) | (x3 & x4) | (o12 & o34);  // >= 2 anti-aligned: s <= 0
+    const uint32_t any = o12 | o34;
+    const uint32_t sel2 = any & ~ge2;                            // exactly one: s = 2
+    const uint32_t sel4 = ~any;                                  // none: s = 4
+    const uint32_t F = ge2 | accept_mask(sel2, sel4, th, g, r, t, (uint32_t)Q, key0, key1);
+    if (OBS) {
+        cnt.anti += __builtin_popcount(x1 ^ F) + __builtin_popcount(x2 ^ F) +
+                    __builtin_popcount(x3 ^ F) + __builtin_popcount(x4 ^ F);
+        cnt.neg += __builtin_popcount(a ^ F) + __builtin_popcount(others);
+    }
+    return F;
+}
+
+// One row of the int8 half-sweep for colour Q.  O = column parity of the colour-Q sites of this
+// row.  bprev: row r-1 sites at parity O (vertical neighbours), bcur: row r sites at parity 1-O
+// (horizontal neighbours).  Returns row r+1's sites at parity O (the next row's bcur).
 template <int Q, int O, bool OBS>
 __device__ __forceinline__ uint32_t sweep_row(Row& cur, const Row& nxt, uint32_t bprev, uint32_t bcur,
                                               uint32_t halo, const Thresholds& th, uint32_t g,
@@ -243,19 +270,8 @@ __device__ __forceinline__ uint32_t sweep_row(Row& cur, const Row& nxt, uint32_t
     // horizontal neighbour that lies in the adjacent group: byte 0 of the right halo dword
     // (O = 1) or byte 3 of the left halo dword (O = 0); bit 1 of a byte is its sign
     const uint32_t hs = O == 1 ? shift_next(bcur, (halo >> 1) & 1u) : shift_prev(bcur, (halo >> 25) & 1u);
-    const uint32_t x1 = a ^ bprev, x2 = a ^ bnext, x3 = a ^ bcur, x4 = a ^ hs;  // anti-aligned
-    const uint32_t o12 = x1 | x2, o34 = x3 | x4;
-    const uint32_t ge2 = (x1 & x2) | (x3 & x4) | (o12 & o34);  // >= 2 anti-aligned: s <= 0
-    const uint32_t any = o12 | o34;
-    const uint32_t sel2 = any & ~ge2;                            // exactly one: s = 2
-    const uint32_t sel4 = ~any;                                  // none: s = 4
-    const uint32_t F = ge2 | accept_mask(sel2, sel4, th, g, r, t, (uint32_t)Q, key0, key1);
+    const uint32_t F = decide<Q, OBS>(a, bprev, bnext, bcur, hs, bcur, th, g, r, t, key0, key1, cnt);
     apply_flips<O>(cur, F);
-    if (OBS) {
-        cnt.anti += __builtin_popcount(x1 ^ F) + __builtin_popcount(x2 ^ F) +
-                    __builtin_popcount(x3 ^ F) + __builtin_popcount(x4 ^ F);
-        cnt.neg += __builtin_popcount(a ^ F) + __builtin_popcount(bcur);
-    }
     return bnext;
 }
 
@@ -464,6 +480,151 @@ __global__ __launch_bounds__(256) void k_fill_int8(int8_t* spins, uint64_t n16, 
         reinterpret_cast<uint4*>(spins)[i] = make_uint4(word, word, word, word);
 }
 
+// ==========================================================================================
+// 1-bit packed layout: plane q holds, for every row r and group g, the word of the 32 colour-q
+// sites of row r with j = c >> 1 in [32 g, 32 g + 32), bit p(i) for site i (the bit the site's
+// uniform uses), set = spin -1.  Word index (q * L + r) * groups + g.
+struct PackedArgs {
+    uint32_t* planes;
+    uint32_t L, groups, rows, n_lanes;
+    uint32_t t, key0, key1;
+    Thresholds th;
+    int64_t* obs;
+    int64_t* zero_slot;
+    uint32_t xcd_remap;
+};
+
+// Half-sweep on the packed layout: a lane owns one group of a strip of `rows` rows and streams
+// down it.  Vertical neighbours of row r's colour-Q sites are the other plane's words of rows
+// r +- 1 (same group); horizontal ones are the other plane's word of row r and its shift by one
+// site, whose edge bit comes from the adjacent group's word.
+template <int Q, bool OBS>
+__global__ __launch_bounds__(256) void k_sweep_packed(PackedArgs a) {
+    const uint32_t lane_id = logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * blockDim.x + threadIdx.x;
+    if (a.zero_slot && lane_id == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
+    const bool active = lane_id < a.n_lanes;
+    Counts cnt{0u, 0u};
+    if (active) {
+        const uint32_t W = a.groups, L = a.L, R = a.rows;
+        const uint32_t g = lane_id % W;
+        const uint32_t r0 = (lane_id / W) * R;
+        const uint32_t gl = g == 0 ? W - 1 : g - 1;
+        const uint32_t gr = g + 1 == W ? 0 : g + 1;
+        uint32_t* const pq = a.planes + (size_t)Q * L * W;        // sites being updated
+        const uint32_t* const po = a.planes + (size_t)(1 - Q) * L * W;  // other colour
+        auto wrapr = [&](uint32_t r) { return r >= L ? r - L : r; };
+        uint32_t bprev = po[(size_t)(r0 == 0 ? L - 1 : r0 - 1) * W + g];
+        uint32_t bcur = po[(size_t)r0 * W + g];
+        uint32_t acur = pq[(size_t)r0 * W + g];
+#pragma unroll 1
+        for (uint32_t s = 0; s < R; s += 2) {
+            const uint32_t r = r0 + s, r1 = r + 1, r2 = wrapr(r + 2);
+            // row r: colour-Q sites at column parity Q (r even); row r + 1: parity 1 - Q
+            const uint32_t bn = po[(size_t)r1 * W + g];
+            const uint32_t a1 = pq[(size_t)r1 * W + g];
+            const uint32_t bn2 = po[(size_t)r2 * W + g];
+            const uint32_t a2 = s + 2 < R ? pq[(size_t)r2 * W + g] : 0u;
+            const uint32_t e0 = Q == 1 ? po[(size_t)r * W + gr] : po[(size_t)r * W + gl];
+            const uint32_t e1 = Q == 1 ? po[(size_t)r1 * W + gl] : po[(size_t)r1 * W + gr];
+            // parity 1 (Q = 1 on even rows): right neighbour is site j + 1 -> shift_next with the
+            // next group's site 0 (bit 0); parity 0: left neighbour j - 1 -> shift_prev with the
+            // previous group's site 31 (bit 31)
+            const uint32_t hs0 = Q == 1 ? shift_next(bcur, e0 & 1u) : shift_prev(bcur, e0 >> 31);
+            uint32_t F = decide<Q, OBS>(acur, bprev, bn, bcur, hs0, bcur, a.th, g, r, a.t, a.key0, a.key1, cnt);
+            pq[(size_t)r * W + g] = acur ^ F;
+            const uint32_t hs1 = Q == 1 ? shift_prev(bn, e1 >> 31) : shift_next(bn, e1 & 1u);
+            F = decide<Q, OBS>(a1, bcur, bn2, bn, hs1, bn, a.th, g, r1, a.t, a.key0, a.key1, cnt);
+            pq[(size_t)r1 * W + g] = a1 ^ F;
+            bprev = bn;
+            bcur = bn2;
+            acur = a2;
+        }
+    }
+    if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, active ? 1u : 0u, 64u * a.rows);
+}
+
+// (M, E) of a packed lattice: every bond has exactly one black (q = 0) end, so the black sites'
+// anti-aligned neighbour counts cover all 2 L^2 bonds once.
+__global__ __launch_bounds__(256) void k_observables_packed(const uint32_t* planes, uint32_t L, uint32_t groups,
+                                                            uint32_t n_lanes, int64_t* out) {
+    const uint32_t lane_id = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = lane_id < n_lanes;
+    uint32_t anti = 0, neg = 0;
+    if (active) {
+        const uint32_t W = groups;
+        const uint32_t g = lane_id % W, r = lane_id / W;
+        const uint32_t gl = g == 0 ? W - 1 : g - 1, gr = g + 1 == W ? 0 : g + 1;
+        const uint32_t* p0 = planes;
+        const uint32_t* p1 = planes + (size_t)L * W;
+        const uint32_t up = r == 0 ? L - 1 : r - 1, dn = r + 1 == L ? 0 : r + 1;
+        const uint32_t b = p0[(size_t)r * W + g];
+        const uint32_t w = p1[(size_t)r * W + g];
+        // black sites of row r sit at column parity r & 1
+        const uint32_t hs = (r & 1u) ? shift_next(w, p1[(size_t)r * W + gr] & 1u)
+                                     : shift_prev(w, p1[(size_t)r * W + gl] >> 31);
+        anti = __builtin_popcount(b ^ p1[(size_t)up * W + g]) + __builtin_popcount(b ^ p1[(size_t)dn * W + g]) +
+               __builtin_popcount(b ^ w) + __builtin_popcount(b ^ hs);
+        neg = __builtin_popcount(b) + __builtin_popcount(w);
+    }
+    block_accumulate(out, anti, neg, active ? 1u : 0u, 64u);
+}
+
+// int8 -> packed: lane per (row, group)
+__global__ __launch_bounds__(256) void k_pack(const int8_t* spins, uint32_t* planes, uint32_t L, uint32_t groups,
+                                              uint32_t n_lanes) {
+    const uint32_t lane_id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane_id >= n_lanes) return;
+    const uint32_t g = lane_id % groups, r = lane_id / groups;
+    Row row;
+    load_row(row, spins + (size_t)r * L + (size_t)g * 64u);
+    const uint32_t even = site_bits<0>(row), odd = site_bits<1>(row);
+    // colour q of row r sits at column parity (r + q) & 1
+    planes[(size_t)r * groups + g] = (r & 1u) ? odd : even;                          // q = 0
+    planes[((size_t)L + r) * groups + g] = (r & 1u) ? even : odd;                    // q = 1
+}
+
+// packed -> int8
+__global__ __launch_bounds__(256) void k_unpack(const uint32_t* planes, int8_t* spins, uint32_t L, uint32_t groups,
+                                                uint32_t n_lanes) {
+    const uint32_t lane_id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane_id >= n_lanes) return;
+    const uint32_t g = lane_id % groups, r = lane_id / groups;
+    const uint32_t q0 = planes[(size_t)r * groups + g], q1 = planes[((size_t)L + r) * groups + g];
+    const uint32_t even = (r & 1u) ? q1 : q0, odd = (r & 1u) ? q0 : q1;
+    Row row;
+    // dword 2k + h: bytes 0, 2 are even-column sites at bits k + 8h, k + 8h + 16; bytes 1, 3 the
+    // odd-column ones at the same bits of the other word.  Sign-extending permute selectors 8..11
+    // replicate bits 15 / 31 of each source into whole bytes.
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t sh = 15 - k - 8 * h;
+            row.d[2 * k + h] = perm(odd << sh, even << sh, 0x0B090A08u) | 0x01010101u;
+        }
+    }
+    store_row(spins + (size_t)r * L + (size_t)g * 64u, row, false);
+}
+
+// packed hot start: the int8 hot start's bits for one group, regrouped by colour
+__global__ __launch_bounds__(256) void k_init_packed(uint32_t* planes, uint32_t L, uint32_t groups, uint32_t n_lanes,
+                                                     uint32_t key0, uint32_t key1) {
+    const uint32_t lane_id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane_id >= n_lanes) return;
+    const uint32_t g = lane_id % groups, r = lane_id / groups;
+    const Words4 w = philox4x32_10(g >> 1, r, 0u, 0x80000000u, key0, key1);
+    const uint32_t lo = (g & 1u) ? w.w2 : w.w0, hi = (g & 1u) ? w.w3 : w.w1;  // columns 0-31, 32-63
+    Row row;
+#pragma unroll
+    for (int d = 0; d < 16; ++d) {
+        const uint32_t src = d < 8 ? lo : hi;
+        row.d[d] = nibble_to_bytes((src >> (4 * (d & 7))) & 15u);
+    }
+    const uint32_t even = site_bits<0>(row), odd = site_bits<1>(row);
+    planes[(size_t)r * groups + g] = (r & 1u) ? odd : even;
+    planes[((size_t)L + r) * groups + g] = (r & 1u) ? even : odd;
+}
+
 }  // namespace ising
 
 // ==========================================================================================
@@ -636,14 +797,63 @@ int ising_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* str
 
 int ising_pack(const int8_t* spins, int64_t L, uint32_t* planes, void* stream) {
     if (!spins || !planes || !valid_L(L) || !aligned16(spins) || !aligned16(planes)) return ISING_EINVAL;
-    (void)stream;
-    return ISING_EUNSUPPORTED;
+    const uint32_t groups = (uint32_t)(L / 64), n = groups * (uint32_t)L;
+    hipLaunchKernelGGL(ising::k_pack, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, spins, planes,
+                       (uint32_t)L, groups, n);
+    return check_launch("k_pack");
 }
 
 int ising_unpack(const uint32_t* planes, int64_t L, int8_t* spins, void* stream) {
     if (!spins || !planes || !valid_L(L) || !aligned16(spins) || !aligned16(planes)) return ISING_EINVAL;
-    (void)stream;
-    return ISING_EUNSUPPORTED;
+    const uint32_t groups = (uint32_t)(L / 64), n = groups * (uint32_t)L;
+    hipLaunchKernelGGL(ising::k_unpack, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, planes, spins,
+                       (uint32_t)L, groups, n);
+    return check_launch("k_unpack");
+}
+
+int ising_init_packed(uint32_t* planes, int64_t L, uint64_t seed, void* stream) {
+    if (!planes || !valid_L(L) || !aligned16(planes)) return ISING_EINVAL;
+    const uint32_t groups = (uint32_t)(L / 64), n = groups * (uint32_t)L;
+    hipLaunchKernelGGL(ising::k_init_packed, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, planes,
+                       (uint32_t)L, groups, n, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return check_launch("k_init_packed");
+}
+
+namespace {
+int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Thresholds& th, uint64_t seed, uint32_t t,
+                             int q, int64_t* obs, int64_t* zero_slot, hipStream_t stream) {
+    ising::PackedArgs a;
+    a.planes = planes;
+    a.L = (uint32_t)L;
+    a.groups = (uint32_t)(L / 64);
+    a.rows = rows_per_lane(L);
+    a.n_lanes = a.groups * (uint32_t)(L / a.rows);
+    a.t = t;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.th = th;
+    a.obs = obs;
+    a.zero_slot = zero_slot;
+    a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
+    const dim3 grid((a.n_lanes + 255u) / 256u), block(256);
+    if (q == 1) {
+        if (obs) hipLaunchKernelGGL((ising::k_sweep_packed<1, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((ising::k_sweep_packed<1, false>), grid, block, 0, stream, a);
+    } else {
+        if (obs) hipLaunchKernelGGL((ising::k_sweep_packed<0, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((ising::k_sweep_packed<0, false>), grid, block, 0, stream, a);
+    }
+    return check_launch("k_sweep_packed");
+}
+}  // namespace
+
+int ising_half_sweep_packed(uint32_t* planes, int64_t L, double beta, uint64_t seed, uint64_t t, int q,
+                            void* stream) {
+    if (!planes || !valid_L(L) || !aligned16(planes) || !valid_beta(beta) || (q != 0 && q != 1) ||
+        t >= (uint64_t(1) << 32))
+        return ISING_EINVAL;
+    return launch_half_sweep_packed(planes, L, make_thresholds(beta), seed, (uint32_t)t, q, nullptr, nullptr,
+                                    (hipStream_t)stream);
 }
 
 int ising_sweep_packed(uint32_t* planes, int64_t L, double beta, int64_t n_sweeps, uint64_t seed,
@@ -651,14 +861,29 @@ int ising_sweep_packed(uint32_t* planes, int64_t L, double beta, int64_t n_sweep
     if (!planes || !valid_L(L) || !aligned16(planes) || !valid_beta(beta) || n_sweeps < 0 ||
         sweep_offset > (uint64_t(1) << 32) || (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset)
         return ISING_EINVAL;
-    (void)seed; (void)trace_ME; (void)stream;
-    return ISING_EUNSUPPORTED;
+    const ising::Thresholds th = make_thresholds(beta);
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t i = 0; i < n_sweeps; ++i) {
+        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
+        int64_t* slot = trace_ME ? trace_ME + 2 * i : nullptr;
+        int rc = launch_half_sweep_packed(planes, L, th, seed, t, 1, nullptr, slot, s);
+        if (rc) return rc;
+        rc = launch_half_sweep_packed(planes, L, th, seed, t, 0, slot, nullptr, s);
+        if (rc) return rc;
+    }
+    return ISING_OK;
 }
 
 int ising_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME, void* stream) {
     if (!planes || !out_ME || !valid_L(L) || !aligned16(planes)) return ISING_EINVAL;
-    (void)stream;
-    return ISING_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(ising::k_zero2, dim3(1), dim3(64), 0, s, out_ME);
+    int rc = check_launch("k_zero2");
+    if (rc) return rc;
+    const uint32_t groups = (uint32_t)(L / 64), n = groups * (uint32_t)L;
+    hipLaunchKernelGGL(ising::k_observables_packed, dim3((n + 255) / 256), dim3(256), 0, s, planes, (uint32_t)L,
+                       groups, n, out_ME);
+    return check_launch("k_observables_packed");
 }
 
 int ising_set_option(const char* name, int64_t value) {

@@ -43,6 +43,9 @@ _SIGNATURES = {
                             ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "ising_observables_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
                                  ctypes.c_int),
+    "ising_init_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p], ctypes.c_int),
+    "ising_half_sweep_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
+                                 ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "ising_thresholds": ([ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
     "ising_set_option": ([ctypes.c_char_p, ctypes.c_int64], ctypes.c_int),
     "ising_get_option": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -146,6 +149,16 @@ def ising_sweep_packed(planes, L: int, beta: float, n_sweeps: int, seed: int, sw
         _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
 
 
+def ising_init_packed(planes, L: int, seed: int, stream=None) -> None:
+    _check("ising_init_packed", library().ising_init_packed(
+        _dev_ptr(planes, "torch.int32", L * L // 32), L, seed, _stream(stream)))
+
+
+def ising_half_sweep_packed(planes, L: int, beta: float, seed: int, t: int, q: int, stream=None) -> None:
+    _check("ising_half_sweep_packed", library().ising_half_sweep_packed(
+        _dev_ptr(planes, "torch.int32", L * L // 32), L, float(beta), seed, t, q, _stream(stream)))
+
+
 def ising_observables_packed(planes, L: int, out_ME, stream=None) -> None:
     _check("ising_observables_packed", library().ising_observables_packed(
         _dev_ptr(planes, "torch.int32", L * L // 32), L, _dev_ptr(out_ME, "torch.int64", 2), _stream(stream)))
@@ -182,6 +195,14 @@ def new_lattice(L: int, seed: int | None = None, device: str = "cuda"):
     else:
         ising_init(spins, L, seed)
     return spins
+
+
+def new_packed(L: int, seed: int, device: str = "cuda"):
+    """Allocate the packed form of an L x L lattice (int32 words) with the hot start of `seed`."""
+    import torch
+    planes = torch.empty(L * L // 32, dtype=torch.int32, device=device)
+    ising_init_packed(planes, L, seed)
+    return planes
 
 
 def observables(spins) -> tuple[int, int]:
