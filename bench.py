@@ -56,7 +56,10 @@ def measured_traffic(layout: str, L: int):
 
 
 def cpu_baseline(L: int, beta: float, seed: int, sweeps: int):
+    """The oracle on `sweeps` sweeps of the same lattice (at most 16384^2, so the sample stays
+    around ten seconds of host time)."""
     import oracle
+    L = min(L, 16384)
     spins = oracle.init(L, seed)
     t0 = time.perf_counter()
     oracle.sweep(spins, beta, sweeps, seed, 0)
@@ -71,6 +74,61 @@ def cpu_baseline(L: int, beta: float, seed: int, sweeps: int):
     }
 
 
+def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream):
+    """Hot start, W warm-up sweeps, K timed sweeps with the (M, E) trace, then `kernel_sweeps`
+    sweeps with every half-sweep launch bracketed by events."""
+    dev = torch.device("cuda:0")
+    if layout == "int8":
+        lat = torch.empty((L, L), dtype=torch.int8, device=dev)
+        ising.ising_init(lat, L, seed, stream)
+        sweep, half = ising.ising_sweep, ising.ising_half_sweep
+    else:
+        lat = torch.empty(L * L // 32, dtype=torch.int32, device=dev)
+        ising.ising_init_packed(lat, L, seed, stream)
+        sweep, half = ising.ising_sweep_packed, ising.ising_half_sweep_packed
+    warm_trace = torch.empty((max(W, 1), 2), dtype=torch.int64, device=dev)
+    trace = torch.empty((max(K, 1), 2), dtype=torch.int64, device=dev)
+    if W:
+        sweep(lat, L, beta, W, seed, 0, warm_trace, stream)
+    torch.cuda.synchronize()
+    print(f"bench: {layout} L={L} warmup={W} done", file=sys.stderr, flush=True)
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sweep(lat, L, beta, K, seed, W, trace, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    print(f"bench: {layout} timed {K} sweeps in {wall:.3f} s wall, {gpu_ms:.1f} ms events", file=sys.stderr,
+          flush=True)
+    final_ME = trace[K - 1].tolist() if K else None
+
+    # dominant kernel: each half-sweep launch bracketed by events on the launch stream
+    nk = kernel_sweeps
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nk + 1)]
+    t = W + K
+    evs[0].record(stream)
+    for i in range(nk):
+        half(lat, L, beta, seed, t + i, 1, stream)
+        evs[2 * i + 1].record(stream)
+        half(lat, L, beta, seed, t + i, 0, stream)
+        evs[2 * i + 2].record(stream)
+    torch.cuda.synchronize()
+    durs = [evs[k].elapsed_time(evs[k + 1]) for k in range(2 * nk)]
+    del lat
+    return {
+        "value": float(L) * L * K / (wall * 1e9),
+        "wall_s": wall,
+        "gpu_ms": gpu_ms,
+        "avg_launch_ms": sum(durs) / len(durs),
+        "final_ME": final_ME,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,7 +138,10 @@ def main() -> int:
     ap.add_argument("--beta", type=float, default=BETA_C)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--kernel-sweeps", type=int, default=50, help="sweeps timed launch by launch")
-    ap.add_argument("--cpu-sweeps", type=int, default=2, help="sweeps in the CPU-oracle sample")
+    ap.add_argument("--cpu-sweeps", type=int, default=8, help="sweeps in the CPU-oracle sample")
+    ap.add_argument("--layout", choices=["int8", "packed"], default="int8")
+    ap.add_argument("--compare-packed", type=int, default=1,
+                    help="with the int8 layout, also time the 1-bit layout on the same workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run this many plain device copies of an L^2-byte buffer (counter calibration)")
@@ -101,64 +162,33 @@ def main() -> int:
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
 
-    spins = torch.empty((L, L), dtype=torch.int8, device=dev)
-    ising.ising_init(spins, L, seed, stream)
-    warm_trace = torch.empty((max(W, 1), 2), dtype=torch.int64, device=dev)
-    trace = torch.empty((max(K, 1), 2), dtype=torch.int64, device=dev)
-    if W:
-        ising.ising_sweep(spins, L, beta, W, seed, 0, warm_trace, stream)
-    torch.cuda.synchronize()
-    print(f"bench: L={L} warmup={W} done", file=sys.stderr, flush=True)
-
-    # ---- timed region: K sweeps with the (M, E) trace
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    ising.ising_sweep(spins, L, beta, K, seed, W, trace, stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    print(f"bench: timed {K} sweeps in {wall:.3f} s wall, {gpu_ms:.1f} ms events", file=sys.stderr, flush=True)
-    attempts = float(L) * L * K
-    value = attempts / (wall * 1e9)
-
-    # ---- dominant kernel: each half-sweep launch bracketed by events on the same stream
-    nk = args.kernel_sweeps
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nk + 1)]
-    t = W + K
-    evs[0].record(stream)
-    for i in range(nk):
-        ising.ising_half_sweep(spins, L, beta, seed, t + i, 1, stream)
-        evs[2 * i + 1].record(stream)
-        ising.ising_half_sweep(spins, L, beta, seed, t + i, 0, stream)
-        evs[2 * i + 2].record(stream)
-    torch.cuda.synchronize()
-    durs = [evs[k].elapsed_time(evs[k + 1]) for k in range(2 * nk)]
-    avg_ms = sum(durs) / len(durs)
-    alg_bytes = 2.0 * L * L          # read + write of the L^2-byte lattice per launch
-    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic("int8", L)
+    main = run_layout(ising, torch, args.layout, L, beta, seed, K, W, args.kernel_sweeps, stream)
+    lat_bytes = L * L if args.layout == "int8" else L * L // 8
+    # int8: each launch reads and writes the L^2-byte lattice.  packed: each launch reads both
+    # colour planes (L^2 / 8 bytes) and writes one (L^2 / 16 bytes).
+    alg_bytes = 2.0 * L * L if args.layout == "int8" else 3.0 * L * L / 16.0
+    achieved = alg_bytes / (main["avg_launch_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(args.layout, L)
 
     result = {
         "metric": METRIC,
-        "value": value,
+        "value": main["value"],
         "unit": "attempts/ns",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": wall * 1e3 / K,
+        "ms_per_step": main["wall_s"] * 1e3 / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": "int8" if args.layout == "int8" else "u32 (1-bit spins)",
         "data": "synthetic: Philox hot start from the seed (no dataset)",
         "config": {
-            "workload": f"single periodic {L}x{L} lattice, T=T_c, hot start seed {seed}, plain exact-threshold "
-                        f"checkerboard Metropolis, int8 layout, (M,E) traced every sweep",
-            "L": L, "beta": beta, "layout": "int8", "sweeps_timed": K,
+            "workload": f"single periodic {L}x{L} lattice, beta={beta:.6g}"
+                        f"{' (T_c)' if abs(beta - BETA_C) < 1e-12 else ''}, hot start seed {seed}, plain "
+                        f"exact-threshold checkerboard Metropolis, {args.layout} layout "
+                        f"({lat_bytes / 2**20:.0f} MiB), (M,E) traced every sweep",
+            "L": L, "beta": beta, "layout": args.layout, "sweeps_timed": K,
         },
         "roofline": {
             "bound": "hbm",
@@ -167,13 +197,23 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_sweep_int8 (one colour per launch)",
-            "avg_launch_us": avg_ms * 1e3,
+            "kernel": "k_sweep_int8 (one colour per launch)" if args.layout == "int8"
+                      else "k_sweep_packed (one colour per launch)",
+            "avg_launch_us": main["avg_launch_ms"] * 1e3,
             "alg_bytes_per_launch": alg_bytes,
         },
-        "gpu_event_ms": gpu_ms,
-        "final_ME": trace[K - 1].tolist() if K else None,
+        "gpu_event_ms": main["gpu_ms"],
+        "final_ME": main["final_ME"],
     }
+    if args.compare_packed and args.layout == "int8":
+        # the same workload on the 1-bit layout (same chain, bit-identical spins), for reference
+        ks = max(K // 4, 1)
+        other = run_layout(ising, torch, "packed", L, beta, seed, ks, W, args.kernel_sweeps, stream)
+        result["packed_layout"] = {
+            "value": other["value"], "unit": "attempts/ns", "steps": ks,
+            "avg_launch_us": other["avg_launch_ms"] * 1e3,
+            "hbm_GBs": 3.0 * L * L / 16.0 / (other["avg_launch_ms"] * 1e-3) / 1e9,
+        }
     if args.copy_calibration:
         # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the
         # per-launch HBM traffic read from the same counters for the sweep kernel.
