@@ -62,6 +62,15 @@ int ising_fill(int8_t* spins, int64_t L, int value, void* stream);
 int ising_sweep(int8_t* spins, int64_t L, double beta, int64_t n_sweeps, uint64_t seed,
                 uint64_t sweep_offset, int64_t* trace_ME, void* stream);
 
+/* The same chain with low-precision acceptance (the paper's bfloat16 experiment, Sec. 4.1):
+ *   fmt 0 = exact (identical to ising_sweep), 1 = bfloat16, 2 = IEEE half.
+ * A site with s > 0 flips iff u < p, where p = exp(-2 beta s) rounded to nearest-even in fmt and
+ * u = (top 16 bits of the site's exact-chain uniform) / 2^16 rounded toward zero in fmt.  Both
+ * chains use the same random numbers; this one is the exact chain with the thresholds of
+ * ising_thresholds_fmt. */
+int ising_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sweeps, uint64_t seed,
+                    uint64_t sweep_offset, int64_t* trace_ME, void* stream);
+
 /* One colour update (half of a sweep) for colour q in {0, 1} with sweep index t.
  * Same arguments as ising_sweep otherwise; t < 2^32. */
 int ising_half_sweep(int8_t* spins, int64_t L, double beta, uint64_t seed, uint64_t t, int q,
@@ -87,6 +96,10 @@ int ising_init_packed(uint32_t* planes, int64_t L, uint64_t seed, void* stream);
 int ising_sweep_packed(uint32_t* planes, int64_t L, double beta, int64_t n_sweeps,
                        uint64_t seed, uint64_t sweep_offset, int64_t* trace_ME, void* stream);
 
+/* ising_sweep_fmt on the packed layout. */
+int ising_sweep_packed_fmt(uint32_t* planes, int64_t L, double beta, int fmt, int64_t n_sweeps,
+                           uint64_t seed, uint64_t sweep_offset, int64_t* trace_ME, void* stream);
+
 /* One colour update on the packed layout (as ising_half_sweep). */
 int ising_half_sweep_packed(uint32_t* planes, int64_t L, double beta, uint64_t seed, uint64_t t,
                             int q, void* stream);
@@ -99,6 +112,16 @@ int ising_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME,
 /* The two acceptance thresholds for beta: out[0] = T_2, out[1] = T_4 (each in [0, 2^32]),
  * T_s = ceil(2^32 exp(-2 beta s)).  Host pointer.  Sec. 3.2, Algorithm 1. */
 int ising_thresholds(double beta, uint64_t out[2]);
+
+/* Integer thresholds of the fmt acceptance: out[k] = R_s 2^16 with R_s the number of 16-bit
+ * uniforms r whose rounded value is below the rounded probability (fmt 0: ising_thresholds). */
+int ising_thresholds_fmt(double beta, int fmt, uint64_t out[2]);
+
+/* FP64 moments of a traced chain (Sec. 4.1: m and the Binder cumulant need <m^2>, <m^4>):
+ * out (device double[5]) = (<|m|>, <m^2>, <m^4>, <e>, <e^2>) over the n traced sweeps, with
+ * m = M / n_sites and e = E / n_sites; the sums run in sweep order, so the result is
+ * deterministic.  trace_ME: device int64[2 n] as written by ising_sweep. */
+int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* out, void* stream);
 
 /* Launch-shape options of the int8 kernels, process-wide; results are bit-identical for every
  * valid setting (the random numbers depend only on site, sweep and colour).  Not thread-safe

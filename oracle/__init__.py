@@ -70,6 +70,15 @@ def _load():
                                 ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                 ctypes.c_int64, i8p]
     lib.oracle_crop.restype = None
+    lib.oracle_round_fmt.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int]
+    lib.oracle_round_fmt.restype = ctypes.c_double
+    lib.oracle_p_fmt.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int]
+    lib.oracle_p_fmt.restype = ctypes.c_double
+    lib.oracle_u_fmt.argtypes = [ctypes.c_uint32, ctypes.c_int]
+    lib.oracle_u_fmt.restype = ctypes.c_double
+    lib.oracle_sweep_fmt.argtypes = [i8p, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_int64,
+                                     ctypes.c_uint64, ctypes.c_uint64, i64p]
+    lib.oracle_sweep_fmt.restype = None
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -153,6 +162,31 @@ def crop(L: int, seed: int, beta: float, n: int, offset: int, r0: int, c0: int, 
     out = np.empty((h, w), dtype=np.int8)
     _load().oracle_crop(L, seed, float(beta), n, offset, r0, c0, h, w, _ptr(out, ctypes.c_int8))
     return out
+
+
+FMT = {"bf16": 1, "fp16": 2}
+
+
+def round_fmt(v: float, fmt: str, toward_zero: bool = False) -> float:
+    return float(_load().oracle_round_fmt(float(v), FMT[fmt], int(toward_zero)))
+
+
+def p_fmt(beta: float, s: int, fmt: str) -> float:
+    return float(_load().oracle_p_fmt(float(beta), s, FMT[fmt]))
+
+
+def u_fmt(x: int, fmt: str) -> float:
+    return float(_load().oracle_u_fmt(x, FMT[fmt]))
+
+
+def sweep_fmt(spins: np.ndarray, beta: float, fmt: str, n: int, seed: int, offset: int = 0,
+              trace: bool = False):
+    """n sweeps with low-precision acceptance (fmt "bf16" or "fp16")."""
+    s = _lattice(spins)
+    tr = np.zeros((max(n, 0), 2), dtype=np.int64) if trace else None
+    _load().oracle_sweep_fmt(_ptr(s, ctypes.c_int8), s.shape[0], float(beta), FMT[fmt], n, seed, offset,
+                             _ptr(tr, ctypes.c_int64) if tr is not None else None)
+    return tr
 
 
 def num_threads() -> int:

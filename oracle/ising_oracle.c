@@ -228,6 +228,59 @@ void oracle_crop(int64_t L, uint64_t seed, double beta, int64_t n, uint64_t offs
     free(win);
 }
 
+/* ---- Low-precision acceptance. */
+double oracle_round_fmt(double v, int fmt, int toward_zero) {
+    if (!(v > 0.0)) return 0.0;                 /* only non-negative values occur here */
+    int digits = (fmt == 1) ? 8 : 11;           /* significant bits of bfloat16 / half   */
+    int min_exp = (fmt == 1) ? -126 : -14;      /* exponent of the smallest normal       */
+    int e;
+    frexp(v, &e);                                /* v = m 2^e, m in [0.5, 1)             */
+    int lead = e - 1;                            /* v in [2^lead, 2^(lead+1))            */
+    if (lead < min_exp) lead = min_exp;          /* subnormal range: fixed quantum        */
+    double quantum = ldexp(1.0, lead - (digits - 1));
+    double k = v / quantum;                      /* exact: division by a power of two      */
+    k = toward_zero ? floor(k) : nearbyint(k);   /* nearbyint: ties to even (default mode) */
+    return k * quantum;
+}
+
+double oracle_p_fmt(double beta, int s, int fmt) {
+    return oracle_round_fmt(exp(-2.0 * beta * (double)s), fmt, 0);
+}
+
+double oracle_u_fmt(uint32_t x, int fmt) {
+    double r16 = (double)(x >> 16);
+    return oracle_round_fmt(ldexp(r16, -16), fmt, 1);
+}
+
+static void half_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, uint64_t seed, uint32_t t,
+                           int q) {
+    double p2 = oracle_p_fmt(beta, 2, fmt), p4 = oracle_p_fmt(beta, 4, fmt);
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < L; ++r) {
+        for (int64_t c = 0; c < L; ++c) {
+            if (((r + c) & 1) != q) continue;
+            int sigma = spins[r * L + c];
+            int s = sigma * neighbour_sum(spins, L, r, c);
+            int flip = 1;
+            if (s > 0) {
+                double u = oracle_u_fmt(oracle_uniform(seed, (uint32_t)r, (uint32_t)c, t, q), fmt);
+                flip = u < ((s == 2) ? p2 : p4);
+            }
+            if (flip) spins[r * L + c] = (int8_t)(-sigma);
+        }
+    }
+}
+
+void oracle_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n, uint64_t seed,
+                      uint64_t offset, int64_t* trace) {
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t t = (uint32_t)(offset + (uint64_t)i);
+        half_sweep_fmt(spins, L, beta, fmt, seed, t, 1);
+        half_sweep_fmt(spins, L, beta, fmt, seed, t, 0);
+        if (trace) oracle_observables(spins, L, trace + 2 * i);
+    }
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

@@ -75,6 +75,19 @@ void oracle_observables(const int8_t* spins, int64_t L, int64_t out[2]);
 void oracle_crop(int64_t L, uint64_t seed, double beta, int64_t n, uint64_t offset,
                  int64_t r0, int64_t c0, int64_t h, int64_t w, int8_t* out);
 
+/* ---- Low-precision acceptance (the paper's bfloat16 experiment, Sec. 4.1).
+ * fmt 1 = bfloat16 (8 significant bits, float32 exponent range), fmt 2 = IEEE half (11
+ * significant bits, smallest normal 2^-14, subnormals down to 2^-24).
+ *   p_fmt(s) = exp(-2 beta s) rounded to nearest-even in fmt (one rounding from double);
+ *   u_fmt    = (top 16 bits of the site's uniform x) / 2^16, rounded toward zero in fmt;
+ *   a site with s > 0 flips iff u_fmt < p_fmt (compared as real numbers).
+ * The random numbers are the exact chain's, so both chains see identical draws. */
+double oracle_round_fmt(double v, int fmt, int toward_zero);
+double oracle_p_fmt(double beta, int s, int fmt);
+double oracle_u_fmt(uint32_t x, int fmt);
+void oracle_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n, uint64_t seed,
+                      uint64_t offset, int64_t* trace);
+
 /* Number of OpenMP threads the oracle's parallel loops use (1 without OpenMP). */
 int oracle_num_threads(void);
 

@@ -12,6 +12,10 @@ from .ising import (  # noqa: F401
     ising_half_sweep,
     ising_half_sweep_packed,
     ising_init_packed,
+    ising_moments,
+    ising_sweep_fmt,
+    ising_sweep_packed_fmt,
+    ising_thresholds_fmt,
     ising_init,
     ising_observables,
     ising_observables_packed,

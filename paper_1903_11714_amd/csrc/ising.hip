@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <string>
 
 #include "ising.h"
@@ -191,6 +192,8 @@ __device__ __forceinline__ bool wave_any(bool v) { return __builtin_amdgcn_ballo
 struct Thresholds {
     uint32_t t2, t4;      // low 32 bits of T_2, T_4
     uint32_t full2, full4;  // 1 when T_s = 2^32 (always accept)
+    uint32_t blocks;        // Philox blocks (4 bit planes each) that can decide: 8, or 4 when
+                            // both thresholds are multiples of 2^16 (16-bit uniforms)
 };
 
 // Exact x < T for every site in sel2 (threshold T_2) or sel4 (T_4), bit plane by bit plane.
@@ -205,7 +208,9 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t sel2, uint32_t sel4, co
     uint32_t tied = sel2 | sel4;
     // sites outside sel2 are compared with T_4 below; make sure only tied ones matter
 #pragma unroll 1
-    for (uint32_t m = 0; m < 8; ++m) {
+    for (uint32_t m = 0; m < th.blocks; ++m) {
+        // a site still tied after the last deciding plane has x >= T (the remaining bits of T
+        // are zero), so it is rejected
         if (!wave_any(tied != 0)) break;
         const Words4 blk = philox4x32_10(g, r, t, 2u * m + q, key0, key1);
         const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
@@ -355,6 +360,17 @@ __global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
         };
         auto wrapr = [&](uint32_t r) { return r >= L ? r - L : r; };
         auto halo = [&](uint32_t r, int o) { return o == 1 ? halo_right(r) : halo_left(r); };
+        // The horizontal neighbour in the adjacent group: byte 0 of the right group (o = 1) or
+        // byte 3 of the left group (o = 0).  When staged, the adjacent groups of row r sit in
+        // the neighbouring lanes, so a lane shuffle provides them and only the two lanes at the
+        // wave's ends read memory.  (Separate 4-byte loads per lane would reach L2 while the
+        // row's own loads are still in flight and fetch every line from DRAM a second time.)
+        auto halo_of = [&](const Row& row, uint32_t r, int o) -> uint32_t {
+            if (!STAGED) return halo(r, o);
+            uint32_t v = o == 1 ? __shfl_down(row.d[0], 1, 64) : __shfl_up(row.d[15], 1, 64);
+            if (o == 1 ? lane == 63u : lane == 0u) v = halo(r, o);
+            return v;
+        };
         // rows r0 (parity offset Q, since r0 is even) and r0 + 1 (offset 1 - Q) alternate.
         // Software pipeline: rows r .. r + 3 and their halo dwords are in registers while
         // rows r + 4, r + 5 are loaded, so HBM latency overlaps two rows of work.
@@ -376,7 +392,7 @@ __global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
         own(nxt, ra);
         fetch(ra, ahead(r0 + 2));
         fetch(rb, ahead(r0 + 3));
-        uint32_t h0 = halo(r0, O0), h1 = halo(wrapr(r0 + 1), O1);
+        uint32_t h0 = halo_of(cur, r0, O0), h1 = halo_of(nxt, wrapr(r0 + 1), O1);
         uint32_t bprev = site_bits<O0>(above);
         uint32_t bcur = site_bits<O1>(cur);
 #pragma unroll 1
@@ -386,7 +402,7 @@ __global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
             own(pb, rb);
             fetch(ra, ahead(r + 4));
             fetch(rb, ahead(r + 5));
-            const uint32_t h2 = halo(ahead(r + 2), O0), h3 = halo(ahead(r + 3), O1);
+            const uint32_t h2 = halo_of(pa, ahead(r + 2), O0), h3 = halo_of(pb, ahead(r + 3), O1);
             uint32_t bn = sweep_row<Q, O0, OBS>(cur, nxt, bprev, bcur, h0, a.th, g, r, a.t, a.key0, a.key1, cnt);
             put(r, cur);
             bprev = bcur;
@@ -625,6 +641,31 @@ __global__ __launch_bounds__(256) void k_init_packed(uint32_t* planes, uint32_t 
     planes[((size_t)L + r) * groups + g] = (r & 1u) ? even : odd;
 }
 
+// FP64 moments of a traced chain, summed in sweep order by one lane so the result does not
+// depend on scheduling: out = (<|m|>, <m^2>, <m^4>, <e>, <e^2>) with m = M / N, e = E / N.
+__global__ void k_moments(const int64_t* trace, int64_t n, int64_t n_sites, double* out) {
+#pragma clang fp contract(off)
+    // separate multiplies and adds (no fused multiply-add), each rounded as written
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double inv = 1.0 / (double)n_sites;
+    double s_abs = 0.0, s_m2 = 0.0, s_m4 = 0.0, s_e = 0.0, s_e2 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double m = (double)trace[2 * i] * inv, e = (double)trace[2 * i + 1] * inv;
+        const double m2 = m * m;
+        s_abs += fabs(m);
+        s_m2 += m2;
+        s_m4 += m2 * m2;
+        s_e += e;
+        s_e2 += e * e;
+    }
+    const double k = 1.0 / (double)n;
+    out[0] = s_abs * k;
+    out[1] = s_m2 * k;
+    out[2] = s_m4 * k;
+    out[3] = s_e * k;
+    out[4] = s_e2 * k;
+}
+
 }  // namespace ising
 
 // ==========================================================================================
@@ -668,14 +709,67 @@ void host_thresholds(double beta, uint64_t T[2]) {
     }
 }
 
-ising::Thresholds make_thresholds(double beta) {
+// ---- Low-precision acceptance (fmt 1 = bfloat16, 2 = IEEE half).  The probability is
+// exp(-2 beta s) rounded to nearest-even in the format; the site's uniform is the top 16 bits
+// r of its exact-chain uniform x, as r / 2^16 rounded toward zero in the format.  Rounding r / 2^16
+// toward zero keeps the leading `digits` significant bits of r (no subnormal case arises: r / 2^16
+// >= 2^-16 is normal in bfloat16, and below 2^-14 the half quantum 2^-24 is finer than 2^-16), so
+// u(r) < p  <=>  r < R, R = the least r with trunc(r) >= p 2^16, and the acceptance becomes the
+// exact-chain test x < R 2^16.
+int fmt_digits(int fmt) { return fmt == 1 ? 8 : 11; }
+
+// nearest-even rounding of p in [0, 1] to `digits` significant bits; half-precision values below
+// 2^-14 are multiples of 2^-24, bfloat16 values below 2^-126 multiples of 2^-133.
+double round_nearest_even(double p, int fmt) {
+    if (!(p > 0.0)) return 0.0;
+    const int digits = fmt_digits(fmt);
+    const int min_normal_exp = fmt == 1 ? -126 : -14;
+    if (p < std::ldexp(1.0, min_normal_exp)) {
+        const double q = std::ldexp(1.0, min_normal_exp - digits + 1);
+        return std::nearbyint(p / q) * q;
+    }
+    uint64_t bits;
+    std::memcpy(&bits, &p, sizeof bits);
+    const int drop = 52 - (digits - 1);                      // mantissa bits to clear
+    const uint64_t half = uint64_t(1) << (drop - 1);
+    const uint64_t lsb = (bits >> drop) & 1u;
+    bits += half - 1 + lsb;                                  // ties go to the even neighbour
+    bits &= ~((uint64_t(1) << drop) - 1);
+    double r;
+    std::memcpy(&r, &bits, sizeof r);
+    return r;
+}
+
+uint32_t keep_leading_bits(uint32_t r, int digits) {
+    if (r == 0) return 0;
+    const int len = 32 - __builtin_clz(r);
+    return len <= digits ? r : r & ~((1u << (len - digits)) - 1u);
+}
+
+void host_thresholds_fmt(double beta, int fmt, uint64_t T[2]) {
+    if (fmt == 0) {
+        host_thresholds(beta, T);
+        return;
+    }
+    for (int k = 0; k < 2; ++k) {
+        const double s = k == 0 ? 2.0 : 4.0;
+        const double p16 = round_nearest_even(std::exp(-2.0 * beta * s), fmt) * 65536.0;
+        uint32_t R = 65536;
+        for (uint32_t r = 0; r < 65536; ++r)
+            if ((double)keep_leading_bits(r, fmt_digits(fmt)) >= p16) { R = r; break; }
+        T[k] = (uint64_t)R << 16;
+    }
+}
+
+ising::Thresholds make_thresholds(double beta, int fmt = 0) {
     uint64_t T[2];
-    host_thresholds(beta, T);
+    host_thresholds_fmt(beta, fmt, T);
     ising::Thresholds th;
     th.full2 = T[0] >= (uint64_t(1) << 32);
     th.full4 = T[1] >= (uint64_t(1) << 32);
     th.t2 = th.full2 ? 0u : (uint32_t)T[0];
     th.t4 = th.full4 ? 0u : (uint32_t)T[1];
+    th.blocks = ((th.t2 | th.t4) & 0xFFFFu) == 0 ? 4u : 8u;
     return th;
 }
 
@@ -731,6 +825,18 @@ int ising_thresholds(double beta, uint64_t out[2]) {
     return ISING_OK;
 }
 
+int ising_thresholds_fmt(double beta, int fmt, uint64_t out[2]) {
+    if (!out || !valid_beta(beta) || fmt < 0 || fmt > 2) return ISING_EINVAL;
+    host_thresholds_fmt(beta, fmt, out);
+    return ISING_OK;
+}
+
+int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* out, void* stream) {
+    if (!trace_ME || !out || n <= 0 || n_sites <= 0) return ISING_EINVAL;
+    hipLaunchKernelGGL(ising::k_moments, dim3(1), dim3(64), 0, (hipStream_t)stream, trace_ME, n, n_sites, out);
+    return check_launch("k_moments");
+}
+
 int ising_init(int8_t* spins, int64_t L, uint64_t seed, void* stream) {
     if (!spins || !valid_L(L) || !aligned16(spins)) return ISING_EINVAL;
     const uint32_t chunks = (uint32_t)((L + 127) / 128);
@@ -762,10 +868,15 @@ int ising_half_sweep(int8_t* spins, int64_t L, double beta, uint64_t seed, uint6
 
 int ising_sweep(int8_t* spins, int64_t L, double beta, int64_t n_sweeps, uint64_t seed, uint64_t sweep_offset,
                 int64_t* trace_ME, void* stream) {
-    if (!spins || !valid_L(L) || !aligned16(spins) || !valid_beta(beta) || n_sweeps < 0 ||
+    return ising_sweep_fmt(spins, L, beta, 0, n_sweeps, seed, sweep_offset, trace_ME, stream);
+}
+
+int ising_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sweeps, uint64_t seed,
+                    uint64_t sweep_offset, int64_t* trace_ME, void* stream) {
+    if (!spins || !valid_L(L) || !aligned16(spins) || !valid_beta(beta) || n_sweeps < 0 || fmt < 0 || fmt > 2 ||
         sweep_offset > (uint64_t(1) << 32) || (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset)
         return ISING_EINVAL;
-    const ising::Thresholds th = make_thresholds(beta);
+    const ising::Thresholds th = make_thresholds(beta, fmt);
     hipStream_t s = (hipStream_t)stream;
     for (int64_t i = 0; i < n_sweeps; ++i) {
         const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
@@ -858,10 +969,16 @@ int ising_half_sweep_packed(uint32_t* planes, int64_t L, double beta, uint64_t s
 
 int ising_sweep_packed(uint32_t* planes, int64_t L, double beta, int64_t n_sweeps, uint64_t seed,
                        uint64_t sweep_offset, int64_t* trace_ME, void* stream) {
-    if (!planes || !valid_L(L) || !aligned16(planes) || !valid_beta(beta) || n_sweeps < 0 ||
-        sweep_offset > (uint64_t(1) << 32) || (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset)
+    return ising_sweep_packed_fmt(planes, L, beta, 0, n_sweeps, seed, sweep_offset, trace_ME, stream);
+}
+
+int ising_sweep_packed_fmt(uint32_t* planes, int64_t L, double beta, int fmt, int64_t n_sweeps, uint64_t seed,
+                           uint64_t sweep_offset, int64_t* trace_ME, void* stream) {
+    if (!planes || !valid_L(L) || !aligned16(planes) || !valid_beta(beta) || n_sweeps < 0 || fmt < 0 ||
+        fmt > 2 || sweep_offset > (uint64_t(1) << 32) ||
+        (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset)
         return ISING_EINVAL;
-    const ising::Thresholds th = make_thresholds(beta);
+    const ising::Thresholds th = make_thresholds(beta, fmt);
     hipStream_t s = (hipStream_t)stream;
     for (int64_t i = 0; i < n_sweeps; ++i) {
         const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);

@@ -47,6 +47,13 @@ _SIGNATURES = {
     "ising_half_sweep_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
                                  ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "ising_thresholds": ([ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "ising_thresholds_fmt": ([ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "ising_sweep_fmt": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_int64,
+                         ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising_sweep_packed_fmt": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_int64,
+                                ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising_moments": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
+                      ctypes.c_int),
     "ising_set_option": ([ctypes.c_char_p, ctypes.c_int64], ctypes.c_int),
     "ising_get_option": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ising_last_error": ([], ctypes.c_char_p),
@@ -168,6 +175,38 @@ def ising_thresholds(beta: float) -> tuple[int, int]:
     out = (ctypes.c_uint64 * 2)()
     _check("ising_thresholds", library().ising_thresholds(float(beta), out))
     return int(out[0]), int(out[1])
+
+
+FMT = {"exact": 0, "bf16": 1, "fp16": 2}
+
+
+def _fmt(fmt) -> int:
+    return FMT[fmt] if isinstance(fmt, str) else int(fmt)
+
+
+def ising_thresholds_fmt(beta: float, fmt) -> tuple[int, int]:
+    out = (ctypes.c_uint64 * 2)()
+    _check("ising_thresholds_fmt", library().ising_thresholds_fmt(float(beta), _fmt(fmt), out))
+    return int(out[0]), int(out[1])
+
+
+def ising_sweep_fmt(spins, L: int, beta: float, fmt, n_sweeps: int, seed: int, sweep_offset: int = 0,
+                    trace_ME=None, stream=None) -> None:
+    _check("ising_sweep_fmt", library().ising_sweep_fmt(
+        _dev_ptr(spins, "torch.int8", L * L), L, float(beta), _fmt(fmt), n_sweeps, seed, sweep_offset,
+        _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
+
+
+def ising_sweep_packed_fmt(planes, L: int, beta: float, fmt, n_sweeps: int, seed: int, sweep_offset: int = 0,
+                           trace_ME=None, stream=None) -> None:
+    _check("ising_sweep_packed_fmt", library().ising_sweep_packed_fmt(
+        _dev_ptr(planes, "torch.int32", L * L // 32), L, float(beta), _fmt(fmt), n_sweeps, seed, sweep_offset,
+        _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
+
+
+def ising_moments(trace_ME, n: int, n_sites: int, out, stream=None) -> None:
+    _check("ising_moments", library().ising_moments(
+        _dev_ptr(trace_ME, "torch.int64", 2 * n), n, n_sites, _dev_ptr(out, "torch.float64", 5), _stream(stream)))
 
 
 def ising_set_option(name: str, value: int) -> None:

@@ -103,3 +103,24 @@ def test_options_round_trip(lib):
             ising.ising_set_option(name, old)
     with pytest.raises(ising.IsingError):
         ising.ising_set_option("no_such_option", 1)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+@pytest.mark.parametrize("beta", [0.0, 0.2, 0.3846153846153846, 0.4, 0.44068679350977147, 0.5, 1.0, 3.0, math.inf])
+def test_library_lowprec_thresholds_match_oracle(oracle_lib, fmt, beta):
+    # The library turns "rounded uniform < rounded probability" into x < R 2^16; R must be the
+    # number of 16-bit uniforms the oracle's literal float comparison accepts.
+    from paper_1903_11714_amd import ising
+    T = ising.ising_thresholds_fmt(beta, fmt)
+    for k, s in enumerate((2, 4)):
+        p = oracle_lib.p_fmt(beta, s, fmt)
+        accepted = [r for r in range(65536) if oracle_lib.u_fmt(r << 16, fmt) < p]
+        R = len(accepted)
+        assert accepted == list(range(R))          # a prefix: the rounded uniform is monotone
+        assert T[k] == R << 16
+
+
+def test_exact_fmt_thresholds_are_the_exact_ones(lib):
+    from paper_1903_11714_amd import ising
+    for beta in (0.1, 0.44068679350977147, 0.7):
+        assert ising.ising_thresholds_fmt(beta, "exact") == ising.ising_thresholds(beta)
