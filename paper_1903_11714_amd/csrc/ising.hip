@@ -777,9 +777,9 @@ ising::Thresholds make_thresholds(double beta, int fmt = 0) {
 uint32_t rows_per_lane(int64_t L) {
     if (g_opt.rows_per_lane > 0 && L % g_opt.rows_per_lane == 0) return (uint32_t)g_opt.rows_per_lane;
     const uint32_t groups = (uint32_t)(L / 64);
-    // keep at least ~2048 workgroups' worth of lanes when the lattice allows it
+    // tall strips re-read fewer boundary rows; keep at least ~1024 workgroups' worth of lanes
     uint32_t R = 32;
-    while (R > 2 && (uint64_t)groups * (uint64_t)(L / R) < 2048ull * 256ull) R >>= 1;
+    while (R > 2 && (uint64_t)groups * (uint64_t)(L / R) < 1024ull * 256ull) R >>= 1;
     return R;
 }
 
