@@ -107,6 +107,42 @@ int ising_half_sweep_packed(uint32_t* planes, int64_t L, double beta, uint64_t s
 /* (M, E) of a packed lattice into device int64[2]. */
 int ising_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME, void* stream);
 
+/* ---- batched replicas ----------------------------------------------------------------------
+ * Many small independent lattices (L = 32, or L % 64 == 0 up to 512), each with its own beta and
+ * seed, run in ONE persistent launch (captured in a hipGraph and replayed on `stream`): one
+ * workgroup per replica keeps its lattice in LDS for every sweep of the run.  Every replica is
+ * the single-lattice chain of its (L, beta, seed): identical spins and (M, E) to
+ * ising_sweep_packed on that lattice alone (the paper's per-(L, T) Markov chains, Sec. 4.1). */
+typedef struct {
+    int64_t L;       /* linear size: 32, or a multiple of 64 up to 512 */
+    double beta;     /* finite >= 0 or +inf */
+    uint64_t seed;   /* Philox key of this replica */
+} ising_replica_t;
+
+/* Device workspace size for the batch (replica table + every replica's packed lattice), or
+ * ISING_EINVAL.  replicas: host array of n entries. */
+int64_t ising_batch_workspace_bytes(const ising_replica_t* replicas, int64_t n);
+
+/* n_therm + n_meas sweeps of every replica (sweep indices sweep_offset ..), all in one launch.
+ *   fmt        acceptance format as for ising_sweep_fmt (0 exact, 1 bfloat16, 2 half).
+ *   start      0 = hot start from each seed, 1 = cold start (all +1), 2 = continue from the
+ *              lattices left in `workspace` by a previous call with the same replicas.
+ *   workspace  device buffer of ising_batch_workspace_bytes bytes (caller-owned, 16-byte aligned);
+ *              holds the lattices between calls.
+ *   trace_ME   device int64[n * n_meas * 2] (replica-major (M, E) after every measurement sweep)
+ *              or NULL.
+ *   moments    device double[n * 5]: per replica <|m|>, <m^2>, <m^4>, <e>, <e^2> over the
+ *              measurement sweeps, summed in FP64 in sweep order, or NULL.
+ * The workgroup size (256, 512 or 1024 threads) is picked once per set of replica sizes by timing
+ * the candidates on the table itself (option "batch_threads" fixes it); every candidate gives
+ * identical results.  The first call for a new set of sizes synchronises for that timing. */
+int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm, int64_t n_meas,
+                    uint64_t sweep_offset, int fmt, int start, void* workspace, int64_t workspace_bytes,
+                    int64_t* trace_ME, double* moments, void* stream);
+
+/* Replica j's lattice from the batch workspace as int8 rows (device int8[L_j * L_j]). */
+int ising_batch_unpack(const void* workspace, int64_t n, int64_t j, int8_t* spins, void* stream);
+
 /* ---- host helpers -------------------------------------------------------------------------- */
 
 /* The two acceptance thresholds for beta: out[0] = T_2, out[1] = T_4 (each in [0, 2^32]),
@@ -131,7 +167,8 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
  *   "xcd_remap"      1 = hand each XCD one contiguous range of row strips (default), 0 = not.
  *   "nt_store"       1 = non-temporal stores of updated rows, 0 = ordinary stores (default).
  *   "staged"         1 = coalesced row loads and stores regrouped through LDS when L is a
- *                    multiple of 4096 (default), 0 = every lane reads its own 64 bytes. */
+ *                    multiple of 4096 (default), 0 = every lane reads its own 64 bytes.
+ *   "batch_threads"  workgroup size of ising_batch_run: 0 = autotune (default), 256, 512, 1024. */
 int ising_set_option(const char* name, int64_t value);
 int ising_get_option(const char* name, int64_t* value);
 

@@ -6,6 +6,10 @@ behind the C ABI in include/ising.h; ``paper_1903_11714_amd.ising`` is its ctype
 from . import ising  # noqa: F401
 from .ising import (  # noqa: F401
     IsingError,
+    batch_run,
+    ising_batch_run,
+    ising_batch_unpack,
+    ising_batch_workspace_bytes,
     ising_fill,
     ising_get_option,
     ising_set_option,

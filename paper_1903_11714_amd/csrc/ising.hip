@@ -25,7 +25,9 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <vector>
 
 #include "ising.h"
 #include "philox.hpp"
@@ -244,20 +246,22 @@ struct Counts {
 // mask; with OBS it also counts the anti-aligned bonds of these sites after the update and
 // the -1 spins among these sites (after) plus `others` (the other colour of the row).
 template <int Q, bool OBS>
+// `valid` marks the sites that exist (all 32 except in a row of only 16 same-colour sites).
 __device__ __forceinline__ uint32_t decide(uint32_t a, uint32_t up, uint32_t down, uint32_t side, uint32_t hs,
                                            uint32_t others, const Thresholds& th, uint32_t g, uint32_t r,
-                                           uint32_t t, uint32_t key0, uint32_t key1, Counts& cnt) {
+                                           uint32_t t, uint32_t key0, uint32_t key1, Counts& cnt,
+                                           uint32_t valid = 0xFFFFFFFFu) {
     const uint32_t x1 = a ^ up, x2 = a ^ down, x3 = a ^ side, x4 = a ^ hs;  // anti-aligned
     const uint32_t o12 = x1 | x2, o34 = x3 | x4;
-    const uint32_t ge2 = (x1 & x2) | (x3 & x4) | (o12 & o34);  // >= 2 anti-aligned: s <= 0
+    const uint32_t ge2 = ((x1 & x2) | (x3 & x4) | (o12 & o34)) & valid;  // >= 2 anti-aligned: s <= 0
     const uint32_t any = o12 | o34;
-    const uint32_t sel2 = any & ~ge2;                            // exactly one: s = 2
-    const uint32_t sel4 = ~any;                                  // none: s = 4
+    const uint32_t sel2 = any & ~ge2 & valid;                              // exactly one: s = 2
+    const uint32_t sel4 = ~any & valid;                                    // none: s = 4
     const uint32_t F = ge2 | accept_mask(sel2, sel4, th, g, r, t, (uint32_t)Q, key0, key1);
     if (OBS) {
-        cnt.anti += __builtin_popcount(x1 ^ F) + __builtin_popcount(x2 ^ F) +
-                    __builtin_popcount(x3 ^ F) + __builtin_popcount(x4 ^ F);
-        cnt.neg += __builtin_popcount(a ^ F) + __builtin_popcount(others);
+        cnt.anti += __builtin_popcount((x1 ^ F) & valid) + __builtin_popcount((x2 ^ F) & valid) +
+                    __builtin_popcount((x3 ^ F) & valid) + __builtin_popcount((x4 ^ F) & valid);
+        cnt.neg += __builtin_popcount((a ^ F) & valid) + __builtin_popcount(others & valid);
     }
     return F;
 }
@@ -641,6 +645,176 @@ __global__ __launch_bounds__(256) void k_init_packed(uint32_t* planes, uint32_t 
     planes[((size_t)L + r) * groups + g] = (r & 1u) ? even : odd;
 }
 
+// ==========================================================================================
+// Batched replicas: one workgroup per replica (L = 32 or L % 64 == 0, L <= 512), the lattice in LDS as
+// the two colour planes of the packed layout, all sweeps of the run in one launch.  Every replica
+// uses the single-lattice chain's random numbers (its own seed, the same counters), so each one is
+// bit-identical to ising_sweep_packed on that replica alone.
+struct BatchReplica {
+    uint32_t L;          // linear size
+    uint32_t W;          // words per row per colour: L / 64, or 1 for L = 32 (16 sites per word)
+    uint32_t key0, key1;
+    uint32_t t0;         // sweep index of the first sweep of this run
+    uint32_t pad;
+    Thresholds th;
+    uint32_t pad2;
+    uint64_t state_off;  // word offset of this replica's planes in the state buffer
+};
+
+constexpr uint32_t kBatchMaxWords = 2u * 512u * 8u;  // both planes at L = 512: 32 KiB of LDS
+
+// Rows of 16 same-colour sites (L = 32): the word wraps onto itself after site 15, and only
+// sites 0..15 (bits 0-3 of each byte in site order) exist.
+__device__ __forceinline__ uint32_t shift_next16(uint32_t y) {
+    const uint32_t top = ((y >> 1) & 0x07u) | ((y & 1u) << 3);
+    return perm(top, y, 0x04010302u);
+}
+__device__ __forceinline__ uint32_t shift_prev16(uint32_t y) {
+    const uint32_t low = ((y >> 23) & 0x0Eu) | ((y >> 27) & 1u);
+    return perm(y, low, 0x05040600u);
+}
+
+// Hot-start words of row r, group g of an L x L lattice: (colour-0 word, colour-1 word).
+__device__ __forceinline__ void hot_start_words(uint32_t L, uint32_t r, uint32_t g, uint32_t key0, uint32_t key1,
+                                                uint32_t& w0, uint32_t& w1) {
+    const Words4 w = philox4x32_10(g >> 1, r, 0u, 0x80000000u, key0, key1);
+    const uint32_t lo = (g & 1u) ? w.w2 : w.w0, hi = (g & 1u) ? w.w3 : w.w1;  // columns 0-31, 32-63
+    Row row;
+#pragma unroll
+    for (int d = 0; d < 16; ++d) {
+        const uint32_t src = d < 8 ? lo : (L >= 64 ? hi : 0u);
+        row.d[d] = nibble_to_bytes((src >> (4 * (d & 7))) & 15u);
+    }
+    const uint32_t even = site_bits<0>(row), odd = site_bits<1>(row);
+    w0 = (r & 1u) ? odd : even;
+    w1 = (r & 1u) ? even : odd;
+}
+
+// One colour update of a replica held in LDS; every thread owns words tid, tid + blockDim, ...
+template <int Q, bool OBS>
+__device__ __forceinline__ void batch_half_sweep(uint32_t* planes, const BatchReplica& rp, uint32_t t,
+                                                 Counts& cnt) {
+    const uint32_t L = rp.L, W = rp.W, words = L * W;
+    const uint32_t valid = L >= 64 ? 0xFFFFFFFFu : 0x0F0F0F0Fu;
+    uint32_t* pq = planes + Q * words;
+    const uint32_t* po = planes + (1 - Q) * words;
+    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) {
+        const uint32_t r = w / W, g = w - r * W;
+        const uint32_t rm = r == 0 ? L - 1 : r - 1, rp1 = r + 1 == L ? 0 : r + 1;
+        const uint32_t a = pq[w], side = po[w];
+        const uint32_t up = po[rm * W + g], down = po[rp1 * W + g];
+        const uint32_t o = (r + Q) & 1u;   // column parity of this row's colour-Q sites
+        uint32_t hs;
+        if (L >= 64) {
+            const uint32_t gl = g == 0 ? W - 1 : g - 1, gr = g + 1 == W ? 0 : g + 1;
+            hs = o ? shift_next(side, po[r * W + gr] & 1u) : shift_prev(side, po[r * W + gl] >> 31);
+        } else {
+            hs = o ? shift_next16(side) : shift_prev16(side);
+        }
+        const uint32_t F = decide<Q, OBS>(a, up, down, side, hs, side, rp.th, g, r, t, rp.key0, rp.key1, cnt, valid);
+        pq[w] = a ^ F;
+    }
+}
+
+// FP64 moment sums of one sample, each operation rounded as written (no fused multiply-add), so
+// the sums equal a plain sequential evaluation in the same order.
+__device__ __forceinline__ void accumulate_moments(int64_t M, int64_t E, double inv, double& s_abs, double& s_m2,
+                                                   double& s_m4, double& s_e, double& s_e2) {
+#pragma clang fp contract(off)
+    const double m = (double)M * inv, e = (double)E * inv, m2 = m * m;
+    s_abs += fabs(m);
+    s_m2 += m2;
+    s_m4 += m2 * m2;
+    s_e += e;
+    s_e2 += e * e;
+}
+
+__device__ __forceinline__ void store_moments(double* mo, uint32_t n, double s_abs, double s_m2, double s_m4,
+                                              double s_e, double s_e2) {
+#pragma clang fp contract(off)
+    const double k = 1.0 / (double)n;
+    mo[0] = s_abs * k;
+    mo[1] = s_m2 * k;
+    mo[2] = s_m4 * k;
+    mo[3] = s_e * k;
+    mo[4] = s_e2 * k;
+}
+
+// start: 0 = hot start from the seed, 1 = cold start (all +1), 2 = continue from `state`.
+__global__ __launch_bounds__(1024) void k_batch(const BatchReplica* table, uint32_t* state, uint32_t start,
+                                                uint32_t n_therm, uint32_t n_meas, int64_t* trace,
+                                                double* moments) {
+    __shared__ uint32_t planes[kBatchMaxWords];
+    __shared__ uint32_t red[2][16];
+    const BatchReplica rp = table[blockIdx.x];
+    const uint32_t words = rp.L * rp.W;
+    uint32_t* gstate = state + rp.state_off;
+    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) {
+        uint32_t w0 = 0u, w1 = 0u;
+        if (start == 0) hot_start_words(rp.L, w / rp.W, w % rp.W, rp.key0, rp.key1, w0, w1);
+        else if (start == 2) { w0 = gstate[w]; w1 = gstate[words + w]; }
+        planes[w] = w0;
+        planes[words + w] = w1;
+    }
+    __syncthreads();
+    const double inv = 1.0 / ((double)rp.L * (double)rp.L);
+    double s_abs = 0.0, s_m2 = 0.0, s_m4 = 0.0, s_e = 0.0, s_e2 = 0.0;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    for (uint32_t i = 0; i < n_therm + n_meas; ++i) {
+        const uint32_t t = rp.t0 + i;
+        Counts cnt{0u, 0u};
+        batch_half_sweep<1, false>(planes, rp, t, cnt);
+        __syncthreads();
+        if (i < n_therm) {
+            batch_half_sweep<0, false>(planes, rp, t, cnt);
+            __syncthreads();
+            continue;
+        }
+        batch_half_sweep<0, true>(planes, rp, t, cnt);
+        const uint32_t anti = wave_sum(cnt.anti), neg = wave_sum(cnt.neg);
+        if (lane == 0) { red[0][wave] = anti; red[1][wave] = neg; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t A = 0, Nn = 0;
+            for (uint32_t k = 0; k < blockDim.x / 64u; ++k) { A += red[0][k]; Nn += red[1][k]; }
+            const int64_t sites = (int64_t)rp.L * rp.L;
+            const int64_t M = sites - 2 * (int64_t)Nn, E = 2 * (int64_t)A - 2 * sites;
+            const uint32_t j = i - n_therm;
+            if (trace) {
+                int64_t* tr = trace + 2 * ((size_t)blockIdx.x * n_meas + j);
+                tr[0] = M;
+                tr[1] = E;
+            }
+            accumulate_moments(M, E, inv, s_abs, s_m2, s_m4, s_e, s_e2);
+        }
+        __syncthreads();  // red[] is reused by the next sweep
+    }
+    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) {
+        gstate[w] = planes[w];
+        gstate[words + w] = planes[words + w];
+    }
+    if (threadIdx.x == 0 && moments && n_meas > 0)
+        store_moments(moments + 5 * (size_t)blockIdx.x, n_meas, s_abs, s_m2, s_m4, s_e, s_e2);
+}
+
+// Unpack one replica's planes (L x L, the packed layout above) to int8 rows.
+__global__ void k_batch_unpack(const BatchReplica* table, const uint32_t* state, uint32_t j, int8_t* spins) {
+    const BatchReplica rp = table[j];
+    const uint32_t L = rp.L, W = rp.W, words = L * W;
+    const uint32_t* p = state + rp.state_off;
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < words; w += gridDim.x * blockDim.x) {
+        const uint32_t r = w / W, g = w % W;
+        const uint32_t q0 = p[w], q1 = p[words + w];
+        const uint32_t even = (r & 1u) ? q1 : q0, odd = (r & 1u) ? q0 : q1;
+        const uint32_t ncol = L >= 64 ? 64u : 32u;
+        for (uint32_t d = 0; d < ncol / 4; ++d) {
+            const uint32_t k = d >> 1, h = d & 1u, sh = 15 - k - 8 * h;
+            const uint32_t v = perm(odd << sh, even << sh, 0x0B090A08u) | 0x01010101u;
+            *reinterpret_cast<uint32_t*>(spins + (size_t)r * L + (size_t)g * 64u + 4u * d) = v;
+        }
+    }
+}
+
 // FP64 moments of a traced chain, summed in sweep order by one lane so the result does not
 // depend on scheduling: out = (<|m|>, <m^2>, <m^4>, <e>, <e^2>) with m = M / N, e = E / N.
 __global__ void k_moments(const int64_t* trace, int64_t n, int64_t n_sites, double* out) {
@@ -680,6 +854,7 @@ struct Options {
     int64_t xcd_remap = 1;
     int64_t nt_store = 0;
     int64_t staged = 1;
+    int64_t batch_threads = 0;  // 0 = autotune
 };
 Options g_opt;
 
@@ -817,6 +992,107 @@ int launch_half_sweep(int8_t* spins, int64_t L, const ising::Thresholds& th, uin
 
 }  // namespace
 
+// ---- batched replicas --------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kTableAlign = 256;
+
+// 32 (one 16-site word per row and colour) or a multiple of 64 (whole 32-site words), at most 512
+bool valid_batch_L(int64_t L) { return L == 32 || (L >= 64 && L <= 512 && L % 64 == 0); }
+
+size_t batch_table_bytes(int64_t n) {
+    return ((size_t)n * sizeof(ising::BatchReplica) + kTableAlign - 1) / kTableAlign * kTableAlign;
+}
+
+uint64_t batch_words(int64_t L) { return 2ull * (uint64_t)L * (uint64_t)(L >= 64 ? L / 64 : 1); }
+
+struct BatchGraph {
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture = nullptr;
+    std::string key;
+};
+BatchGraph g_batch_graph;
+std::map<std::string, int> g_batch_tuned;  // replica-size signature -> threads per block
+
+std::string batch_signature(const ising_replica_t* reps, int64_t n) {
+    std::string sig;
+    for (int64_t i = 0; i < n; ++i) sig += std::to_string(reps[i].L) + ",";
+    return sig;
+}
+
+int launch_batch_direct(const ising::BatchReplica* table, uint32_t* state, int64_t n, int threads, uint32_t start,
+                        uint32_t n_therm, uint32_t n_meas, int64_t* trace, double* moments, hipStream_t stream) {
+    hipLaunchKernelGGL(ising::k_batch, dim3((unsigned)n), dim3((unsigned)threads), 0, stream, table, state, start,
+                       n_therm, n_meas, trace, moments);
+    return check_launch("k_batch");
+}
+
+// Time the three block sizes on the replica table itself (a few thermalisation sweeps, which the
+// real run overwrites) and keep the fastest; results are identical for every block size.
+int autotune_batch(const ising_replica_t* reps, int64_t n, const ising::BatchReplica* table, uint32_t* state,
+                   uint32_t start, hipStream_t stream, int* threads_out) {
+    const std::string sig = batch_signature(reps, n);
+    auto it = g_batch_tuned.find(sig);
+    if (it != g_batch_tuned.end()) { *threads_out = it->second; return ISING_OK; }
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return hip_failed(e, "hipEventCreate");
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) { (void)hipEventDestroy(e0); return hip_failed(e, "hipEventCreate"); }
+    int best = 256;
+    float best_ms = 1e30f;
+    int rc = ISING_OK;
+    for (int threads : {256, 512, 1024}) {
+        for (int rep = 0; rep < 2 && rc == ISING_OK; ++rep) {
+            (void)hipEventRecord(e0, stream);
+            rc = launch_batch_direct(table, state, n, threads, start, 8u, 0u, nullptr, nullptr, stream);
+            (void)hipEventRecord(e1, stream);
+            if (rc) break;
+            e = hipEventSynchronize(e1);
+            if (e != hipSuccess) { rc = hip_failed(e, "hipEventSynchronize"); break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep == 1 && ms < best_ms) { best_ms = ms; best = threads; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    g_batch_tuned[sig] = best;
+    *threads_out = best;
+    return ISING_OK;
+}
+
+}  // namespace
+
+namespace {
+int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Thresholds& th, uint64_t seed, uint32_t t,
+                             int q, int64_t* obs, int64_t* zero_slot, hipStream_t stream) {
+    ising::PackedArgs a;
+    a.planes = planes;
+    a.L = (uint32_t)L;
+    a.groups = (uint32_t)(L / 64);
+    a.rows = rows_per_lane(L);
+    a.n_lanes = a.groups * (uint32_t)(L / a.rows);
+    a.t = t;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.th = th;
+    a.obs = obs;
+    a.zero_slot = zero_slot;
+    a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
+    const dim3 grid((a.n_lanes + 255u) / 256u), block(256);
+    if (q == 1) {
+        if (obs) hipLaunchKernelGGL((ising::k_sweep_packed<1, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((ising::k_sweep_packed<1, false>), grid, block, 0, stream, a);
+    } else {
+        if (obs) hipLaunchKernelGGL((ising::k_sweep_packed<0, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((ising::k_sweep_packed<0, false>), grid, block, 0, stream, a);
+    }
+    return check_launch("k_sweep_packed");
+}
+}  // namespace
+
 extern "C" {
 
 int ising_thresholds(double beta, uint64_t out[2]) {
@@ -930,33 +1206,6 @@ int ising_init_packed(uint32_t* planes, int64_t L, uint64_t seed, void* stream) 
     return check_launch("k_init_packed");
 }
 
-namespace {
-int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Thresholds& th, uint64_t seed, uint32_t t,
-                             int q, int64_t* obs, int64_t* zero_slot, hipStream_t stream) {
-    ising::PackedArgs a;
-    a.planes = planes;
-    a.L = (uint32_t)L;
-    a.groups = (uint32_t)(L / 64);
-    a.rows = rows_per_lane(L);
-    a.n_lanes = a.groups * (uint32_t)(L / a.rows);
-    a.t = t;
-    a.key0 = (uint32_t)seed;
-    a.key1 = (uint32_t)(seed >> 32);
-    a.th = th;
-    a.obs = obs;
-    a.zero_slot = zero_slot;
-    a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
-    const dim3 grid((a.n_lanes + 255u) / 256u), block(256);
-    if (q == 1) {
-        if (obs) hipLaunchKernelGGL((ising::k_sweep_packed<1, true>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((ising::k_sweep_packed<1, false>), grid, block, 0, stream, a);
-    } else {
-        if (obs) hipLaunchKernelGGL((ising::k_sweep_packed<0, true>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((ising::k_sweep_packed<0, false>), grid, block, 0, stream, a);
-    }
-    return check_launch("k_sweep_packed");
-}
-}  // namespace
 
 int ising_half_sweep_packed(uint32_t* planes, int64_t L, double beta, uint64_t seed, uint64_t t, int q,
                             void* stream) {
@@ -1015,6 +1264,9 @@ int ising_set_option(const char* name, int64_t value) {
     } else if (n == "nt_store") {
         if (value != 0 && value != 1) return ISING_EINVAL;
         g_opt.nt_store = value;
+    } else if (n == "batch_threads") {
+        if (value != 0 && value != 256 && value != 512 && value != 1024) return ISING_EINVAL;
+        g_opt.batch_threads = value;
     } else if (n == "staged") {
         if (value != 0 && value != 1) return ISING_EINVAL;
         g_opt.staged = value;
@@ -1031,8 +1283,104 @@ int ising_get_option(const char* name, int64_t* value) {
     else if (n == "xcd_remap") *value = g_opt.xcd_remap;
     else if (n == "nt_store") *value = g_opt.nt_store;
     else if (n == "staged") *value = g_opt.staged;
+    else if (n == "batch_threads") *value = g_opt.batch_threads;
     else return ISING_EINVAL;
     return ISING_OK;
+}
+
+int64_t ising_batch_workspace_bytes(const ising_replica_t* replicas, int64_t n) {
+    if (!replicas || n <= 0 || n > 65535) return ISING_EINVAL;
+    uint64_t words = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!valid_batch_L(replicas[i].L)) return ISING_EINVAL;
+        words += batch_words(replicas[i].L);
+    }
+    return (int64_t)(batch_table_bytes(n) + words * 4u);
+}
+
+int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm, int64_t n_meas, uint64_t sweep_offset,
+                    int fmt, int start, void* workspace, int64_t workspace_bytes, int64_t* trace_ME, double* moments,
+                    void* stream) {
+    const int64_t need = ising_batch_workspace_bytes(replicas, n);
+    if (need < 0 || !workspace || workspace_bytes < need || !aligned16(workspace) || n_therm < 0 || n_meas < 0 ||
+        fmt < 0 || fmt > 2 || start < 0 || start > 2 || (uint64_t)(n_therm + n_meas) > (uint64_t(1) << 32) ||
+        sweep_offset > (uint64_t(1) << 32) - (uint64_t)(n_therm + n_meas))
+        return ISING_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (!valid_beta(replicas[i].beta)) return ISING_EINVAL;
+    // replica table (host) -> workspace head (device)
+    std::vector<ising::BatchReplica> table((size_t)n);
+    uint64_t off = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        ising::BatchReplica& b = table[(size_t)i];
+        std::memset(&b, 0, sizeof b);
+        b.L = (uint32_t)replicas[i].L;
+        b.W = replicas[i].L >= 64 ? (uint32_t)(replicas[i].L / 64) : 1u;
+        b.key0 = (uint32_t)replicas[i].seed;
+        b.key1 = (uint32_t)(replicas[i].seed >> 32);
+        b.t0 = (uint32_t)sweep_offset;
+        b.th = make_thresholds(replicas[i].beta, fmt);
+        b.state_off = off;
+        off += batch_words(replicas[i].L);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    auto* dtable = reinterpret_cast<ising::BatchReplica*>(workspace);
+    auto* state = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(workspace) + batch_table_bytes(n));
+    hipError_t e = hipMemcpyAsync(dtable, table.data(), table.size() * sizeof(ising::BatchReplica),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_failed(e, "hipMemcpyAsync(replica table)");
+    int threads = (int)g_opt.batch_threads;
+    if (threads == 0) {
+        if (start == 2) threads = 1024;  // tuning would overwrite the state being continued
+        else {
+            const int rc = autotune_batch(replicas, n, dtable, state, (uint32_t)start, s, &threads);
+            if (rc) return rc;
+        }
+    }
+    // One persistent launch, captured once into a hipGraph and replayed on the caller's stream.
+    char keybuf[256];
+    std::snprintf(keybuf, sizeof keybuf, "%p|%p|%p|%p|%lld|%d|%d|%lld|%lld", workspace, (void*)state,
+                  (void*)trace_ME, (void*)moments, (long long)n, threads, start, (long long)n_therm,
+                  (long long)n_meas);
+    const std::string key(keybuf);
+    if (g_batch_graph.key != key || !g_batch_graph.exec) {
+        if (g_batch_graph.exec) {
+            (void)hipDeviceSynchronize();
+            (void)hipGraphExecDestroy(g_batch_graph.exec);
+            g_batch_graph.exec = nullptr;
+        }
+        if (!g_batch_graph.capture) {
+            e = hipStreamCreateWithFlags(&g_batch_graph.capture, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_failed(e, "hipStreamCreateWithFlags");
+        }
+        hipStream_t cs = g_batch_graph.capture;
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_failed(e, "hipStreamBeginCapture");
+        hipLaunchKernelGGL(ising::k_batch, dim3((unsigned)n), dim3((unsigned)threads), 0, cs, dtable, state,
+                           (uint32_t)start, (uint32_t)n_therm, (uint32_t)n_meas, trace_ME, moments);
+        hipGraph_t graph = nullptr;
+        const hipError_t launch_err = hipGetLastError();
+        e = hipStreamEndCapture(cs, &graph);
+        if (launch_err != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return hip_failed(launch_err, "k_batch"); }
+        if (e != hipSuccess) return hip_failed(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&g_batch_graph.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) { g_batch_graph.exec = nullptr; return hip_failed(e, "hipGraphInstantiate"); }
+        g_batch_graph.key = key;
+    }
+    e = hipGraphLaunch(g_batch_graph.exec, s);
+    if (e != hipSuccess) return hip_failed(e, "hipGraphLaunch");
+    return ISING_OK;
+}
+
+int ising_batch_unpack(const void* workspace, int64_t n, int64_t j, int8_t* spins, void* stream) {
+    if (!workspace || !spins || n <= 0 || j < 0 || j >= n || !aligned16(workspace)) return ISING_EINVAL;
+    const auto* dtable = reinterpret_cast<const ising::BatchReplica*>(workspace);
+    const auto* state =
+        reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(workspace) + batch_table_bytes(n));
+    hipLaunchKernelGGL(ising::k_batch_unpack, dim3(16), dim3(256), 0, (hipStream_t)stream, dtable, state,
+                       (uint32_t)j, spins);
+    return check_launch("k_batch_unpack");
 }
 
 const char* ising_last_error(void) { return g_last_error.c_str(); }

@@ -29,6 +29,11 @@ class IsingError(RuntimeError):
         super().__init__(msg)
 
 
+class ReplicaT(ctypes.Structure):
+    """ising_replica_t: one lattice of a batch."""
+    _fields_ = [("L", ctypes.c_int64), ("beta", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
 _SIGNATURES = {
     "ising_init": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p], ctypes.c_int),
     "ising_fill": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
@@ -54,6 +59,12 @@ _SIGNATURES = {
                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "ising_moments": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
                       ctypes.c_int),
+    "ising_batch_workspace_bytes": ([ctypes.POINTER(ReplicaT), ctypes.c_int64], ctypes.c_int64),
+    "ising_batch_run": ([ctypes.POINTER(ReplicaT), ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+                         ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising_batch_unpack": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
+                           ctypes.c_int),
     "ising_set_option": ([ctypes.c_char_p, ctypes.c_int64], ctypes.c_int),
     "ising_get_option": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ising_last_error": ([], ctypes.c_char_p),
@@ -209,6 +220,36 @@ def ising_moments(trace_ME, n: int, n_sites: int, out, stream=None) -> None:
         _dev_ptr(trace_ME, "torch.int64", 2 * n), n, n_sites, _dev_ptr(out, "torch.float64", 5), _stream(stream)))
 
 
+def _replica_array(replicas):
+    arr = (ReplicaT * len(replicas))()
+    for i, (L, beta, seed) in enumerate(replicas):
+        arr[i] = ReplicaT(int(L), float(beta), int(seed))
+    return arr
+
+
+def ising_batch_workspace_bytes(replicas) -> int:
+    """replicas: sequence of (L, beta, seed)."""
+    n = int(library().ising_batch_workspace_bytes(_replica_array(replicas), len(replicas)))
+    if n < 0:
+        raise IsingError("ising_batch_workspace_bytes", n, "invalid replica table")
+    return n
+
+
+def ising_batch_run(replicas, n_therm: int, n_meas: int, workspace, sweep_offset: int = 0, fmt=0, start: int = 0,
+                    trace_ME=None, moments=None, stream=None) -> None:
+    n = len(replicas)
+    _check("ising_batch_run", library().ising_batch_run(
+        _replica_array(replicas), n, n_therm, n_meas, sweep_offset, _fmt(fmt), start,
+        _dev_ptr(workspace, "torch.uint8"), workspace.numel(),
+        _opt_ptr(trace_ME, "torch.int64", 2 * n * n_meas), _opt_ptr(moments, "torch.float64", 5 * n),
+        _stream(stream)))
+
+
+def ising_batch_unpack(workspace, n: int, j: int, spins, stream=None) -> None:
+    _check("ising_batch_unpack", library().ising_batch_unpack(
+        _dev_ptr(workspace, "torch.uint8"), n, j, _dev_ptr(spins, "torch.int8"), _stream(stream)))
+
+
 def ising_set_option(name: str, value: int) -> None:
     _check("ising_set_option", library().ising_set_option(name.encode(), int(value)))
 
@@ -242,6 +283,22 @@ def new_packed(L: int, seed: int, device: str = "cuda"):
     planes = torch.empty(L * L // 32, dtype=torch.int32, device=device)
     ising_init_packed(planes, L, seed)
     return planes
+
+
+def batch_run(replicas, n_therm: int, n_meas: int, fmt=0, start: int = 0, sweep_offset: int = 0,
+              trace: bool = True, workspace=None, device: str = "cuda"):
+    """Run a batch of (L, beta, seed) replicas in one persistent launch.  Returns
+    (moments [n, 5] float64: <|m|>, <m^2>, <m^4>, <e>, <e^2>; trace [n, n_meas, 2] int64 or None;
+    workspace, which holds the lattices for a later start=2 call)."""
+    import torch
+    n = len(replicas)
+    if workspace is None:
+        workspace = torch.empty(ising_batch_workspace_bytes(replicas), dtype=torch.uint8, device=device)
+    moments = torch.empty((n, 5), dtype=torch.float64, device=device)
+    tr = torch.empty((n, max(n_meas, 1), 2), dtype=torch.int64, device=device) if trace and n_meas else None
+    ising_batch_run(replicas, n_therm, n_meas, workspace, sweep_offset, fmt, start,
+                    tr.view(-1)[: 2 * n * n_meas] if tr is not None else None, moments)
+    return moments, tr, workspace
 
 
 def observables(spins) -> tuple[int, int]:

@@ -1,0 +1,119 @@
+"""GPU parity of the batched persistent form: many replicas of uneven L and temperature in one
+launch.  Each replica must equal the oracle's single-lattice chain of its (L, beta, seed) bit for
+bit (every spin and every traced (M, E)), and the FP64 moments must equal a sequential evaluation
+of the trace.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+BETA_C = 0.5 * math.log1p(math.sqrt(2.0))
+
+REPLICAS = [(32, 0.5, 1001), (64, BETA_C, 1002), (192, 0.41, 1003), (128, 0.0, 1004), (320, 1 / 2.6, 1005),
+            (256, math.inf, 1006), (512, BETA_C, 1007), (32, 0.3, 1008), (64, 1 / 2.2, 1009)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_11714_amd import ising
+    ising.library()
+    return ising
+
+
+def _replica(dev, ws, n, j, L):
+    s = torch.empty((L, L), dtype=torch.int8, device="cuda")
+    dev.ising_batch_unpack(ws, n, j, s)
+    return s.cpu().numpy()
+
+
+def _seq_moments(tr, N):
+    inv = 1.0 / N
+    acc = [0.0] * 5
+    for M, E in tr.tolist():
+        m, e = M * inv, E * inv
+        m2 = m * m
+        acc[0] += abs(m)
+        acc[1] += m2
+        acc[2] += m2 * m2
+        acc[3] += e
+        acc[4] += e * e
+    return [a * (1.0 / len(tr)) for a in acc]
+
+
+def test_batch_matches_oracle(dev, oracle_lib):
+    n_therm, n_meas = 3, 6
+    print("batch", len(REPLICAS), flush=True)
+    moments, trace, ws = dev.batch_run(REPLICAS, n_therm, n_meas, start=0, sweep_offset=40)
+    torch.cuda.synchronize()
+    for j, (L, beta, seed) in enumerate(REPLICAS):
+        host = oracle_lib.init(L, seed)
+        oracle_lib.sweep(host, beta, n_therm, seed, 40)
+        ref = oracle_lib.sweep(host, beta, n_meas, seed, 40 + n_therm, trace=True)
+        assert np.array_equal(_replica(dev, ws, len(REPLICAS), j, L), host), (L, beta)
+        assert np.array_equal(trace[j].cpu().numpy(), ref), (L, beta)
+        assert moments[j].cpu().tolist() == _seq_moments(ref, L * L), (L, beta)
+
+
+def test_batch_equals_single_lattice_path(dev):
+    reps = [(64, BETA_C, 7), (256, 0.4, 8), (512, 0.5, 9)]
+    _, trace, ws = dev.batch_run(reps, 0, 5, start=0, sweep_offset=2)
+    for j, (L, beta, seed) in enumerate(reps):
+        p = torch.empty(L * L // 32, dtype=torch.int32, device="cuda")
+        dev.ising_init_packed(p, L, seed)
+        t = torch.empty((5, 2), dtype=torch.int64, device="cuda")
+        dev.ising_sweep_packed(p, L, beta, 5, seed, 2, t)
+        s = torch.empty((L, L), dtype=torch.int8, device="cuda")
+        dev.ising_unpack(p, L, s)
+        assert np.array_equal(_replica(dev, ws, len(reps), j, L), s.cpu().numpy())
+        assert torch.equal(trace[j], t)
+
+
+def test_batch_block_sizes_and_continuation_identical(dev):
+    reps = REPLICAS
+    ref = None
+    try:
+        for threads in (256, 512, 1024, 0):
+            dev.ising_set_option("batch_threads", threads)
+            mo, tr, ws = dev.batch_run(reps, 2, 4, start=0)
+            if ref is None:
+                ref = (mo, tr)
+            else:
+                assert torch.equal(mo, ref[0]) and torch.equal(tr, ref[1]), threads
+        # 2 + 4 sweeps in one call == 2 therm, then continue for the 4 measured ones
+        dev.ising_set_option("batch_threads", 512)
+        _, _, ws = dev.batch_run(reps, 2, 0, start=0)
+        mo2, tr2, _ = dev.batch_run(reps, 0, 4, start=2, sweep_offset=2, workspace=ws)
+        assert torch.equal(tr2, ref[1]) and torch.equal(mo2, ref[0])
+    finally:
+        dev.ising_set_option("batch_threads", 0)
+
+
+def test_batch_graph_replay_deterministic(dev):
+    reps = [(128, BETA_C, 5), (32, 0.6, 6)]
+    ws = torch.empty(dev.ising_batch_workspace_bytes(reps), dtype=torch.uint8, device="cuda")
+    out = []
+    for _ in range(3):
+        mo, tr, _ = dev.batch_run(reps, 4, 4, start=1, workspace=ws)
+        torch.cuda.synchronize()
+        out.append((mo.clone(), tr.clone()))
+    for mo, tr in out[1:]:
+        assert torch.equal(mo, out[0][0]) and torch.equal(tr, out[0][1])
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_batch_lowprec_matches_oracle(dev, oracle_lib, fmt):
+    reps = [(32, BETA_C, 11), (128, 0.45, 12)]
+    _, trace, ws = dev.batch_run(reps, 1, 4, fmt=fmt)
+    for j, (L, beta, seed) in enumerate(reps):
+        host = oracle_lib.init(L, seed)
+        oracle_lib.sweep_fmt(host, beta, fmt, 1, seed, 0)
+        ref = oracle_lib.sweep_fmt(host, beta, fmt, 4, seed, 1, trace=True)
+        assert np.array_equal(_replica(dev, ws, 2, j, L), host)
+        assert np.array_equal(trace[j].cpu().numpy(), ref)
