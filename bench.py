@@ -142,6 +142,11 @@ def main() -> int:
     ap.add_argument("--layout", choices=["int8", "packed"], default="int8")
     ap.add_argument("--compare-packed", type=int, default=1,
                     help="with the int8 layout, also time the 1-bit layout on the same workload")
+    ap.add_argument("--form", choices=["plain", "precision", "batch"], default="plain",
+                    help="plain: the timed sweep (default); precision: bfloat16/half vs exact chains on "
+                         "the --L lattice; batch: the 255-replica Binder-crossing run in one launch")
+    ap.add_argument("--meas", type=int, default=None, help="measurement sweeps of the precision/batch forms")
+    ap.add_argument("--therm", type=int, default=None, help="thermalisation sweeps of the precision/batch forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run this many plain device copies of an L^2-byte buffer (counter calibration)")
@@ -161,6 +166,17 @@ def main() -> int:
     L, beta, seed, K, W = args.L, args.beta, args.seed, args.steps, args.warmup
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+
+    if args.form != "plain":
+        from paper_1903_11714_amd import studies
+        if args.form == "precision":
+            res = studies.precision_study(L=L, n_therm=args.therm if args.therm is not None else 1000,
+                                          n_meas=args.meas if args.meas is not None else 10000, seed=seed)
+        else:
+            res = studies.batch_study(n_therm=args.therm if args.therm is not None else 2000,
+                                      n_meas=args.meas if args.meas is not None else 20000)
+        print(json.dumps({"form": args.form, **res}), flush=True)
+        return 0
 
     main = run_layout(ising, torch, args.layout, L, beta, seed, K, W, args.kernel_sweeps, stream)
     lat_bytes = L * L if args.layout == "int8" else L * L // 8

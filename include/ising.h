@@ -88,6 +88,9 @@ int ising_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* str
 int ising_pack(const int8_t* spins, int64_t L, uint32_t* planes, void* stream);
 int ising_unpack(const uint32_t* planes, int64_t L, int8_t* spins, void* stream);
 
+/* Cold start in the packed layout: every spin `value` (+1 or -1). */
+int ising_fill_packed(uint32_t* planes, int64_t L, int value, void* stream);
+
 /* Hot start written directly in the packed layout (equals ising_pack of ising_init). */
 int ising_init_packed(uint32_t* planes, int64_t L, uint64_t seed, void* stream);
 
@@ -126,7 +129,9 @@ int64_t ising_batch_workspace_bytes(const ising_replica_t* replicas, int64_t n);
 /* n_therm + n_meas sweeps of every replica (sweep indices sweep_offset ..), all in one launch.
  *   fmt        acceptance format as for ising_sweep_fmt (0 exact, 1 bfloat16, 2 half).
  *   start      0 = hot start from each seed, 1 = cold start (all +1), 2 = continue from the
- *              lattices left in `workspace` by a previous call with the same replicas.
+ *              lattices left in `workspace` by a previous call with the same replicas,
+ *              3 = cold start where beta > beta_c = ln(1 + sqrt 2) / 2 (ordered phase, where a
+ *              hot start would only coarsen slowly), hot start elsewhere.
  *   workspace  device buffer of ising_batch_workspace_bytes bytes (caller-owned, 16-byte aligned);
  *              holds the lattices between calls.
  *   trace_ME   device int64[n * n_meas * 2] (replica-major (M, E) after every measurement sweep)

@@ -11,6 +11,7 @@ from .ising import (  # noqa: F401
     ising_batch_unpack,
     ising_batch_workspace_bytes,
     ising_fill,
+    ising_fill_packed,
     ising_get_option,
     ising_set_option,
     ising_half_sweep,

@@ -655,7 +655,7 @@ struct BatchReplica {
     uint32_t W;          // words per row per colour: L / 64, or 1 for L = 32 (16 sites per word)
     uint32_t key0, key1;
     uint32_t t0;         // sweep index of the first sweep of this run
-    uint32_t pad;
+    uint32_t ordered;    // 1 when beta > beta_c (start mode 3 begins from the ordered state)
     Thresholds th;
     uint32_t pad2;
     uint64_t state_off;  // word offset of this replica's planes in the state buffer
@@ -740,7 +740,8 @@ __device__ __forceinline__ void store_moments(double* mo, uint32_t n, double s_a
     mo[4] = s_e2 * k;
 }
 
-// start: 0 = hot start from the seed, 1 = cold start (all +1), 2 = continue from `state`.
+// start: 0 = hot start from the seed, 1 = cold start (all +1), 2 = continue from `state`,
+// 3 = cold start for replicas with beta above the critical value, hot start otherwise.
 __global__ __launch_bounds__(1024) void k_batch(const BatchReplica* table, uint32_t* state, uint32_t start,
                                                 uint32_t n_therm, uint32_t n_meas, int64_t* trace,
                                                 double* moments) {
@@ -749,10 +750,11 @@ __global__ __launch_bounds__(1024) void k_batch(const BatchReplica* table, uint3
     const BatchReplica rp = table[blockIdx.x];
     const uint32_t words = rp.L * rp.W;
     uint32_t* gstate = state + rp.state_off;
+    const uint32_t mode = start == 3 ? (rp.ordered ? 1u : 0u) : start;
     for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) {
         uint32_t w0 = 0u, w1 = 0u;
-        if (start == 0) hot_start_words(rp.L, w / rp.W, w % rp.W, rp.key0, rp.key1, w0, w1);
-        else if (start == 2) { w0 = gstate[w]; w1 = gstate[words + w]; }
+        if (mode == 0) hot_start_words(rp.L, w / rp.W, w % rp.W, rp.key0, rp.key1, w0, w1);
+        else if (mode == 2) { w0 = gstate[w]; w1 = gstate[words + w]; }
         planes[w] = w0;
         planes[words + w] = w1;
     }
@@ -1198,6 +1200,17 @@ int ising_unpack(const uint32_t* planes, int64_t L, int8_t* spins, void* stream)
     return check_launch("k_unpack");
 }
 
+int ising_fill_packed(uint32_t* planes, int64_t L, int value, void* stream) {
+    if (!planes || !valid_L(L) || !aligned16(planes) || (value != 1 && value != -1)) return ISING_EINVAL;
+    // both planes together are L^2 / 8 bytes = L^2 / 128 16-byte chunks; a set bit is spin -1
+    const uint64_t n16 = (uint64_t)L * (uint64_t)L / 128u;
+    uint64_t blocks = (n16 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(ising::k_fill_int8, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       reinterpret_cast<int8_t*>(planes), n16, value == 1 ? 0u : 0xFFFFFFFFu);
+    return check_launch("k_fill_int8");
+}
+
 int ising_init_packed(uint32_t* planes, int64_t L, uint64_t seed, void* stream) {
     if (!planes || !valid_L(L) || !aligned16(planes)) return ISING_EINVAL;
     const uint32_t groups = (uint32_t)(L / 64), n = groups * (uint32_t)L;
@@ -1303,7 +1316,7 @@ int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm,
                     void* stream) {
     const int64_t need = ising_batch_workspace_bytes(replicas, n);
     if (need < 0 || !workspace || workspace_bytes < need || !aligned16(workspace) || n_therm < 0 || n_meas < 0 ||
-        fmt < 0 || fmt > 2 || start < 0 || start > 2 || (uint64_t)(n_therm + n_meas) > (uint64_t(1) << 32) ||
+        fmt < 0 || fmt > 2 || start < 0 || start > 3 || (uint64_t)(n_therm + n_meas) > (uint64_t(1) << 32) ||
         sweep_offset > (uint64_t(1) << 32) - (uint64_t)(n_therm + n_meas))
         return ISING_EINVAL;
     for (int64_t i = 0; i < n; ++i)
@@ -1319,6 +1332,7 @@ int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm,
         b.key0 = (uint32_t)replicas[i].seed;
         b.key1 = (uint32_t)(replicas[i].seed >> 32);
         b.t0 = (uint32_t)sweep_offset;
+        b.ordered = replicas[i].beta > 0.44068679350977147 ? 1u : 0u;  // ln(1 + sqrt 2) / 2
         b.th = make_thresholds(replicas[i].beta, fmt);
         b.state_off = off;
         off += batch_words(replicas[i].L);

@@ -49,6 +49,7 @@ _SIGNATURES = {
     "ising_observables_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
                                  ctypes.c_int),
     "ising_init_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p], ctypes.c_int),
+    "ising_fill_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "ising_half_sweep_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
                                  ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "ising_thresholds": ([ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -172,6 +173,11 @@ def ising_init_packed(planes, L: int, seed: int, stream=None) -> None:
         _dev_ptr(planes, "torch.int32", L * L // 32), L, seed, _stream(stream)))
 
 
+def ising_fill_packed(planes, L: int, value: int, stream=None) -> None:
+    _check("ising_fill_packed", library().ising_fill_packed(
+        _dev_ptr(planes, "torch.int32", L * L // 32), L, value, _stream(stream)))
+
+
 def ising_half_sweep_packed(planes, L: int, beta: float, seed: int, t: int, q: int, stream=None) -> None:
     _check("ising_half_sweep_packed", library().ising_half_sweep_packed(
         _dev_ptr(planes, "torch.int32", L * L // 32), L, float(beta), seed, t, q, _stream(stream)))
@@ -277,11 +283,15 @@ def new_lattice(L: int, seed: int | None = None, device: str = "cuda"):
     return spins
 
 
-def new_packed(L: int, seed: int, device: str = "cuda"):
-    """Allocate the packed form of an L x L lattice (int32 words) with the hot start of `seed`."""
+def new_packed(L: int, seed: int | None, device: str = "cuda"):
+    """Allocate the packed form of an L x L lattice (int32 words): hot start of `seed`, or all +1
+    when seed is None."""
     import torch
     planes = torch.empty(L * L // 32, dtype=torch.int32, device=device)
-    ising_init_packed(planes, L, seed)
+    if seed is None:
+        ising_fill_packed(planes, L, 1)
+    else:
+        ising_init_packed(planes, L, seed)
     return planes
 
 

@@ -117,3 +117,14 @@ def test_batch_lowprec_matches_oracle(dev, oracle_lib, fmt):
         ref = oracle_lib.sweep_fmt(host, beta, fmt, 4, seed, 1, trace=True)
         assert np.array_equal(_replica(dev, ws, 2, j, L), host)
         assert np.array_equal(trace[j].cpu().numpy(), ref)
+
+
+def test_batch_ordered_start_below_tc(dev, oracle_lib):
+    # start 3: beta > beta_c begins from all +1, the others from their hot start
+    reps = [(64, 0.5, 21), (64, 0.4, 22)]
+    _, trace, ws = dev.batch_run(reps, 0, 3, start=3)
+    for j, (L, beta, seed) in enumerate(reps):
+        host = np.ones((L, L), dtype=np.int8) if beta > BETA_C else oracle_lib.init(L, seed)
+        ref = oracle_lib.sweep(host, beta, 3, seed, 0, trace=True)
+        assert np.array_equal(_replica(dev, ws, 2, j, L), host)
+        assert np.array_equal(trace[j].cpu().numpy(), ref)
