@@ -71,6 +71,27 @@ int ising_sweep(int8_t* spins, int64_t L, double beta, int64_t n_sweeps, uint64_
 int ising_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sweeps, uint64_t seed,
                     uint64_t sweep_offset, int64_t* trace_ME, void* stream);
 
+/* ising_sweep_fmt with both colours of a sweep in ONE pass over the lattice (Sec. 3.1: given one
+ * colour, the other colour's sites are independent, so the black sites of a row can be updated as
+ * soon as the white sites of the rows around it are).  Each pass reads one L x L buffer and writes
+ * the other:
+ *   scratch   device int8[L * L], 16-byte aligned, disjoint from spins; its contents on return
+ *             are unspecified.  The caller owns it.
+ * On return `spins` holds the lattice after n_sweeps sweeps, bit-identical to ising_sweep_fmt
+ * with the same arguments, and so is trace_ME.  Sweeps go spins -> scratch -> spins in pairs;
+ * an odd count runs its first sweep in place.  Above L = 65536 every sweep runs in place as in
+ * ising_sweep_fmt (scratch unused).  Returns ISING_EINVAL for the checks of ising_sweep_fmt,
+ * for a null, misaligned or overlapping scratch. */
+int ising_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, int fmt, int64_t n_sweeps,
+                      uint64_t seed, uint64_t sweep_offset, int64_t* trace_ME, void* stream);
+
+/* One sweep with sweep index t (< 2^32) out of place: dst = the sweep of src (both device
+ * int8[L * L], 16-byte aligned, disjoint; src is not modified).  out_ME: NULL or device int64[2]
+ * receiving (M, E) of dst.  For a caller that manages its own pair of buffers (a captured graph
+ * of alternating steps, say).  Above L = 65536: a device copy, then the two half-sweeps on dst. */
+int ising_sweep_fused_step(const int8_t* src, int8_t* dst, int64_t L, double beta, int fmt, uint64_t seed,
+                           uint64_t t, int64_t* out_ME, void* stream);
+
 /* One colour update (half of a sweep) for colour q in {0, 1} with sweep index t.
  * Same arguments as ising_sweep otherwise; t < 2^32. */
 int ising_half_sweep(int8_t* spins, int64_t L, double beta, uint64_t seed, uint64_t t, int q,
@@ -173,7 +194,9 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
  *   "nt_store"       1 = non-temporal stores of updated rows, 0 = ordinary stores (default).
  *   "staged"         1 = coalesced row loads and stores regrouped through LDS when L is a
  *                    multiple of 4096 (default), 0 = every lane reads its own 64 bytes.
- *   "batch_threads"  workgroup size of ising_batch_run: 0 = autotune (default), 256, 512, 1024. */
+ *   "batch_threads"  workgroup size of ising_batch_run: 0 = autotune (default), 256, 512, 1024.
+ *   "fused_rows"     rows per workgroup strip of ising_sweep_fused: 0 = automatic, else a power
+ *                    of two in [2, 256] (ignored for lattices it does not divide). */
 int ising_set_option(const char* name, int64_t value);
 int ising_get_option(const char* name, int64_t* value);
 

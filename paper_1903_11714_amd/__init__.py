@@ -19,6 +19,8 @@ from .ising import (  # noqa: F401
     ising_init_packed,
     ising_moments,
     ising_sweep_fmt,
+    ising_sweep_fused,
+    ising_sweep_fused_step,
     ising_sweep_packed_fmt,
     ising_thresholds_fmt,
     ising_init,

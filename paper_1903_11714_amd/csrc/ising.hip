@@ -21,6 +21,7 @@
 //   * flips go back into the bytes with a sign-extending byte permute and one xor.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -294,7 +295,7 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // sites_per_lane: sites each active lane covered; bonds: 2 per site.
 __device__ __forceinline__ void block_accumulate(int64_t* out, uint32_t anti, uint32_t neg, uint32_t active,
                                                  uint32_t sites_per_lane) {
-    __shared__ uint32_t red[3][8];
+    __shared__ uint32_t red[3][16];
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     anti = wave_sum(anti);
     neg = wave_sum(neg);
@@ -424,6 +425,178 @@ __global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
     if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, active ? 1u : 0u, 64u * a.rows);
 }
 
+// ---- Fused sweep: both colours of one sweep in one pass over the lattice, out of place.
+//
+// A workgroup owns a strip of R rows across the full width of the lattice (thread g = column
+// group g) and streams down it.  At step x it updates the white sites of row x and then the black
+// sites of row x - 1, whose four neighbours (the white sites of rows x - 2, x - 1 and x) are final
+// by then.  A white update reads only values the sweep has not changed yet, so the strip also
+// recomputes the white sites of the rows just outside it (r0 - 1 and r0 + R) rather than waiting
+// for the neighbouring strips: it reads rows r0 - 2 .. r0 + R + 1 of `src` and writes rows
+// r0 .. r0 + R - 1 of `dst`.  Every decision takes the same uniform as in the half-sweep kernels,
+// so one fused sweep equals a white and then a black half-sweep, bit for bit (Sec. 3.1: sites of
+// one colour are independent given the other colour).
+//
+// Rows are held as two bit words per thread (even and odd columns, site order), so the window of
+// four rows costs eight registers.  The neighbour across a group edge comes from the adjacent
+// thread through LDS: after step x every thread publishes the edge bits of row x (white sites
+// updated) and of row x + 1 (unchanged), and one workgroup barrier per step orders the exchange.
+// The barrier fences LDS only, so prefetched row loads and row stores stay in flight across it.
+struct FusedArgs {
+    const int8_t* src;
+    int8_t* dst;
+    uint32_t L, groups, rows;  // rows = R, even, divides L; one workgroup per strip of R rows
+    uint32_t t, key0, key1;
+    Thresholds th;
+    int64_t* obs;        // OBS: (M, E) accumulator, zeroed beforehand
+    uint32_t xcd_remap;  // renumber blocks per XCD (see logical_block)
+    uint32_t nt_store;   // non-temporal stores of the output rows
+};
+
+struct RowBits {
+    uint32_t e, o;  // sign bits of the even / odd columns of one group of one row, site order
+};
+
+__device__ __forceinline__ RowBits row_bits(const Row& row) { return RowBits{site_bits<0>(row), site_bits<1>(row)}; }
+
+// inverse of row_bits: +1 -> 0x01, -1 -> 0xFF
+__device__ __forceinline__ void bits_to_row(Row& row, const RowBits& b) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t sh = 15 - k - 8 * h;
+            row.d[2 * k + h] = perm(b.o << sh, b.e << sh, 0x0B090A08u) | 0x01010101u;
+        }
+    }
+}
+
+// Edge bits a thread publishes after step x: bit 0 / 1 = site 0 of the even columns / site 31 of
+// the odd columns of row x + 1, bit 2 / 3 = the same sites of row x.
+__device__ __forceinline__ uint32_t edge_word(const RowBits& next, const RowBits& cur) {
+    return (next.e & 1u) | ((next.o >> 31) << 1) | ((cur.e & 1u) << 2) | ((cur.o >> 31) << 3);
+}
+
+__device__ __forceinline__ void workgroup_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One step at row x: the white sites of row x (w0), then, with B, the black sites of row x - 1 (w1).
+// O = column parity of row x's white sites, which is also that of row x - 1's black sites.
+// w2 = row x - 2, wn = row x + 1; nb = the edge word of the right neighbour group (O = 1) or of the
+// left one (O = 0), published after step x - 1.
+template <int O, bool B, bool OBS>
+__device__ __forceinline__ void fused_step(const RowBits& w2, RowBits& w1, RowBits& w0, const RowBits& wn, uint32_t nb,
+                                           const Thresholds& th, uint32_t g, uint32_t x, uint32_t xm1, uint32_t t,
+                                           uint32_t key0, uint32_t key1, Counts& cnt) {
+    {
+        const uint32_t side = O ? w0.e : w0.o;
+        const uint32_t hs = O ? shift_next(side, nb & 1u) : shift_prev(side, (nb >> 1) & 1u);
+        const uint32_t F = decide<1, false>(O ? w0.o : w0.e, O ? w1.o : w1.e, O ? wn.o : wn.e, side, hs, 0u, th, g,
+                                            x, t, key0, key1, cnt);
+        if (O) w0.o ^= F; else w0.e ^= F;
+    }
+    if (B) {
+        const uint32_t side = O ? w1.e : w1.o;
+        const uint32_t hs = O ? shift_next(side, (nb >> 2) & 1u) : shift_prev(side, (nb >> 3) & 1u);
+        const uint32_t F = decide<0, OBS>(O ? w1.o : w1.e, O ? w2.o : w2.e, O ? w0.o : w0.e, side, hs, side, th, g,
+                                          xm1, t, key0, key1, cnt);
+        if (O) w1.o ^= F; else w1.e ^= F;
+    }
+}
+
+// STAGED: groups % 64 == 0 and every wave moves its 64 groups' rows with coalesced loads and
+// stores through LDS; otherwise every thread reads and writes its own 64 bytes, and threads past
+// the last group shadow it without storing (they still take part in the barriers).
+template <bool OBS, bool STAGED>
+__global__ __launch_bounds__(1024) void k_sweep_fused(FusedArgs a) {
+    extern __shared__ uint4 fused_lds[];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t G = a.groups, L = a.L, R = a.rows;
+    uint4* const stage = fused_lds + (tid >> 6) * 256u;  // STAGED: 4 KiB per wave
+    uint32_t* const xch = reinterpret_cast<uint32_t*>(fused_lds + (STAGED ? (blockDim.x >> 6) * 256u : 0u));
+    const bool active = tid < G;
+    const uint32_t g = active ? tid : G - 1;
+    const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
+    const uint32_t lane = tid & 63u;
+    const uint32_t r0 = logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * R;
+    const size_t col = (size_t)(STAGED ? g - lane : g) * 64u;
+    // row r0 + k - 2 for k = 0 .. R + 3, wrapped onto the torus; prefetches past the strip's last
+    // input row are clamped to it (already in cache), so every load stays unconditional
+    auto vrow = [&](uint32_t k) {
+        const uint32_t v = r0 + L + (k < R + 3 ? k : R + 3) - 2;  // < 2L + 2
+        return v >= 2 * L ? v - 2 * L : v >= L ? v - L : v;
+    };
+    auto fetch = [&](Row& raw, uint32_t r) {
+        if (STAGED) load_row_coalesced(raw, a.src + (size_t)r * L + col, lane);
+        else load_row(raw, a.src + (size_t)r * L + col);
+    };
+    auto own = [&](const Row& raw) {
+        if (!STAGED) return row_bits(raw);
+        Row row;
+        regroup_to_owner(row, raw, stage, lane);
+        return row_bits(row);
+    };
+    auto put = [&](uint32_t r, const RowBits& b) {
+        Row row;
+        bits_to_row(row, b);
+        if (STAGED) store_row_coalesced(a.dst + (size_t)r * L + col, row, stage, lane, a.nt_store);
+        else if (active) store_row(a.dst + (size_t)r * L + col, row, a.nt_store);
+    };
+    Counts cnt{0u, 0u};
+    const uint32_t t = a.t, k0 = a.key0, k1 = a.key1;
+    // prologue: rows r0 - 2 .. r0 + 1 in bits, rows r0 + 2, r0 + 3 in flight
+    Row p0, p1, p2, p3, ra, rb;
+    fetch(p0, vrow(0));
+    fetch(p1, vrow(1));
+    fetch(p2, vrow(2));
+    fetch(p3, vrow(3));
+    fetch(ra, vrow(4));
+    fetch(rb, vrow(5));
+    RowBits w2{0u, 0u};
+    RowBits w1 = own(p0), w0 = own(p1), n0 = own(p2), n1 = own(p3);
+    xch[blockDim.x + tid] = edge_word(w0, w0);  // slot 1: row r0 - 1 (bits 2, 3 unused)
+    workgroup_lds_sync();
+    // step x = r0 - 1 (odd: white sites on even columns), white only
+    fused_step<0, false, false>(w2, w1, w0, n0, xch[blockDim.x + gl], a.th, g, vrow(1), 0u, t, k0, k1, cnt);
+    xch[tid] = edge_word(n0, w0);
+    workgroup_lds_sync();
+    w2 = w1; w1 = w0; w0 = n0;
+    // step x = r0, white only (row r0 - 1 belongs to the strip above)
+    fused_step<1, false, false>(w2, w1, w0, n1, xch[gr], a.th, g, vrow(2), 0u, t, k0, k1, cnt);
+    xch[blockDim.x + tid] = edge_word(n1, w0);
+    workgroup_lds_sync();
+    w2 = w1; w1 = w0; w0 = n1;
+    n0 = own(ra);
+    n1 = own(rb);
+    fetch(ra, vrow(6));
+    fetch(rb, vrow(7));
+    // Rows are regrouped at the end of the iteration after the one that requested them, behind
+    // that iteration's stores: the wait for a row's loads then leaves the stores in flight, and
+    // every path into the loop head has the same memory operations outstanding.
+#pragma unroll 1
+    for (uint32_t k = 2; k < R + 2; k += 2) {
+        // steps x = r0 + k - 1 and r0 + k (rows r0 + k, r0 + k + 1 in n0, n1)
+        fused_step<0, true, OBS>(w2, w1, w0, n0, xch[blockDim.x + gl], a.th, g, vrow(k + 1), vrow(k), t, k0, k1, cnt);
+        put(vrow(k), w1);
+        xch[tid] = edge_word(n0, w0);
+        workgroup_lds_sync();
+        w2 = w1; w1 = w0; w0 = n0;
+        fused_step<1, true, OBS>(w2, w1, w0, n1, xch[gr], a.th, g, vrow(k + 2), vrow(k + 1), t, k0, k1, cnt);
+        put(vrow(k + 1), w1);
+        xch[blockDim.x + tid] = edge_word(n1, w0);
+        workgroup_lds_sync();
+        w2 = w1; w1 = w0; w0 = n1;
+        n0 = own(ra);  // rows r0 + k + 2, r0 + k + 3 for the next iteration
+        n1 = own(rb);
+        fetch(ra, vrow(k + 6));
+        fetch(rb, vrow(k + 7));
+    }
+    if (OBS) block_accumulate(a.obs, active ? cnt.anti : 0u, active ? cnt.neg : 0u, active ? 1u : 0u, 64u * R);
+}
+
 // ---- observables of an int8 lattice: M = sum of spins, E = -sum over bonds (right, down).
 struct ObsArgs {
     const int8_t* spins;
@@ -462,6 +635,10 @@ __global__ __launch_bounds__(256) void k_observables_int8(ObsArgs a) {
     }
     // every site contributes 2 bonds; block_accumulate converts counts to (M, E)
     block_accumulate(a.out, anti, neg, active ? 1u : 0u, 64u * a.rows);
+}
+
+__global__ void k_zero_n(int64_t* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
 __global__ void k_zero2(int64_t* p) {
@@ -857,6 +1034,7 @@ struct Options {
     int64_t nt_store = 0;
     int64_t staged = 1;
     int64_t batch_threads = 0;  // 0 = autotune
+    int64_t fused_rows = 0;     // rows per strip of the fused sweep; 0 = choose from L
 };
 Options g_opt;
 
@@ -990,6 +1168,66 @@ int launch_half_sweep(int8_t* spins, int64_t L, const ising::Thresholds& th, uin
     }
 #undef ISING_LAUNCH_SWEEP
     return check_launch("k_sweep_int8");
+}
+
+// The fused sweep puts a whole row in one workgroup (one thread per 64-column group).
+constexpr int64_t kFusedMaxL = 64 * 1024;
+
+// rows per strip of the fused sweep: even, divides L.  Every strip re-reads 4 rows and recomputes
+// the white sites of 2, so taller is cheaper; keep at least ~4096 waves in the grid, and 8..64 rows.
+uint32_t fused_rows(int64_t L) {
+    if (g_opt.fused_rows > 0 && L % g_opt.fused_rows == 0 && g_opt.fused_rows <= L) return (uint32_t)g_opt.fused_rows;
+    const uint64_t waves = (uint64_t)(L / 64 + 63) / 64;
+    uint32_t R = 64;
+    while (R > 8 && (uint64_t)(L / R) * waves < 4096ull) R >>= 1;
+    return R;
+}
+
+// one fused sweep src -> dst (L <= kFusedMaxL, src and dst disjoint); obs: (M, E), zeroed beforehand
+int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::Thresholds& th, uint64_t seed,
+                       uint32_t t, int64_t* obs, hipStream_t stream) {
+    ising::FusedArgs a;
+    a.src = src;
+    a.dst = dst;
+    a.L = (uint32_t)L;
+    a.groups = (uint32_t)(L / 64);
+    a.rows = fused_rows(L);
+    a.t = t;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.th = th;
+    a.obs = obs;
+    a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
+    a.nt_store = g_opt.nt_store ? 1u : 0u;
+    const uint32_t threads = (a.groups + 63u) / 64u * 64u;
+    const bool staged = g_opt.staged && a.groups % 64u == 0;
+    const size_t lds = (staged ? (size_t)(threads / 64u) * 4096u : 0u) + 2u * threads * sizeof(uint32_t);
+    const dim3 grid(a.L / a.rows), block(threads);
+#define ISING_LAUNCH_FUSED(OO, SS)                                                                       \
+    do {                                                                                                 \
+        if (lds > 65536) {                                                                               \
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ising::k_sweep_fused<OO, SS>), \
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+            if (e != hipSuccess) return hip_failed(e, "hipFuncSetAttribute(k_sweep_fused)");            \
+        }                                                                                                \
+        hipLaunchKernelGGL((ising::k_sweep_fused<OO, SS>), grid, block, lds, stream, a);                \
+    } while (0)
+    if (staged) { if (obs) ISING_LAUNCH_FUSED(true, true); else ISING_LAUNCH_FUSED(false, true); }
+    else { if (obs) ISING_LAUNCH_FUSED(true, false); else ISING_LAUNCH_FUSED(false, false); }
+#undef ISING_LAUNCH_FUSED
+    return check_launch("k_sweep_fused");
+}
+
+bool disjoint(const void* a, const void* b, uint64_t bytes) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x + bytes <= y || y + bytes <= x;
+}
+
+int zero_trace(int64_t* p, int64_t n, hipStream_t stream) {
+    if (n <= 0) return ISING_OK;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(ising::k_zero_n, dim3((unsigned)blocks), dim3(256), 0, stream, p, n);
+    return check_launch("k_zero_n");
 }
 
 }  // namespace
@@ -1167,6 +1405,53 @@ int ising_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sw
     return ISING_OK;
 }
 
+int ising_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, int fmt, int64_t n_sweeps,
+                      uint64_t seed, uint64_t sweep_offset, int64_t* trace_ME, void* stream) {
+    if (!spins || !scratch || !valid_L(L) || !aligned16(spins) || !aligned16(scratch) || !valid_beta(beta) ||
+        n_sweeps < 0 || fmt < 0 || fmt > 2 || sweep_offset > (uint64_t(1) << 32) ||
+        (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset || !disjoint(spins, scratch, (uint64_t)L * (uint64_t)L))
+        return ISING_EINVAL;
+    if (L > kFusedMaxL) return ising_sweep_fmt(spins, L, beta, fmt, n_sweeps, seed, sweep_offset, trace_ME, stream);
+    const ising::Thresholds th = make_thresholds(beta, fmt);
+    hipStream_t s = (hipStream_t)stream;
+    int64_t i = 0;
+    if (n_sweeps & 1) {  // an odd count: the first sweep in place, so that the pairs end in `spins`
+        const int rc = ising_sweep_fmt(spins, L, beta, fmt, 1, seed, sweep_offset, trace_ME, stream);
+        if (rc) return rc;
+        i = 1;
+    }
+    if (trace_ME) {
+        const int rc = zero_trace(trace_ME + 2 * i, 2 * (n_sweeps - i), s);
+        if (rc) return rc;
+    }
+    for (; i < n_sweeps; i += 2) {
+        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
+        int rc = launch_fused_sweep(spins, scratch, L, th, seed, t, trace_ME ? trace_ME + 2 * i : nullptr, s);
+        if (rc) return rc;
+        rc = launch_fused_sweep(scratch, spins, L, th, seed, t + 1, trace_ME ? trace_ME + 2 * i + 2 : nullptr, s);
+        if (rc) return rc;
+    }
+    return ISING_OK;
+}
+
+int ising_sweep_fused_step(const int8_t* src, int8_t* dst, int64_t L, double beta, int fmt, uint64_t seed,
+                           uint64_t t, int64_t* out_ME, void* stream) {
+    if (!src || !dst || !valid_L(L) || !aligned16(src) || !aligned16(dst) || !valid_beta(beta) || fmt < 0 ||
+        fmt > 2 || t >= (uint64_t(1) << 32) || !disjoint(src, dst, (uint64_t)L * (uint64_t)L))
+        return ISING_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (L > kFusedMaxL) {  // a copy, then the two half-sweeps in place on the copy
+        const hipError_t e = hipMemcpyAsync(dst, src, (size_t)L * (size_t)L, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_failed(e, "hipMemcpyAsync");
+        return ising_sweep_fmt(dst, L, beta, fmt, 1, seed, t, out_ME, stream);
+    }
+    if (out_ME) {
+        const int rc = zero_trace(out_ME, 2, s);
+        if (rc) return rc;
+    }
+    return launch_fused_sweep(src, dst, L, make_thresholds(beta, fmt), seed, (uint32_t)t, out_ME, s);
+}
+
 int ising_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* stream) {
     if (!spins || !out_ME || !valid_L(L) || !aligned16(spins)) return ISING_EINVAL;
     hipStream_t s = (hipStream_t)stream;
@@ -1283,6 +1568,9 @@ int ising_set_option(const char* name, int64_t value) {
     } else if (n == "staged") {
         if (value != 0 && value != 1) return ISING_EINVAL;
         g_opt.staged = value;
+    } else if (n == "fused_rows") {
+        if (value != 0 && (value < 2 || value > 256 || (value & (value - 1)) != 0)) return ISING_EINVAL;
+        g_opt.fused_rows = value;
     } else {
         return ISING_EINVAL;
     }
@@ -1297,6 +1585,7 @@ int ising_get_option(const char* name, int64_t* value) {
     else if (n == "nt_store") *value = g_opt.nt_store;
     else if (n == "staged") *value = g_opt.staged;
     else if (n == "batch_threads") *value = g_opt.batch_threads;
+    else if (n == "fused_rows") *value = g_opt.fused_rows;
     else return ISING_EINVAL;
     return ISING_OK;
 }

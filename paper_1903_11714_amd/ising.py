@@ -58,6 +58,11 @@ _SIGNATURES = {
                          ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "ising_sweep_packed_fmt": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_int64,
                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising_sweep_fused": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
+                           ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p],
+                          ctypes.c_int),
+    "ising_sweep_fused_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
+                                ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "ising_moments": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
                       ctypes.c_int),
     "ising_batch_workspace_bytes": ([ctypes.POINTER(ReplicaT), ctypes.c_int64], ctypes.c_int64),
@@ -212,6 +217,20 @@ def ising_sweep_fmt(spins, L: int, beta: float, fmt, n_sweeps: int, seed: int, s
     _check("ising_sweep_fmt", library().ising_sweep_fmt(
         _dev_ptr(spins, "torch.int8", L * L), L, float(beta), _fmt(fmt), n_sweeps, seed, sweep_offset,
         _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
+
+
+def ising_sweep_fused(spins, scratch, L: int, beta: float, fmt, n_sweeps: int, seed: int, sweep_offset: int = 0,
+                      trace_ME=None, stream=None) -> None:
+    _check("ising_sweep_fused", library().ising_sweep_fused(
+        _dev_ptr(spins, "torch.int8", L * L), _dev_ptr(scratch, "torch.int8", L * L), L, float(beta), _fmt(fmt),
+        n_sweeps, seed, sweep_offset, _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
+
+
+def ising_sweep_fused_step(src, dst, L: int, beta: float, fmt, seed: int, t: int, out_ME=None,
+                           stream=None) -> None:
+    _check("ising_sweep_fused_step", library().ising_sweep_fused_step(
+        _dev_ptr(src, "torch.int8", L * L), _dev_ptr(dst, "torch.int8", L * L), L, float(beta), _fmt(fmt), seed, t,
+        _opt_ptr(out_ME, "torch.int64", 2), _stream(stream)))
 
 
 def ising_sweep_packed_fmt(planes, L: int, beta: float, fmt, n_sweeps: int, seed: int, sweep_offset: int = 0,

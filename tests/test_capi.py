@@ -79,18 +79,34 @@ def test_argument_checks_before_any_launch(lib):
     assert lib.ising_unpack(null, 64, fake, null) == EINVAL
     assert lib.ising_sweep_packed(null, 64, 0.4, 1, 1, 0, null, null) == EINVAL
     assert lib.ising_observables_packed(fake, 32, fake, null) == EINVAL
+    # fused sweep: the scratch buffer must be present, aligned and disjoint from the lattice
+    other = ctypes.c_void_p(4096 + 64 * 64)
+    assert lib.ising_sweep_fused(fake, null, 64, 0.4, 0, 2, 1, 0, null, null) == EINVAL
+    assert lib.ising_sweep_fused(fake, fake, 64, 0.4, 0, 2, 1, 0, null, null) == EINVAL
+    assert lib.ising_sweep_fused(fake, ctypes.c_void_p(4096 + 64 * 64 - 16), 64, 0.4, 0, 2, 1, 0, null,
+                                 null) == EINVAL                                       # overlaps by 16 B
+    assert lib.ising_sweep_fused(fake, ctypes.c_void_p(4096 + 64 * 64 + 8), 64, 0.4, 0, 2, 1, 0, null,
+                                 null) == EINVAL                                       # misaligned
+    assert lib.ising_sweep_fused(fake, other, 64, 0.4, 3, 2, 1, 0, null, null) == EINVAL  # fmt
+    assert lib.ising_sweep_fused(fake, other, 64, 0.4, 0, 2, 1, 2**32 - 1, null, null) == EINVAL
+    assert lib.ising_sweep_fused_step(fake, fake, 64, 0.4, 0, 1, 0, null, null) == EINVAL
+    assert lib.ising_sweep_fused_step(fake, other, 64, 0.4, 0, 1, 2**32, null, null) == EINVAL
+    assert lib.ising_sweep_fused_step(fake, other, 96, 0.4, 0, 1, 0, null, null) == EINVAL
 
 
 def test_zero_sweeps_is_a_no_op(lib):
     # n_sweeps = 0 enqueues nothing, so it succeeds without touching the device.
     fake = ctypes.c_void_p(4096)
     assert lib.ising_sweep(fake, 64, 0.4, 0, 1, 0, ctypes.c_void_p(0), ctypes.c_void_p(0)) == 0
+    assert lib.ising_sweep_fused(fake, ctypes.c_void_p(4096 + 64 * 64), 64, 0.4, 0, 0, 1, 0, ctypes.c_void_p(0),
+                                 ctypes.c_void_p(0)) == 0
 
 
 def test_options_round_trip(lib):
     from paper_1903_11714_amd import ising
     for name, good, bad in (("rows_per_lane", [0, 2, 64], [1, 3, 128, -2]), ("xcd_remap", [0, 1], [2]),
-                            ("staged", [0, 1], [-1]), ("nt_store", [0, 1], [5])):
+                            ("staged", [0, 1], [-1]), ("nt_store", [0, 1], [5]),
+                            ("fused_rows", [0, 2, 16, 256], [1, 6, 512, -4])):
         old = ising.ising_get_option(name)
         try:
             for v in good:

@@ -1,0 +1,171 @@
+"""GPU parity of the fused sweep (both colours in one pass, out of place) against the CPU oracle.
+
+The fused pass reads one buffer and writes the other; every decision uses the site's own uniform,
+so the lattice and the (M, E) trace must equal the oracle's two half-sweeps bit for bit.  Cases:
+one workgroup thread per 64-column group with threads past the last group idle (L = 64, 192,
+320), whole waves staged through LDS (L = 4096, 8192), the full 16384^2 benchmark lattice, the
+largest fused lattice (65536^2, 1024 threads per workgroup) and the in-place path above it.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from tests import inputs
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+BETA_C = 0.5 * math.log1p(math.sqrt(2.0))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_11714_amd import ising
+    ising.library()
+    return ising
+
+
+def _to_dev(a: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.mark.parametrize("fmt", ["exact", "bf16", "fp16"])
+@pytest.mark.parametrize("L,beta,n,seed,offset", [
+    (64, BETA_C, 1, 1, 0), (64, BETA_C, 6, 2, 5), (128, 0.3, 4, 3, 0), (192, 0.7, 5, 2**40 + 3, 11),
+    (320, 1 / 2.6, 2, 8, 1000), (256, 0.0, 3, 9, 0), (128, math.inf, 4, 10, 2**32 - 4)])
+def test_fused_sweeps_match_oracle(dev, oracle_lib, L, beta, n, seed, offset, fmt):
+    _say("fused", L, beta, n, seed, offset, fmt)
+    host = inputs.random_lattice(L, seed=L + n)
+    s, scratch = _to_dev(host), torch.empty((L, L), dtype=torch.int8, device="cuda")
+    trace = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising_sweep_fused(s, scratch, L, beta, fmt, n, seed, offset, trace)
+    if fmt == "exact":
+        ref = oracle_lib.sweep(host, beta, n, seed, offset, trace=True)
+    else:
+        ref = oracle_lib.sweep_fmt(host, beta, fmt, n, seed, offset, trace=True)
+    assert np.array_equal(s.cpu().numpy(), host)
+    assert np.array_equal(trace.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("L", [64, 192, 4096])
+def test_fused_step_is_one_sweep_out_of_place(dev, oracle_lib, L):
+    _say("fused step", L)
+    host = oracle_lib.init(L, 21)
+    src = _to_dev(host)
+    keep = src.clone()
+    dst = torch.empty_like(src)
+    me = torch.empty(2, dtype=torch.int64, device="cuda")
+    dev.ising_sweep_fused_step(src, dst, L, BETA_C, "exact", 21, 7, me)
+    oracle_lib.sweep(host, BETA_C, 1, 21, 7)
+    assert torch.equal(src, keep)
+    assert np.array_equal(dst.cpu().numpy(), host)
+    assert tuple(me.tolist()) == oracle_lib.observables(host)
+
+
+@pytest.mark.parametrize("L,n", [(4096, 2), (8192, 1)])
+def test_fused_staged_full_lattice_matches_oracle(dev, oracle_lib, L, n):
+    _say("fused staged", L, n)
+    s = torch.empty((L, L), dtype=torch.int8, device="cuda")
+    dev.ising_init(s, L, 6)
+    scratch = torch.empty_like(s)
+    trace = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", n, 6, 3, trace)
+    host = oracle_lib.init(L, 6)
+    ref = oracle_lib.sweep(host, BETA_C, n, 6, 3, trace=True)
+    assert np.array_equal(s.cpu().numpy(), host)
+    assert np.array_equal(trace.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("L", [192, 4096, 16384])
+def test_fused_equals_two_half_sweeps_for_every_strip_height(dev, L):
+    # Strip heights change which rows each workgroup recomputes; none may change a spin.
+    _say("fused strips", L)
+    base = torch.empty((L, L), dtype=torch.int8, device="cuda")
+    dev.ising_init(base, L, 17)
+    ref = base.clone()
+    ref_tr = torch.empty((4, 2), dtype=torch.int64, device="cuda")
+    dev.ising_sweep_fmt(ref, L, BETA_C, "exact", 4, 17, 40, ref_tr)
+    scratch = torch.empty_like(base)
+    try:
+        for rows in (0, 2, 4, 8, 16, 32, 64, 128, 256):
+            if rows and (L % rows or rows > L):
+                continue
+            for remap in (1, 0):
+                for staged in (1, 0):
+                    dev.ising_set_option("fused_rows", rows)
+                    dev.ising_set_option("xcd_remap", remap)
+                    dev.ising_set_option("staged", staged)
+                    s = base.clone()
+                    tr = torch.empty((4, 2), dtype=torch.int64, device="cuda")
+                    dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", 4, 17, 40, tr)
+                    assert torch.equal(s, ref), (rows, remap, staged)
+                    assert torch.equal(tr, ref_tr), (rows, remap, staged)
+    finally:
+        for k, v in (("fused_rows", 0), ("xcd_remap", 1), ("staged", 1)):
+            dev.ising_set_option(k, v)
+
+
+def test_fused_full_size_16384_crops_and_trace(dev, oracle_lib):
+    # The benchmark's lattice and launch configuration: L = 16384, hot start, beta_c.
+    L, n, seed = 16384, 64, 1
+    _say("fused full-size", L, n)
+    s = torch.empty((L, L), dtype=torch.int8, device="cuda")
+    dev.ising_init(s, L, seed)
+    scratch = torch.empty_like(s)
+    trace = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", n, seed, 0, trace)
+    torch.cuda.synchronize()
+    for (r0, c0, h, w) in [(0, 0, 16, 64), (L - 8, L - 40, 16, 80), (8191, 4097, 24, 24), (100, L - 1, 5, 3)]:
+        ref = oracle_lib.crop(L, seed, BETA_C, n, 0, r0, c0, h, w)
+        rows = [(r0 + a) % L for a in range(h)]
+        cols = [(c0 + b) % L for b in range(w)]
+        assert np.array_equal(s[rows][:, cols].cpu().numpy(), ref), (r0, c0)
+    out = torch.empty(2, dtype=torch.int64, device="cuda")
+    dev.ising_observables(s, L, out)
+    assert out.tolist() == trace[-1].tolist()
+    # the same run through the two-launch path: identical lattice and trace
+    s2 = torch.empty_like(s)
+    dev.ising_init(s2, L, seed)
+    tr2 = torch.empty_like(trace)
+    dev.ising_sweep(s2, L, BETA_C, n, seed, 0, tr2)
+    assert torch.equal(s, s2)
+    assert torch.equal(trace, tr2)
+
+
+def test_fused_largest_lattice_and_in_place_above_it(dev):
+    # L = 65536: 1024 threads per workgroup, 72 KiB of LDS.  L = 65600: above the fused limit,
+    # every sweep runs in place and the scratch buffer is not touched.
+    for L, n in ((65536, 2), (65600, 2)):
+        _say("fused large", L, n)
+        s = torch.empty((L, L), dtype=torch.int8, device="cuda")
+        dev.ising_init(s, L, 5)
+        ref = s.clone()
+        tr_ref = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+        dev.ising_sweep(ref, L, BETA_C, n, 5, 9, tr_ref)
+        scratch = torch.zeros_like(s)
+        tr = torch.empty_like(tr_ref)
+        dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", n, 5, 9, tr)
+        assert torch.equal(s, ref), L
+        assert torch.equal(tr, tr_ref), L
+        if L > 65536:
+            assert int(scratch.abs().sum()) == 0
+        del s, ref, scratch
+        torch.cuda.empty_cache()
+
+
+def test_fused_rejects_overlap(dev):
+    s = torch.empty((128, 128), dtype=torch.int8, device="cuda")
+    with pytest.raises(dev.IsingError):
+        dev.ising_sweep_fused(s, s, 128, BETA_C, "exact", 2, 1)
+    with pytest.raises(dev.IsingError):
+        dev.ising_sweep_fused_step(s, s, 128, BETA_C, "exact", 1, 0)
