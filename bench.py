@@ -7,10 +7,14 @@ start from seed 1, beta = beta_c = ln(1 + sqrt 2) / 2, exact-threshold acceptanc
 (M, E) trace recorded after every sweep.  One "step" is one sweep.  The lattice is resident in
 HBM before the timed region starts.
 
+Layouts: "fused" (default) sweeps the int8 lattice with both colours in one pass, alternating
+between the lattice and a second L^2-byte buffer; "int8" runs one launch per colour in place;
+"packed" is the 1-bit layout.  All three run the same chain (bit-identical spins).
+
 Prints one JSON line with the throughput (spin-flip attempts per ns), the roofline of the
-dominant kernel (the half-sweep kernel; algorithmic bytes = one read and one write of the
-L^2-byte lattice per launch, measured with HIP events on the launch stream) and the CPU
-oracle's throughput on a bounded sample of the same workload.
+dominant kernel (algorithmic bytes = one read and one write of the L^2-byte lattice per launch,
+measured with HIP events on the launch stream) and the CPU oracle's throughput on a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
@@ -55,6 +59,22 @@ def measured_traffic(layout: str, L: int):
     return entry.get("hbm_bytes_per_launch")
 
 
+FUSED_MAX_L = 65536  # one workgroup thread per 64-column group, at most 1024 threads
+
+KERNEL_NAME = {
+    "fused": "k_sweep_fused (both colours per launch)",
+    "int8": "k_sweep_int8 (one colour per launch)",
+    "packed": "k_sweep_packed (one colour per launch)",
+}
+
+
+def algorithmic_bytes(layout: str, L: int) -> float:
+    """Bytes one launch must move: fused reads the L^2-byte lattice and writes the other buffer;
+    int8 reads and writes the lattice for one colour; packed reads both colour planes (L^2 / 8
+    bytes) and writes one (L^2 / 16 bytes)."""
+    return 3.0 * L * L / 16.0 if layout == "packed" else 2.0 * L * L
+
+
 def cpu_baseline(L: int, beta: float, seed: int, sweeps: int):
     """The oracle on `sweeps` sweeps of the same lattice (at most 16384^2, so the sample stays
     around ten seconds of host time)."""
@@ -76,20 +96,30 @@ def cpu_baseline(L: int, beta: float, seed: int, sweeps: int):
 
 def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream):
     """Hot start, W warm-up sweeps, K timed sweeps with the (M, E) trace, then `kernel_sweeps`
-    sweeps with every half-sweep launch bracketed by events."""
+    sweeps with every launch bracketed by events (one launch per sweep for "fused", per colour
+    otherwise)."""
     dev = torch.device("cuda:0")
-    if layout == "int8":
-        lat = torch.empty((L, L), dtype=torch.int8, device=dev)
+    if layout in ("int8", "fused"):
+        # the fused sweep's two buffers come from one allocation (their relative placement in
+        # HBM is then the same on every run)
+        buf = torch.empty((2 if layout == "fused" else 1) * L * L, dtype=torch.int8, device=dev)
+        lat = buf[:L * L].view(L, L)
         ising.ising_init(lat, L, seed, stream)
-        sweep, half = ising.ising_sweep, ising.ising_half_sweep
+        if layout == "fused":
+            scratch = buf[L * L:].view(L, L)
+
+            def sweep(lat, L, beta, n, seed, off, trace, st):
+                ising.ising_sweep_fused(lat, scratch, L, beta, "exact", n, seed, off, trace, st)
+        else:
+            sweep = ising.ising_sweep
     else:
         lat = torch.empty(L * L // 32, dtype=torch.int32, device=dev)
         ising.ising_init_packed(lat, L, seed, stream)
-        sweep, half = ising.ising_sweep_packed, ising.ising_half_sweep_packed
+        sweep = ising.ising_sweep_packed
     warm_trace = torch.empty((max(W, 1), 2), dtype=torch.int64, device=dev)
     trace = torch.empty((max(K, 1), 2), dtype=torch.int64, device=dev)
     if W:
-        sweep(lat, L, beta, W, seed, 0, warm_trace, stream)
+        sweep(lat, L, beta, W, seed, 0, warm_trace[:W], stream)
     torch.cuda.synchronize()
     print(f"bench: {layout} L={L} warmup={W} done", file=sys.stderr, flush=True)
 
@@ -98,7 +128,7 @@ def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
-    sweep(lat, L, beta, K, seed, W, trace, stream)
+    sweep(lat, L, beta, K, seed, W, trace[:K], stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -107,18 +137,28 @@ def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream)
           flush=True)
     final_ME = trace[K - 1].tolist() if K else None
 
-    # dominant kernel: each half-sweep launch bracketed by events on the launch stream
-    nk = kernel_sweeps
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nk + 1)]
+    # dominant kernel: each launch bracketed by events on the launch stream
+    nk = kernel_sweeps + (kernel_sweeps & 1)
     t = W + K
-    evs[0].record(stream)
-    for i in range(nk):
-        half(lat, L, beta, seed, t + i, 1, stream)
-        evs[2 * i + 1].record(stream)
-        half(lat, L, beta, seed, t + i, 0, stream)
-        evs[2 * i + 2].record(stream)
+    if layout == "fused":
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(nk + 1)]
+        evs[0].record(stream)
+        src, dst = lat, scratch
+        for i in range(nk):
+            ising.ising_sweep_fused_step(src, dst, L, beta, "exact", seed, t + i, None, stream)
+            evs[i + 1].record(stream)
+            src, dst = dst, src
+    else:
+        half = ising.ising_half_sweep if layout == "int8" else ising.ising_half_sweep_packed
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nk + 1)]
+        evs[0].record(stream)
+        for i in range(nk):
+            half(lat, L, beta, seed, t + i, 1, stream)
+            evs[2 * i + 1].record(stream)
+            half(lat, L, beta, seed, t + i, 0, stream)
+            evs[2 * i + 2].record(stream)
     torch.cuda.synchronize()
-    durs = [evs[k].elapsed_time(evs[k + 1]) for k in range(2 * nk)]
+    durs = [evs[k].elapsed_time(evs[k + 1]) for k in range(len(evs) - 1)]
     del lat
     return {
         "value": float(L) * L * K / (wall * 1e9),
@@ -139,9 +179,11 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--kernel-sweeps", type=int, default=50, help="sweeps timed launch by launch")
     ap.add_argument("--cpu-sweeps", type=int, default=8, help="sweeps in the CPU-oracle sample")
-    ap.add_argument("--layout", choices=["int8", "packed"], default="int8")
-    ap.add_argument("--compare-packed", type=int, default=1,
-                    help="with the int8 layout, also time the 1-bit layout on the same workload")
+    ap.add_argument("--layout", choices=["fused", "int8", "packed"], default="fused",
+                    help="fused: int8, both colours per launch, two buffers (default); int8: one launch "
+                         "per colour, in place; packed: 1-bit spins, one launch per colour")
+    ap.add_argument("--compare", type=int, default=1,
+                    help="with the fused layout, also time the other two layouts on the same workload")
     ap.add_argument("--form", choices=["plain", "precision", "batch"], default="plain",
                     help="plain: the timed sweep (default); precision: bfloat16/half vs exact chains on "
                          "the --L lattice; batch: the 255-replica Binder-crossing run in one launch")
@@ -178,13 +220,20 @@ def main() -> int:
         print(json.dumps({"form": args.form, **res}), flush=True)
         return 0
 
+    if args.layout == "fused" and L > FUSED_MAX_L:
+        print(f"bench: L={L} is above the fused sweep's limit ({FUSED_MAX_L}); timing the int8 layout",
+              file=sys.stderr, flush=True)
+        args.layout = "int8"
     main = run_layout(ising, torch, args.layout, L, beta, seed, K, W, args.kernel_sweeps, stream)
-    lat_bytes = L * L if args.layout == "int8" else L * L // 8
-    # int8: each launch reads and writes the L^2-byte lattice.  packed: each launch reads both
-    # colour planes (L^2 / 8 bytes) and writes one (L^2 / 16 bytes).
-    alg_bytes = 2.0 * L * L if args.layout == "int8" else 3.0 * L * L / 16.0
+    lat_bytes = L * L // 8 if args.layout == "packed" else L * L
+    alg_bytes = algorithmic_bytes(args.layout, L)
     achieved = alg_bytes / (main["avg_launch_ms"] * 1e-3) / 1e9
     traffic = measured_traffic(args.layout, L)
+    layout_text = {
+        "fused": f"int8 layout, both colours per launch, lattice + scratch buffer ({2 * lat_bytes / 2**20:.0f} MiB)",
+        "int8": f"int8 layout, one launch per colour, in place ({lat_bytes / 2**20:.0f} MiB)",
+        "packed": f"1-bit layout, one launch per colour ({lat_bytes / 2**20:.0f} MiB)",
+    }[args.layout]
 
     result = {
         "metric": METRIC,
@@ -197,13 +246,12 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8" if args.layout == "int8" else "u32 (1-bit spins)",
+        "dtype": "u32 (1-bit spins)" if args.layout == "packed" else "int8",
         "data": "synthetic: Philox hot start from the seed (no dataset)",
         "config": {
             "workload": f"single periodic {L}x{L} lattice, beta={beta:.6g}"
                         f"{' (T_c)' if abs(beta - BETA_C) < 1e-12 else ''}, hot start seed {seed}, plain "
-                        f"exact-threshold checkerboard Metropolis, {args.layout} layout "
-                        f"({lat_bytes / 2**20:.0f} MiB), (M,E) traced every sweep",
+                        f"exact-threshold checkerboard Metropolis, {layout_text}, (M,E) traced every sweep",
             "L": L, "beta": beta, "layout": args.layout, "sweeps_timed": K,
         },
         "roofline": {
@@ -213,23 +261,23 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_sweep_int8 (one colour per launch)" if args.layout == "int8"
-                      else "k_sweep_packed (one colour per launch)",
+            "kernel": KERNEL_NAME[args.layout],
             "avg_launch_us": main["avg_launch_ms"] * 1e3,
             "alg_bytes_per_launch": alg_bytes,
         },
         "gpu_event_ms": main["gpu_ms"],
         "final_ME": main["final_ME"],
     }
-    if args.compare_packed and args.layout == "int8":
-        # the same workload on the 1-bit layout (same chain, bit-identical spins), for reference
+    if args.compare and args.layout == "fused":
+        # the same workload on the other layouts (same chain, bit-identical spins), for reference
         ks = max(K // 4, 1)
-        other = run_layout(ising, torch, "packed", L, beta, seed, ks, W, args.kernel_sweeps, stream)
-        result["packed_layout"] = {
-            "value": other["value"], "unit": "attempts/ns", "steps": ks,
-            "avg_launch_us": other["avg_launch_ms"] * 1e3,
-            "hbm_GBs": 3.0 * L * L / 16.0 / (other["avg_launch_ms"] * 1e-3) / 1e9,
-        }
+        for lay in ("int8", "packed"):
+            other = run_layout(ising, torch, lay, L, beta, seed, ks, W, args.kernel_sweeps, stream)
+            result[f"{lay}_layout"] = {
+                "value": other["value"], "unit": "attempts/ns", "steps": ks, "kernel": KERNEL_NAME[lay],
+                "avg_launch_us": other["avg_launch_ms"] * 1e3,
+                "hbm_GBs": algorithmic_bytes(lay, L) / (other["avg_launch_ms"] * 1e-3) / 1e9,
+            }
     if args.copy_calibration:
         # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the
         # per-launch HBM traffic read from the same counters for the sweep kernel.

@@ -196,7 +196,8 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
  *                    multiple of 4096 (default), 0 = every lane reads its own 64 bytes.
  *   "batch_threads"  workgroup size of ising_batch_run: 0 = autotune (default), 256, 512, 1024.
  *   "fused_rows"     rows per workgroup strip of ising_sweep_fused: 0 = automatic, else a power
- *                    of two in [2, 256] (ignored for lattices it does not divide). */
+ *                    of two in [2, 256] (ignored for lattices it does not divide).
+ *   "fused_alternate" 1 = odd strips of ising_sweep_fused walk upwards (default), 0 = all down. */
 int ising_set_option(const char* name, int64_t value);
 int ising_get_option(const char* name, int64_t* value);
 

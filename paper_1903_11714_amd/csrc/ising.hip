@@ -451,6 +451,7 @@ struct FusedArgs {
     int64_t* obs;        // OBS: (M, E) accumulator, zeroed beforehand
     uint32_t xcd_remap;  // renumber blocks per XCD (see logical_block)
     uint32_t nt_store;   // non-temporal stores of the output rows
+    uint32_t alternate;  // walk odd strips upwards
 };
 
 struct RowBits {
@@ -507,26 +508,31 @@ __device__ __forceinline__ void fused_step(const RowBits& w2, RowBits& w1, RowBi
     }
 }
 
+// One strip of the fused sweep.  UP: the strip is walked from its last row to its first (the
+// same updates in mirror order: white sites of row x, then black sites of row x + 1).  Strips
+// alternate direction so that two neighbouring strips read the rows around their common boundary
+// at the same time (both at the end, or both at the start), and the second read hits in L2.
 // STAGED: groups % 64 == 0 and every wave moves its 64 groups' rows with coalesced loads and
 // stores through LDS; otherwise every thread reads and writes its own 64 bytes, and threads past
 // the last group shadow it without storing (they still take part in the barriers).
-template <bool OBS, bool STAGED>
-__global__ __launch_bounds__(1024) void k_sweep_fused(FusedArgs a) {
-    extern __shared__ uint4 fused_lds[];
-    const uint32_t tid = threadIdx.x;
+template <bool OBS, bool STAGED, bool UP>
+__device__ __forceinline__ void fused_strip(const FusedArgs& a, uint32_t strip, uint4* fused_lds, Counts& cnt) {
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
     const uint32_t G = a.groups, L = a.L, R = a.rows;
     uint4* const stage = fused_lds + (tid >> 6) * 256u;  // STAGED: 4 KiB per wave
-    uint32_t* const xch = reinterpret_cast<uint32_t*>(fused_lds + (STAGED ? (blockDim.x >> 6) * 256u : 0u));
+    uint32_t* const xch = reinterpret_cast<uint32_t*>(fused_lds + (STAGED ? (nt >> 6) * 256u : 0u));
     const bool active = tid < G;
     const uint32_t g = active ? tid : G - 1;
     const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
     const uint32_t lane = tid & 63u;
-    const uint32_t r0 = logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * R;
+    const uint32_t r0 = strip * R;
     const size_t col = (size_t)(STAGED ? g - lane : g) * 64u;
-    // row r0 + k - 2 for k = 0 .. R + 3, wrapped onto the torus; prefetches past the strip's last
-    // input row are clamped to it (already in cache), so every load stays unconditional
+    // k-th row of the walk, k = 0 .. R + 3: r0 - 2 .. r0 + R + 1 (down) or r0 + R + 1 .. r0 - 2
+    // (up), wrapped onto the torus.  Prefetches past the walk's last row are clamped to it (already
+    // in cache), so every load stays unconditional.
     auto vrow = [&](uint32_t k) {
-        const uint32_t v = r0 + L + (k < R + 3 ? k : R + 3) - 2;  // < 2L + 2
+        const uint32_t kk = k < R + 3 ? k : R + 3;
+        const uint32_t v = UP ? r0 + R + 1 + L - kk : r0 + L + kk - 2;  // in [L - 2, 2L + 2)
         return v >= 2 * L ? v - 2 * L : v >= L ? v - L : v;
     };
     auto fetch = [&](Row& raw, uint32_t r) {
@@ -545,28 +551,33 @@ __global__ __launch_bounds__(1024) void k_sweep_fused(FusedArgs a) {
         if (STAGED) store_row_coalesced(a.dst + (size_t)r * L + col, row, stage, lane, a.nt_store);
         else if (active) store_row(a.dst + (size_t)r * L + col, row, a.nt_store);
     };
-    Counts cnt{0u, 0u};
+    // The white sites of walk row k + 1 lie on columns of parity OA for even k, OB for odd k
+    // (r0 and R are even).  A step with parity 1 takes the edge word of the right neighbour
+    // group, one with parity 0 that of the left one; step k reads slot (k + 1) & 1.
+    constexpr int OA = UP ? 1 : 0, OB = 1 - OA;
+    const uint32_t nbA = OA ? gr : gl, nbB = OB ? gr : gl;
     const uint32_t t = a.t, k0 = a.key0, k1 = a.key1;
-    // prologue: rows r0 - 2 .. r0 + 1 in bits, rows r0 + 2, r0 + 3 in flight
-    Row p0, p1, p2, p3, ra, rb;
-    fetch(p0, vrow(0));
-    fetch(p1, vrow(1));
-    fetch(p2, vrow(2));
-    fetch(p3, vrow(3));
+    // prologue: walk rows 0 .. 3 in bits, rows 4, 5 in flight
+    // (two row buffers throughout, which keeps the register count at four waves per SIMD)
+    Row ra, rb;
+    fetch(ra, vrow(0));
+    fetch(rb, vrow(1));
+    RowBits w2{0u, 0u};
+    RowBits w1 = own(ra), w0 = own(rb);
+    fetch(ra, vrow(2));
+    fetch(rb, vrow(3));
+    RowBits n0 = own(ra), n1 = own(rb);
     fetch(ra, vrow(4));
     fetch(rb, vrow(5));
-    RowBits w2{0u, 0u};
-    RowBits w1 = own(p0), w0 = own(p1), n0 = own(p2), n1 = own(p3);
-    xch[blockDim.x + tid] = edge_word(w0, w0);  // slot 1: row r0 - 1 (bits 2, 3 unused)
+    xch[nt + tid] = edge_word(w0, w0);  // slot 1: walk row 1 (bits 2, 3 unused)
     workgroup_lds_sync();
-    // step x = r0 - 1 (odd: white sites on even columns), white only
-    fused_step<0, false, false>(w2, w1, w0, n0, xch[blockDim.x + gl], a.th, g, vrow(1), 0u, t, k0, k1, cnt);
+    // walk rows 1 and 2: white sites only (walk row 1 belongs to the neighbouring strip)
+    fused_step<OA, false, false>(w2, w1, w0, n0, xch[nt + nbA], a.th, g, vrow(1), 0u, t, k0, k1, cnt);
     xch[tid] = edge_word(n0, w0);
     workgroup_lds_sync();
     w2 = w1; w1 = w0; w0 = n0;
-    // step x = r0, white only (row r0 - 1 belongs to the strip above)
-    fused_step<1, false, false>(w2, w1, w0, n1, xch[gr], a.th, g, vrow(2), 0u, t, k0, k1, cnt);
-    xch[blockDim.x + tid] = edge_word(n1, w0);
+    fused_step<OB, false, false>(w2, w1, w0, n1, xch[nbB], a.th, g, vrow(2), 0u, t, k0, k1, cnt);
+    xch[nt + tid] = edge_word(n1, w0);
     workgroup_lds_sync();
     w2 = w1; w1 = w0; w0 = n1;
     n0 = own(ra);
@@ -578,23 +589,33 @@ __global__ __launch_bounds__(1024) void k_sweep_fused(FusedArgs a) {
     // every path into the loop head has the same memory operations outstanding.
 #pragma unroll 1
     for (uint32_t k = 2; k < R + 2; k += 2) {
-        // steps x = r0 + k - 1 and r0 + k (rows r0 + k, r0 + k + 1 in n0, n1)
-        fused_step<0, true, OBS>(w2, w1, w0, n0, xch[blockDim.x + gl], a.th, g, vrow(k + 1), vrow(k), t, k0, k1, cnt);
+        // steps k, k + 1: white sites of walk rows k + 1, k + 2, black sites of walk rows k, k + 1
+        fused_step<OA, true, OBS>(w2, w1, w0, n0, xch[nt + nbA], a.th, g, vrow(k + 1), vrow(k), t, k0, k1, cnt);
         put(vrow(k), w1);
         xch[tid] = edge_word(n0, w0);
         workgroup_lds_sync();
         w2 = w1; w1 = w0; w0 = n0;
-        fused_step<1, true, OBS>(w2, w1, w0, n1, xch[gr], a.th, g, vrow(k + 2), vrow(k + 1), t, k0, k1, cnt);
+        fused_step<OB, true, OBS>(w2, w1, w0, n1, xch[nbB], a.th, g, vrow(k + 2), vrow(k + 1), t, k0, k1, cnt);
         put(vrow(k + 1), w1);
-        xch[blockDim.x + tid] = edge_word(n1, w0);
+        xch[nt + tid] = edge_word(n1, w0);
         workgroup_lds_sync();
         w2 = w1; w1 = w0; w0 = n1;
-        n0 = own(ra);  // rows r0 + k + 2, r0 + k + 3 for the next iteration
+        n0 = own(ra);  // walk rows k + 4, k + 5 for the next iteration
         n1 = own(rb);
         fetch(ra, vrow(k + 6));
         fetch(rb, vrow(k + 7));
     }
-    if (OBS) block_accumulate(a.obs, active ? cnt.anti : 0u, active ? cnt.neg : 0u, active ? 1u : 0u, 64u * R);
+}
+
+template <bool OBS, bool STAGED>
+__global__ __launch_bounds__(1024) void k_sweep_fused(FusedArgs a) {
+    extern __shared__ uint4 fused_lds[];
+    const uint32_t strip = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
+    Counts cnt{0u, 0u};
+    if (a.alternate && (strip & 1u)) fused_strip<OBS, STAGED, true>(a, strip, fused_lds, cnt);
+    else fused_strip<OBS, STAGED, false>(a, strip, fused_lds, cnt);
+    const bool active = threadIdx.x < a.groups;
+    if (OBS) block_accumulate(a.obs, active ? cnt.anti : 0u, active ? cnt.neg : 0u, active ? 1u : 0u, 64u * a.rows);
 }
 
 // ---- observables of an int8 lattice: M = sum of spins, E = -sum over bonds (right, down).
@@ -1035,6 +1056,7 @@ struct Options {
     int64_t staged = 1;
     int64_t batch_threads = 0;  // 0 = autotune
     int64_t fused_rows = 0;     // rows per strip of the fused sweep; 0 = choose from L
+    int64_t fused_alternate = 1;  // fused sweep: odd strips walk upwards
 };
 Options g_opt;
 
@@ -1199,6 +1221,7 @@ int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::T
     a.obs = obs;
     a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
     a.nt_store = g_opt.nt_store ? 1u : 0u;
+    a.alternate = g_opt.fused_alternate ? 1u : 0u;
     const uint32_t threads = (a.groups + 63u) / 64u * 64u;
     const bool staged = g_opt.staged && a.groups % 64u == 0;
     const size_t lds = (staged ? (size_t)(threads / 64u) * 4096u : 0u) + 2u * threads * sizeof(uint32_t);
@@ -1568,6 +1591,9 @@ int ising_set_option(const char* name, int64_t value) {
     } else if (n == "staged") {
         if (value != 0 && value != 1) return ISING_EINVAL;
         g_opt.staged = value;
+    } else if (n == "fused_alternate") {
+        if (value != 0 && value != 1) return ISING_EINVAL;
+        g_opt.fused_alternate = value;
     } else if (n == "fused_rows") {
         if (value != 0 && (value < 2 || value > 256 || (value & (value - 1)) != 0)) return ISING_EINVAL;
         g_opt.fused_rows = value;
@@ -1586,6 +1612,7 @@ int ising_get_option(const char* name, int64_t* value) {
     else if (n == "staged") *value = g_opt.staged;
     else if (n == "batch_threads") *value = g_opt.batch_threads;
     else if (n == "fused_rows") *value = g_opt.fused_rows;
+    else if (n == "fused_alternate") *value = g_opt.fused_alternate;
     else return ISING_EINVAL;
     return ISING_OK;
 }

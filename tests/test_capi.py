@@ -106,7 +106,7 @@ def test_options_round_trip(lib):
     from paper_1903_11714_amd import ising
     for name, good, bad in (("rows_per_lane", [0, 2, 64], [1, 3, 128, -2]), ("xcd_remap", [0, 1], [2]),
                             ("staged", [0, 1], [-1]), ("nt_store", [0, 1], [5]),
-                            ("fused_rows", [0, 2, 16, 256], [1, 6, 512, -4])):
+                            ("fused_rows", [0, 2, 16, 256], [1, 6, 512, -4]), ("fused_alternate", [0, 1], [2])):
         old = ising.ising_get_option(name)
         try:
             for v in good:

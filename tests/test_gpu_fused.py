@@ -88,7 +88,8 @@ def test_fused_staged_full_lattice_matches_oracle(dev, oracle_lib, L, n):
 
 @pytest.mark.parametrize("L", [192, 4096, 16384])
 def test_fused_equals_two_half_sweeps_for_every_strip_height(dev, L):
-    # Strip heights change which rows each workgroup recomputes; none may change a spin.
+    # Strip heights and walking directions change which rows each workgroup recomputes and in
+    # which order; none may change a spin.
     _say("fused strips", L)
     base = torch.empty((L, L), dtype=torch.int8, device="cuda")
     dev.ising_init(base, L, 17)
@@ -100,18 +101,18 @@ def test_fused_equals_two_half_sweeps_for_every_strip_height(dev, L):
         for rows in (0, 2, 4, 8, 16, 32, 64, 128, 256):
             if rows and (L % rows or rows > L):
                 continue
-            for remap in (1, 0):
-                for staged in (1, 0):
-                    dev.ising_set_option("fused_rows", rows)
-                    dev.ising_set_option("xcd_remap", remap)
-                    dev.ising_set_option("staged", staged)
-                    s = base.clone()
-                    tr = torch.empty((4, 2), dtype=torch.int64, device="cuda")
-                    dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", 4, 17, 40, tr)
-                    assert torch.equal(s, ref), (rows, remap, staged)
-                    assert torch.equal(tr, ref_tr), (rows, remap, staged)
+            for remap, staged, alt in ((1, 1, 1), (0, 1, 1), (1, 0, 1), (1, 1, 0), (0, 0, 0)):
+                dev.ising_set_option("fused_rows", rows)
+                dev.ising_set_option("xcd_remap", remap)
+                dev.ising_set_option("staged", staged)
+                dev.ising_set_option("fused_alternate", alt)
+                s = base.clone()
+                tr = torch.empty((4, 2), dtype=torch.int64, device="cuda")
+                dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", 4, 17, 40, tr)
+                assert torch.equal(s, ref), (rows, remap, staged, alt)
+                assert torch.equal(tr, ref_tr), (rows, remap, staged, alt)
     finally:
-        for k, v in (("fused_rows", 0), ("xcd_remap", 1), ("staged", 1)):
+        for k, v in (("fused_rows", 0), ("xcd_remap", 1), ("staged", 1), ("fused_alternate", 1)):
             dev.ising_set_option(k, v)
 
 
