@@ -75,6 +75,25 @@ def algorithmic_bytes(layout: str, L: int) -> float:
     return 3.0 * L * L / 16.0 if layout == "packed" else 2.0 * L * L
 
 
+def copy_bandwidth(torch, L: int, stream, reps: int = 20) -> float:
+    """GB/s (bytes read + written) of torch's device-to-device copy of an L^2-byte buffer."""
+    n = min(L, 16384) ** 2
+    src = torch.ones(n, dtype=torch.int8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * n / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(L: int, beta: float, seed: int, sweeps: int):
     """The oracle on `sweeps` sweeps of the same lattice (at most 16384^2, so the sample stays
     around ten seconds of host time)."""
@@ -274,15 +293,21 @@ def main() -> int:
         "gpu_event_ms": main["gpu_ms"],
         "final_ME": main["final_ME"],
     }
+    # context for the roofline: a plain device-to-device copy of an L^2-byte buffer (out of place,
+    # as the fused sweep moves its bytes) on the same GPU
+    cb = copy_bandwidth(torch, L, stream)
+    result["roofline"]["copy_GBs"] = cb
+    result["roofline"]["frac_of_copy"] = achieved / cb if cb else None
     if args.compare and args.layout == "fused":
         # the same workload on the other layouts (same chain, bit-identical spins), for reference
         ks = max(K // 4, 1)
         for lay in ("int8", "packed"):
             other = run_layout(ising, torch, lay, L, beta, seed, ks, W, args.kernel_sweeps, stream)
+            gbs = algorithmic_bytes(lay, L) / (other["avg_launch_ms"] * 1e-3) / 1e9
             result[f"{lay}_layout"] = {
                 "value": other["value"], "unit": "attempts/ns", "steps": ks, "kernel": KERNEL_NAME[lay],
                 "avg_launch_us": other["avg_launch_ms"] * 1e3,
-                "hbm_GBs": algorithmic_bytes(lay, L) / (other["avg_launch_ms"] * 1e-3) / 1e9,
+                "hbm_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
             }
     if args.copy_calibration:
         # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the
