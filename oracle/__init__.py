@@ -81,6 +81,23 @@ def _load():
     lib.oracle_sweep_fmt.restype = None
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle3_thresholds.argtypes = [ctypes.c_double, u64p]
+    lib.oracle3_thresholds.restype = None
+    lib.oracle3_init.argtypes = [i8p, ctypes.c_int64, ctypes.c_uint64]
+    lib.oracle3_init.restype = None
+    lib.oracle3_local_field.argtypes = [i8p, ctypes.c_int64, i8p]
+    lib.oracle3_local_field.restype = None
+    lib.oracle3_half_sweep.argtypes = [i8p, ctypes.c_int64, u64p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
+    lib.oracle3_half_sweep.restype = None
+    lib.oracle3_sweep.argtypes = [i8p, ctypes.c_int64, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64,
+                                  ctypes.c_uint64, i64p]
+    lib.oracle3_sweep.restype = None
+    lib.oracle3_observables.argtypes = [i8p, ctypes.c_int64, i64p]
+    lib.oracle3_observables.restype = None
+    lib.oracle3_crop.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64,
+                                 ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_int64, i8p]
+    lib.oracle3_crop.restype = None
     _lib = lib
     return lib
 
@@ -187,6 +204,63 @@ def sweep_fmt(spins: np.ndarray, beta: float, fmt: str, n: int, seed: int, offse
     _load().oracle_sweep_fmt(_ptr(s, ctypes.c_int8), s.shape[0], float(beta), FMT[fmt], n, seed, offset,
                              _ptr(tr, ctypes.c_int64) if tr is not None else None)
     return tr
+
+
+# ---- three dimensions: L x L x L torus, int8 array of shape (L, L, L) indexed [z, y, x]
+
+def _cube(spins: np.ndarray) -> np.ndarray:
+    if spins.dtype != np.int8 or spins.ndim != 3 or not (spins.shape[0] == spins.shape[1] == spins.shape[2]):
+        raise ValueError("lattice must be a cubic int8 array")
+    if not spins.flags.c_contiguous:
+        raise ValueError("lattice must be C-contiguous")
+    return spins
+
+
+def thresholds3(beta: float) -> tuple[int, int, int]:
+    T = np.zeros(3, dtype=np.uint64)
+    _load().oracle3_thresholds(float(beta), _ptr(T, ctypes.c_uint64))
+    return int(T[0]), int(T[1]), int(T[2])
+
+
+def init3(L: int, seed: int) -> np.ndarray:
+    s = np.empty((L, L, L), dtype=np.int8)
+    _load().oracle3_init(_ptr(s, ctypes.c_int8), L, seed)
+    return s
+
+
+def local_field3(spins: np.ndarray) -> np.ndarray:
+    s = _cube(spins)
+    nn = np.empty_like(s)
+    _load().oracle3_local_field(_ptr(s, ctypes.c_int8), s.shape[0], _ptr(nn, ctypes.c_int8))
+    return nn
+
+
+def half_sweep3(spins: np.ndarray, beta: float, seed: int, t: int, q: int) -> None:
+    s = _cube(spins)
+    T = np.array(thresholds3(beta), dtype=np.uint64)
+    _load().oracle3_half_sweep(_ptr(s, ctypes.c_int8), s.shape[0], _ptr(T, ctypes.c_uint64), seed, t, q)
+
+
+def sweep3(spins: np.ndarray, beta: float, n: int, seed: int, offset: int = 0, trace: bool = False):
+    s = _cube(spins)
+    tr = np.zeros((max(n, 0), 2), dtype=np.int64) if trace else None
+    _load().oracle3_sweep(_ptr(s, ctypes.c_int8), s.shape[0], float(beta), n, seed, offset,
+                          _ptr(tr, ctypes.c_int64) if tr is not None else None)
+    return tr
+
+
+def observables3(spins: np.ndarray) -> tuple[int, int]:
+    s = _cube(spins)
+    out = np.zeros(2, dtype=np.int64)
+    _load().oracle3_observables(_ptr(s, ctypes.c_int8), s.shape[0], _ptr(out, ctypes.c_int64))
+    return int(out[0]), int(out[1])
+
+
+def crop3(L: int, seed: int, beta: float, n: int, offset: int, z0: int, y0: int, x0: int, d: int, h: int,
+          w: int) -> np.ndarray:
+    out = np.empty((d, h, w), dtype=np.int8)
+    _load().oracle3_crop(L, seed, float(beta), n, offset, z0, y0, x0, d, h, w, _ptr(out, ctypes.c_int8))
+    return out
 
 
 def num_threads() -> int:

@@ -39,6 +39,37 @@ def enumerate_states(L: int):
     return E, M
 
 
+def enumerate_states3(L: int):
+    """Return (E, M) int64 arrays over all 2^(L^3) states of the L x L x L torus (tiny L only).
+
+    E = -sum over every site of sigma (sigma_{x+1} + sigma_{y+1} + sigma_{z+1}): each bond once,
+    so on the L = 2 torus the two bonds between a pair of sites both count.
+    """
+    n = L ** 3
+    if n > 20:
+        raise ValueError("enumeration is only meant for tiny lattices")
+    idx = np.arange(1 << n, dtype=np.int64)
+    bits = ((idx[:, None] >> np.arange(n, dtype=np.int64)[None, :]) & 1).astype(np.int8)
+    spins = (1 - 2 * bits).reshape(-1, L, L, L).astype(np.int64)
+    M = spins.sum(axis=(1, 2, 3))
+    E = -sum((spins * np.roll(spins, -1, axis=ax)).sum(axis=(1, 2, 3)) for ax in (1, 2, 3))
+    return E, M
+
+
+def boltzmann_moments3(L: int, beta: float) -> dict[str, float]:
+    """Exact <E>/N, <|M|>/N, <M^2>/N^2, <M^4>/N^4 and U4 of the L x L x L torus."""
+    E, M = enumerate_states3(L)
+    N = L ** 3
+    w = -beta * E.astype(np.float64)
+    p = np.exp(w - w.max())
+    p /= p.sum()
+    m = M.astype(np.float64) / N
+    m2 = float((p * m * m).sum())
+    m4 = float((p * m ** 4).sum())
+    return {"e": float((p * E).sum()) / N, "abs_m": float((p * np.abs(m)).sum()), "m2": m2, "m4": m4,
+            "U4": 1.0 - m4 / (3.0 * m2 * m2)}
+
+
 def density_of_states(L: int) -> dict[int, int]:
     E, _ = enumerate_states(L)
     vals, counts = np.unique(E, return_counts=True)

@@ -281,6 +281,145 @@ void oracle_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n,
     }
 }
 
+/* ==== Three dimensions (Sec. 3: the Hamiltonian on a d-dimensional hypercubic lattice; the
+ * checkerboard colouring of Fig. 1 extends to any dimension).  Same Metropolis rule, six
+ * neighbours, thresholds for s = 2, 4, 6; the random numbers are the 2-D contract's with the
+ * row index r = z L + y. */
+void oracle3_thresholds(double beta, uint64_t T[3]) {
+    for (int k = 0; k < 3; ++k) {
+        double p = exp(-2.0 * beta * (2.0 * (k + 1)));   /* s = 2, 4, 6 */
+        double y = ceil(ldexp(p, 32));
+        if (y > 4294967296.0) y = 4294967296.0;
+        if (!(y >= 0.0)) y = 0.0;
+        T[k] = (uint64_t)y;
+    }
+}
+
+void oracle3_init(int8_t* spins, int64_t L, uint64_t seed) {
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < L * L; ++r)           /* r = z L + y */
+        for (int64_t x = 0; x < L; ++x)
+            spins[r * L + x] = (int8_t)oracle_init_site(seed, (uint32_t)r, (uint32_t)x);
+}
+
+static int64_t at3(int64_t L, int64_t z, int64_t y, int64_t x) {
+    return (wrap(z, L) * L + wrap(y, L)) * L + wrap(x, L);
+}
+
+static int neighbour_sum3(const int8_t* s, int64_t L, int64_t z, int64_t y, int64_t x) {
+    return s[at3(L, z - 1, y, x)] + s[at3(L, z + 1, y, x)] + s[at3(L, z, y - 1, x)] +
+           s[at3(L, z, y + 1, x)] + s[at3(L, z, y, x - 1)] + s[at3(L, z, y, x + 1)];
+}
+
+void oracle3_local_field(const int8_t* spins, int64_t L, int8_t* nn) {
+    for (int64_t z = 0; z < L; ++z)
+        for (int64_t y = 0; y < L; ++y)
+            for (int64_t x = 0; x < L; ++x)
+                nn[(z * L + y) * L + x] = (int8_t)neighbour_sum3(spins, L, z, y, x);
+}
+
+/* s = sigma nn; s <= 0 always flips, otherwise the uniform of site (z, y, x) is compared with T_s. */
+static int accept_flip3(int sigma, int nn, const uint64_t T[3], uint64_t seed, uint32_t r, uint32_t x,
+                        uint32_t t, int q) {
+    int s = sigma * nn;
+    if (s <= 0) return 1;
+    uint64_t thr = T[s / 2 - 1];
+    return (uint64_t)oracle_uniform(seed, r, x, t, q) < thr;
+}
+
+void oracle3_half_sweep(int8_t* spins, int64_t L, const uint64_t T[3], uint64_t seed, uint32_t t, int q) {
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < L * L; ++r) {
+        int64_t z = r / L, y = r % L;
+        for (int64_t x = 0; x < L; ++x) {
+            if (((x + y + z) & 1) != q) continue;
+            int sigma = spins[r * L + x];
+            int nn = neighbour_sum3(spins, L, z, y, x);
+            if (accept_flip3(sigma, nn, T, seed, (uint32_t)r, (uint32_t)x, t, q))
+                spins[r * L + x] = (int8_t)(-sigma);
+        }
+    }
+}
+
+void oracle3_observables(const int8_t* spins, int64_t L, int64_t out[2]) {
+    int64_t M = 0, E = 0;
+    for (int64_t z = 0; z < L; ++z)
+        for (int64_t y = 0; y < L; ++y)
+            for (int64_t x = 0; x < L; ++x) {
+                int sigma = spins[(z * L + y) * L + x];
+                M += sigma;
+                E -= sigma * (spins[at3(L, z, y, x + 1)] + spins[at3(L, z, y + 1, x)] + spins[at3(L, z + 1, y, x)]);
+            }
+    out[0] = M;
+    out[1] = E;
+}
+
+void oracle3_sweep(int8_t* spins, int64_t L, double beta, int64_t n, uint64_t seed, uint64_t offset,
+                   int64_t* trace) {
+    uint64_t T[3];
+    oracle3_thresholds(beta, T);
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t t = (uint32_t)(offset + (uint64_t)i);
+        oracle3_half_sweep(spins, L, T, seed, t, 1);   /* white */
+        oracle3_half_sweep(spins, L, T, seed, t, 0);   /* black */
+        if (trace) oracle3_observables(spins, L, trace + 2 * i);
+    }
+}
+
+/* Light-cone block: after 2 n half-sweeps a site depends only on sites within distance 2 n, so
+ * the window is the block grown by R = 2 n on every side, and half-sweep k updates only the part
+ * still exact afterwards (the block grown by R - k - 1).  Falls back to the whole lattice when the
+ * window would wrap onto itself. */
+void oracle3_crop(int64_t L, uint64_t seed, double beta, int64_t n, uint64_t offset, int64_t z0, int64_t y0,
+                  int64_t x0, int64_t d, int64_t h, int64_t w, int8_t* out) {
+    int64_t R = 2 * n;
+    if (d + 2 * R >= L || h + 2 * R >= L || w + 2 * R >= L) {
+        int8_t* full = (int8_t*)malloc((size_t)(L * L * L));
+        oracle3_init(full, L, seed);
+        oracle3_sweep(full, L, beta, n, seed, offset, NULL);
+        for (int64_t a = 0; a < d; ++a)
+            for (int64_t b = 0; b < h; ++b)
+                for (int64_t c = 0; c < w; ++c)
+                    out[(a * h + b) * w + c] = full[at3(L, z0 + a, y0 + b, x0 + c)];
+        free(full);
+        return;
+    }
+    int64_t D = d + 2 * R, H = h + 2 * R, W = w + 2 * R;
+    int8_t* win = (int8_t*)malloc((size_t)(D * H * W));
+    for (int64_t a = 0; a < D; ++a)
+        for (int64_t b = 0; b < H; ++b)
+            for (int64_t c = 0; c < W; ++c)
+                win[(a * H + b) * W + c] = (int8_t)oracle_init_site(
+                    seed, (uint32_t)(wrap(z0 - R + a, L) * L + wrap(y0 - R + b, L)), (uint32_t)wrap(x0 - R + c, L));
+    uint64_t T[3];
+    oracle3_thresholds(beta, T);
+    for (int64_t k = 0; k < 2 * n; ++k) {
+        uint32_t t = (uint32_t)(offset + (uint64_t)(k / 2));
+        int q = (k % 2 == 0) ? 1 : 0;
+        int64_t lo = k + 1;
+#pragma omp parallel for schedule(static)
+        for (int64_t a = lo; a < D - lo; ++a) {
+            int64_t z = wrap(z0 - R + a, L);
+            for (int64_t b = lo; b < H - lo; ++b) {
+                int64_t y = wrap(y0 - R + b, L);
+                for (int64_t c = lo; c < W - lo; ++c) {
+                    int64_t x = wrap(x0 - R + c, L);
+                    if (((x + y + z) & 1) != q) continue;
+                    int64_t i = (a * H + b) * W + c;
+                    int sigma = win[i];
+                    int nn = win[i - H * W] + win[i + H * W] + win[i - W] + win[i + W] + win[i - 1] + win[i + 1];
+                    if (accept_flip3(sigma, nn, T, seed, (uint32_t)(z * L + y), (uint32_t)x, t, q))
+                        win[i] = (int8_t)(-sigma);
+                }
+            }
+        }
+    }
+    for (int64_t a = 0; a < d; ++a)
+        for (int64_t b = 0; b < h; ++b)
+            memcpy(out + (a * h + b) * w, win + ((a + R) * H + (b + R)) * W + R, (size_t)w);
+    free(win);
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

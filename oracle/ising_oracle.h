@@ -88,6 +88,26 @@ double oracle_u_fmt(uint32_t x, int fmt);
 void oracle_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n, uint64_t seed,
                       uint64_t offset, int64_t* trace);
 
+/* ---- Three dimensions (the d-dimensional hypercubic lattice of Sec. 3; the checkerboard
+ * colouring extends to any dimension, Fig. 1).  An L x L x L torus, L even, stored z-major:
+ * site (z, y, x) at index (z L + y) L + x.  Colour q = (x + y + z) mod 2, white (q = 1) first.
+ * nn = sum of the six neighbours, s = sigma nn in {-6, ..., 6}; a site flips iff s <= 0 or its
+ * uniform is below T_s = ceil(2^32 exp(-2 beta s)), s in {2, 4, 6}.  Random numbers: the 2-D
+ * contract with row index r = z L + y (oracle_uniform(seed, z L + y, x, t, q)), hot start
+ * oracle_init_site(seed, z L + y, x). */
+void oracle3_thresholds(double beta, uint64_t T[3]);
+void oracle3_init(int8_t* spins, int64_t L, uint64_t seed);
+void oracle3_local_field(const int8_t* spins, int64_t L, int8_t* nn);
+void oracle3_half_sweep(int8_t* spins, int64_t L, const uint64_t T[3], uint64_t seed, uint32_t t, int q);
+void oracle3_sweep(int8_t* spins, int64_t L, double beta, int64_t n, uint64_t seed, uint64_t offset,
+                   int64_t* trace);
+/* out[0] = M, out[1] = E = -sum over the 3 L^3 bonds (each site's +x, +y, +z neighbour). */
+void oracle3_observables(const int8_t* spins, int64_t L, int64_t out[2]);
+/* The d x h x w block with corner (z0, y0, x0) (mod L) after n sweeps from the hot start,
+ * computed on the light-cone window (the block grown by 2 n on every side). */
+void oracle3_crop(int64_t L, uint64_t seed, double beta, int64_t n, uint64_t offset, int64_t z0, int64_t y0,
+                  int64_t x0, int64_t d, int64_t h, int64_t w, int8_t* out);
+
 /* Number of OpenMP threads the oracle's parallel loops use (1 without OpenMP). */
 int oracle_num_threads(void);
 
