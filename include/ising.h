@@ -101,6 +101,25 @@ int ising_half_sweep(int8_t* spins, int64_t L, double beta, uint64_t seed, uint6
  * Sec. 4.1).  Exact integer sums; the result does not depend on the launch order. */
 int ising_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* stream);
 
+/* ---- Three dimensions -----------------------------------------------------------------------
+ * The d-dimensional hypercubic lattice of Sec. 3 at d = 3, with the checkerboard colouring of
+ * Fig. 1 extended to three dimensions.  spins: device int8[L * L * L], 16-byte aligned, site
+ * (z, y, x) at index (z L + y) L + x, values +1 / -1; L a power of two, 64 <= L <= 2048.
+ * Colour q = (x + y + z) mod 2; a sweep updates white (q = 1) then black.  nn = sum of the six
+ * neighbours, s = sigma nn; a site flips iff s <= 0 or its uniform x < T_s = ceil(2^32
+ * exp(-2 beta s)) for s = 2, 4, 6.  The random numbers are those of the square lattice with row
+ * index r = z L + y (Philox counter (x >> 6, z L + y, t, 2m + q), hot start as ising_init on L^2
+ * rows).  E = -sum over the 3 L^3 bonds of sigma_i sigma_j (each site's +x, +y, +z neighbour).
+ * Same conventions and error codes as the square-lattice calls. */
+int ising3_init(int8_t* spins, int64_t L, uint64_t seed, void* stream);
+int ising3_fill(int8_t* spins, int64_t L, int value, void* stream);
+int ising3_sweep(int8_t* spins, int64_t L, double beta, int64_t n_sweeps, uint64_t seed, uint64_t sweep_offset,
+                 int64_t* trace_ME, void* stream);
+int ising3_half_sweep(int8_t* spins, int64_t L, double beta, uint64_t seed, uint64_t t, int q, void* stream);
+int ising3_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* stream);
+/* out[0..2] = T_2, T_4, T_6 (host). */
+int ising3_thresholds(double beta, uint64_t out[3]);
+
 /* ---- 1-bit packed layout -----------------------------------------------------------------
  * planes: device uint32[L * L / 32], two colour planes of L rows x (L / 64) words each:
  * word (q * L + r) * (L / 64) + g holds the colour-q sites of row r with j = c >> 1 in
@@ -197,7 +216,9 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
  *   "batch_threads"  workgroup size of ising_batch_run: 0 = autotune (default), 256, 512, 1024.
  *   "fused_rows"     rows per workgroup strip of ising_sweep_fused: 0 = automatic, else a power
  *                    of two in [2, 256] (ignored for lattices it does not divide).
- *   "fused_alternate" 1 = odd strips of ising_sweep_fused walk upwards (default), 0 = all down. */
+ *   "fused_alternate" 1 = odd strips of ising_sweep_fused walk upwards (default), 0 = all down.
+ *   "planes3"        planes each workgroup of ising3_sweep walks: 0 = automatic, else a power of
+ *                    two in [2, 256] (ignored for lattices it does not divide). */
 int ising_set_option(const char* name, int64_t value);
 int ising_get_option(const char* name, int64_t* value);
 

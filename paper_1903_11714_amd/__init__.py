@@ -20,6 +20,12 @@ from .ising import (  # noqa: F401
     ising_moments,
     ising_sweep_fmt,
     ising_sweep_fused,
+    ising3_fill,
+    ising3_half_sweep,
+    ising3_init,
+    ising3_observables,
+    ising3_sweep,
+    ising3_thresholds,
     ising_sweep_fused_step,
     ising_sweep_packed_fmt,
     ising_thresholds_fmt,

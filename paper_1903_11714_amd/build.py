@@ -7,7 +7,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = [os.path.join(PKG, "csrc", "ising.hip")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("ising.hip", "ising3d.hip")]
 LIB = os.path.join(PKG, "libising.so")
 ARCH = os.environ.get("ISING_OFFLOAD_ARCH", "gfx950")
 

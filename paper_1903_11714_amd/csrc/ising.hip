@@ -32,211 +32,11 @@
 
 #include "ising.h"
 #include "philox.hpp"
+#include "host.hpp"
+#include "rows.hpp"
 
 namespace ising {
 
-// ------------------------------------------------------------------------------------------
-// Bit-word helpers.  "Site order": site i (0..31) of a group sits at bit p(i) =
-// 8 * (0, 2, 1, 3)[i & 3] + (i >> 2), the bit position its uniform uses in each Philox word.
-
-struct Row {
-    uint32_t d[16];  // 64 bytes = one group of one row; dword k holds columns 4k .. 4k + 3
-};
-
-__device__ __forceinline__ uint32_t perm(uint32_t s0, uint32_t s1, uint32_t sel) {
-    return __builtin_amdgcn_perm(s0, s1, sel);
-}
-
-__device__ __forceinline__ void load_row(Row& row, const int8_t* p) {
-    const uint4* v = reinterpret_cast<const uint4*>(p);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint4 x = v[i];
-        row.d[4 * i + 0] = x.x;
-        row.d[4 * i + 1] = x.y;
-        row.d[4 * i + 2] = x.z;
-        row.d[4 * i + 3] = x.w;
-    }
-}
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void store_row(int8_t* p, const Row& row, bool streaming) {
-    u32x4* v = reinterpret_cast<u32x4*>(p);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const u32x4 x = {row.d[4 * i], row.d[4 * i + 1], row.d[4 * i + 2], row.d[4 * i + 3]};
-        if (streaming) __builtin_nontemporal_store(x, v + i);
-        else v[i] = x;
-    }
-}
-
-// ---- Coalesced row I/O through LDS.  When a wave's 64 lanes own 64 consecutive groups of
-// one row (4 KiB), loading "64 contiguous bytes per lane" wastes most of every memory
-// instruction.  Instead lane l moves 16-byte chunks l, l + 64, l + 128, l + 192 of the wave's
-// row segment (each instruction covers 1 KiB contiguous) and the bytes are regrouped per lane
-// through a 4 KiB per-wave LDS buffer.  Chunk c belongs to lane c / 4, quarter c % 4, and is
-// kept in LDS slot 4 (c / 4) + ((c % 4 + c / 8) mod 4): any 8 consecutive lanes then touch 8
-// distinct 16-byte bank groups on both the write and the read side.
-__device__ __forceinline__ uint32_t lds_slot(uint32_t owner, uint32_t quarter) {
-    return 4u * owner + ((quarter + (owner >> 1)) & 3u);
-}
-
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// raw: this lane's four coalesced chunks (chunk l + 64 k in raw.d[4k .. 4k + 3]).
-__device__ __forceinline__ void load_row_coalesced(Row& raw, const int8_t* seg, uint32_t lane) {
-    const uint4* v = reinterpret_cast<const uint4*>(seg) + lane;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint4 x = v[64 * k];
-        raw.d[4 * k + 0] = x.x;
-        raw.d[4 * k + 1] = x.y;
-        raw.d[4 * k + 2] = x.z;
-        raw.d[4 * k + 3] = x.w;
-    }
-}
-
-// coalesced chunks -> this lane's own 64 bytes
-__device__ __forceinline__ void regroup_to_owner(Row& row, const Row& raw, uint4* lds, uint32_t lane) {
-#pragma unroll
-    for (uint32_t k = 0; k < 4; ++k) {
-        const uint32_t c = lane + 64u * k;
-        lds[lds_slot(c >> 2, c & 3u)] = make_uint4(raw.d[4 * k], raw.d[4 * k + 1], raw.d[4 * k + 2], raw.d[4 * k + 3]);
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (uint32_t q = 0; q < 4; ++q) {
-        const uint4 x = lds[lds_slot(lane, q)];
-        row.d[4 * q + 0] = x.x;
-        row.d[4 * q + 1] = x.y;
-        row.d[4 * q + 2] = x.z;
-        row.d[4 * q + 3] = x.w;
-    }
-    wave_lds_sync();
-}
-
-// this lane's own 64 bytes -> coalesced stores of the wave's row segment
-__device__ __forceinline__ void store_row_coalesced(int8_t* seg, const Row& row, uint4* lds, uint32_t lane,
-                                                    bool streaming) {
-#pragma unroll
-    for (uint32_t q = 0; q < 4; ++q)
-        lds[lds_slot(lane, q)] = make_uint4(row.d[4 * q], row.d[4 * q + 1], row.d[4 * q + 2], row.d[4 * q + 3]);
-    wave_lds_sync();
-    u32x4* v = reinterpret_cast<u32x4*>(seg) + lane;
-#pragma unroll
-    for (uint32_t k = 0; k < 4; ++k) {
-        const uint32_t c = lane + 64u * k;
-        const uint4 x = lds[lds_slot(c >> 2, c & 3u)];
-        const u32x4 y = {x.x, x.y, x.z, x.w};
-        if (streaming) __builtin_nontemporal_store(y, v + 64 * k);
-        else v[64 * k] = y;
-    }
-    wave_lds_sync();
-}
-
-// Workgroups are dispatched to the eight XCDs round robin (block b runs on XCD b mod 8).
-// Renumbering them so that each XCD receives one contiguous range of logical blocks keeps
-// neighbouring row strips, which read each other's boundary rows, inside one L2.
-__device__ __forceinline__ uint32_t logical_block(uint32_t b, uint32_t nb, bool remap) {
-    if (!remap) return b;
-    const uint32_t x = b & 7u, i = b >> 3, per = nb >> 3, rem = nb & 7u;
-    return x * per + (x < rem ? x : rem) + i;
-}
-
-// Sign bits (1 = spin -1) of the 32 sites at columns of parity OFF, in site order.
-// A +-1 byte is 0x01 or 0xFF, so bits 1..7 of the byte all equal its sign.
-template <int OFF>
-__device__ __forceinline__ uint32_t site_bits(const Row& row) {
-    // bytes of the compact word: (site 4k, site 4k+2, site 4k+1, site 4k+3)
-    constexpr uint32_t sel = OFF | ((4 + OFF) << 8) | ((OFF + 2) << 16) | ((6 + OFF) << 24);
-    uint32_t acc = (perm(row.d[1], row.d[0], sel) >> 1) & 0x01010101u;
-#pragma unroll
-    for (int k = 1; k < 8; ++k) acc |= perm(row.d[2 * k + 1], row.d[2 * k], sel) & (0x01010101u << k);
-    return acc;
-}
-
-// S[p(i)] = y[p(i + 1)] for i < 31, S[p(31)] = bit0 (site 0 of the next group).
-__device__ __forceinline__ uint32_t shift_next(uint32_t y, uint32_t bit0) {
-    const uint32_t top = ((y >> 1) & 0x7Fu) | (bit0 << 7);
-    return perm(top, y, 0x04010302u);
-}
-
-// S[p(i)] = y[p(i - 1)] for i > 0, S[p(0)] = bit31 (site 31 of the previous group).
-__device__ __forceinline__ uint32_t shift_prev(uint32_t y, uint32_t bit31) {
-    const uint32_t low = ((y >> 23) & 0xFEu) | bit31;
-    return perm(y, low, 0x05040600u);
-}
-
-// Flip the colour-OFF bytes of `row` whose site bit is set in F.  The two sites of dword
-// 2k + h sit at bits k + 8h and k + 8h + 16; shifting them to bits 15 and 31 lets the
-// sign-extending selectors 8 and 9 of v_perm produce 0xFF at exactly those bytes.
-template <int OFF>
-__device__ __forceinline__ void apply_flips(Row& row, uint32_t F) {
-    constexpr uint32_t sel = OFF == 0 ? 0x0C090C08u : 0x090C080Cu;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const uint32_t m = perm(0u, F << (15 - k - 8 * h), sel);
-            row.d[2 * k + h] ^= m & 0xFEFEFEFEu;  // 0x01 <-> 0xFF
-        }
-    }
-}
-
-__device__ __forceinline__ bool wave_any(bool v) { return __builtin_amdgcn_ballot_w64(v) != 0; }
-
-// Metropolis thresholds of one launch (uniform): a site with a anti-aligned neighbours has
-// s = 4 - 2a; a >= 2 always flips, a = 1 compares with T_2, a = 0 with T_4.
-struct Thresholds {
-    uint32_t t2, t4;      // low 32 bits of T_2, T_4
-    uint32_t full2, full4;  // 1 when T_s = 2^32 (always accept)
-    uint32_t blocks;        // Philox blocks (4 bit planes each) that can decide: 8, or 4 when
-                            // both thresholds are multiples of 2^16 (16-bit uniforms)
-};
-
-// Exact x < T for every site in sel2 (threshold T_2) or sel4 (T_4), bit plane by bit plane.
-// Returns the accepted sites.  Planes come four per Philox block with counter
-// (g, r, t, 2m + q), plane k = 4m + w is bit 31 - k of each site's uniform.
-__device__ __forceinline__ uint32_t accept_mask(uint32_t sel2, uint32_t sel4, const Thresholds& th,
-                                                uint32_t g, uint32_t r, uint32_t t, uint32_t q,
-                                                uint32_t key0, uint32_t key1) {
-    uint32_t acc = 0;
-    if (th.full2) { acc |= sel2; sel2 = 0; }
-    if (th.full4) { acc |= sel4; sel4 = 0; }
-    uint32_t tied = sel2 | sel4;
-    // sites outside sel2 are compared with T_4 below; make sure only tied ones matter
-#pragma unroll 1
-    for (uint32_t m = 0; m < th.blocks; ++m) {
-        // a site still tied after the last deciding plane has x >= T (the remaining bits of T
-        // are zero), so it is rejected
-        if (!wave_any(tied != 0)) break;
-        const Words4 blk = philox4x32_10(g, r, t, 2u * m + q, key0, key1);
-        const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const uint32_t k = 4u * m + (uint32_t)w;
-            // threshold bit of every site: bit 31 - k of T_2 on sel2, of T_4 elsewhere (the
-            // value outside sel2 | sel4 is never used because those sites are not tied)
-            const uint32_t m2 = 0u - ((th.t2 >> (31u - k)) & 1u);
-            const uint32_t m4 = 0u - ((th.t4 >> (31u - k)) & 1u);
-            const uint32_t tbit = (sel2 & m2) | (~sel2 & m4);
-            const uint32_t x = planes[w];
-            acc |= tied & tbit & ~x;   // first difference: x has 0 where T has 1 -> x < T
-            tied &= ~(x ^ tbit);       // still equal so far
-        }
-    }
-    return acc;
-}
-
-struct Counts {
-    uint32_t anti;  // anti-aligned bonds seen from this colour's sites after the update
-    uint32_t neg;   // spins equal to -1 in the rows processed
-};
 
 // One row of the half-sweep for colour Q.  O = column parity of the colour-Q sites of this row.
 // bprev: row r-1 sites at parity O (vertical neighbours), bcur: row r sites at parity 1-O
@@ -283,34 +83,6 @@ __device__ __forceinline__ uint32_t sweep_row(Row& cur, const Row& nxt, uint32_t
     const uint32_t F = decide<Q, OBS>(a, bprev, bnext, bcur, hs, bcur, th, g, r, t, key0, key1, cnt);
     apply_flips<O>(cur, F);
     return bnext;
-}
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Block-level sum of (anti, neg) -> one pair of 64-bit atomics per block.
-// sites_per_lane: sites each active lane covered; bonds: 2 per site.
-__device__ __forceinline__ void block_accumulate(int64_t* out, uint32_t anti, uint32_t neg, uint32_t active,
-                                                 uint32_t sites_per_lane) {
-    __shared__ uint32_t red[3][16];
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    anti = wave_sum(anti);
-    neg = wave_sum(neg);
-    active = wave_sum(active);
-    if (lane == 0) { red[0][wave] = anti; red[1][wave] = neg; red[2][wave] = active; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t A = 0, Nn = 0, act = 0;
-        for (uint32_t w = 0; w < blockDim.x / 64u; ++w) { A += red[0][w]; Nn += red[1][w]; act += red[2][w]; }
-        const int64_t sites = (int64_t)act * sites_per_lane;
-        const int64_t M = sites - 2 * (int64_t)Nn;            // sum of spins
-        const int64_t E = 2 * (int64_t)A - 2 * sites;         // #anti - #aligned over 2 bonds/site
-        atomicAdd(reinterpret_cast<unsigned long long*>(out), (unsigned long long)M);
-        atomicAdd(reinterpret_cast<unsigned long long*>(out + 1), (unsigned long long)E);
-    }
 }
 
 struct SweepArgs {
@@ -454,34 +226,10 @@ struct FusedArgs {
     uint32_t alternate;  // walk odd strips upwards
 };
 
-struct RowBits {
-    uint32_t e, o;  // sign bits of the even / odd columns of one group of one row, site order
-};
-
-__device__ __forceinline__ RowBits row_bits(const Row& row) { return RowBits{site_bits<0>(row), site_bits<1>(row)}; }
-
-// inverse of row_bits: +1 -> 0x01, -1 -> 0xFF
-__device__ __forceinline__ void bits_to_row(Row& row, const RowBits& b) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const uint32_t sh = 15 - k - 8 * h;
-            row.d[2 * k + h] = perm(b.o << sh, b.e << sh, 0x0B090A08u) | 0x01010101u;
-        }
-    }
-}
-
 // Edge bits a thread publishes after step x: bit 0 / 1 = site 0 of the even columns / site 31 of
 // the odd columns of row x + 1, bit 2 / 3 = the same sites of row x.
 __device__ __forceinline__ uint32_t edge_word(const RowBits& next, const RowBits& cur) {
     return (next.e & 1u) | ((next.o >> 31) << 1) | ((cur.e & 1u) << 2) | ((cur.o >> 31) << 3);
-}
-
-__device__ __forceinline__ void workgroup_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // One step at row x: the white sites of row x (w0), then, with B, the black sites of row x - 1 (w1).
@@ -1057,6 +805,7 @@ struct Options {
     int64_t batch_threads = 0;  // 0 = autotune
     int64_t fused_rows = 0;     // rows per strip of the fused sweep; 0 = choose from L
     int64_t fused_alternate = 1;  // fused sweep: odd strips walk upwards
+    int64_t planes3 = 0;          // 3-D sweep: planes per workgroup; 0 = choose from L
 };
 Options g_opt;
 
@@ -1356,6 +1105,20 @@ int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Threshold
 }
 }  // namespace
 
+// Definitions of the helpers declared in host.hpp (used by the 3-D translation unit).
+namespace ising_host {
+int hip_failed(hipError_t e, const char* what) { return ::hip_failed(e, what); }
+int check_launch(const char* what) { return ::check_launch(what); }
+bool valid_beta(double beta) { return ::valid_beta(beta); }
+bool aligned16(const void* p) { return ::aligned16(p); }
+bool xcd_remap() { return g_opt.xcd_remap != 0; }
+int64_t option(const char* name) {
+    int64_t v = 0;
+    return ising_get_option(name, &v) == ISING_OK ? v : 0;
+}
+int zero_trace(int64_t* p, int64_t n, hipStream_t stream) { return ::zero_trace(p, n, stream); }
+}  // namespace ising_host
+
 extern "C" {
 
 int ising_thresholds(double beta, uint64_t out[2]) {
@@ -1394,6 +1157,28 @@ int ising_fill(int8_t* spins, int64_t L, int value, void* stream) {
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(ising::k_fill_int8, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, spins,
                        n16, word);
+    return check_launch("k_fill_int8");
+}
+
+// 3-D lattices (L x L x L, L a power of two in [64, 2048]): the hot start is the square lattice's
+// with L^2 rows (r = z L + y) of length L.
+int ising3_init(int8_t* spins, int64_t L, uint64_t seed, void* stream) {
+    if (!spins || L < 64 || L > 2048 || (L & (L - 1)) != 0 || !aligned16(spins)) return ISING_EINVAL;
+    const uint32_t chunks = (uint32_t)((L + 127) / 128);
+    const uint64_t n_lanes = (uint64_t)chunks * (uint64_t)L * (uint64_t)L;
+    const dim3 grid((unsigned)((n_lanes + 255) / 256)), block(256);
+    hipLaunchKernelGGL(ising::k_init_int8, grid, block, 0, (hipStream_t)stream, spins, (uint32_t)L, chunks,
+                       n_lanes, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return check_launch("k_init_int8");
+}
+
+int ising3_fill(int8_t* spins, int64_t L, int value, void* stream) {
+    if (!spins || L < 64 || L > 2048 || (L & (L - 1)) != 0 || !aligned16(spins) || (value != 1 && value != -1))
+        return ISING_EINVAL;
+    const uint64_t n16 = (uint64_t)L * (uint64_t)L * (uint64_t)L / 16u;
+    const uint32_t word = value == 1 ? 0x01010101u : 0xFFFFFFFFu;
+    hipLaunchKernelGGL(ising::k_fill_int8, dim3((unsigned)std::min<uint64_t>((n16 + 255) / 256, 8192)), dim3(256), 0,
+                       (hipStream_t)stream, spins, n16, word);
     return check_launch("k_fill_int8");
 }
 
@@ -1591,6 +1376,9 @@ int ising_set_option(const char* name, int64_t value) {
     } else if (n == "staged") {
         if (value != 0 && value != 1) return ISING_EINVAL;
         g_opt.staged = value;
+    } else if (n == "planes3") {
+        if (value != 0 && (value < 2 || value > 256 || (value & (value - 1)) != 0)) return ISING_EINVAL;
+        g_opt.planes3 = value;
     } else if (n == "fused_alternate") {
         if (value != 0 && value != 1) return ISING_EINVAL;
         g_opt.fused_alternate = value;
@@ -1613,6 +1401,7 @@ int ising_get_option(const char* name, int64_t* value) {
     else if (n == "batch_threads") *value = g_opt.batch_threads;
     else if (n == "fused_rows") *value = g_opt.fused_rows;
     else if (n == "fused_alternate") *value = g_opt.fused_alternate;
+    else if (n == "planes3") *value = g_opt.planes3;
     else return ISING_EINVAL;
     return ISING_OK;
 }

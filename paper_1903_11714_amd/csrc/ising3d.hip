@@ -1,0 +1,383 @@
+// ising3d.hip — checkerboard Metropolis sweep of the 3-D Ising model on gfx950.
+//
+// Paper: Yang, Chen, Roumpos, Colby, Anderson, "High Performance Monte Carlo Simulation of
+// Ising Model on TPU Clusters" (arXiv 1903.11714).  Sec. 3 states the Hamiltonian on a
+// d-dimensional hypercubic lattice; the checkerboard colouring of Fig. 1 extends to any
+// dimension, and the conclusion names the three-dimensional model as the next workload.  Here:
+// an L x L x L torus of int8 spins stored z-major (site (z, y, x) at (z L + y) L + x), colour
+// q = (x + y + z) mod 2, white (q = 1) then black each sweep, six neighbours, thresholds
+// T_s = ceil(2^32 exp(-2 beta s)) for s = 2, 4, 6.  The random numbers are the square lattice's
+// with the row index r = z L + y: counter (group, z L + y, sweep, 2m + q).
+//
+// One colour per launch, in place.  A workgroup owns Y whole rows (y0 .. y0 + Y - 1) of a plane,
+// W * 4 KiB contiguous, so every wave moves its rows with the coalesced LDS-regrouped I/O of the
+// square-lattice kernels, and walks Rz consecutive planes in z with a three-plane window of bit
+// words.  Per plane: the y neighbours are the rows of other lanes (one LDS exchange and one
+// workgroup barrier per plane), or, for the workgroup's first and last row when Y < L, rows loaded
+// from the neighbouring strip; the x neighbour across a group edge is a bit of the adjacent
+// lane's word.  The six-neighbour count is two bit-sliced full adders; the acceptance is the
+// bit-plane compare with three thresholds.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "host.hpp"
+#include "ising.h"
+#include "philox.hpp"
+#include "rows.hpp"
+
+namespace ising {
+
+// Thresholds for s = 2, 4, 6 (index 0, 1, 2): low 32 bits, and 1 where T_s = 2^32.
+struct Thresholds3 {
+    uint32_t t[3];
+    uint32_t full[3];
+    uint32_t blocks;  // Philox blocks (4 bit planes each) that can decide
+};
+
+// Exact x < T_s for the sites of sel2 / sel4 / sel6, bit plane by bit plane (as accept_mask).
+__device__ __forceinline__ uint32_t accept_mask3(uint32_t sel2, uint32_t sel4, uint32_t sel6, const Thresholds3& th,
+                                                 uint32_t g, uint32_t r, uint32_t t, uint32_t q, uint32_t key0,
+                                                 uint32_t key1) {
+    uint32_t acc = 0;
+    if (th.full[0]) { acc |= sel2; sel2 = 0; }
+    if (th.full[1]) { acc |= sel4; sel4 = 0; }
+    if (th.full[2]) { acc |= sel6; sel6 = 0; }
+    uint32_t tied = sel2 | sel4 | sel6;
+#pragma unroll 1
+    for (uint32_t m = 0; m < th.blocks; ++m) {
+        if (!wave_any(tied != 0)) break;
+        const Words4 blk = philox4x32_10(g, r, t, 2u * m + q, key0, key1);
+        const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t k = 4u * m + (uint32_t)w;
+            const uint32_t m2 = 0u - ((th.t[0] >> (31u - k)) & 1u);
+            const uint32_t m4 = 0u - ((th.t[1] >> (31u - k)) & 1u);
+            const uint32_t m6 = 0u - ((th.t[2] >> (31u - k)) & 1u);
+            const uint32_t tbit = (sel2 & m2) | (sel4 & m4) | (sel6 & m6);  // the site's threshold bit
+            const uint32_t x = planes[w];
+            acc |= tied & tbit & ~x;
+            tied &= ~(x ^ tbit);
+        }
+    }
+    return acc;
+}
+
+// Metropolis decision for 32 sites a (bit words, site order) with neighbour words nb[0..5].
+// c = number of anti-aligned neighbours (0..6), s = 6 - 2c: c >= 3 always flips, c = 2, 1, 0
+// compare with T_2, T_4, T_6.  With OBS: anti-aligned bonds of these sites after the update and
+// -1 spins among them and `others` (the other colour of the same row segment).
+template <bool OBS>
+__device__ __forceinline__ uint32_t decide3(uint32_t a, const uint32_t (&nb)[6], uint32_t others, const Thresholds3& th,
+                                            uint32_t g, uint32_t r, uint32_t t, uint32_t q, uint32_t key0,
+                                            uint32_t key1, Counts& cnt) {
+    uint32_t x[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) x[k] = a ^ nb[k];
+    const uint32_t s1 = x[0] ^ x[1] ^ x[2], c1 = (x[0] & x[1]) | (x[2] & (x[0] ^ x[1]));
+    const uint32_t s2 = x[3] ^ x[4] ^ x[5], c2 = (x[3] & x[4]) | (x[5] & (x[3] ^ x[4]));
+    const uint32_t b0 = s1 ^ s2, k0 = s1 & s2;
+    const uint32_t b1 = c1 ^ c2 ^ k0, b2 = (c1 & c2) | (k0 & (c1 ^ c2));  // c = b0 + 2 b1 + 4 b2
+    const uint32_t ge3 = b2 | (b1 & b0);
+    const uint32_t sel2 = b1 & ~b0 & ~b2;
+    const uint32_t sel4 = b0 & ~b1 & ~b2;
+    const uint32_t sel6 = ~(b0 | b1 | b2);
+    const uint32_t F = ge3 | accept_mask3(sel2, sel4, sel6, th, g, r, t, q, key0, key1);
+    if (OBS) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) cnt.anti += __builtin_popcount(x[k] ^ F);
+        cnt.neg += __builtin_popcount(a ^ F) + __builtin_popcount(others);
+    }
+    return F;
+}
+
+struct Sweep3Args {
+    int8_t* spins;
+    uint32_t L, G;        // G = L / 64 groups per row
+    uint32_t Y, ystrips;  // rows per workgroup (W * 4096 / L) and L / Y
+    uint32_t Rz;          // planes per workgroup (even, divides L)
+    uint32_t t, key0, key1;
+    Thresholds3 th;
+    int64_t* obs;        // OBS: (M, E) accumulator, zeroed beforehand
+    int64_t* zero_slot;  // if non-null, the first workgroup zeroes these two int64
+    uint32_t xcd_remap;
+};
+
+// HALO: Y < L, so the first and last row of the workgroup take their outer y neighbour from the
+// adjacent strip's row in memory; otherwise the workgroup holds whole planes and y wraps inside.
+template <int Q, bool OBS, bool HALO>
+__global__ __launch_bounds__(512) void k_sweep3(Sweep3Args a) {
+    extern __shared__ uint4 s3_lds[];
+    const uint32_t tid = threadIdx.x, nt = blockDim.x, lane = tid & 63u;
+    uint4* const stage = s3_lds + (tid >> 6) * 256u;                            // 4 KiB per wave
+    uint2* const xch = reinterpret_cast<uint2*>(s3_lds + (nt >> 6) * 256u);  // two slots of nt words
+    const uint32_t b = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
+    const uint32_t L = a.L, G = a.G, Y = a.Y, Rz = a.Rz;
+    const uint32_t y0 = (b % a.ystrips) * Y, z0 = (b / a.ystrips) * Rz;
+    const uint32_t yy = tid / G, g = tid % G, y = y0 + yy;
+    if (a.zero_slot && blockIdx.x == 0 && tid == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
+    const size_t plane = (size_t)L * L;
+    const size_t seg = (size_t)y0 * L + (size_t)(tid >> 6) * 4096u;  // this wave's rows in a plane
+    // plane of walk step k = 0 .. Rz + 1 (z0 - 1 .. z0 + Rz, wrapped); prefetches past the last
+    // one are clamped to it, so every load stays unconditional
+    auto zplane = [&](uint32_t k) {
+        const uint32_t v = z0 + L - 1 + (k < Rz + 1 ? k : Rz + 1);  // < 2L + 1
+        return v >= 2 * L ? v - 2 * L : v >= L ? v - L : v;
+    };
+    // the outer y neighbour row this lane loads when HALO (lanes in the upper half of the
+    // workgroup's rows the row above it, the others the row below)
+    const uint32_t hrow = yy < Y / 2 ? (y0 == 0 ? L - 1 : y0 - 1) : (y0 + Y == L ? 0 : y0 + Y);
+    auto hplane = [&](uint32_t j) { return z0 + (j < Rz ? j : Rz - 1); };  // plane of halo step j
+    auto fetch = [&](Row& raw, uint32_t z) { load_row_coalesced(raw, a.spins + z * plane + seg, lane); };
+    auto own = [&](const Row& raw) {
+        Row row;
+        regroup_to_owner(row, raw, stage, lane);
+        return row_bits(row);
+    };
+    auto fetch_halo = [&](Row& raw, uint32_t z) {
+        load_row(raw, a.spins + ((size_t)z * L + hrow) * L + (size_t)g * 64u);
+    };
+    auto put = [&](uint32_t z, const RowBits& bits) {
+        Row row;
+        bits_to_row(row, bits);
+        store_row_coalesced(a.spins + z * plane + seg, row, stage, lane, false);
+    };
+    Counts cnt{0u, 0u};
+    const uint32_t ir = g + 1 < G ? tid + 1 : tid + 1 - G;  // same row, next group (wrapping)
+    const uint32_t il = g > 0 ? tid - 1 : tid + G - 1;      // same row, previous group
+    const uint32_t iym = yy > 0 ? tid - G : tid + (Y - 1) * G;
+    const uint32_t iyp = yy + 1 < Y ? tid + G : tid - (Y - 1) * G;
+    // one plane: prev / cur / next = planes z - 1, z, z + 1 of this lane's row segment, hb = its
+    // halo row's bits in plane z
+    auto step = [&](uint32_t z, const RowBits& prev, RowBits& cur, const RowBits& next, const RowBits& hb,
+                    uint32_t slot) {
+        uint2* const x = xch + slot * nt;
+        x[tid] = make_uint2(cur.e, cur.o);
+        workgroup_lds_sync();
+        uint2 ym = x[iym], yp = x[iyp];
+        if (HALO && yy == 0) ym = make_uint2(hb.e, hb.o);
+        if (HALO && yy + 1 == Y) yp = make_uint2(hb.e, hb.o);
+        const uint32_t right_e = x[ir].x, left_o = x[il].y;
+        const bool O = ((Q + y + z) & 1u) != 0;  // column parity of this row's colour-Q sites
+        const uint32_t sites = O ? cur.o : cur.e, side = O ? cur.e : cur.o;
+        const uint32_t hs = O ? shift_next(cur.e, right_e & 1u) : shift_prev(cur.o, left_o >> 31);
+        const uint32_t nb[6] = {O ? ym.y : ym.x, O ? yp.y : yp.x, O ? prev.o : prev.e, O ? next.o : next.e,
+                                side, hs};
+        const uint32_t F = decide3<OBS>(sites, nb, side, a.th, g, z * L + y, a.t, (uint32_t)Q, a.key0, a.key1, cnt);
+        if (O) cur.o ^= F; else cur.e ^= F;
+        put(z, cur);
+    };
+    // prologue: planes z0 - 1 .. z0 + 2 in bits, z0 + 3, z0 + 4 in flight; halo rows of planes
+    // z0, z0 + 1 in bits, z0 + 2, z0 + 3 in flight
+    Row ra, rb, ha, hb;
+    fetch(ra, zplane(0));
+    fetch(rb, zplane(1));
+    RowBits p = own(ra), c = own(rb);
+    fetch(ra, zplane(2));
+    fetch(rb, zplane(3));
+    RowBits n0 = own(ra), n1 = own(rb);
+    fetch(ra, zplane(4));
+    fetch(rb, zplane(5));
+    RowBits h0{0u, 0u}, h1{0u, 0u};
+    if (HALO) {
+        fetch_halo(ha, hplane(0));
+        fetch_halo(hb, hplane(1));
+        h0 = row_bits(ha);
+        h1 = row_bits(hb);
+        fetch_halo(ha, hplane(2));
+        fetch_halo(hb, hplane(3));
+    }
+#pragma unroll 1
+    for (uint32_t k = 0; k < Rz; k += 2) {
+        const uint32_t z = zplane(k + 1);
+        step(z, p, c, n0, h0, 0);
+        p = c;
+        c = n0;
+        step(zplane(k + 2), p, c, n1, h1, 1);
+        p = c;
+        c = n1;
+        n0 = own(ra);  // planes of walk steps k + 4, k + 5
+        n1 = own(rb);
+        fetch(ra, zplane(k + 6));
+        fetch(rb, zplane(k + 7));
+        if (HALO) {
+            h0 = row_bits(ha);  // halo rows of planes z + 2, z + 3
+            h1 = row_bits(hb);
+            fetch_halo(ha, hplane(k + 4));
+            fetch_halo(hb, hplane(k + 5));
+        }
+    }
+    if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, 1u, 64u * Rz, 3u);
+}
+
+// (M, E) of a cubic lattice: each lane one 64-column group of one row; bonds to +x, +y, +z.
+__global__ __launch_bounds__(256) void k_observables3(const int8_t* spins, uint32_t L, uint32_t G, uint64_t n_lanes,
+                                                      int64_t* out) {
+    const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = id < n_lanes;
+    uint32_t anti = 0, neg = 0;
+    if (active) {
+        const uint32_t g = (uint32_t)(id % G);
+        const uint64_t r = id / G;  // z L + y
+        const uint32_t z = (uint32_t)(r / L), y = (uint32_t)(r % L);
+        const uint32_t gr = g + 1 == G ? 0 : g + 1;
+        const size_t base = (size_t)r * L;
+        const size_t down = ((size_t)z * L + (y + 1 == L ? 0 : y + 1)) * L;
+        const size_t back = ((size_t)(z + 1 == L ? 0 : z + 1) * L + y) * L;
+        Row cur, dn, bk;
+        load_row(cur, spins + base + (size_t)g * 64u);
+        load_row(dn, spins + down + (size_t)g * 64u);
+        load_row(bk, spins + back + (size_t)g * 64u);
+        const uint32_t right = *reinterpret_cast<const uint32_t*>(spins + base + (size_t)gr * 64u);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t nbw = k < 15 ? cur.d[k + 1] : right;
+            const uint32_t rn = __builtin_amdgcn_alignbyte(nbw, cur.d[k], 1);  // right neighbours
+            neg += __builtin_popcount(cur.d[k] & 0x80808080u);
+            anti += __builtin_popcount((cur.d[k] ^ rn) & 0x80808080u);
+            anti += __builtin_popcount((cur.d[k] ^ dn.d[k]) & 0x80808080u);
+            anti += __builtin_popcount((cur.d[k] ^ bk.d[k]) & 0x80808080u);
+        }
+    }
+    block_accumulate(out, anti, neg, active ? 1u : 0u, 64u, 3u);
+}
+
+}  // namespace ising
+
+// ==========================================================================================
+// Host side.
+namespace {
+
+// 3-D lattices: L a power of two, 64 <= L <= 2048 (a wave's 4 KiB is then whole rows).
+bool valid_L3(int64_t L) { return L >= 64 && L <= 2048 && (L & (L - 1)) == 0; }
+
+void host_thresholds3(double beta, uint64_t T[3]) {
+    for (int k = 0; k < 3; ++k) {
+        const double s = 2.0 * (k + 1);
+        double y = std::ceil(std::ldexp(std::exp(-2.0 * beta * s), 32));
+        if (y > 4294967296.0) y = 4294967296.0;
+        if (!(y >= 0.0)) y = 0.0;
+        T[k] = (uint64_t)y;
+    }
+}
+
+ising::Thresholds3 make_thresholds3(double beta) {
+    uint64_t T[3];
+    host_thresholds3(beta, T);
+    ising::Thresholds3 th;
+    for (int k = 0; k < 3; ++k) {
+        th.full[k] = T[k] >= (uint64_t(1) << 32);
+        th.t[k] = th.full[k] ? 0u : (uint32_t)T[k];
+    }
+    th.blocks = 8;
+    return th;
+}
+
+struct Shape3 {
+    uint32_t W, Y, ystrips, Rz;
+};
+
+// W waves per workgroup (whole planes up to 4 waves, 8 waves from L = 1024), Y = W * 4096 / L
+// rows; Rz planes per workgroup: the tallest even divisor of L up to 32 that keeps >= 4096 waves.
+Shape3 shape3(int64_t L) {
+    Shape3 s;
+    const uint64_t waves_per_plane = (uint64_t)L * (uint64_t)L / 4096u;
+    s.W = (uint32_t)std::min<uint64_t>(waves_per_plane, L >= 1024 ? 8u : 4u);
+    s.Y = (uint32_t)(s.W * 4096u / (uint64_t)L);
+    s.ystrips = (uint32_t)(L / s.Y);
+    const int64_t forced = ising_host::option("planes3");
+    if (forced > 0 && L % forced == 0) {
+        s.Rz = (uint32_t)forced;
+        return s;
+    }
+    uint32_t Rz = 32;
+    while (Rz > 2 && (waves_per_plane * (uint64_t)(L / Rz) < 4096u || L % Rz != 0)) Rz >>= 1;
+    s.Rz = Rz;
+    return s;
+}
+
+int launch_half_sweep3(int8_t* spins, int64_t L, const ising::Thresholds3& th, uint64_t seed, uint32_t t, int q,
+                       int64_t* obs, int64_t* zero_slot, hipStream_t stream) {
+    const Shape3 sh = shape3(L);
+    ising::Sweep3Args a;
+    a.spins = spins;
+    a.L = (uint32_t)L;
+    a.G = (uint32_t)(L / 64);
+    a.Y = sh.Y;
+    a.ystrips = sh.ystrips;
+    a.Rz = sh.Rz;
+    a.t = t;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.th = th;
+    a.obs = obs;
+    a.zero_slot = zero_slot;
+    a.xcd_remap = ising_host::xcd_remap() ? 1u : 0u;
+    const uint32_t threads = sh.W * 64u;
+    const size_t lds = (size_t)sh.W * 4096u + 2u * threads * sizeof(uint2);
+    const dim3 grid(sh.ystrips * (uint32_t)(L / sh.Rz)), block(threads);
+    const bool halo = (int64_t)sh.Y < L;
+#define ISING_LAUNCH3(QQ, OO, HH) hipLaunchKernelGGL((ising::k_sweep3<QQ, OO, HH>), grid, block, lds, stream, a)
+    if (q == 1) {
+        if (halo) { if (obs) ISING_LAUNCH3(1, true, true); else ISING_LAUNCH3(1, false, true); }
+        else { if (obs) ISING_LAUNCH3(1, true, false); else ISING_LAUNCH3(1, false, false); }
+    } else {
+        if (halo) { if (obs) ISING_LAUNCH3(0, true, true); else ISING_LAUNCH3(0, false, true); }
+        else { if (obs) ISING_LAUNCH3(0, true, false); else ISING_LAUNCH3(0, false, false); }
+    }
+#undef ISING_LAUNCH3
+    return ising_host::check_launch("k_sweep3");
+}
+
+}  // namespace
+
+extern "C" {
+
+int ising3_thresholds(double beta, uint64_t out[3]) {
+    if (!out || !ising_host::valid_beta(beta)) return ISING_EINVAL;
+    host_thresholds3(beta, out);
+    return ISING_OK;
+}
+
+int ising3_half_sweep(int8_t* spins, int64_t L, double beta, uint64_t seed, uint64_t t, int q, void* stream) {
+    if (!spins || !valid_L3(L) || !ising_host::aligned16(spins) || !ising_host::valid_beta(beta) ||
+        (q != 0 && q != 1) || t >= (uint64_t(1) << 32))
+        return ISING_EINVAL;
+    return launch_half_sweep3(spins, L, make_thresholds3(beta), seed, (uint32_t)t, q, nullptr, nullptr,
+                              (hipStream_t)stream);
+}
+
+int ising3_sweep(int8_t* spins, int64_t L, double beta, int64_t n_sweeps, uint64_t seed, uint64_t sweep_offset,
+                 int64_t* trace_ME, void* stream) {
+    if (!spins || !valid_L3(L) || !ising_host::aligned16(spins) || !ising_host::valid_beta(beta) || n_sweeps < 0 ||
+        sweep_offset > (uint64_t(1) << 32) || (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset)
+        return ISING_EINVAL;
+    const ising::Thresholds3 th = make_thresholds3(beta);
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t i = 0; i < n_sweeps; ++i) {
+        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
+        int64_t* slot = trace_ME ? trace_ME + 2 * i : nullptr;
+        int rc = launch_half_sweep3(spins, L, th, seed, t, 1, nullptr, slot, s);  // white (zeroes the slot)
+        if (rc) return rc;
+        rc = launch_half_sweep3(spins, L, th, seed, t, 0, slot, nullptr, s);      // black (+ M, E)
+        if (rc) return rc;
+    }
+    return ISING_OK;
+}
+
+int ising3_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* stream) {
+    if (!spins || !out_ME || !valid_L3(L) || !ising_host::aligned16(spins)) return ISING_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ising_host::zero_trace(out_ME, 2, s);
+    if (rc) return rc;
+    const uint32_t G = (uint32_t)(L / 64);
+    const uint64_t n_lanes = (uint64_t)L * (uint64_t)L * G;
+    hipLaunchKernelGGL(ising::k_observables3, dim3((unsigned)((n_lanes + 255) / 256)), dim3(256), 0, s, spins,
+                       (uint32_t)L, G, n_lanes, out_ME);
+    return ising_host::check_launch("k_observables3");
+}
+
+}  // extern "C"

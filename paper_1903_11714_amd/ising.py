@@ -63,6 +63,14 @@ _SIGNATURES = {
                           ctypes.c_int),
     "ising_sweep_fused_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising3_init": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p], ctypes.c_int),
+    "ising3_fill": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "ising3_sweep": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64,
+                      ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising3_half_sweep": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                           ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "ising3_observables": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising3_thresholds": ([ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
     "ising_moments": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
                       ctypes.c_int),
     "ising_batch_workspace_bytes": ([ctypes.POINTER(ReplicaT), ctypes.c_int64], ctypes.c_int64),
@@ -231,6 +239,37 @@ def ising_sweep_fused_step(src, dst, L: int, beta: float, fmt, seed: int, t: int
     _check("ising_sweep_fused_step", library().ising_sweep_fused_step(
         _dev_ptr(src, "torch.int8", L * L), _dev_ptr(dst, "torch.int8", L * L), L, float(beta), _fmt(fmt), seed, t,
         _opt_ptr(out_ME, "torch.int64", 2), _stream(stream)))
+
+
+def ising3_init(spins, L: int, seed: int, stream=None) -> None:
+    _check("ising3_init", library().ising3_init(_dev_ptr(spins, "torch.int8", L ** 3), L, seed, _stream(stream)))
+
+
+def ising3_fill(spins, L: int, value: int, stream=None) -> None:
+    _check("ising3_fill", library().ising3_fill(_dev_ptr(spins, "torch.int8", L ** 3), L, value, _stream(stream)))
+
+
+def ising3_sweep(spins, L: int, beta: float, n_sweeps: int, seed: int, sweep_offset: int = 0, trace_ME=None,
+                 stream=None) -> None:
+    _check("ising3_sweep", library().ising3_sweep(
+        _dev_ptr(spins, "torch.int8", L ** 3), L, float(beta), n_sweeps, seed, sweep_offset,
+        _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
+
+
+def ising3_half_sweep(spins, L: int, beta: float, seed: int, t: int, q: int, stream=None) -> None:
+    _check("ising3_half_sweep", library().ising3_half_sweep(
+        _dev_ptr(spins, "torch.int8", L ** 3), L, float(beta), seed, t, q, _stream(stream)))
+
+
+def ising3_observables(spins, L: int, out_ME, stream=None) -> None:
+    _check("ising3_observables", library().ising3_observables(
+        _dev_ptr(spins, "torch.int8", L ** 3), L, _dev_ptr(out_ME, "torch.int64", 2), _stream(stream)))
+
+
+def ising3_thresholds(beta: float) -> tuple[int, int, int]:
+    out = (ctypes.c_uint64 * 3)()
+    _check("ising3_thresholds", library().ising3_thresholds(float(beta), out))
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def ising_sweep_packed_fmt(planes, L: int, beta: float, fmt, n_sweeps: int, seed: int, sweep_offset: int = 0,

@@ -79,6 +79,16 @@ def test_argument_checks_before_any_launch(lib):
     assert lib.ising_unpack(null, 64, fake, null) == EINVAL
     assert lib.ising_sweep_packed(null, 64, 0.4, 1, 1, 0, null, null) == EINVAL
     assert lib.ising_observables_packed(fake, 32, fake, null) == EINVAL
+    # 3-D: L a power of two in [64, 2048]
+    for bad_L in (32, 96, 192, 4096):
+        assert lib.ising3_init(fake, bad_L, 1, null) == EINVAL, bad_L
+        assert lib.ising3_sweep(fake, bad_L, 0.2, 1, 1, 0, null, null) == EINVAL, bad_L
+    assert lib.ising3_fill(fake, 64, 0, null) == EINVAL
+    assert lib.ising3_sweep(fake, 64, float("nan"), 1, 1, 0, null, null) == EINVAL
+    assert lib.ising3_sweep(fake, 64, 0.2, 2, 1, 2**32 - 1, null, null) == EINVAL
+    assert lib.ising3_half_sweep(fake, 64, 0.2, 1, 0, 2, null) == EINVAL
+    assert lib.ising3_half_sweep(ctypes.c_void_p(4097), 64, 0.2, 1, 0, 0, null) == EINVAL
+    assert lib.ising3_observables(fake, 64, null, null) == EINVAL
     # fused sweep: the scratch buffer must be present, aligned and disjoint from the lattice
     other = ctypes.c_void_p(4096 + 64 * 64)
     assert lib.ising_sweep_fused(fake, null, 64, 0.4, 0, 2, 1, 0, null, null) == EINVAL
@@ -94,6 +104,12 @@ def test_argument_checks_before_any_launch(lib):
     assert lib.ising_sweep_fused_step(fake, other, 96, 0.4, 0, 1, 0, null, null) == EINVAL
 
 
+@pytest.mark.parametrize("beta", [0.0, 0.1, 0.2216546, 0.35, 2.0, math.inf])
+def test_library_3d_thresholds_match_oracle(oracle_lib, beta):
+    from paper_1903_11714_amd import ising
+    assert ising.ising3_thresholds(beta) == oracle_lib.thresholds3(beta)
+
+
 def test_zero_sweeps_is_a_no_op(lib):
     # n_sweeps = 0 enqueues nothing, so it succeeds without touching the device.
     fake = ctypes.c_void_p(4096)
@@ -106,7 +122,8 @@ def test_options_round_trip(lib):
     from paper_1903_11714_amd import ising
     for name, good, bad in (("rows_per_lane", [0, 2, 64], [1, 3, 128, -2]), ("xcd_remap", [0, 1], [2]),
                             ("staged", [0, 1], [-1]), ("nt_store", [0, 1], [5]),
-                            ("fused_rows", [0, 2, 16, 256], [1, 6, 512, -4]), ("fused_alternate", [0, 1], [2])):
+                            ("fused_rows", [0, 2, 16, 256], [1, 6, 512, -4]), ("fused_alternate", [0, 1], [2]),
+                            ("planes3", [0, 2, 32, 256], [1, 3, 512])):
         old = ising.ising_get_option(name)
         try:
             for v in good:

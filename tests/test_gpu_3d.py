@@ -1,0 +1,158 @@
+"""GPU parity of the 3-D sweep (L x L x L torus, six neighbours) against the CPU oracle.
+
+Integer work, so the bar is bit-exactness: every spin and every traced (M, E).  Sizes cover
+workgroups that hold whole planes (L = 64, 128: y wraps inside the workgroup), workgroups of a
+few rows that take their outer rows from the neighbouring strip (L = 256, 512, 1024, 2048, with
+4 and 8 waves), every plane count per workgroup, and the limits beta = 0 and zero temperature.
+Lattices above 256^3 are checked on light-cone blocks across the torus seams.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+BETA_C3 = 0.2216546  # simple-cubic critical coupling (Monte Carlo estimate; only a test temperature)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_11714_amd import ising
+    ising.library()
+    return ising
+
+
+def _cube(L, seed, p_down=0.5):
+    rng = np.random.default_rng(seed)
+    return np.where(rng.random((L, L, L)) < p_down, -1, 1).astype(np.int8)
+
+
+def _to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _parity(L):
+    z, y, x = np.indices((L, L, L))
+    return (x + y + z) & 1
+
+
+@pytest.mark.parametrize("L,seed", [(64, 1), (128, 2**40 + 5), (256, 3)])
+def test_init3_matches_oracle(dev, oracle_lib, L, seed):
+    _say("init3", L)
+    s = torch.empty((L, L, L), dtype=torch.int8, device="cuda")
+    dev.ising3_init(s, L, seed)
+    assert np.array_equal(s.cpu().numpy(), oracle_lib.init3(L, seed))
+
+
+@pytest.mark.parametrize("L", [64, 128, 256])
+def test_observables3_match_oracle(dev, oracle_lib, L):
+    _say("observables3", L)
+    out = torch.empty(2, dtype=torch.int64, device="cuda")
+    for host in (_cube(L, L), _cube(L, L + 1, 0.1), np.ones((L, L, L), dtype=np.int8),
+                 np.where(_parity(L) == 0, 1, -1).astype(np.int8)):
+        dev.ising3_observables(_to_dev(host), L, out)
+        assert tuple(out.tolist()) == oracle_lib.observables3(host)
+
+
+@pytest.mark.parametrize("q", [1, 0])
+@pytest.mark.parametrize("L,beta", [(64, BETA_C3), (128, 0.15), (256, 0.3), (256, 0.0), (128, math.inf)])
+def test_half_sweep3_matches_oracle(dev, oracle_lib, L, beta, q):
+    _say("half_sweep3", L, beta, q)
+    host = _cube(L, 7 * L + q)
+    s = _to_dev(host)
+    dev.ising3_half_sweep(s, L, beta, 99, 13, q)
+    oracle_lib.half_sweep3(host, beta, 99, 13, q)
+    assert np.array_equal(s.cpu().numpy(), host)
+
+
+@pytest.mark.parametrize("L,beta,n,seed,offset", [(64, BETA_C3, 10, 1, 0), (128, 0.25, 4, 2**33 + 1, 7),
+                                                  (256, BETA_C3, 2, 5, 2**32 - 2)])
+def test_sweeps3_match_oracle(dev, oracle_lib, L, beta, n, seed, offset):
+    _say("sweep3", L, beta, n)
+    s = torch.empty((L, L, L), dtype=torch.int8, device="cuda")
+    dev.ising3_init(s, L, seed)
+    tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising3_sweep(s, L, beta, n, seed, offset, tr)
+    host = oracle_lib.init3(L, seed)
+    ref = oracle_lib.sweep3(host, beta, n, seed, offset, trace=True)
+    assert np.array_equal(s.cpu().numpy(), host)
+    assert np.array_equal(tr.cpu().numpy(), ref)
+
+
+def test_limits3(dev):
+    L = 128
+    s0 = torch.from_numpy(_cube(L, 9)).cuda()
+    s = s0.clone()
+    dev.ising3_sweep(s, L, 0.0, 1, 4)               # beta = 0: every site flips
+    assert torch.equal(s, -s0)
+    s = _to_dev(np.where(_parity(L) == 0, 1, -1).astype(np.int8))
+    dev.ising3_sweep(s, L, math.inf, 1, 4)          # white sites see six anti-aligned neighbours
+    assert bool((s == 1).all())
+
+
+@pytest.mark.parametrize("L,n", [(512, 4), (1024, 3), (2048, 2)])
+def test_large3_light_cone_blocks(dev, oracle_lib, L, n):
+    seed, beta = 1, BETA_C3
+    _say("large3", L, n)
+    s = torch.empty((L, L, L), dtype=torch.int8, device="cuda")
+    dev.ising3_init(s, L, seed)
+    tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising3_sweep(s, L, beta, n, seed, 0, tr)
+    torch.cuda.synchronize()
+    for (z0, y0, x0, d, h, w) in [(L - 6, L - 5, L - 40, 12, 10, 80), (L // 2 + 3, 17, 100, 8, 9, 70)]:
+        ref = oracle_lib.crop3(L, seed, beta, n, 0, z0, y0, x0, d, h, w)
+        zz = torch.tensor([(z0 + a) % L for a in range(d)], device="cuda")
+        yy = torch.tensor([(y0 + a) % L for a in range(h)], device="cuda")
+        xx = torch.tensor([(x0 + a) % L for a in range(w)], device="cuda")
+        got = s.index_select(0, zz).index_select(1, yy).index_select(2, xx).cpu().numpy()
+        assert np.array_equal(got, ref), (z0, y0, x0)
+    out = torch.empty(2, dtype=torch.int64, device="cuda")
+    dev.ising3_observables(s, L, out)
+    assert out.tolist() == tr[-1].tolist()
+    assert bool(((s == 1) | (s == -1)).all())
+    del s
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("L", [256, 512])
+def test_every_plane_count_gives_identical_lattices(dev, L):
+    _say("planes3", L)
+    base = torch.empty((L, L, L), dtype=torch.int8, device="cuda")
+    dev.ising3_init(base, L, 17)
+    ref = None
+    try:
+        for rz in (0, 2, 4, 8, 16, 32, 64):
+            for remap in (1, 0):
+                dev.ising_set_option("planes3", rz)
+                dev.ising_set_option("xcd_remap", remap)
+                s = base.clone()
+                tr = torch.empty((3, 2), dtype=torch.int64, device="cuda")
+                dev.ising3_sweep(s, L, BETA_C3, 3, 17, 40, tr)
+                if ref is None:
+                    ref = (s, tr)
+                else:
+                    assert torch.equal(s, ref[0]), (rz, remap)
+                    assert torch.equal(tr, ref[1]), (rz, remap)
+    finally:
+        dev.ising_set_option("planes3", 0)
+        dev.ising_set_option("xcd_remap", 1)
+
+
+def test_invalid_3d_arguments_raise(dev):
+    s = torch.empty(96 ** 3, dtype=torch.int8, device="cuda")
+    with pytest.raises(dev.IsingError):
+        dev.ising3_init(s, 96, 1)
+    s = torch.empty(64 ** 3, dtype=torch.int8, device="cuda")
+    with pytest.raises(dev.IsingError):
+        dev.ising3_sweep(s, 64, -0.5, 1, 1)
