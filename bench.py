@@ -34,7 +34,7 @@ BETA_C = 0.5 * math.log1p(math.sqrt(2.0))
 HBM_PEAK_GBS = 8000.0
 METRIC = "spin-flip attempts/ns (L=16384², T_c) + % HBM peak, exact vs bf16 accept"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_11714_amd", "csrc", f) for f in ("ising.hip", "philox.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_11714_amd", "csrc", f) for f in ("ising.hip", "philox.hpp", "rows.hpp")]
 
 
 def kernel_source_hash() -> str:
@@ -75,23 +75,105 @@ def algorithmic_bytes(layout: str, L: int) -> float:
     return 3.0 * L * L / 16.0 if layout == "packed" else 2.0 * L * L
 
 
-def copy_bandwidth(torch, L: int, stream, reps: int = 20) -> float:
-    """GB/s (bytes read + written) of torch's device-to-device copy of an L^2-byte buffer."""
+def copy_bandwidth(torch, L: int, stream, reps: int = 20, in_place: bool = False) -> float:
+    """GB/s (bytes read + written) of a plain pass over an L^2-byte buffer: torch's device-to-device
+    copy into a second buffer, or (in_place) an elementwise negation written back in place."""
     n = min(L, 16384) ** 2
     src = torch.ones(n, dtype=torch.int8, device="cuda")
-    dst = torch.empty_like(src)
+    dst = src if in_place else torch.empty_like(src)
+
+    def one():
+        if in_place:
+            src.neg_()
+        else:
+            dst.copy_(src)
     for _ in range(3):
-        dst.copy_(src)
+        one()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        dst.copy_(src)
+        one()
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     del src, dst
     return 2.0 * n / (ms * 1e-3) / 1e9
+
+
+def calibration_copies(torch, nbytes: int, reps: int) -> None:
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the per-launch
+    HBM traffic read from the same counters for a sweep kernel.  (int8 -> uint8 goes through an
+    elementwise copy kernel that reads and writes nbytes, like a sweep; a same-dtype copy would use
+    the runtime's blit kernel.)"""
+    src = torch.ones(nbytes, dtype=torch.int8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+BETA_C3 = 0.2216546  # simple-cubic critical coupling (Monte Carlo estimate)
+
+
+def bench_3d(ising, torch, args, stream) -> dict:
+    """The cubic lattice: hot start, W warm-up sweeps, K timed sweeps with the (M, E) trace, the
+    roofline of the half-sweep kernel (one read and one write of the L^3-byte lattice per launch)
+    and the oracle on a bounded sample."""
+    L, K, W, seed = args.L3, args.steps, args.warmup, args.seed
+    beta = BETA_C3 if args.beta == BETA_C else args.beta
+    dev = torch.device("cuda:0")
+    lat = torch.empty((L, L, L), dtype=torch.int8, device=dev)
+    ising.ising3_init(lat, L, seed, stream)
+    trace = torch.empty((max(K, W, 1), 2), dtype=torch.int64, device=dev)
+    if W:
+        ising.ising3_sweep(lat, L, beta, W, seed, 0, trace[:W], stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    ising.ising3_sweep(lat, L, beta, K, seed, W, trace[:K], stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    launch_us = gpu_ms * 1e3 / (2 * K)
+    alg = 2.0 * L ** 3
+    achieved = alg / (launch_us * 1e-6) / 1e9
+    cb = copy_bandwidth(torch, 16384, stream, in_place=True)  # the 3-D sweep writes back in place
+    res = {
+        "form": "3d",
+        "metric": f"spin-flip attempts/ns (3-D, L={L}^3, beta={beta:g})",
+        "value": float(L) ** 3 * K / (wall * 1e9),
+        "unit": "attempts/ns",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": wall * 1e3 / K,
+        "higher_is_better": True, "dtype": "int8", "data": "synthetic: Philox hot start from the seed (no dataset)",
+        "config": {"workload": f"single periodic {L}^3 cubic lattice, beta={beta:g}, hot start seed {seed}, plain "
+                               f"exact-threshold checkerboard Metropolis, int8 ({L ** 3 / 2 ** 20:.0f} MiB), one "
+                               "launch per colour, (M,E) traced every sweep", "L": L, "beta": beta},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sweep3 (one colour per launch)",
+                     "avg_launch_us": launch_us, "alg_bytes_per_launch": alg, "copy_GBs": cb,
+                     "copy_kind": "in place", "frac_of_copy": achieved / cb if cb else None},
+        "final_ME": trace[K - 1].tolist() if K else None,
+    }
+    del lat
+    if args.copy_calibration:
+        calibration_copies(torch, 16384 * 16384, args.copy_calibration)
+    if not args.no_cpu_baseline:
+        import oracle
+        Lc = min(L, 256)
+        spins = oracle.init3(Lc, seed)
+        n = 16 * args.cpu_sweeps
+        t0 = time.perf_counter()
+        oracle.sweep3(spins, beta, n, seed, 0)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": Lc ** 3 * n / (dt * 1e9), "unit": "attempts/ns", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"{n} sweeps of a {Lc}^3 lattice from the seed-{seed} hot "
+                                                           f"start ({dt:.1f} s; plain C oracle, OpenMP over rows)"}
+    return res
 
 
 def cpu_baseline(L: int, beta: float, seed: int, sweeps: int):
@@ -208,9 +290,11 @@ def main() -> int:
                          "per colour, in place; packed: 1-bit spins, one launch per colour")
     ap.add_argument("--compare", type=int, default=1,
                     help="with the fused layout, also time the other two layouts on the same workload")
-    ap.add_argument("--form", choices=["plain", "precision", "batch"], default="plain",
+    ap.add_argument("--form", choices=["plain", "precision", "batch", "3d"], default="plain",
                     help="plain: the timed sweep (default); precision: bfloat16/half vs exact chains on "
-                         "the --L lattice; batch: the 255-replica Binder-crossing run in one launch")
+                         "the --L lattice; batch: the 255-replica Binder-crossing run in one launch; "
+                         "3d: the cubic lattice (--L3, default 1024) at the 3-D critical coupling")
+    ap.add_argument("--L3", type=int, default=1024, help="edge of the cubic lattice for --form 3d")
     ap.add_argument("--meas", type=int, default=None, help="measurement sweeps of the precision/batch forms")
     ap.add_argument("--therm", type=int, default=None, help="thermalisation sweeps of the precision/batch forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -233,6 +317,9 @@ def main() -> int:
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
 
+    if args.form == "3d":
+        print(json.dumps(bench_3d(ising, torch, args, stream)), flush=True)
+        return 0
     if args.form != "plain":
         from paper_1903_11714_amd import studies
         if args.form == "precision":
@@ -297,6 +384,7 @@ def main() -> int:
     # as the fused sweep moves its bytes) on the same GPU
     cb = copy_bandwidth(torch, L, stream)
     result["roofline"]["copy_GBs"] = cb
+    result["roofline"]["copy_kind"] = "out of place"
     result["roofline"]["frac_of_copy"] = achieved / cb if cb else None
     if args.compare and args.layout == "fused":
         # the same workload on the other layouts (same chain, bit-identical spins), for reference
@@ -310,17 +398,7 @@ def main() -> int:
                 "hbm_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
             }
     if args.copy_calibration:
-        # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the
-        # per-launch HBM traffic read from the same counters for the sweep kernel.
-        # (int8 -> uint8 goes through an elementwise copy kernel that reads L^2 bytes and writes
-        # L^2 bytes, like the sweep; a same-dtype copy would use the runtime's blit kernel.)
-        src = torch.empty((L, L), dtype=torch.int8, device=dev)
-        ising.ising_fill(src, L, 1, stream)
-        dst = torch.empty((L, L), dtype=torch.uint8, device=dev)
-        for _ in range(args.copy_calibration):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copies(torch, L * L, args.copy_calibration)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(L, beta, seed, args.cpu_sweeps)
