@@ -160,6 +160,24 @@ def bench_3d(ising, torch, args, stream) -> dict:
         "final_ME": trace[K - 1].tolist() if K else None,
     }
     del lat
+    if args.compare:
+        # the same chain on the 1-bit layout (bit-identical spins), for reference
+        planes = torch.empty(L ** 3 // 32, dtype=torch.int32, device=dev)
+        ising.ising3_init_packed(planes, L, seed, stream)
+        kp = max(K // 4, 1)
+        if W:
+            ising.ising3_sweep_packed(planes, L, beta, W, seed, 0, trace[:W], stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        ising.ising3_sweep_packed(planes, L, beta, kp, seed, W, trace[:kp], stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t0
+        res["packed_layout"] = {"value": float(L) ** 3 * kp / (pw * 1e9), "unit": "attempts/ns", "steps": kp,
+                                "kernel": "k_sweep3_packed (one colour per launch)",
+                                "avg_launch_us": ev0.elapsed_time(ev1) * 1e3 / (2 * kp)}
+        del planes
     if args.copy_calibration:
         calibration_copies(torch, 16384 * 16384, args.copy_calibration)
     if not args.no_cpu_baseline:

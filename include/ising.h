@@ -120,6 +120,20 @@ int ising3_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* st
 /* out[0..2] = T_2, T_4, T_6 (host). */
 int ising3_thresholds(double beta, uint64_t out[3]);
 
+/* 1-bit layout of the cubic lattice: the square lattice's packed layout over the L^2 rows
+ * r = z L + y.  planes: device uint32[L^3 / 32]; word (q L^2 + r) (L / 64) + g holds the colour-q
+ * sites of row r with j = x >> 1 in [32 g, 32 g + 32), site i at bit 8 (0, 2, 1, 3)[i & 3] + (i >> 2);
+ * colour q of row (z, y) sits at column parity (q + y + z) mod 2; a set bit is spin -1.  The same
+ * chain as the int8 calls (bit-identical spins and (M, E)). */
+int ising3_pack(const int8_t* spins, int64_t L, uint32_t* planes, void* stream);
+int ising3_unpack(const uint32_t* planes, int64_t L, int8_t* spins, void* stream);
+int ising3_init_packed(uint32_t* planes, int64_t L, uint64_t seed, void* stream);
+int ising3_sweep_packed(uint32_t* planes, int64_t L, double beta, int64_t n_sweeps, uint64_t seed,
+                        uint64_t sweep_offset, int64_t* trace_ME, void* stream);
+int ising3_half_sweep_packed(uint32_t* planes, int64_t L, double beta, uint64_t seed, uint64_t t, int q,
+                             void* stream);
+int ising3_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME, void* stream);
+
 /* ---- 1-bit packed layout -----------------------------------------------------------------
  * planes: device uint32[L * L / 32], two colour planes of L rows x (L / 64) words each:
  * word (q * L + r) * (L / 64) + g holds the colour-q sites of row r with j = c >> 1 in
@@ -217,8 +231,9 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
  *   "fused_rows"     rows per workgroup strip of ising_sweep_fused: 0 = automatic, else a power
  *                    of two in [2, 256] (ignored for lattices it does not divide).
  *   "fused_alternate" 1 = odd strips of ising_sweep_fused walk upwards (default), 0 = all down.
- *   "planes3"        planes each workgroup of ising3_sweep walks: 0 = automatic, else a power of
- *                    two in [2, 256] (ignored for lattices it does not divide). */
+ *   "planes3"        planes each workgroup of ising3_sweep (each lane of ising3_sweep_packed)
+ *                    walks: 0 = automatic, else a power of two in [2, 256] (ignored for lattices it
+ *                    does not divide). */
 int ising_set_option(const char* name, int64_t value);
 int ising_get_option(const char* name, int64_t* value);
 

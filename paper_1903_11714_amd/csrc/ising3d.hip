@@ -245,6 +245,148 @@ __global__ __launch_bounds__(256) void k_observables3(const int8_t* spins, uint3
     block_accumulate(out, anti, neg, active ? 1u : 0u, 64u, 3u);
 }
 
+// ---- 1-bit layout in 3-D: the square lattice's packed layout over the L^2 rows r = z L + y.
+// Plane q holds, for every row r and group g, the word of the 32 colour-q sites of the group
+// (bit p(i) for site i, set = spin -1); word index (q L^2 + r) G + g.  Colour q of row (z, y) sits
+// at column parity (q + y + z) mod 2.
+__device__ __forceinline__ uint32_t row_parity3(uint32_t r, uint32_t L) { return ((r / L) + r) & 1u; }
+
+__global__ __launch_bounds__(256) void k_pack3(const int8_t* spins, uint32_t* planes, uint32_t L, uint32_t G,
+                                               uint64_t n_lanes) {
+    const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n_lanes) return;
+    const uint32_t g = (uint32_t)(id % G), r = (uint32_t)(id / G);
+    Row row;
+    load_row(row, spins + (size_t)r * L + (size_t)g * 64u);
+    const uint32_t even = site_bits<0>(row), odd = site_bits<1>(row), par = row_parity3(r, L);
+    const size_t rows = (size_t)L * L;
+    planes[(size_t)r * G + g] = par ? odd : even;           // q = 0 at column parity par
+    planes[(rows + r) * G + g] = par ? even : odd;          // q = 1
+}
+
+__global__ __launch_bounds__(256) void k_unpack3(const uint32_t* planes, int8_t* spins, uint32_t L, uint32_t G,
+                                                 uint64_t n_lanes) {
+    const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n_lanes) return;
+    const uint32_t g = (uint32_t)(id % G), r = (uint32_t)(id / G);
+    const size_t rows = (size_t)L * L;
+    const uint32_t q0 = planes[(size_t)r * G + g], q1 = planes[(rows + r) * G + g];
+    const uint32_t par = row_parity3(r, L);
+    RowBits b;
+    b.e = par ? q1 : q0;
+    b.o = par ? q0 : q1;
+    Row row;
+    bits_to_row(row, b);
+    store_row(spins + (size_t)r * L + (size_t)g * 64u, row, false);
+}
+
+// packed hot start: the int8 hot start's bits of one group (row r = z L + y), split by colour
+__global__ __launch_bounds__(256) void k_init_packed3(uint32_t* planes, uint32_t L, uint32_t G, uint64_t n_lanes,
+                                                      uint32_t key0, uint32_t key1) {
+    const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n_lanes) return;
+    const uint32_t g = (uint32_t)(id % G), r = (uint32_t)(id / G);
+    const Words4 w = philox4x32_10(g >> 1, r, 0u, 0x80000000u, key0, key1);
+    const uint32_t lo = (g & 1u) ? w.w2 : w.w0, hi = (g & 1u) ? w.w3 : w.w1;  // columns 0-31, 32-63
+    // bit c of (lo, hi) set = spin -1 at column c; gather the even and the odd columns in site order
+    Row row;
+#pragma unroll
+    for (int d = 0; d < 16; ++d) {
+        const uint32_t src = d < 8 ? lo : hi;
+        const uint32_t nib = (src >> (4 * (d & 7))) & 15u;
+        row.d[d] = ((nib & 1u) ? 0xFFu : 0x01u) | ((nib & 2u) ? 0xFF00u : 0x0100u) |
+                   ((nib & 4u) ? 0xFF0000u : 0x010000u) | ((nib & 8u) ? 0xFF000000u : 0x01000000u);
+    }
+    const uint32_t even = site_bits<0>(row), odd = site_bits<1>(row), par = row_parity3(r, L);
+    const size_t rows = (size_t)L * L;
+    planes[(size_t)r * G + g] = par ? odd : even;
+    planes[(rows + r) * G + g] = par ? even : odd;
+}
+
+struct Packed3Args {
+    uint32_t* planes;
+    uint32_t L, G, Rz;   // Rz planes per lane (even, divides L)
+    uint64_t n_lanes;    // L * G * (L / Rz): lane = ((zs * L + y) * G + g)
+    uint32_t t, key0, key1;
+    Thresholds3 th;
+    int64_t* obs;
+    int64_t* zero_slot;
+    uint32_t xcd_remap;
+};
+
+// Half-sweep of colour Q on the packed layout: a lane owns group g of row y and walks Rz planes in
+// z.  The six neighbours of its 32 colour-Q sites are the other plane's words of rows (z, y +- 1),
+// (z +- 1, y) in the same group, of row (z, y) itself, and that word shifted by one site with the
+// edge bit from the adjacent group.  Consecutive lanes take consecutive groups and rows of a plane,
+// so every load of a wave is one contiguous run of words.
+template <int Q, bool OBS>
+__global__ __launch_bounds__(256) void k_sweep3_packed(Packed3Args a) {
+    const uint64_t id = (uint64_t)logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * blockDim.x + threadIdx.x;
+    if (a.zero_slot && blockIdx.x == 0 && threadIdx.x == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
+    const bool active = id < a.n_lanes;
+    Counts cnt{0u, 0u};
+    if (active) {
+        const uint32_t L = a.L, G = a.G, Rz = a.Rz;
+        const uint32_t g = (uint32_t)(id % G);
+        const uint64_t zy = id / G;
+        const uint32_t y = (uint32_t)(zy % L), z0 = (uint32_t)(zy / L) * Rz;
+        const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
+        const uint32_t ym = y == 0 ? L - 1 : y - 1, yp = y + 1 == L ? 0 : y + 1;
+        const size_t rows = (size_t)L * L;
+        uint32_t* const pq = a.planes + (size_t)Q * rows * G;
+        const uint32_t* const po = a.planes + (size_t)(1 - Q) * rows * G;
+        auto word = [&](const uint32_t* p, uint32_t z, uint32_t yy, uint32_t gg) {
+            return p[((size_t)z * L + yy) * G + gg];
+        };
+        uint32_t zprev = word(po, z0 == 0 ? L - 1 : z0 - 1, y, g);
+        uint32_t zcur = word(po, z0, y, g);
+#pragma unroll 1
+        for (uint32_t k = 0; k < Rz; ++k) {
+            const uint32_t z = z0 + k, zn = z + 1 == L ? 0 : z + 1;
+            const uint32_t zpn = word(po, zn, y, g);
+            const uint32_t sites = word(pq, z, y, g);
+            const uint32_t up = word(po, z, ym, g), dn = word(po, z, yp, g);
+            const bool O = ((Q + y + z) & 1u) != 0;  // column parity of the colour-Q sites of row (z, y)
+            const uint32_t edge = word(po, z, y, O ? gr : gl);
+            const uint32_t hs = O ? shift_next(zcur, edge & 1u) : shift_prev(zcur, edge >> 31);
+            const uint32_t nb[6] = {up, dn, zprev, zpn, zcur, hs};
+            const uint32_t F = decide3<OBS>(sites, nb, zcur, a.th, g, z * L + y, a.t, (uint32_t)Q, a.key0, a.key1, cnt);
+            pq[((size_t)z * L + y) * G + g] = sites ^ F;
+            zprev = zcur;
+            zcur = zpn;
+        }
+    }
+    if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, active ? 1u : 0u, 64u * a.Rz, 3u);
+}
+
+// (M, E) of a packed cubic lattice: every bond has one black end, so the black sites' anti-aligned
+// neighbour counts cover all 3 L^3 bonds once.
+__global__ __launch_bounds__(256) void k_observables3_packed(const uint32_t* planes, uint32_t L, uint32_t G,
+                                                             uint64_t n_lanes, int64_t* out) {
+    const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = id < n_lanes;
+    uint32_t anti = 0, neg = 0;
+    if (active) {
+        const uint32_t g = (uint32_t)(id % G);
+        const uint32_t r = (uint32_t)(id / G), z = r / L, y = r % L;
+        const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
+        const size_t rows = (size_t)L * L;
+        const uint32_t* p0 = planes;
+        const uint32_t* p1 = planes + rows * G;
+        auto w1 = [&](uint32_t zz, uint32_t yy, uint32_t gg) { return p1[((size_t)zz * L + yy) * G + gg]; };
+        const uint32_t b = p0[(size_t)r * G + g], w = w1(z, y, g);
+        const bool O = ((y + z) & 1u) != 0;  // column parity of the black sites of row (z, y)
+        const uint32_t hs = O ? shift_next(w, w1(z, y, gr) & 1u) : shift_prev(w, w1(z, y, gl) >> 31);
+        anti = __builtin_popcount(b ^ w) + __builtin_popcount(b ^ hs) +
+               __builtin_popcount(b ^ w1(z, y == 0 ? L - 1 : y - 1, g)) +
+               __builtin_popcount(b ^ w1(z, y + 1 == L ? 0 : y + 1, g)) +
+               __builtin_popcount(b ^ w1(z == 0 ? L - 1 : z - 1, y, g)) +
+               __builtin_popcount(b ^ w1(z + 1 == L ? 0 : z + 1, y, g));
+        neg = __builtin_popcount(b) + __builtin_popcount(w);
+    }
+    block_accumulate(out, anti, neg, active ? 1u : 0u, 64u, 3u);
+}
+
 }  // namespace ising
 
 // ==========================================================================================
@@ -332,9 +474,108 @@ int launch_half_sweep3(int8_t* spins, int64_t L, const ising::Thresholds3& th, u
     return ising_host::check_launch("k_sweep3");
 }
 
+// planes per lane of the packed 3-D sweep: the tallest even divisor of L up to 32 that leaves
+// >= 4096 waves (option "planes3" applies here too)
+uint32_t packed_planes3(int64_t L) {
+    const int64_t forced = ising_host::option("planes3");
+    if (forced > 0 && L % forced == 0) return (uint32_t)forced;
+    const uint64_t lanes_per_plane = (uint64_t)L * (uint64_t)(L / 64);
+    uint32_t Rz = 32;
+    while (Rz > 2 && lanes_per_plane * (uint64_t)(L / Rz) < 4096u * 64u) Rz >>= 1;
+    return Rz;
+}
+
+int launch_half_sweep3_packed(uint32_t* planes, int64_t L, const ising::Thresholds3& th, uint64_t seed, uint32_t t,
+                              int q, int64_t* obs, int64_t* zero_slot, hipStream_t stream) {
+    ising::Packed3Args a;
+    a.planes = planes;
+    a.L = (uint32_t)L;
+    a.G = (uint32_t)(L / 64);
+    a.Rz = packed_planes3(L);
+    a.n_lanes = (uint64_t)L * a.G * (uint64_t)(L / a.Rz);
+    a.t = t;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.th = th;
+    a.obs = obs;
+    a.zero_slot = zero_slot;
+    a.xcd_remap = ising_host::xcd_remap() ? 1u : 0u;
+    const dim3 grid((unsigned)((a.n_lanes + 255) / 256)), block(256);
+#define ISING_LAUNCH3P(QQ, OO) hipLaunchKernelGGL((ising::k_sweep3_packed<QQ, OO>), grid, block, 0, stream, a)
+    if (q == 1) { if (obs) ISING_LAUNCH3P(1, true); else ISING_LAUNCH3P(1, false); }
+    else { if (obs) ISING_LAUNCH3P(0, true); else ISING_LAUNCH3P(0, false); }
+#undef ISING_LAUNCH3P
+    return ising_host::check_launch("k_sweep3_packed");
+}
+
+uint64_t lanes3(int64_t L) { return (uint64_t)L * (uint64_t)L * (uint64_t)(L / 64); }
+
+dim3 grid3(uint64_t n_lanes) { return dim3((unsigned)((n_lanes + 255) / 256)); }
+
 }  // namespace
 
 extern "C" {
+
+int ising3_pack(const int8_t* spins, int64_t L, uint32_t* planes, void* stream) {
+    if (!spins || !planes || !valid_L3(L) || !ising_host::aligned16(spins)) return ISING_EINVAL;
+    const uint64_t n = lanes3(L);
+    hipLaunchKernelGGL(ising::k_pack3, grid3(n), dim3(256), 0, (hipStream_t)stream, spins, planes, (uint32_t)L,
+                       (uint32_t)(L / 64), n);
+    return ising_host::check_launch("k_pack3");
+}
+
+int ising3_unpack(const uint32_t* planes, int64_t L, int8_t* spins, void* stream) {
+    if (!spins || !planes || !valid_L3(L) || !ising_host::aligned16(spins)) return ISING_EINVAL;
+    const uint64_t n = lanes3(L);
+    hipLaunchKernelGGL(ising::k_unpack3, grid3(n), dim3(256), 0, (hipStream_t)stream, planes, spins, (uint32_t)L,
+                       (uint32_t)(L / 64), n);
+    return ising_host::check_launch("k_unpack3");
+}
+
+int ising3_init_packed(uint32_t* planes, int64_t L, uint64_t seed, void* stream) {
+    if (!planes || !valid_L3(L)) return ISING_EINVAL;
+    const uint64_t n = lanes3(L);
+    hipLaunchKernelGGL(ising::k_init_packed3, grid3(n), dim3(256), 0, (hipStream_t)stream, planes, (uint32_t)L,
+                       (uint32_t)(L / 64), n, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return ising_host::check_launch("k_init_packed3");
+}
+
+int ising3_half_sweep_packed(uint32_t* planes, int64_t L, double beta, uint64_t seed, uint64_t t, int q,
+                             void* stream) {
+    if (!planes || !valid_L3(L) || !ising_host::valid_beta(beta) || (q != 0 && q != 1) || t >= (uint64_t(1) << 32))
+        return ISING_EINVAL;
+    return launch_half_sweep3_packed(planes, L, make_thresholds3(beta), seed, (uint32_t)t, q, nullptr, nullptr,
+                                     (hipStream_t)stream);
+}
+
+int ising3_sweep_packed(uint32_t* planes, int64_t L, double beta, int64_t n_sweeps, uint64_t seed,
+                        uint64_t sweep_offset, int64_t* trace_ME, void* stream) {
+    if (!planes || !valid_L3(L) || !ising_host::valid_beta(beta) || n_sweeps < 0 ||
+        sweep_offset > (uint64_t(1) << 32) || (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset)
+        return ISING_EINVAL;
+    const ising::Thresholds3 th = make_thresholds3(beta);
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t i = 0; i < n_sweeps; ++i) {
+        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
+        int64_t* slot = trace_ME ? trace_ME + 2 * i : nullptr;
+        int rc = launch_half_sweep3_packed(planes, L, th, seed, t, 1, nullptr, slot, s);
+        if (rc) return rc;
+        rc = launch_half_sweep3_packed(planes, L, th, seed, t, 0, slot, nullptr, s);
+        if (rc) return rc;
+    }
+    return ISING_OK;
+}
+
+int ising3_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME, void* stream) {
+    if (!planes || !out_ME || !valid_L3(L)) return ISING_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ising_host::zero_trace(out_ME, 2, s);
+    if (rc) return rc;
+    const uint64_t n = lanes3(L);
+    hipLaunchKernelGGL(ising::k_observables3_packed, grid3(n), dim3(256), 0, s, planes, (uint32_t)L,
+                       (uint32_t)(L / 64), n, out_ME);
+    return ising_host::check_launch("k_observables3_packed");
+}
 
 int ising3_thresholds(double beta, uint64_t out[3]) {
     if (!out || !ising_host::valid_beta(beta)) return ISING_EINVAL;

@@ -71,6 +71,14 @@ _SIGNATURES = {
                            ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "ising3_observables": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "ising3_thresholds": ([ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "ising3_pack": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising3_unpack": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising3_init_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p], ctypes.c_int),
+    "ising3_sweep_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64,
+                             ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising3_half_sweep_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                                  ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "ising3_observables_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "ising_moments": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
                       ctypes.c_int),
     "ising_batch_workspace_bytes": ([ctypes.POINTER(ReplicaT), ctypes.c_int64], ctypes.c_int64),
@@ -270,6 +278,38 @@ def ising3_thresholds(beta: float) -> tuple[int, int, int]:
     out = (ctypes.c_uint64 * 3)()
     _check("ising3_thresholds", library().ising3_thresholds(float(beta), out))
     return int(out[0]), int(out[1]), int(out[2])
+
+
+def ising3_pack(spins, L: int, planes, stream=None) -> None:
+    _check("ising3_pack", library().ising3_pack(
+        _dev_ptr(spins, "torch.int8", L ** 3), L, _dev_ptr(planes, "torch.int32", L ** 3 // 32), _stream(stream)))
+
+
+def ising3_unpack(planes, L: int, spins, stream=None) -> None:
+    _check("ising3_unpack", library().ising3_unpack(
+        _dev_ptr(planes, "torch.int32", L ** 3 // 32), L, _dev_ptr(spins, "torch.int8", L ** 3), _stream(stream)))
+
+
+def ising3_init_packed(planes, L: int, seed: int, stream=None) -> None:
+    _check("ising3_init_packed", library().ising3_init_packed(
+        _dev_ptr(planes, "torch.int32", L ** 3 // 32), L, seed, _stream(stream)))
+
+
+def ising3_sweep_packed(planes, L: int, beta: float, n_sweeps: int, seed: int, sweep_offset: int = 0,
+                        trace_ME=None, stream=None) -> None:
+    _check("ising3_sweep_packed", library().ising3_sweep_packed(
+        _dev_ptr(planes, "torch.int32", L ** 3 // 32), L, float(beta), n_sweeps, seed, sweep_offset,
+        _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
+
+
+def ising3_half_sweep_packed(planes, L: int, beta: float, seed: int, t: int, q: int, stream=None) -> None:
+    _check("ising3_half_sweep_packed", library().ising3_half_sweep_packed(
+        _dev_ptr(planes, "torch.int32", L ** 3 // 32), L, float(beta), seed, t, q, _stream(stream)))
+
+
+def ising3_observables_packed(planes, L: int, out_ME, stream=None) -> None:
+    _check("ising3_observables_packed", library().ising3_observables_packed(
+        _dev_ptr(planes, "torch.int32", L ** 3 // 32), L, _dev_ptr(out_ME, "torch.int64", 2), _stream(stream)))
 
 
 def ising_sweep_packed_fmt(planes, L: int, beta: float, fmt, n_sweeps: int, seed: int, sweep_offset: int = 0,

@@ -4,7 +4,8 @@ Integer work, so the bar is bit-exactness: every spin and every traced (M, E).  
 workgroups that hold whole planes (L = 64, 128: y wraps inside the workgroup), workgroups of a
 few rows that take their outer rows from the neighbouring strip (L = 256, 512, 1024, 2048, with
 4 and 8 waves), every plane count per workgroup, and the limits beta = 0 and zero temperature.
-Lattices above 256^3 are checked on light-cone blocks across the torus seams.
+Lattices above 256^3 are checked on light-cone blocks across the torus seams.  The 1-bit layout is
+checked against the oracle and, spin for spin, against the int8 layout.
 """
 import math
 import sys
@@ -156,3 +157,71 @@ def test_invalid_3d_arguments_raise(dev):
     s = torch.empty(64 ** 3, dtype=torch.int8, device="cuda")
     with pytest.raises(dev.IsingError):
         dev.ising3_sweep(s, 64, -0.5, 1, 1)
+
+
+# ---- 1-bit layout of the cubic lattice ----------------------------------------------------------
+
+def _planes3(L):
+    return torch.empty(L ** 3 // 32, dtype=torch.int32, device="cuda")
+
+
+def _unpacked3(dev, p, L):
+    s = torch.empty((L, L, L), dtype=torch.int8, device="cuda")
+    dev.ising3_unpack(p, L, s)
+    return s
+
+
+@pytest.mark.parametrize("L", [64, 128, 256])
+def test_pack3_round_trip_and_packed_hot_start(dev, oracle_lib, L):
+    _say("pack3", L)
+    host = _cube(L, 3 * L)
+    p = _planes3(L)
+    dev.ising3_pack(_to_dev(host), L, p)
+    assert np.array_equal(_unpacked3(dev, p, L).cpu().numpy(), host)
+    dev.ising3_init_packed(p, L, 77)
+    assert np.array_equal(_unpacked3(dev, p, L).cpu().numpy(), oracle_lib.init3(L, 77))
+    out = torch.empty(2, dtype=torch.int64, device="cuda")
+    dev.ising3_observables_packed(p, L, out)
+    assert tuple(out.tolist()) == oracle_lib.observables3(oracle_lib.init3(L, 77))
+
+
+@pytest.mark.parametrize("q", [1, 0])
+@pytest.mark.parametrize("L,beta", [(64, BETA_C3), (128, 0.15), (256, 0.0), (128, math.inf)])
+def test_half_sweep3_packed_matches_oracle(dev, oracle_lib, L, beta, q):
+    _say("half_sweep3_packed", L, beta, q)
+    host = _cube(L, 11 * L + q)
+    p = _planes3(L)
+    dev.ising3_pack(_to_dev(host), L, p)
+    dev.ising3_half_sweep_packed(p, L, beta, 99, 13, q)
+    oracle_lib.half_sweep3(host, beta, 99, 13, q)
+    assert np.array_equal(_unpacked3(dev, p, L).cpu().numpy(), host)
+
+
+@pytest.mark.parametrize("L,beta,n,seed,offset", [(64, BETA_C3, 10, 1, 0), (128, 0.25, 4, 2**33 + 1, 7)])
+def test_sweeps3_packed_match_oracle(dev, oracle_lib, L, beta, n, seed, offset):
+    _say("sweep3_packed", L, n)
+    p = _planes3(L)
+    dev.ising3_init_packed(p, L, seed)
+    tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising3_sweep_packed(p, L, beta, n, seed, offset, tr)
+    host = oracle_lib.init3(L, seed)
+    ref = oracle_lib.sweep3(host, beta, n, seed, offset, trace=True)
+    assert np.array_equal(_unpacked3(dev, p, L).cpu().numpy(), host)
+    assert np.array_equal(tr.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("L,n", [(256, 3), (1024, 2)])
+def test_packed3_equals_int8(dev, L, n):
+    _say("packed3 == int8", L, n)
+    s = torch.empty((L, L, L), dtype=torch.int8, device="cuda")
+    dev.ising3_init(s, L, 8)
+    p = _planes3(L)
+    dev.ising3_init_packed(p, L, 8)
+    t8 = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    tp = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising3_sweep(s, L, BETA_C3, n, 8, 3, t8)
+    dev.ising3_sweep_packed(p, L, BETA_C3, n, 8, 3, tp)
+    assert torch.equal(t8, tp)
+    assert torch.equal(_unpacked3(dev, p, L), s)
+    del s, p
+    torch.cuda.empty_cache()
