@@ -170,3 +170,63 @@ def test_fused_rejects_overlap(dev):
         dev.ising_sweep_fused(s, s, 128, BETA_C, "exact", 2, 1)
     with pytest.raises(dev.IsingError):
         dev.ising_sweep_fused_step(s, s, 128, BETA_C, "exact", 1, 0)
+
+
+def test_fused_steps_replay_in_a_hip_graph(dev):
+    # A caller that keeps its own pair of buffers can capture alternating steps once and replay
+    # them: every launch of the path is a kernel (the trace slot is cleared by a kernel, not a
+    # memset).  Each replay, with eager work in between, must equal the eager sequence.
+    L, n, seed = 4096, 4, 9
+    a = torch.empty((L, L), dtype=torch.int8, device="cuda")
+    dev.ising_init(a, L, seed)
+    start = a.clone()
+    b = torch.empty_like(a)
+    me = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    # eager reference: sweeps t = 0 .. n - 1 from the same start
+    ref = start.clone()
+    ref_tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising_sweep(ref, L, BETA_C, n, seed, 0, ref_tr)
+    ref_state = start.clone()
+    dev.ising_sweep(ref_state, L, BETA_C, n, seed, 0)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    a.copy_(start)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        src, dst = a, b
+        for i in range(n):
+            dev.ising_sweep_fused_step(src, dst, L, BETA_C, "exact", seed, i, me[i], stream=s)
+            src, dst = dst, src
+    # the capture recorded sweeps 0..3; replaying recomputes them from `a`
+    a.copy_(start)
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(a, ref_state), rep
+        assert torch.equal(me, ref_tr[:n]), rep
+        x = a.float().sum()                      # eager work between replays
+        torch.cuda.synchronize()
+        assert int(x.item()) == int(ref_state.float().sum().item())
+        a.copy_(start)
+
+
+def test_two_streams_at_once_match_one_at_a_time(dev):
+    L, n = 4096, 6
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    lat = [torch.empty((L, L), dtype=torch.int8, device="cuda") for _ in range(2)]
+    scr = [torch.empty_like(lat[0]) for _ in range(2)]
+    tr = [torch.empty((n, 2), dtype=torch.int64, device="cuda") for _ in range(2)]
+    for k in range(2):
+        dev.ising_init(lat[k], L, 100 + k)
+    torch.cuda.synchronize()
+    for i in range(0, n, 2):                      # interleaved pairs of fused sweeps on two streams
+        for k, st in enumerate((s1, s2)):
+            dev.ising_sweep_fused(lat[k], scr[k], L, BETA_C, "exact", 2, 100 + k, i, tr[k][i:i + 2], stream=st)
+    torch.cuda.synchronize()
+    for k in range(2):
+        ref = torch.empty_like(lat[k])
+        dev.ising_init(ref, L, 100 + k)
+        rt = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+        dev.ising_sweep(ref, L, BETA_C, n, 100 + k, 0, rt)
+        assert torch.equal(lat[k], ref), k
+        assert torch.equal(tr[k], rt), k
