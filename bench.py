@@ -11,6 +11,10 @@ Layouts: "fused" (default) sweeps the int8 lattice with both colours in one pass
 between the lattice and a second L^2-byte buffer; "int8" runs one launch per colour in place;
 "packed" is the 1-bit layout.  All three run the same chain (bit-identical spins).
 
+With --compare (default) the line also carries the same fused workload with the acceptance test
+in bfloat16 and in half ("bf16_accept", "fp16_accept": u < p with both rounded to the format, a
+different chain) and the int8 and packed layouts on the exact chain.
+
 Prints one JSON line with the throughput (spin-flip attempts per ns), the roofline of the
 dominant kernel (algorithmic bytes = one read and one write of the L^2-byte lattice per launch,
 over the average launch time of the timed region, from HIP events on the launch stream) and the
@@ -213,10 +217,11 @@ def cpu_baseline(L: int, beta: float, seed: int, sweeps: int):
     }
 
 
-def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream):
+def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream, fmt="exact"):
     """Hot start, W warm-up sweeps, K timed sweeps with the (M, E) trace, then `kernel_sweeps`
     sweeps with every launch bracketed by events (one launch per sweep for "fused", per colour
-    otherwise)."""
+    otherwise).  `fmt` is the acceptance format of the fused layout (exact, bf16 or fp16)."""
+    assert fmt == "exact" or layout == "fused"
     dev = torch.device("cuda:0")
     if layout in ("int8", "fused"):
         # the fused sweep's two buffers come from one allocation (their relative placement in
@@ -228,7 +233,7 @@ def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream)
             scratch = buf[L * L:].view(L, L)
 
             def sweep(lat, L, beta, n, seed, off, trace, st):
-                ising.ising_sweep_fused(lat, scratch, L, beta, "exact", n, seed, off, trace, st)
+                ising.ising_sweep_fused(lat, scratch, L, beta, fmt, n, seed, off, trace, st)
         else:
             sweep = ising.ising_sweep
     else:
@@ -240,7 +245,7 @@ def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream)
     if W:
         sweep(lat, L, beta, W, seed, 0, warm_trace[:W], stream)
     torch.cuda.synchronize()
-    print(f"bench: {layout} L={L} warmup={W} done", file=sys.stderr, flush=True)
+    print(f"bench: {layout} ({fmt}) L={L} warmup={W} done", file=sys.stderr, flush=True)
 
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -264,7 +269,7 @@ def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream)
         evs[0].record(stream)
         src, dst = lat, scratch
         for i in range(nk):
-            ising.ising_sweep_fused_step(src, dst, L, beta, "exact", seed, t + i, None, stream)
+            ising.ising_sweep_fused_step(src, dst, L, beta, fmt, seed, t + i, None, stream)
             evs[i + 1].record(stream)
             src, dst = dst, src
     else:
@@ -405,6 +410,16 @@ def main() -> int:
     result["roofline"]["copy_kind"] = "out of place"
     result["roofline"]["frac_of_copy"] = achieved / cb if cb else None
     if args.compare and args.layout == "fused":
+        # the same workload with the acceptance test in bfloat16 and in half (the chain differs:
+        # u < p with both rounded to the format), on the same fused kernel
+        for fmt in ("bf16", "fp16"):
+            low = run_layout(ising, torch, "fused", L, beta, seed, K, W, args.kernel_sweeps, stream, fmt=fmt)
+            gbs = alg_bytes / (low["avg_launch_ms"] * 1e-3) / 1e9
+            result[f"{fmt}_accept"] = {
+                "value": low["value"], "unit": "attempts/ns", "steps": K, "kernel": KERNEL_NAME["fused"],
+                "avg_launch_us": low["avg_launch_ms"] * 1e3, "hbm_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                "vs_exact": low["value"] / main["value"], "final_ME": low["final_ME"],
+            }
         # the same workload on the other layouts (same chain, bit-identical spins), for reference
         ks = max(K // 4, 1)
         for lay in ("int8", "packed"):
