@@ -166,18 +166,23 @@ int ising_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME,
 
 /* ---- batched replicas ----------------------------------------------------------------------
  * Many small independent lattices (L = 32, or L % 64 == 0 up to 512), each with its own beta and
- * seed, run in ONE persistent launch (captured in a hipGraph and replayed on `stream`): one
- * workgroup per replica keeps its lattice in LDS for every sweep of the run.  Every replica is
- * the single-lattice chain of its (L, beta, seed): identical spins and (M, E) to
- * ising_sweep_packed on that lattice alone (the paper's per-(L, T) Markov chains, Sec. 4.1). */
+ * seed, run in ONE persistent launch (captured in a hipGraph and replayed on `stream`).  Each
+ * replica is held in LDS for every sweep of the run, by one workgroup or, when it is split, by 2,
+ * 4 or 8 slabs of at least 16 rows (so large replicas do not hold the whole run on one compute
+ * unit).  A slab also holds and updates d rows beyond either edge, so it trades its outer d rows
+ * with its neighbours through the workspace only every d colour updates (d = 1, 2 or 4).  With
+ * a split, slabs and whole replicas are packed into one or two work lists per compute unit,
+ * balanced by size (largest first onto the least loaded list), one workgroup per list.  Every replica is the single-lattice chain of its (L, beta, seed):
+ * identical spins and (M, E) to ising_sweep_packed on that lattice alone, for every split (the
+ * paper's per-(L, T) Markov chains, Sec. 4.1). */
 typedef struct {
     int64_t L;       /* linear size: 32, or a multiple of 64 up to 512 */
     double beta;     /* finite >= 0 or +inf */
     uint64_t seed;   /* Philox key of this replica */
 } ising_replica_t;
 
-/* Device workspace size for the batch (replica table + every replica's packed lattice), or
- * ISING_EINVAL.  replicas: host array of n entries. */
+/* Device workspace size for the batch (replica table, every replica's packed lattice, the slab
+ * table and the row-exchange areas), or ISING_EINVAL.  replicas: host array of n entries. */
 int64_t ising_batch_workspace_bytes(const ising_replica_t* replicas, int64_t n);
 
 /* n_therm + n_meas sweeps of every replica (sweep indices sweep_offset ..), all in one launch.
@@ -192,12 +197,25 @@ int64_t ising_batch_workspace_bytes(const ising_replica_t* replicas, int64_t n);
  *              or NULL.
  *   moments    device double[n * 5]: per replica <|m|>, <m^2>, <m^4>, <e>, <e^2> over the
  *              measurement sweeps, summed in FP64 in sweep order, or NULL.
- * The workgroup size (256, 512 or 1024 threads) is picked once per set of replica sizes by timing
- * the candidates on the table itself (option "batch_threads" fixes it); every candidate gives
- * identical results.  The first call for a new set of sizes synchronises for that timing. */
+ * n_therm + n_meas < 2^31.
+ * The schedule -- workgroup size (256, 512 or 1024 threads), split (no split, or slabs of at most
+ * 65536, 32768 or 16384 sites), d and lists per compute unit -- is picked once per set of replica
+ * sizes by timing the candidates on the table itself (options "batch_threads",
+ * "batch_slab_sites", "batch_depth" and "batch_lists_per_cu" fix them);
+ * every schedule gives identical results.  The first call for a new set of sizes synchronises
+ * for that timing.  A split schedule is used only if all its workgroups fit on the GPU at once
+ * (slabs wait for their neighbours' rows); its waits are bounded, and a run in which one gave up
+ * (possible only if other work keeps its workgroups off the GPU, e.g. two batch runs at once on
+ * different streams) writes NaN moments for the replicas concerned. */
 int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm, int64_t n_meas,
                     uint64_t sweep_offset, int fmt, int start, void* workspace, int64_t workspace_bytes,
                     int64_t* trace_ME, double* moments, void* stream);
+
+/* The schedule ising_batch_run picked for this set of replica sizes: out[0] = threads per
+ * workgroup, out[1] = split target in sites per slab (-1: no split), out[2] = colour updates
+ * between exchanges of a split replica, out[3] = work lists per compute unit of a split
+ * schedule.  Host pointers; returns ISING_EINVAL if no run has tuned this set of sizes yet. */
+int ising_batch_schedule(const ising_replica_t* replicas, int64_t n, int64_t out[4]);
 
 /* Replica j's lattice from the batch workspace as int8 rows (device int8[L_j * L_j]). */
 int ising_batch_unpack(const void* workspace, int64_t n, int64_t j, int8_t* spins, void* stream);
@@ -228,6 +246,13 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
  *   "staged"         1 = coalesced row loads and stores regrouped through LDS when L is a
  *                    multiple of 4096 (default), 0 = every lane reads its own 64 bytes.
  *   "batch_threads"  workgroup size of ising_batch_run: 0 = autotune (default), 256, 512, 1024.
+ *   "batch_slab_sites"  ising_batch_run: split replicas into row slabs of at most this many sites
+ *                    (a power of two from 1024 to 262144; slabs keep at least 16 rows, at most 8
+ *                    per replica), -1 = never split, 0 = autotune (default).
+ *   "batch_depth"    ising_batch_run: colour updates between row exchanges of a split replica
+ *                    (1, 2 or 4), 0 = autotune (default).
+ *   "batch_lists_per_cu"  ising_batch_run: work lists per compute unit of a split schedule (1 or
+ *                    2), 0 = autotune (default).
  *   "fused_rows"     rows per workgroup strip of ising_sweep_fused: 0 = automatic, else a power
  *                    of two in [2, 256] (ignored for lattices it does not divide).
  *   "fused_alternate" 1 = odd strips of ising_sweep_fused walk upwards (default), 0 = all down.

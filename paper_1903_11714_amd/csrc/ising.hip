@@ -27,6 +27,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -607,7 +608,6 @@ struct BatchReplica {
     uint64_t state_off;  // word offset of this replica's planes in the state buffer
 };
 
-constexpr uint32_t kBatchMaxWords = 2u * 512u * 8u;  // both planes at L = 512: 32 KiB of LDS
 
 // Rows of 16 same-colour sites (L = 32): the word wraps onto itself after site 15, and only
 // sites 0..15 (bits 0-3 of each byte in site order) exist.
@@ -636,30 +636,190 @@ __device__ __forceinline__ void hot_start_words(uint32_t L, uint32_t r, uint32_t
     w1 = (r & 1u) ? even : odd;
 }
 
-// One colour update of a replica held in LDS; every thread owns words tid, tid + blockDim, ...
-template <int Q, bool OBS>
-__device__ __forceinline__ void batch_half_sweep(uint32_t* planes, const BatchReplica& rp, uint32_t t,
-                                                 Counts& cnt) {
-    const uint32_t L = rp.L, W = rp.W, words = L * W;
-    const uint32_t valid = L >= 64 ? 0xFFFFFFFFu : 0x0F0F0F0Fu;
-    uint32_t* pq = planes + Q * words;
-    const uint32_t* po = planes + (1 - Q) * words;
-    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) {
-        const uint32_t r = w / W, g = w - r * W;
-        const uint32_t rm = r == 0 ? L - 1 : r - 1, rp1 = r + 1 == L ? 0 : r + 1;
-        const uint32_t a = pq[w], side = po[w];
-        const uint32_t up = po[rm * W + g], down = po[rp1 * W + g];
-        const uint32_t o = (r + Q) & 1u;   // column parity of this row's colour-Q sites
-        uint32_t hs;
-        if (L >= 64) {
-            const uint32_t gl = g == 0 ? W - 1 : g - 1, gr = g + 1 == W ? 0 : g + 1;
-            hs = o ? shift_next(side, po[r * W + gr] & 1u) : shift_prev(side, po[r * W + gl] >> 31);
-        } else {
-            hs = o ? shift_next16(side) : shift_prev16(side);
-        }
-        const uint32_t F = decide<Q, OBS>(a, up, down, side, hs, side, rp.th, g, r, t, rp.key0, rp.key1, cnt, valid);
-        pq[w] = a ^ F;
+// One entry of a workgroup's work list: a whole replica (depth 0, its rows wrap inside LDS) or
+// one slab of a split replica, rows [row0, row0 + rows).  A slab also holds `depth` rows beyond
+// either edge (halo rows, local rows 0 .. depth - 1 and depth + rows ..) and updates rows 1 ..
+// rows + 2 depth - 2 at every colour update: each update leaves one more outer row stale on
+// either side, so its own rows stay exact for `depth` updates, after which neighbouring slabs
+// trade their outer `depth` rows through the exchange area.
+struct BatchUnit {
+    uint32_t rep;        // replica index
+    uint32_t slab, slabs;
+    uint32_t row0, rows;
+    uint32_t depth;      // halo rows per side (= colour updates between exchanges); 0 unsplit
+    uint32_t lag;        // measurement sweeps between a sweep and the combination of its counts
+    uint32_t lds;        // word offset of its two colour planes in the workgroup's LDS
+    uint32_t first;      // first wave slot (64 words) of its words in one colour update of the workgroup
+    uint32_t xfirst;     // first flat index of its words in one exchange of the workgroup
+    uint64_t xoff;       // offset (64-bit words) of the replica's exchange area
+};
+
+// A workgroup's work list: units [begin, end) of the unit table.
+struct BatchGroup {
+    uint32_t begin, end;
+    uint32_t words;      // wave slots (64 words each) of one colour update over all its units
+    uint32_t xwords;     // words of one exchange over all its units
+};
+
+constexpr uint32_t kMaxSlabs = 8;
+constexpr uint32_t kMaxDepth = 4;
+constexpr uint32_t kMaxUnits = 32;           // units per workgroup
+constexpr uint32_t kCountSlots = 32;         // ring of per-slab count slots (> 2 x the largest lag)
+constexpr uint32_t kPollLimit = 1u << 20;    // polls of one tagged word before the run gives up
+
+__host__ __device__ constexpr uint32_t unit_words(uint32_t rows, uint32_t depth, uint32_t W) {
+    return (depth ? rows + 2u * depth - 2u : rows) * W;
+}
+__host__ __device__ constexpr uint32_t unit_xwords(uint32_t depth, uint32_t W) { return 2u * depth * 2u * W; }
+__host__ __device__ constexpr uint32_t unit_plane(uint32_t rows, uint32_t depth, uint32_t W) {
+    return (rows + 2u * depth) * W;
+}
+
+// 64-bit words of one replica's exchange area: two alternating slots of every slab's outer rows
+// (2 sides x depth rows x 2 colours), then kCountSlots x slabs x (anti, neg) counts.  Every word
+// is (tag << 32) | value, written and read as one atomic, so a reader that sees the tag it waits
+// for sees its value.
+__host__ __device__ constexpr uint64_t exchange_words(uint32_t W) {
+    return 2ull * kMaxSlabs * 2u * kMaxDepth * 2u * W + (uint64_t)kCountSlots * kMaxSlabs * 2u;
+}
+
+__device__ __forceinline__ uint64_t* edge_word(uint64_t* x, uint32_t W, uint32_t slot, uint32_t slab, uint32_t side,
+                                               uint32_t k, uint32_t c, uint32_t g) {
+    return x + ((((uint64_t)slot * kMaxSlabs + slab) * 2u + side) * kMaxDepth * 2u + k * 2u + c) * W + g;
+}
+
+__device__ __forceinline__ uint64_t* count_word(uint64_t* x, uint32_t W, uint32_t j, uint32_t slab) {
+    return x + 2ull * kMaxSlabs * 2u * kMaxDepth * 2u * W + ((uint64_t)(j % kCountSlots) * kMaxSlabs + slab) * 2u;
+}
+
+__device__ __forceinline__ void put_tagged(uint64_t* p, uint32_t tag, uint32_t v) {
+    __hip_atomic_store(p, ((uint64_t)tag << 32) | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait (bounded) until *p carries `tag`; false when the wait gave up.
+__device__ __forceinline__ bool get_tagged(const uint64_t* p, uint32_t tag, uint32_t& v) {
+    for (uint32_t k = 0; k < kPollLimit; ++k) {
+        const uint64_t x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(x >> 32) == tag) { v = (uint32_t)x; return true; }
+        __builtin_amdgcn_s_sleep(1);
     }
+    return false;
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Colour update of every unit of the workgroup (colour Q, sweep i).  Each unit's words are
+// padded to whole waves ("slots" of 64 words): wave w takes slots w, w + waves, ..., so a wave
+// always works inside one unit, whose parameters it holds in scalar registers.  Counts of owned
+// rows go to cnt[unit] with OBS, one wave sum per unit.
+template <int Q, bool OBS>
+__device__ __forceinline__ void batch_update(uint32_t* lds, const BatchUnit* us, const BatchReplica* rs, uint32_t nu,
+                                             uint32_t slots, uint32_t i, uint32_t (*cnt)[2]) {
+    const uint32_t waves = blockDim.x >> 6, lane = threadIdx.x & 63u;
+    uint32_t u = 0;
+    uint32_t uend = nu > 1 ? us[1].first : slots;
+    Counts c{0u, 0u};
+    auto flush = [&]() {
+        if (OBS) {
+            const uint32_t A = wave_sum(c.anti), Nn = wave_sum(c.neg);
+            if (lane == 0 && (A | Nn)) { atomicAdd(&cnt[u][0], A); atomicAdd(&cnt[u][1], Nn); }
+            c = Counts{0u, 0u};
+        }
+    };
+    for (uint32_t sl = threadIdx.x >> 6; sl < slots; sl += waves) {
+        while (sl >= uend) {
+            flush();
+            ++u;
+            uend = u + 1 < nu ? us[u + 1].first : slots;
+        }
+        const BatchUnit& x = us[u];
+        const BatchReplica& rp = rs[u];
+        const uint32_t W = uni(rp.W), L = uni(rp.L), K = uni(x.depth), rows = uni(x.rows);
+        const uint32_t n = (K ? rows + 2u * K - 2u : rows) * W;
+        const uint32_t local = (sl - uni(x.first)) * 64u + lane;
+        if (local < n) {
+            const uint32_t pw = (rows + 2u * K) * W, base = uni(x.lds);
+            uint32_t* pq = lds + base + Q * pw;
+            const uint32_t* po = lds + base + (1 - Q) * pw;
+            const Thresholds th{uni(rp.th.t2), uni(rp.th.t4), uni(rp.th.full2), uni(rp.th.full4), uni(rp.th.blocks)};
+            const uint32_t t = uni(rp.t0) + i, key0 = uni(rp.key0), key1 = uni(rp.key1);
+            uint32_t lr, lup, ldn, r;
+            bool own;
+            if (K == 0) {
+                lr = local / W;
+                lup = lr == 0 ? rows - 1 : lr - 1;
+                ldn = lr + 1 == rows ? 0 : lr + 1;
+                r = lr;
+                own = true;
+            } else {
+                lr = local / W + 1u;
+                lup = lr - 1;
+                ldn = lr + 1;
+                r = (uni(x.row0) + L - K + lr) % L;
+                own = lr >= K && lr < K + rows;
+            }
+            const uint32_t g = local - (K ? lr - 1u : lr) * W;
+            const uint32_t valid = L >= 64 ? 0xFFFFFFFFu : 0x0F0F0F0Fu;
+            const uint32_t w = lr * W + g;
+            const uint32_t a = pq[w], side = po[w];
+            const uint32_t up = po[lup * W + g], down = po[ldn * W + g];
+            const uint32_t o = (r + Q) & 1u;   // column parity of this row's colour-Q sites
+            uint32_t hs;
+            if (L >= 64) {
+                const uint32_t gl = g == 0 ? W - 1 : g - 1, gr = g + 1 == W ? 0 : g + 1;
+                hs = o ? shift_next(side, po[lr * W + gr] & 1u) : shift_prev(side, po[lr * W + gl] >> 31);
+            } else {
+                hs = o ? shift_next16(side) : shift_prev16(side);
+            }
+            Counts cw{0u, 0u};
+            const uint32_t F = decide<Q, OBS>(a, up, down, side, hs, side, th, g, r, t, key0, key1, cw, valid);
+            if (OBS && own) { c.anti += cw.anti; c.neg += cw.neg; }
+            pq[w] = a ^ F;
+        }
+    }
+    flush();
+}
+
+// Exchange e of the split units (after colour updates e depth .. (e + 1) depth - 1): publish
+// each slab's outer `depth` rows of both colours (slot e mod 2, tag e + 1), then take the
+// neighbouring slabs' as its halo rows.  A slab overwrites a slot only after taking its
+// neighbours' next publication, which they make after reading this one, so two alternating slots
+// suffice.  Returns false if a wait gave up.
+__device__ __forceinline__ bool batch_exchange(uint32_t* lds, const BatchUnit* us, const BatchReplica* rs, uint32_t nu,
+                                               uint32_t xwords, uint64_t* exchange, uint32_t e) {
+    const uint32_t slot = e & 1u, tag = e + 1u;
+    bool ok = true;
+    for (int pass = 0; pass < 2; ++pass) {
+        uint32_t u = 0;
+        uint32_t uend = nu > 1 ? us[1].xfirst : xwords;
+        for (uint32_t f = threadIdx.x; f < xwords; f += blockDim.x) {
+            while (f >= uend) {
+                ++u;
+                uend = u + 1 < nu ? us[u + 1].xfirst : xwords;
+            }
+            const BatchUnit& x = us[u];
+            const uint32_t W = rs[u].W, K = x.depth, rows = x.rows, pw = unit_plane(rows, K, W);
+            const uint32_t i = f - x.xfirst;
+            const uint32_t g = i % W, c = (i / W) & 1u, k = (i / (2u * W)) % K, side = i / (2u * W * K);
+            uint64_t* xchg = exchange + x.xoff;
+            uint32_t* plane = lds + x.lds + c * pw;
+            if (pass == 0) {
+                // side 0: own rows 0 .. K - 1 (local K + k); side 1: own rows rows - K .. rows - 1
+                put_tagged(edge_word(xchg, W, slot, x.slab, side, k, c, g), tag, plane[(side == 0 ? K + k : rows + k) * W + g]);
+            } else {
+                // side 0: halo above = the previous slab's last rows; side 1: halo below = the next
+                // slab's first rows
+                const uint32_t prev = x.slab == 0 ? x.slabs - 1 : x.slab - 1;
+                const uint32_t next = x.slab + 1 == x.slabs ? 0 : x.slab + 1;
+                const uint64_t* src = side == 0 ? edge_word(xchg, W, slot, prev, 1, k, c, g)
+                                                : edge_word(xchg, W, slot, next, 0, k, c, g);
+                uint32_t v = 0;
+                ok = get_tagged(src, tag, v) && ok;
+                plane[(side == 0 ? k : K + rows + k) * W + g] = v;
+            }
+        }
+    }
+    return ok;
 }
 
 // FP64 moment sums of one sample, each operation rounded as written (no fused multiply-add), so
@@ -688,61 +848,127 @@ __device__ __forceinline__ void store_moments(double* mo, uint32_t n, double s_a
 
 // start: 0 = hot start from the seed, 1 = cold start (all +1), 2 = continue from `state`,
 // 3 = cold start for replicas with beta above the critical value, hot start otherwise.
-__global__ __launch_bounds__(1024) void k_batch(const BatchReplica* table, uint32_t* state, uint32_t start,
-                                                uint32_t n_therm, uint32_t n_meas, int64_t* trace,
-                                                double* moments) {
-    __shared__ uint32_t planes[kBatchMaxWords];
-    __shared__ uint32_t red[2][16];
-    const BatchReplica rp = table[blockIdx.x];
-    const uint32_t words = rp.L * rp.W;
-    uint32_t* gstate = state + rp.state_off;
-    const uint32_t mode = start == 3 ? (rp.ordered ? 1u : 0u) : start;
-    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) {
-        uint32_t w0 = 0u, w1 = 0u;
-        if (mode == 0) hot_start_words(rp.L, w / rp.W, w % rp.W, rp.key0, rp.key1, w0, w1);
-        else if (mode == 2) { w0 = gstate[w]; w1 = gstate[words + w]; }
-        planes[w] = w0;
-        planes[words + w] = w1;
+// One workgroup per work list; `lds` (dynamic) holds both colour planes of every unit of the list.
+// `depth`: colour updates between exchanges when the list has split units (0 when none does).  A
+// split replica's (M, E) of a measurement sweep is the sum of its slabs' counts, combined by its
+// slab 0 `lag` sweeps later (or at the end); a run in which a wait gave up leaves NaN moments.
+__global__ __launch_bounds__(1024) void k_batch(const BatchReplica* table, const BatchGroup* groups,
+                                                const BatchUnit* units, uint32_t* state, uint64_t* exchange,
+                                                uint32_t depth, uint32_t start, uint32_t n_therm, uint32_t n_meas,
+                                                int64_t* trace, double* moments) {
+    extern __shared__ uint32_t lds[];
+    __shared__ BatchUnit us[kMaxUnits];
+    __shared__ BatchReplica rs[kMaxUnits];
+    __shared__ uint32_t cnt[kMaxUnits][2];
+    __shared__ double acc[kMaxUnits][5];
+    __shared__ uint32_t took[kMaxUnits];
+    const BatchGroup grp = groups[blockIdx.x];
+    const uint32_t nu = grp.end - grp.begin;
+    for (uint32_t u = threadIdx.x; u < nu; u += blockDim.x) {
+        us[u] = units[grp.begin + u];
+        rs[u] = table[us[u].rep];
+        cnt[u][0] = cnt[u][1] = 0u;
+        for (int k = 0; k < 5; ++k) acc[u][k] = 0.0;
+        took[u] = 0u;
     }
     __syncthreads();
-    const double inv = 1.0 / ((double)rp.L * (double)rp.L);
-    double s_abs = 0.0, s_m2 = 0.0, s_m4 = 0.0, s_e = 0.0, s_e2 = 0.0;
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    for (uint32_t i = 0; i < n_therm + n_meas; ++i) {
-        const uint32_t t = rp.t0 + i;
-        Counts cnt{0u, 0u};
-        batch_half_sweep<1, false>(planes, rp, t, cnt);
-        __syncthreads();
-        if (i < n_therm) {
-            batch_half_sweep<0, false>(planes, rp, t, cnt);
-            __syncthreads();
-            continue;
+    // every unit's rows and halo rows (global rows row0 - depth .. row0 + rows + depth - 1)
+    for (uint32_t u = 0; u < nu; ++u) {
+        const BatchUnit& x = us[u];
+        const BatchReplica& rp = rs[u];
+        const uint32_t W = rp.W, L = rp.L, words = L * W, pw = unit_plane(x.rows, x.depth, W);
+        const uint32_t mode = start == 3 ? (rp.ordered ? 1u : 0u) : start;
+        const uint32_t* gstate = state + rp.state_off;
+        for (uint32_t w = threadIdx.x; w < pw; w += blockDim.x) {
+            const uint32_t lr = w / W, g = w - lr * W;
+            const uint32_t r = (x.row0 + L - x.depth + lr) % L;
+            uint32_t w0 = 0u, w1 = 0u;
+            if (mode == 0) hot_start_words(L, r, g, rp.key0, rp.key1, w0, w1);
+            else if (mode == 2) { w0 = gstate[r * W + g]; w1 = gstate[words + r * W + g]; }
+            lds[x.lds + w] = w0;
+            lds[x.lds + pw + w] = w1;
         }
-        batch_half_sweep<0, true>(planes, rp, t, cnt);
-        const uint32_t anti = wave_sum(cnt.anti), neg = wave_sum(cnt.neg);
-        if (lane == 0) { red[0][wave] = anti; red[1][wave] = neg; }
+    }
+    __syncthreads();
+    bool ok = true;        // this thread's waits so far
+    bool aborted = false;  // some wait of the workgroup gave up
+    // (M, E) of measurement sweep j of unit u's replica (slab 0, or the whole replica)
+    auto take = [&](uint32_t u, int64_t M, int64_t E, uint32_t j) {
+        const BatchReplica& rp = rs[u];
+        if (trace) {
+            int64_t* tr = trace + 2 * ((size_t)us[u].rep * n_meas + j);
+            tr[0] = M;
+            tr[1] = E;
+        }
+        accumulate_moments(M, E, 1.0 / ((double)rp.L * (double)rp.L), acc[u][0], acc[u][1], acc[u][2], acc[u][3],
+                           acc[u][4]);
+    };
+    auto combine = [&](uint32_t u, uint32_t j) {
+        const BatchUnit& x = us[u];
+        const int64_t sites = (int64_t)rs[u].L * rs[u].L;
+        uint64_t A = 0, Nn = 0;
+        uint64_t* xchg = exchange + x.xoff;
+        for (uint32_t p = 0; p < x.slabs && ok; ++p) {
+            uint32_t a = 0, n = 0;
+            const uint64_t* cw = count_word(xchg, rs[u].W, j, p);
+            ok = get_tagged(cw, j + 1u, a) && get_tagged(cw + 1, j + 1u, n);
+            A += a;
+            Nn += n;
+        }
+        take(u, sites - 2 * (int64_t)Nn, 2 * (int64_t)A - 2 * sites, j);
+    };
+    const uint32_t H = 2u * (n_therm + n_meas);
+    for (uint32_t h = 0; h < H; ++h) {
+        const uint32_t i = h >> 1;
+        const bool obs = (h & 1u) && i >= n_therm;
+        if (!(h & 1u)) batch_update<1, false>(lds, us, rs, nu, grp.words, i, cnt);
+        else if (!obs) batch_update<0, false>(lds, us, rs, nu, grp.words, i, cnt);
+        else batch_update<0, true>(lds, us, rs, nu, grp.words, i, cnt);
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint64_t A = 0, Nn = 0;
-            for (uint32_t k = 0; k < blockDim.x / 64u; ++k) { A += red[0][k]; Nn += red[1][k]; }
-            const int64_t sites = (int64_t)rp.L * rp.L;
-            const int64_t M = sites - 2 * (int64_t)Nn, E = 2 * (int64_t)A - 2 * sites;
+        const bool exch = depth > 0 && (h + 1u) % depth == 0 && h + 1u < H;
+        if (exch) ok = batch_exchange(lds, us, rs, nu, grp.xwords, exchange, h / depth) && ok;
+        if (obs) {
             const uint32_t j = i - n_therm;
-            if (trace) {
-                int64_t* tr = trace + 2 * ((size_t)blockIdx.x * n_meas + j);
-                tr[0] = M;
-                tr[1] = E;
+            for (uint32_t u = threadIdx.x; u < nu; u += blockDim.x) {
+                const BatchUnit& x = us[u];
+                const uint32_t A = cnt[u][0], Nn = cnt[u][1];
+                cnt[u][0] = cnt[u][1] = 0u;   // next added to after the next colour update's barrier
+                if (x.slabs == 1) {
+                    const int64_t sites = (int64_t)rs[u].L * rs[u].L;
+                    take(u, sites - 2 * (int64_t)Nn, 2 * (int64_t)A - 2 * sites, j);
+                } else {
+                    uint64_t* cw = count_word(exchange + x.xoff, rs[u].W, j, x.slab);
+                    put_tagged(cw, j + 1u, A);
+                    put_tagged(cw + 1, j + 1u, Nn);
+                    if (x.slab == 0 && j >= x.lag) combine(u, took[u]++);
+                }
             }
-            accumulate_moments(M, E, inv, s_abs, s_m2, s_m4, s_e, s_e2);
         }
-        __syncthreads();  // red[] is reused by the next sweep
+        // halo rows and the abort decision settled for every thread
+        if (depth > 0 && (exch || obs) && __syncthreads_or(!ok)) { aborted = true; break; }
     }
-    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) {
-        gstate[w] = planes[w];
-        gstate[words + w] = planes[words + w];
+    if (!aborted)
+        for (uint32_t u = threadIdx.x; u < nu; u += blockDim.x)
+            if (us[u].slabs > 1 && us[u].slab == 0)
+                while (ok && took[u] < n_meas) combine(u, took[u]++);
+    // every unit's own rows (local rows depth .. depth + rows - 1) back to the state buffer
+    for (uint32_t u = 0; u < nu; ++u) {
+        const BatchUnit& x = us[u];
+        const BatchReplica& rp = rs[u];
+        const uint32_t W = rp.W, words = rp.L * W, pw = unit_plane(x.rows, x.depth, W);
+        uint32_t* gstate = state + rp.state_off;
+        for (uint32_t w = threadIdx.x; w < x.rows * W; w += blockDim.x) {
+            gstate[x.row0 * W + w] = lds[x.lds + x.depth * W + w];
+            gstate[words + x.row0 * W + w] = lds[x.lds + pw + x.depth * W + w];
+        }
     }
-    if (threadIdx.x == 0 && moments && n_meas > 0)
-        store_moments(moments + 5 * (size_t)blockIdx.x, n_meas, s_abs, s_m2, s_m4, s_e, s_e2);
+    if (moments && n_meas > 0)
+        for (uint32_t u = threadIdx.x; u < nu; u += blockDim.x) {
+            if (us[u].slab != 0) continue;
+            double* mo = moments + 5 * (size_t)us[u].rep;
+            if (ok && !aborted) store_moments(mo, n_meas, acc[u][0], acc[u][1], acc[u][2], acc[u][3], acc[u][4]);
+            else for (int k = 0; k < 5; ++k) mo[k] = __builtin_nan("");
+        }
 }
 
 // Unpack one replica's planes (L x L, the packed layout above) to int8 rows.
@@ -803,6 +1029,10 @@ struct Options {
     int64_t nt_store = 0;
     int64_t staged = 1;
     int64_t batch_threads = 0;  // 0 = autotune
+    int64_t batch_slab_sites = 0;  // batch: split replicas into slabs of at most this many sites;
+                                   // 0 = autotune, -1 = never split
+    int64_t batch_depth = 0;       // batch: colour updates between exchanges of split replicas; 0 = autotune
+    int64_t batch_lists_per_cu = 0;  // batch: work lists per compute unit of a split schedule; 0 = autotune
     int64_t fused_rows = 0;     // rows per strip of the fused sweep; 0 = choose from L
     int64_t fused_alternate = 1;  // fused sweep: odd strips walk upwards
     int64_t planes3 = 0;          // 3-D sweep: planes per workgroup; 0 = choose from L
@@ -1008,15 +1238,143 @@ int zero_trace(int64_t* p, int64_t n, hipStream_t stream) {
 namespace {
 
 constexpr size_t kTableAlign = 256;
+// dynamic LDS of a work list that leaves room for at most `per_cu` workgroups on a compute unit
+// (160 KiB of LDS; the kernel's static LDS adds about 5 KiB)
+size_t lds_floor(int per_cu) { return per_cu == 1 ? 81920 : 55296; }
+size_t lds_cap(int per_cu) { return per_cu == 1 ? 131072 : 73728; }
+
+size_t align_up(size_t x) { return (x + kTableAlign - 1) / kTableAlign * kTableAlign; }
 
 // 32 (one 16-site word per row and colour) or a multiple of 64 (whole 32-site words), at most 512
 bool valid_batch_L(int64_t L) { return L == 32 || (L >= 64 && L <= 512 && L % 64 == 0); }
 
-size_t batch_table_bytes(int64_t n) {
-    return ((size_t)n * sizeof(ising::BatchReplica) + kTableAlign - 1) / kTableAlign * kTableAlign;
+uint32_t batch_W(int64_t L) { return L >= 64 ? (uint32_t)(L / 64) : 1u; }
+
+uint64_t batch_words(int64_t L) { return 2ull * (uint64_t)L * batch_W(L); }
+
+// Workspace: replica table | both colour planes of every replica | work lists | units |
+// exchange areas.
+struct BatchLayout {
+    size_t state, groups, units, exchange, total;
+};
+
+BatchLayout batch_layout(const ising_replica_t* reps, int64_t n) {
+    BatchLayout b{};
+    b.state = align_up((size_t)n * sizeof(ising::BatchReplica));
+    uint64_t words = 0, xwords = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        words += batch_words(reps[i].L);
+        xwords += ising::exchange_words(batch_W(reps[i].L));
+    }
+    b.groups = align_up(b.state + words * 4u);
+    b.units = align_up(b.groups + (size_t)n * ising::kMaxSlabs * sizeof(ising::BatchGroup));
+    b.exchange = align_up(b.units + (size_t)n * ising::kMaxSlabs * sizeof(ising::BatchUnit));
+    b.total = b.exchange + xwords * 8u;
+    return b;
 }
 
-uint64_t batch_words(int64_t L) { return 2ull * (uint64_t)L * (uint64_t)(L >= 64 ? L / 64 : 1); }
+// Slabs of replica L for a split target (sites per slab; <= 0: one slab): halve the rows while
+// the slab holds more than `target` sites, keeping at least 16 rows and at most kMaxSlabs slabs.
+uint32_t slabs_for(int64_t L, int64_t target) {
+    uint32_t P = 1;
+    if (target <= 0 || L < 64) return 1;
+    while (P < ising::kMaxSlabs && L * L / P > target && L % (2 * P) == 0 && L / (2 * P) >= 16) P *= 2;
+    return P;
+}
+
+// Work lists of a schedule.  Unsplit: one replica per workgroup.  Split: the units (slabs and
+// whole replicas) are packed into `per_cu` workgroups per compute unit, largest first onto the
+// least loaded list, and each workgroup asks for enough LDS that no more than `per_cu` share a
+// compute unit -- every workgroup is then resident at once, which the slabs' waits for their
+// neighbours need.
+struct BatchPlan {
+    std::vector<ising::BatchGroup> groups;
+    std::vector<ising::BatchUnit> units;   // in work-list order
+    size_t lds = 0;                        // dynamic LDS bytes per workgroup
+    uint32_t depth = 0;                    // colour updates between exchanges (0: nothing split)
+    int per_cu = 1;                        // workgroups per compute unit (split plans)
+    bool ok = false;
+};
+
+BatchPlan plan_batch(const ising_replica_t* reps, int64_t n, int64_t target, uint32_t depth, int per_cu, int cus) {
+    BatchPlan plan;
+    std::vector<ising::BatchUnit> all;
+    std::vector<uint32_t> cost;
+    uint64_t xoff = 0;
+    bool split = false;
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t P = slabs_for(reps[i].L, target), rows = (uint32_t)reps[i].L / P, W = batch_W(reps[i].L);
+        const uint32_t K = P > 1 ? depth : 0u;
+        for (uint32_t p = 0; p < P; ++p) {
+            ising::BatchUnit x{};
+            x.rep = (uint32_t)i;
+            x.slab = p;
+            x.slabs = P;
+            x.row0 = p * rows;
+            x.rows = rows;
+            x.depth = K;
+            // a slab starts exchange period e + 1 only after its neighbours finished period e, so
+            // one d slabs away has finished at least (d + 1) K colour updates fewer: the counts
+            // of sweep j are all in place (P / 2 + 1) K / 2 sweeps later
+            x.lag = ((P / 2 + 1) * K + 1) / 2;
+            x.xoff = xoff;
+            all.push_back(x);
+            cost.push_back((ising::unit_words(rows, K, W) + 63u) / 64u * 64u + 64u);
+        }
+        split = split || P > 1;
+        xoff += ising::exchange_words(W);
+    }
+    std::vector<std::vector<uint32_t>> lists;
+    if (!split) {
+        for (uint32_t k = 0; k < all.size(); ++k) lists.push_back({k});
+    } else {
+        const size_t G = std::min<size_t>(all.size(), (size_t)std::max(cus, 1) * (size_t)per_cu);
+        lists.resize(G);
+        std::vector<uint32_t> order(all.size());
+        for (uint32_t k = 0; k < order.size(); ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+        using Load = std::pair<uint64_t, uint32_t>;
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+        for (uint32_t g = 0; g < G; ++g) heap.push({0, g});
+        for (uint32_t k : order) {
+            Load top = heap.top();
+            heap.pop();
+            lists[top.second].push_back(k);
+            top.first += cost[k];
+            heap.push(top);
+        }
+    }
+    size_t lds_max = 0;
+    for (const auto& list : lists) {
+        if (list.empty()) continue;
+        if (list.size() > ising::kMaxUnits) return plan;
+        ising::BatchGroup grp{};
+        grp.begin = (uint32_t)plan.units.size();
+        uint32_t lds = 0, first = 0, xfirst = 0;
+        for (uint32_t k : list) {
+            ising::BatchUnit x = all[k];
+            const uint32_t W = batch_W(reps[x.rep].L);
+            x.lds = lds;
+            x.first = first;
+            x.xfirst = xfirst;
+            lds += 2u * ising::unit_plane(x.rows, x.depth, W);
+            first += (ising::unit_words(x.rows, x.depth, W) + 63u) / 64u;   // whole waves
+            xfirst += x.depth ? ising::unit_xwords(x.depth, W) : 0u;
+            plan.units.push_back(x);
+        }
+        grp.end = (uint32_t)plan.units.size();
+        grp.words = first;
+        grp.xwords = xfirst;
+        plan.groups.push_back(grp);
+        lds_max = std::max(lds_max, (size_t)lds * 4u);
+    }
+    if (split && lds_max > lds_cap(per_cu)) return plan;
+    plan.lds = split ? std::max(lds_max, lds_floor(per_cu)) : lds_max;
+    plan.per_cu = per_cu;
+    plan.depth = split ? depth : 0u;
+    plan.ok = true;
+    return plan;
+}
 
 struct BatchGraph {
     hipGraphExec_t exec = nullptr;
@@ -1024,7 +1382,14 @@ struct BatchGraph {
     std::string key;
 };
 BatchGraph g_batch_graph;
-std::map<std::string, int> g_batch_tuned;  // replica-size signature -> threads per block
+
+struct BatchSchedule {
+    int threads;
+    int64_t target;  // split target (sites per slab), -1 = none
+    int depth;       // colour updates between exchanges of a split replica
+    int per_cu;      // work lists per compute unit of a split schedule
+};
+std::map<std::string, BatchSchedule> g_batch_tuned;  // replica-size signature -> schedule
 
 std::string batch_signature(const ising_replica_t* reps, int64_t n) {
     std::string sig;
@@ -1032,46 +1397,119 @@ std::string batch_signature(const ising_replica_t* reps, int64_t n) {
     return sig;
 }
 
-int launch_batch_direct(const ising::BatchReplica* table, uint32_t* state, int64_t n, int threads, uint32_t start,
-                        uint32_t n_therm, uint32_t n_meas, int64_t* trace, double* moments, hipStream_t stream) {
-    hipLaunchKernelGGL(ising::k_batch, dim3((unsigned)n), dim3((unsigned)threads), 0, stream, table, state, start,
-                       n_therm, n_meas, trace, moments);
+int compute_units() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus;
+}
+
+// A split plan runs only if its workgroups can all be resident at once.
+bool plan_fits(const BatchPlan& plan, int threads, int cus) {
+    if (!plan.ok) return false;
+    if (plan.depth == 0) return true;
+    if (plan.lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ising::k_batch),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds);
+        if (e != hipSuccess) return false;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ising::k_batch, threads, plan.lds) != hipSuccess)
+        return false;
+    return per_cu >= plan.per_cu && (int64_t)plan.groups.size() <= (int64_t)cus * plan.per_cu;
+}
+
+struct BatchBuffers {
+    const ising::BatchReplica* table;
+    ising::BatchGroup* groups;
+    ising::BatchUnit* units;
+    uint32_t* state;
+    uint64_t* exchange;
+    int64_t exchange_words;
+};
+
+// Copy a plan's tables into the workspace (the host vectors may be reused on return: a copy from
+// pageable memory has read them by then).
+int upload_plan(const BatchBuffers& b, const BatchPlan& plan, hipStream_t stream) {
+    hipError_t e = hipMemcpyAsync(b.groups, plan.groups.data(), plan.groups.size() * sizeof(ising::BatchGroup),
+                                  hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_failed(e, "hipMemcpyAsync(work lists)");
+    e = hipMemcpyAsync(b.units, plan.units.data(), plan.units.size() * sizeof(ising::BatchUnit), hipMemcpyHostToDevice,
+                       stream);
+    if (e != hipSuccess) return hip_failed(e, "hipMemcpyAsync(units)");
+    return ISING_OK;
+}
+
+// The exchange area is cleared by a kernel (tags start at 0 for every run), then the run.
+int launch_batch(const BatchBuffers& b, const BatchPlan& plan, int threads, uint32_t start, uint32_t n_therm,
+                 uint32_t n_meas, int64_t* trace, double* moments, hipStream_t stream) {
+    if (plan.depth > 0) {
+        const int rc = zero_trace(reinterpret_cast<int64_t*>(b.exchange), b.exchange_words, stream);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(ising::k_batch, dim3((unsigned)plan.groups.size()), dim3((unsigned)threads), plan.lds, stream,
+                       b.table, b.groups, b.units, b.state, b.exchange, plan.depth, start, n_therm, n_meas, trace,
+                       moments);
     return check_launch("k_batch");
 }
 
-// Time the three block sizes on the replica table itself (a few thermalisation sweeps, which the
-// real run overwrites) and keep the fastest; results are identical for every block size.
-int autotune_batch(const ising_replica_t* reps, int64_t n, const ising::BatchReplica* table, uint32_t* state,
-                   uint32_t start, hipStream_t stream, int* threads_out) {
+// Time each schedule on the replica table itself (a few thermalisation sweeps, which the real run
+// overwrites) and keep the fastest; every schedule gives identical results.
+int autotune_batch(const ising_replica_t* reps, int64_t n, const BatchBuffers& b, uint32_t start, hipStream_t stream,
+                   BatchSchedule fixed, int cus, BatchSchedule* out) {
     const std::string sig = batch_signature(reps, n);
     auto it = g_batch_tuned.find(sig);
-    if (it != g_batch_tuned.end()) { *threads_out = it->second; return ISING_OK; }
+    if (it != g_batch_tuned.end()) { *out = it->second; return ISING_OK; }
+    std::vector<BatchSchedule> cands;
+    for (int64_t target : {int64_t(-1), int64_t(65536), int64_t(32768), int64_t(16384)}) {
+        if (fixed.target && target != fixed.target) continue;
+        for (int depth : {1, 2, 4}) {
+            if (fixed.depth && depth != fixed.depth) continue;
+            for (int per_cu : {1, 2}) {
+                if (fixed.per_cu && per_cu != fixed.per_cu) continue;
+                // depth and lists per CU only matter for split replicas
+                if (target == -1 && (depth != (fixed.depth ? fixed.depth : 1) ||
+                                     per_cu != (fixed.per_cu ? fixed.per_cu : 1)))
+                    continue;
+                for (int threads : {256, 512, 1024}) {
+                    if (fixed.threads && threads != fixed.threads) continue;
+                    if (target != -1 && threads == 256 && !fixed.threads) continue;   // few lists: wide groups
+                    cands.push_back(BatchSchedule{threads, target, depth, per_cu});
+                }
+            }
+        }
+    }
+    if (fixed.target > 0 && cands.empty()) cands.push_back(fixed);
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
     if (e != hipSuccess) return hip_failed(e, "hipEventCreate");
     e = hipEventCreate(&e1);
     if (e != hipSuccess) { (void)hipEventDestroy(e0); return hip_failed(e, "hipEventCreate"); }
-    int best = 256;
+    BatchSchedule best{1024, -1, 1, 1};
     float best_ms = 1e30f;
     int rc = ISING_OK;
-    for (int threads : {256, 512, 1024}) {
+    for (const BatchSchedule& c : cands) {
+        const BatchPlan plan = plan_batch(reps, n, c.target, (uint32_t)c.depth, c.per_cu, cus);
+        if (!plan_fits(plan, c.threads, cus)) continue;
+        rc = upload_plan(b, plan, stream);
         for (int rep = 0; rep < 2 && rc == ISING_OK; ++rep) {
             (void)hipEventRecord(e0, stream);
-            rc = launch_batch_direct(table, state, n, threads, start, 8u, 0u, nullptr, nullptr, stream);
+            rc = launch_batch(b, plan, c.threads, start, 8u, 0u, nullptr, nullptr, stream);
             (void)hipEventRecord(e1, stream);
             if (rc) break;
             e = hipEventSynchronize(e1);
             if (e != hipSuccess) { rc = hip_failed(e, "hipEventSynchronize"); break; }
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            if (rep == 1 && ms < best_ms) { best_ms = ms; best = threads; }
+            if (rep == 1 && ms < best_ms) { best_ms = ms; best = c; }
         }
+        if (rc) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     g_batch_tuned[sig] = best;
-    *threads_out = best;
+    *out = best;
     return ISING_OK;
 }
 
@@ -1373,6 +1811,16 @@ int ising_set_option(const char* name, int64_t value) {
     } else if (n == "batch_threads") {
         if (value != 0 && value != 256 && value != 512 && value != 1024) return ISING_EINVAL;
         g_opt.batch_threads = value;
+    } else if (n == "batch_slab_sites") {
+        if (value != 0 && value != -1 && (value < 1024 || value > (1 << 18) || (value & (value - 1)) != 0))
+            return ISING_EINVAL;
+        g_opt.batch_slab_sites = value;
+    } else if (n == "batch_depth") {
+        if (value != 0 && value != 1 && value != 2 && value != 4) return ISING_EINVAL;
+        g_opt.batch_depth = value;
+    } else if (n == "batch_lists_per_cu") {
+        if (value != 0 && value != 1 && value != 2) return ISING_EINVAL;
+        g_opt.batch_lists_per_cu = value;
     } else if (n == "staged") {
         if (value != 0 && value != 1) return ISING_EINVAL;
         g_opt.staged = value;
@@ -1399,6 +1847,9 @@ int ising_get_option(const char* name, int64_t* value) {
     else if (n == "nt_store") *value = g_opt.nt_store;
     else if (n == "staged") *value = g_opt.staged;
     else if (n == "batch_threads") *value = g_opt.batch_threads;
+    else if (n == "batch_slab_sites") *value = g_opt.batch_slab_sites;
+    else if (n == "batch_depth") *value = g_opt.batch_depth;
+    else if (n == "batch_lists_per_cu") *value = g_opt.batch_lists_per_cu;
     else if (n == "fused_rows") *value = g_opt.fused_rows;
     else if (n == "fused_alternate") *value = g_opt.fused_alternate;
     else if (n == "planes3") *value = g_opt.planes3;
@@ -1408,12 +1859,9 @@ int ising_get_option(const char* name, int64_t* value) {
 
 int64_t ising_batch_workspace_bytes(const ising_replica_t* replicas, int64_t n) {
     if (!replicas || n <= 0 || n > 65535) return ISING_EINVAL;
-    uint64_t words = 0;
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < n; ++i)
         if (!valid_batch_L(replicas[i].L)) return ISING_EINVAL;
-        words += batch_words(replicas[i].L);
-    }
-    return (int64_t)(batch_table_bytes(n) + words * 4u);
+    return (int64_t)batch_layout(replicas, n).total;
 }
 
 int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm, int64_t n_meas, uint64_t sweep_offset,
@@ -1421,11 +1869,12 @@ int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm,
                     void* stream) {
     const int64_t need = ising_batch_workspace_bytes(replicas, n);
     if (need < 0 || !workspace || workspace_bytes < need || !aligned16(workspace) || n_therm < 0 || n_meas < 0 ||
-        fmt < 0 || fmt > 2 || start < 0 || start > 3 || (uint64_t)(n_therm + n_meas) > (uint64_t(1) << 32) ||
+        fmt < 0 || fmt > 2 || start < 0 || start > 3 || (uint64_t)(n_therm + n_meas) >= (uint64_t(1) << 31) ||
         sweep_offset > (uint64_t(1) << 32) - (uint64_t)(n_therm + n_meas))
         return ISING_EINVAL;
     for (int64_t i = 0; i < n; ++i)
         if (!valid_beta(replicas[i].beta)) return ISING_EINVAL;
+    const BatchLayout lay = batch_layout(replicas, n);
     // replica table (host) -> workspace head (device)
     std::vector<ising::BatchReplica> table((size_t)n);
     uint64_t off = 0;
@@ -1433,7 +1882,7 @@ int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm,
         ising::BatchReplica& b = table[(size_t)i];
         std::memset(&b, 0, sizeof b);
         b.L = (uint32_t)replicas[i].L;
-        b.W = replicas[i].L >= 64 ? (uint32_t)(replicas[i].L / 64) : 1u;
+        b.W = batch_W(replicas[i].L);
         b.key0 = (uint32_t)replicas[i].seed;
         b.key1 = (uint32_t)(replicas[i].seed >> 32);
         b.t0 = (uint32_t)sweep_offset;
@@ -1443,24 +1892,51 @@ int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm,
         off += batch_words(replicas[i].L);
     }
     hipStream_t s = (hipStream_t)stream;
-    auto* dtable = reinterpret_cast<ising::BatchReplica*>(workspace);
-    auto* state = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(workspace) + batch_table_bytes(n));
-    hipError_t e = hipMemcpyAsync(dtable, table.data(), table.size() * sizeof(ising::BatchReplica),
+    char* ws = reinterpret_cast<char*>(workspace);
+    BatchBuffers bufs{};
+    bufs.table = reinterpret_cast<const ising::BatchReplica*>(ws);
+    bufs.groups = reinterpret_cast<ising::BatchGroup*>(ws + lay.groups);
+    bufs.units = reinterpret_cast<ising::BatchUnit*>(ws + lay.units);
+    bufs.state = reinterpret_cast<uint32_t*>(ws + lay.state);
+    bufs.exchange = reinterpret_cast<uint64_t*>(ws + lay.exchange);
+    bufs.exchange_words = (int64_t)((lay.total - lay.exchange) / 8u);
+    hipError_t e = hipMemcpyAsync(ws, table.data(), table.size() * sizeof(ising::BatchReplica),
                                   hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_failed(e, "hipMemcpyAsync(replica table)");
-    int threads = (int)g_opt.batch_threads;
-    if (threads == 0) {
-        if (start == 2) threads = 1024;  // tuning would overwrite the state being continued
-        else {
-            const int rc = autotune_batch(replicas, n, dtable, state, (uint32_t)start, s, &threads);
+    const int cus = compute_units();
+    BatchSchedule sched{(int)g_opt.batch_threads, g_opt.batch_slab_sites, (int)g_opt.batch_depth,
+                        (int)g_opt.batch_lists_per_cu};
+    if (sched.threads == 0 || sched.target == 0 || sched.depth == 0 || sched.per_cu == 0) {
+        auto it = g_batch_tuned.find(batch_signature(replicas, n));
+        if (it != g_batch_tuned.end()) {
+            if (sched.threads == 0) sched.threads = it->second.threads;
+            if (sched.target == 0) sched.target = it->second.target;
+            if (sched.depth == 0) sched.depth = it->second.depth;
+            if (sched.per_cu == 0) sched.per_cu = it->second.per_cu;
+        } else if (start == 2) {
+            // tuning would overwrite the state being continued
+            if (sched.threads == 0) sched.threads = 1024;
+            if (sched.target == 0) sched.target = -1;
+            if (sched.depth == 0) sched.depth = 1;
+            if (sched.per_cu == 0) sched.per_cu = 1;
+        } else {
+            BatchSchedule tuned{};
+            const int rc = autotune_batch(replicas, n, bufs, (uint32_t)start, s, sched, cus, &tuned);
             if (rc) return rc;
+            sched = tuned;
         }
     }
-    // One persistent launch, captured once into a hipGraph and replayed on the caller's stream.
-    char keybuf[256];
-    std::snprintf(keybuf, sizeof keybuf, "%p|%p|%p|%p|%lld|%d|%d|%lld|%lld", workspace, (void*)state,
-                  (void*)trace_ME, (void*)moments, (long long)n, threads, start, (long long)n_therm,
-                  (long long)n_meas);
+    BatchPlan plan = plan_batch(replicas, n, sched.target, (uint32_t)sched.depth, sched.per_cu, cus);
+    if (!plan_fits(plan, sched.threads, cus)) plan = plan_batch(replicas, n, -1, 1u, 1, cus);  // unsplit fallback
+    if (!plan.ok) return ISING_EINVAL;
+    int rc = upload_plan(bufs, plan, s);
+    if (rc) return rc;
+    // One persistent launch (after the clearing of the exchange area), captured once into a
+    // hipGraph and replayed on the caller's stream.
+    char keybuf[320];
+    std::snprintf(keybuf, sizeof keybuf, "%p|%p|%p|%lld|%d|%lld|%d|%d|%zu|%u|%d|%lld|%lld|%zu", workspace,
+                  (void*)trace_ME, (void*)moments, (long long)n, sched.threads, (long long)sched.target, sched.depth,
+                  plan.per_cu, plan.groups.size(), plan.depth, start, (long long)n_therm, (long long)n_meas, plan.lds);
     const std::string key(keybuf);
     if (g_batch_graph.key != key || !g_batch_graph.exec) {
         if (g_batch_graph.exec) {
@@ -1475,12 +1951,11 @@ int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm,
         hipStream_t cs = g_batch_graph.capture;
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_failed(e, "hipStreamBeginCapture");
-        hipLaunchKernelGGL(ising::k_batch, dim3((unsigned)n), dim3((unsigned)threads), 0, cs, dtable, state,
-                           (uint32_t)start, (uint32_t)n_therm, (uint32_t)n_meas, trace_ME, moments);
+        const int launch_rc = launch_batch(bufs, plan, sched.threads, (uint32_t)start, (uint32_t)n_therm,
+                                           (uint32_t)n_meas, trace_ME, moments, cs);
         hipGraph_t graph = nullptr;
-        const hipError_t launch_err = hipGetLastError();
         e = hipStreamEndCapture(cs, &graph);
-        if (launch_err != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return hip_failed(launch_err, "k_batch"); }
+        if (launch_rc) { if (graph) (void)hipGraphDestroy(graph); return launch_rc; }
         if (e != hipSuccess) return hip_failed(e, "hipStreamEndCapture");
         e = hipGraphInstantiate(&g_batch_graph.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
@@ -1492,11 +1967,23 @@ int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm,
     return ISING_OK;
 }
 
+int ising_batch_schedule(const ising_replica_t* replicas, int64_t n, int64_t out[4]) {
+    if (!replicas || n <= 0 || !out) return ISING_EINVAL;
+    auto it = g_batch_tuned.find(batch_signature(replicas, n));
+    if (it == g_batch_tuned.end()) return ISING_EINVAL;
+    out[0] = it->second.threads;
+    out[1] = it->second.target;
+    out[2] = it->second.depth;
+    out[3] = it->second.per_cu;
+    return ISING_OK;
+}
+
 int ising_batch_unpack(const void* workspace, int64_t n, int64_t j, int8_t* spins, void* stream) {
     if (!workspace || !spins || n <= 0 || j < 0 || j >= n || !aligned16(workspace)) return ISING_EINVAL;
     const auto* dtable = reinterpret_cast<const ising::BatchReplica*>(workspace);
     const auto* state =
-        reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(workspace) + batch_table_bytes(n));
+        reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(workspace) +
+                                          align_up((size_t)n * sizeof(ising::BatchReplica)));
     hipLaunchKernelGGL(ising::k_batch_unpack, dim3(16), dim3(256), 0, (hipStream_t)stream, dtable, state,
                        (uint32_t)j, spins);
     return check_launch("k_batch_unpack");

@@ -85,6 +85,7 @@ _SIGNATURES = {
     "ising_batch_run": ([ctypes.POINTER(ReplicaT), ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                          ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                          ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising_batch_schedule": ([ctypes.POINTER(ReplicaT), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ising_batch_unpack": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
                            ctypes.c_int),
     "ising_set_option": ([ctypes.c_char_p, ctypes.c_int64], ctypes.c_int),
@@ -347,6 +348,15 @@ def ising_batch_run(replicas, n_therm: int, n_meas: int, workspace, sweep_offset
         _dev_ptr(workspace, "torch.uint8"), workspace.numel(),
         _opt_ptr(trace_ME, "torch.int64", 2 * n * n_meas), _opt_ptr(moments, "torch.float64", 5 * n),
         _stream(stream)))
+
+
+def ising_batch_schedule(replicas) -> tuple[int, int, int, int]:
+    """(threads per workgroup, split target in sites per slab or -1, colour updates between
+    exchanges, work lists per compute unit) that ising_batch_run tuned for this set of replica
+    sizes."""
+    out = (ctypes.c_int64 * 4)()
+    _check("ising_batch_schedule", library().ising_batch_schedule(_replica_array(replicas), len(replicas), out))
+    return int(out[0]), int(out[1]), int(out[2]), int(out[3])
 
 
 def ising_batch_unpack(workspace, n: int, j: int, spins, stream=None) -> None:

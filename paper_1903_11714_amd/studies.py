@@ -110,6 +110,15 @@ def config5_replicas(Ls=(32, 64, 128, 256, 512), n_temps: int = 51, t_lo: float 
     return reps, temps
 
 
+def _schedule(reps) -> tuple[int, int, int, int]:
+    """The batch schedule in use: the tuned one, or the one the options fix."""
+    try:
+        return ising.ising_batch_schedule(reps)
+    except ising.IsingError:
+        return tuple(ising.ising_get_option(k)
+                     for k in ("batch_threads", "batch_slab_sites", "batch_depth", "batch_lists_per_cu"))
+
+
 def batch_study(Ls=(32, 64, 128, 256, 512), n_temps: int = 51, n_therm: int = 2000, n_meas: int = 20000,
                 fmt="exact", device: str = "cuda", check_plain: int = 4, start: int = 3) -> dict:
     """start 3: replicas below T_c begin ordered (all +1), the others from their hot start."""
@@ -128,7 +137,7 @@ def batch_study(Ls=(32, 64, 128, 256, 512), n_temps: int = 51, n_therm: int = 20
     mo = moments.cpu().numpy()
     res = {"Ls": list(Ls), "temps": [float(t) for t in temps], "n_therm": n_therm, "n_meas": n_meas,
            "replicas": len(reps), "seconds": wall, "attempts_per_ns": attempts / (wall * 1e9),
-           "batch_threads": ising.ising_get_option("batch_threads") or "autotuned", "curves": {}}
+           "schedule": dict(zip(("threads", "slab_sites", "depth", "lists_per_cu"), _schedule(reps))), "curves": {}}
     idx = 0
     u4 = {}
     for L in Ls:

@@ -47,11 +47,19 @@ def _seq_moments(tr, N):
     return [a * (1.0 / len(tr)) for a in acc]
 
 
-def test_batch_matches_oracle(dev, oracle_lib):
+@pytest.mark.parametrize("slab_sites,depth", [(-1, 1), (4096, 1), (4096, 4), (16384, 2)])
+def test_batch_matches_oracle(dev, oracle_lib, slab_sites, depth):
+    # 9 sweeps = 18 colour updates: with 4 updates between exchanges the last period is partial
     n_therm, n_meas = 3, 6
-    print("batch", len(REPLICAS), flush=True)
-    moments, trace, ws = dev.batch_run(REPLICAS, n_therm, n_meas, start=0, sweep_offset=40)
-    torch.cuda.synchronize()
+    print("batch", len(REPLICAS), slab_sites, depth, flush=True)
+    try:
+        dev.ising_set_option("batch_slab_sites", slab_sites)
+        dev.ising_set_option("batch_depth", depth)
+        moments, trace, ws = dev.batch_run(REPLICAS, n_therm, n_meas, start=0, sweep_offset=40)
+        torch.cuda.synchronize()
+    finally:
+        dev.ising_set_option("batch_slab_sites", 0)
+        dev.ising_set_option("batch_depth", 0)
     for j, (L, beta, seed) in enumerate(REPLICAS):
         host = oracle_lib.init(L, seed)
         oracle_lib.sweep(host, beta, n_therm, seed, 40)
@@ -75,24 +83,43 @@ def test_batch_equals_single_lattice_path(dev):
         assert torch.equal(trace[j], t)
 
 
-def test_batch_block_sizes_and_continuation_identical(dev):
+def test_batch_schedules_and_continuation_identical(dev):
+    # every workgroup size with every split of the replicas into row slabs (1, 2, 4 or 8 slabs of
+    # at least 16 rows) and every number of colour updates between row exchanges gives the same
+    # chains
     reps = REPLICAS
     ref = None
     try:
-        for threads in (256, 512, 1024, 0):
+        for sites in (-1, 65536, 16384, 4096, 1024):
+            dev.ising_set_option("batch_slab_sites", sites)
+            for depth, per_cu in (((1, 1),) if sites == -1 else ((1, 1), (2, 2), (4, 1), (4, 2))):
+                dev.ising_set_option("batch_depth", depth)
+                dev.ising_set_option("batch_lists_per_cu", per_cu)
+                for threads in (256, 512, 1024):
+                    print("schedule", sites, depth, per_cu, threads, flush=True)
+                    dev.ising_set_option("batch_threads", threads)
+                    mo, tr, ws = dev.batch_run(reps, 2, 5, start=0)
+                    if ref is None:
+                        ref = (mo, tr)
+                    else:
+                        assert torch.equal(mo, ref[0]) and torch.equal(tr, ref[1]), (sites, depth, per_cu, threads)
+        for k in ("batch_threads", "batch_slab_sites", "batch_depth", "batch_lists_per_cu"):
+            dev.ising_set_option(k, 0)
+        mo, tr, _ = dev.batch_run(reps, 2, 5, start=0)          # autotuned schedule
+        assert torch.equal(mo, ref[0]) and torch.equal(tr, ref[1])
+        assert len(dev.ising_batch_schedule(reps)) == 4
+        # 2 + 5 sweeps in one call == 2 therm, then continue for the 5 measured ones
+        for sites, depth, threads in ((-1, 1, 512), (4096, 1, 256), (4096, 4, 512)):
+            print("continuation", sites, depth, threads, flush=True)
+            dev.ising_set_option("batch_slab_sites", sites)
+            dev.ising_set_option("batch_depth", depth)
             dev.ising_set_option("batch_threads", threads)
-            mo, tr, ws = dev.batch_run(reps, 2, 4, start=0)
-            if ref is None:
-                ref = (mo, tr)
-            else:
-                assert torch.equal(mo, ref[0]) and torch.equal(tr, ref[1]), threads
-        # 2 + 4 sweeps in one call == 2 therm, then continue for the 4 measured ones
-        dev.ising_set_option("batch_threads", 512)
-        _, _, ws = dev.batch_run(reps, 2, 0, start=0)
-        mo2, tr2, _ = dev.batch_run(reps, 0, 4, start=2, sweep_offset=2, workspace=ws)
-        assert torch.equal(tr2, ref[1]) and torch.equal(mo2, ref[0])
+            _, _, ws = dev.batch_run(reps, 2, 0, start=0)
+            mo2, tr2, _ = dev.batch_run(reps, 0, 5, start=2, sweep_offset=2, workspace=ws)
+            assert torch.equal(tr2, ref[1]) and torch.equal(mo2, ref[0]), (sites, depth, threads)
     finally:
-        dev.ising_set_option("batch_threads", 0)
+        for k in ("batch_threads", "batch_slab_sites", "batch_depth", "batch_lists_per_cu"):
+            dev.ising_set_option(k, 0)
 
 
 def test_batch_graph_replay_deterministic(dev):
