@@ -1453,7 +1453,7 @@ int launch_batch(const BatchBuffers& b, const BatchPlan& plan, int threads, uint
     return check_launch("k_batch");
 }
 
-// Time each schedule on the replica table itself (a few thermalisation sweeps, which the real run
+// Time each schedule on the replica table itself (thermalisation sweeps, which the real run
 // overwrites) and keep the fastest; every schedule gives identical results.
 int autotune_batch(const ising_replica_t* reps, int64_t n, const BatchBuffers& b, uint32_t start, hipStream_t stream,
                    BatchSchedule fixed, int cus, BatchSchedule* out) {
@@ -1492,16 +1492,17 @@ int autotune_batch(const ising_replica_t* reps, int64_t n, const BatchBuffers& b
         const BatchPlan plan = plan_batch(reps, n, c.target, (uint32_t)c.depth, c.per_cu, cus);
         if (!plan_fits(plan, c.threads, cus)) continue;
         rc = upload_plan(b, plan, stream);
-        for (int rep = 0; rep < 2 && rc == ISING_OK; ++rep) {
+        // the fastest of three 32-sweep runs, after one untimed run
+        for (int rep = 0; rep < 4 && rc == ISING_OK; ++rep) {
             (void)hipEventRecord(e0, stream);
-            rc = launch_batch(b, plan, c.threads, start, 8u, 0u, nullptr, nullptr, stream);
+            rc = launch_batch(b, plan, c.threads, start, 32u, 0u, nullptr, nullptr, stream);
             (void)hipEventRecord(e1, stream);
             if (rc) break;
             e = hipEventSynchronize(e1);
             if (e != hipSuccess) { rc = hip_failed(e, "hipEventSynchronize"); break; }
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            if (rep == 1 && ms < best_ms) { best_ms = ms; best = c; }
+            if (rep > 0 && ms < best_ms) { best_ms = ms; best = c; }
         }
         if (rc) break;
     }
