@@ -71,15 +71,17 @@ int ising_sweep(int8_t* spins, int64_t L, double beta, int64_t n_sweeps, uint64_
 int ising_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sweeps, uint64_t seed,
                     uint64_t sweep_offset, int64_t* trace_ME, void* stream);
 
-/* ising_sweep_fmt with both colours of a sweep in ONE pass over the lattice (Sec. 3.1: given one
- * colour, the other colour's sites are independent, so the black sites of a row can be updated as
- * soon as the white sites of the rows around it are).  Each pass reads one L x L buffer and writes
- * the other:
+/* ising_sweep_fmt with both colours of a sweep -- and by default two whole sweeps -- in ONE pass
+ * over the lattice (Sec. 3.1: given one colour, the other colour's sites are independent, so the
+ * black sites of a row can be updated as soon as the white sites of the rows around it are, and
+ * the next sweep's white sites of a row as soon as the black sites around it are).  Each pass
+ * reads one L x L buffer and writes the other:
  *   scratch   device int8[L * L], 16-byte aligned, disjoint from spins; its contents on return
  *             are unspecified.  The caller owns it.
  * On return `spins` holds the lattice after n_sweeps sweeps, bit-identical to ising_sweep_fmt
- * with the same arguments, and so is trace_ME.  Sweeps go spins -> scratch -> spins in pairs;
- * an odd count runs its first sweep in place.  Above L = 65536 every sweep runs in place as in
+ * with the same arguments, and so is trace_ME.  Passes alternate spins -> scratch -> spins, an
+ * even number of them; an odd count runs its first sweep in place.  Option "fused_sweeps" sets
+ * the sweeps per pass (2 by default, 1).  Above L = 65536 every sweep runs in place as in
  * ising_sweep_fmt (scratch unused).  Returns ISING_EINVAL for the checks of ising_sweep_fmt,
  * for a null, misaligned or overlapping scratch. */
 int ising_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, int fmt, int64_t n_sweeps,
@@ -90,6 +92,13 @@ int ising_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, in
  * receiving (M, E) of dst.  For a caller that manages its own pair of buffers (a captured graph
  * of alternating steps, say).  Above L = 65536: a device copy, then the two half-sweeps on dst. */
 int ising_sweep_fused_step(const int8_t* src, int8_t* dst, int64_t L, double beta, int fmt, uint64_t seed,
+                           uint64_t t, int64_t* out_ME, void* stream);
+
+/* Two sweeps, t and t + 1 (t + 1 < 2^32), in one pass out of place: dst = src after both (same
+ * buffers and conventions as ising_sweep_fused_step).  out_ME: NULL or device int64[4] receiving
+ * (M, E) after sweep t, then after sweep t + 1.  Above L = 65536: a device copy, then the four
+ * half-sweeps on dst. */
+int ising_sweep_fused_pair(const int8_t* src, int8_t* dst, int64_t L, double beta, int fmt, uint64_t seed,
                            uint64_t t, int64_t* out_ME, void* stream);
 
 /* One colour update (half of a sweep) for colour q in {0, 1} with sweep index t.
@@ -256,6 +265,7 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
  *   "fused_rows"     rows per workgroup strip of ising_sweep_fused: 0 = automatic, else a power
  *                    of two in [2, 256] (ignored for lattices it does not divide).
  *   "fused_alternate" 1 = odd strips of ising_sweep_fused walk upwards (default), 0 = all down.
+ *   "fused_sweeps"   sweeps per pass of ising_sweep_fused: 2 (default) or 1.
  *   "planes3"        planes each workgroup of ising3_sweep (each lane of ising3_sweep_packed)
  *                    walks: 0 = automatic, else a power of two in [2, 256] (ignored for lattices it
  *                    does not divide). */

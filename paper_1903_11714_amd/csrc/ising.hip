@@ -367,6 +367,171 @@ __global__ __launch_bounds__(1024) void k_sweep_fused(FusedArgs a) {
     if (OBS) block_accumulate(a.obs, active ? cnt.anti : 0u, active ? cnt.neg : 0u, active ? 1u : 0u, 64u * a.rows);
 }
 
+
+// ---- Two sweeps per pass: sweeps t and t + 1 in one walk down the strip.
+//
+// The walk of the one-sweep pass extended by one lagging row per colour update: at step x the
+// strip updates the white sites of row x (sweep t), the black sites of row x - 1 (sweep t), the
+// white sites of row x - 2 (sweep t + 1) and the black sites of row x - 3 (sweep t + 1).  Each
+// update finds its neighbours final for its sweep (the row below it was updated one update
+// earlier in the same step, the row above one step earlier), and all four share one column
+// parity, so one edge word per step (two bits per row, four rows) carries every horizontal
+// neighbour across a group edge.  The strip recomputes the rows its neighbours own that its own
+// rows depend on: it reads rows r0 - 4 .. r0 + R + 3, updates white sites of rows r0 - 3 ..
+// r0 + R + 2 and r0 - 1 .. r0 + R and black sites of rows r0 - 2 .. r0 + R + 1 and r0 ..
+// r0 + R - 1, and writes rows r0 .. r0 + R - 1 after sweep t + 1.  The result is two fused
+// sweeps, bit for bit.
+
+// Edge bits after a step: bits 2k, 2k + 1 = site 0 of the even columns and site 31 of the odd
+// columns of the k-th row (k = 0: the next row to be updated; then the updated rows below it).
+__device__ __forceinline__ uint32_t edge_word4(const RowBits& r0, const RowBits& r1, const RowBits& r2,
+                                               const RowBits& r3) {
+    return (r0.e & 1u) | ((r0.o >> 31) << 1) | ((r1.e & 1u) << 2) | ((r1.o >> 31) << 3) | ((r2.e & 1u) << 4) |
+           ((r2.o >> 31) << 5) | ((r3.e & 1u) << 6) | ((r3.o >> 31) << 7);
+}
+
+// One colour-Q update of the sites of `own` at column parity O; v0 / v1 = the rows on either side;
+// P = which bit pair of the edge word holds this row's neighbour across the group edge.  With
+// OBS and `count`, the sites' anti-aligned bonds and the row's -1 spins go to cnt.
+template <int O, int Q, int P, bool OBS>
+__device__ __forceinline__ void fused_update(RowBits& own, const RowBits& v0, const RowBits& v1, uint32_t nb,
+                                             const Thresholds& th, uint32_t g, uint32_t row, uint32_t t,
+                                             uint32_t key0, uint32_t key1, Counts& cnt, bool count) {
+    const uint32_t side = O ? own.e : own.o;
+    const uint32_t hs = O ? shift_next(side, (nb >> (2 * P)) & 1u) : shift_prev(side, (nb >> (2 * P + 1)) & 1u);
+    Counts c{0u, 0u};
+    const uint32_t F = decide<Q, OBS>(O ? own.o : own.e, O ? v0.o : v0.e, O ? v1.o : v1.e, side, hs,
+                                      Q == 0 ? side : 0u, th, g, row, t, key0, key1, c);
+    if (OBS && count) { cnt.anti += c.anti; cnt.neg += c.neg; }
+    if (O) own.o ^= F; else own.e ^= F;
+}
+
+// One step of the two-sweep walk with the first NU of its four updates (the walk's first steps
+// have rows below them that are not there yet).  w0 = the row of the white update of sweep t, w1
+// .. w4 the rows after it, wn the row before it; rows[k] = global row of update k.
+template <int O, int NU, bool OBS>
+__device__ __forceinline__ void fused2_step(RowBits& w4, RowBits& w3, RowBits& w2, RowBits& w1, RowBits& w0,
+                                            const RowBits& wn, uint32_t nb, const Thresholds& th, uint32_t g,
+                                            const uint32_t (&rows)[4], uint32_t t, uint32_t key0, uint32_t key1,
+                                            Counts& ct, Counts& ct1, bool count_t) {
+    fused_update<O, 1, 0, false>(w0, w1, wn, nb, th, g, rows[0], t, key0, key1, ct, false);
+    if (NU >= 2) fused_update<O, 0, 1, OBS>(w1, w2, w0, nb, th, g, rows[1], t, key0, key1, ct, count_t);
+    if (NU >= 3) fused_update<O, 1, 2, false>(w2, w3, w1, nb, th, g, rows[2], t + 1, key0, key1, ct1, false);
+    if (NU >= 4) fused_update<O, 0, 3, OBS>(w3, w4, w2, nb, th, g, rows[3], t + 1, key0, key1, ct1, true);
+}
+
+template <bool OBS, bool STAGED, bool UP>
+__device__ __forceinline__ void fused2_strip(const FusedArgs& a, uint32_t strip, uint4* fused_lds, Counts& ct,
+                                             Counts& ct1) {
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t G = a.groups, L = a.L, R = a.rows;
+    uint4* const stage = fused_lds + (tid >> 6) * 256u;  // STAGED: 4 KiB per wave
+    uint32_t* const xch = reinterpret_cast<uint32_t*>(fused_lds + (STAGED ? (nt >> 6) * 256u : 0u));
+    const bool active = tid < G;
+    const uint32_t g = active ? tid : G - 1;
+    const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
+    const uint32_t lane = tid & 63u;
+    const uint32_t r0 = strip * R;
+    const size_t col = (size_t)(STAGED ? g - lane : g) * 64u;
+    // walk row k = 0 .. R + 7: r0 - 4 .. r0 + R + 3 (down) or r0 + R + 3 .. r0 - 4 (up), wrapped
+    // onto the torus; prefetches past the last walk row are clamped to it
+    auto vrow = [&](uint32_t k) {
+        const uint32_t kk = k < R + 7 ? k : R + 7;
+        return (UP ? r0 + R + 3 + L - kk : r0 + L - 4 + kk) % L;
+    };
+    auto fetch = [&](Row& raw, uint32_t r) {
+        if (STAGED) load_row_coalesced(raw, a.src + (size_t)r * L + col, lane);
+        else load_row(raw, a.src + (size_t)r * L + col);
+    };
+    auto own = [&](const Row& raw) {
+        if (!STAGED) return row_bits(raw);
+        Row row;
+        regroup_to_owner(row, raw, stage, lane);
+        return row_bits(row);
+    };
+    auto put = [&](uint32_t r, const RowBits& b) {
+        Row row;
+        bits_to_row(row, b);
+        if (STAGED) store_row_coalesced(a.dst + (size_t)r * L + col, row, stage, lane, a.nt_store);
+        else if (active) store_row(a.dst + (size_t)r * L + col, row, a.nt_store);
+    };
+    // step s (s = 0 .. R + 5) updates walk rows s + 1 (white, t), s (black, t), s - 1 (white,
+    // t + 1), s - 2 (black, t + 1); its sites lie on columns of parity OA for even s, OB for odd s.
+    // A step with parity 1 takes the edge word of the right neighbour group, one with parity 0
+    // that of the left one; step s reads slot s & 1 and publishes into the other.
+    constexpr int OA = UP ? 1 : 0, OB = 1 - OA;
+    const uint32_t nbA = OA ? gr : gl, nbB = OB ? gr : gl;
+    const uint32_t t = a.t, k0 = a.key0, k1 = a.key1;
+    Row ra, rb;
+    fetch(ra, vrow(0));
+    fetch(rb, vrow(1));
+    RowBits w4{0u, 0u}, w3{0u, 0u}, w2{0u, 0u};
+    RowBits w1 = own(ra), w0 = own(rb);
+    fetch(ra, vrow(2));
+    fetch(rb, vrow(3));
+    RowBits n0 = own(ra), n1 = own(rb);
+    fetch(ra, vrow(4));
+    fetch(rb, vrow(5));
+    xch[tid] = edge_word4(w0, w1, w1, w1);  // slot 0: walk row 1 (the other pairs are not read)
+    workgroup_lds_sync();
+#define ISING_FUSED2_STEP(O, NU, NB, S, NEXT)                                                                 \
+    do {                                                                                                      \
+        const uint32_t s_ = (S);                                                                              \
+        const uint32_t rw[4] = {vrow(s_ + 1), vrow(s_), s_ >= 1 ? vrow(s_ - 1) : 0u, s_ >= 2 ? vrow(s_ - 2) : 0u}; \
+        fused2_step<O, NU, OBS>(w4, w3, w2, w1, w0, NEXT, xch[(s_ & 1u) * nt + (NB)], a.th, g, rw, t, k0, k1, ct, \
+                                ct1, s_ >= 4 && s_ <= R + 3);                                                 \
+        if (NU == 4) put(rw[3], w3);                                                                          \
+        xch[((s_ + 1) & 1u) * nt + tid] = edge_word4(NEXT, w0, w1, w2);                                       \
+        workgroup_lds_sync();                                                                                 \
+        w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = NEXT;                                                        \
+    } while (0)
+    // steps 0 .. 5: the updates that have rows below them
+    ISING_FUSED2_STEP(OA, 1, nbA, 0u, n0);
+    ISING_FUSED2_STEP(OB, 1, nbB, 1u, n1);
+    n0 = own(ra);
+    n1 = own(rb);
+    fetch(ra, vrow(6));
+    fetch(rb, vrow(7));
+    ISING_FUSED2_STEP(OA, 2, nbA, 2u, n0);
+    ISING_FUSED2_STEP(OB, 2, nbB, 3u, n1);
+    n0 = own(ra);
+    n1 = own(rb);
+    fetch(ra, vrow(8));
+    fetch(rb, vrow(9));
+    ISING_FUSED2_STEP(OA, 3, nbA, 4u, n0);
+    ISING_FUSED2_STEP(OB, 3, nbB, 5u, n1);
+    n0 = own(ra);
+    n1 = own(rb);
+    fetch(ra, vrow(10));
+    fetch(rb, vrow(11));
+    // steps 6 .. R + 5: all four updates, and the row of the last one is final
+#pragma unroll 1
+    for (uint32_t s = 6; s < R + 6; s += 2) {
+        ISING_FUSED2_STEP(OA, 4, nbA, s, n0);
+        ISING_FUSED2_STEP(OB, 4, nbB, s + 1, n1);
+        n0 = own(ra);  // walk rows s + 4, s + 5 for the next two steps
+        n1 = own(rb);
+        fetch(ra, vrow(s + 6));
+        fetch(rb, vrow(s + 7));
+    }
+#undef ISING_FUSED2_STEP
+}
+
+template <bool OBS, bool STAGED>
+__global__ __launch_bounds__(1024) void k_sweep_fused2(FusedArgs a) {
+    extern __shared__ uint4 fused_lds[];
+    const uint32_t strip = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
+    Counts ct{0u, 0u}, ct1{0u, 0u};
+    if (a.alternate && (strip & 1u)) fused2_strip<OBS, STAGED, true>(a, strip, fused_lds, ct, ct1);
+    else fused2_strip<OBS, STAGED, false>(a, strip, fused_lds, ct, ct1);
+    const bool active = threadIdx.x < a.groups;
+    if (OBS) {
+        block_accumulate(a.obs, active ? ct.anti : 0u, active ? ct.neg : 0u, active ? 1u : 0u, 64u * a.rows);
+        __syncthreads();  // block_accumulate's LDS is reused
+        block_accumulate(a.obs + 2, active ? ct1.anti : 0u, active ? ct1.neg : 0u, active ? 1u : 0u, 64u * a.rows);
+    }
+}
+
 // ---- observables of an int8 lattice: M = sum of spins, E = -sum over bonds (right, down).
 struct ObsArgs {
     const int8_t* spins;
@@ -1035,6 +1200,7 @@ struct Options {
     int64_t batch_lists_per_cu = 0;  // batch: work lists per compute unit of a split schedule; 0 = autotune
     int64_t fused_rows = 0;     // rows per strip of the fused sweep; 0 = choose from L
     int64_t fused_alternate = 1;  // fused sweep: odd strips walk upwards
+    int64_t fused_sweeps = 2;     // fused sweep: sweeps per pass over the lattice (1 or 2)
     int64_t planes3 = 0;          // 3-D sweep: planes per workgroup; 0 = choose from L
 };
 Options g_opt;
@@ -1176,23 +1342,28 @@ constexpr int64_t kFusedMaxL = 64 * 1024;
 
 // rows per strip of the fused sweep: even, divides L.  Every strip re-reads 4 rows and recomputes
 // the white sites of 2, so taller is cheaper; keep at least ~4096 waves in the grid, and 8..64 rows.
-uint32_t fused_rows(int64_t L) {
+// Rows per strip of a fused pass: the tallest (fewest re-read and recomputed rows around each
+// strip) that still leaves 4096 waves; a two-sweep pass recomputes four rows on either side, so
+// it starts from taller strips.
+uint32_t fused_rows(int64_t L, int sweeps = 1) {
     if (g_opt.fused_rows > 0 && L % g_opt.fused_rows == 0 && g_opt.fused_rows <= L) return (uint32_t)g_opt.fused_rows;
     const uint64_t waves = (uint64_t)(L / 64 + 63) / 64;
-    uint32_t R = 64;
+    uint32_t R = sweeps == 2 ? 128 : 64;
     while (R > 8 && (uint64_t)(L / R) * waves < 4096ull) R >>= 1;
     return R;
 }
 
 // one fused sweep src -> dst (L <= kFusedMaxL, src and dst disjoint); obs: (M, E), zeroed beforehand
+// One pass of the fused kernel: `sweeps` (1 or 2) sweeps t, t + 1 from src to dst; obs: NULL or
+// 2 * sweeps int64, zeroed beforehand.
 int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::Thresholds& th, uint64_t seed,
-                       uint32_t t, int64_t* obs, hipStream_t stream) {
+                       uint32_t t, int64_t* obs, hipStream_t stream, int sweeps = 1) {
     ising::FusedArgs a;
     a.src = src;
     a.dst = dst;
     a.L = (uint32_t)L;
     a.groups = (uint32_t)(L / 64);
-    a.rows = fused_rows(L);
+    a.rows = fused_rows(L, sweeps);
     a.t = t;
     a.key0 = (uint32_t)seed;
     a.key1 = (uint32_t)(seed >> 32);
@@ -1205,17 +1376,22 @@ int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::T
     const bool staged = g_opt.staged && a.groups % 64u == 0;
     const size_t lds = (staged ? (size_t)(threads / 64u) * 4096u : 0u) + 2u * threads * sizeof(uint32_t);
     const dim3 grid(a.L / a.rows), block(threads);
-#define ISING_LAUNCH_FUSED(OO, SS)                                                                       \
+#define ISING_LAUNCH_FUSED(K, OO, SS)                                                                    \
     do {                                                                                                 \
         if (lds > 65536) {                                                                               \
-            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ising::k_sweep_fused<OO, SS>), \
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ising::K<OO, SS>),   \
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-            if (e != hipSuccess) return hip_failed(e, "hipFuncSetAttribute(k_sweep_fused)");            \
+            if (e != hipSuccess) return hip_failed(e, "hipFuncSetAttribute(" #K ")");                   \
         }                                                                                                \
-        hipLaunchKernelGGL((ising::k_sweep_fused<OO, SS>), grid, block, lds, stream, a);                \
+        hipLaunchKernelGGL((ising::K<OO, SS>), grid, block, lds, stream, a);                            \
     } while (0)
-    if (staged) { if (obs) ISING_LAUNCH_FUSED(true, true); else ISING_LAUNCH_FUSED(false, true); }
-    else { if (obs) ISING_LAUNCH_FUSED(true, false); else ISING_LAUNCH_FUSED(false, false); }
+    if (sweeps == 2) {
+        if (staged) { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused2, true, true); else ISING_LAUNCH_FUSED(k_sweep_fused2, false, true); }
+        else { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused2, true, false); else ISING_LAUNCH_FUSED(k_sweep_fused2, false, false); }
+        return check_launch("k_sweep_fused2");
+    }
+    if (staged) { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused, true, true); else ISING_LAUNCH_FUSED(k_sweep_fused, false, true); }
+    else { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused, true, false); else ISING_LAUNCH_FUSED(k_sweep_fused, false, false); }
 #undef ISING_LAUNCH_FUSED
     return check_launch("k_sweep_fused");
 }
@@ -1671,12 +1847,23 @@ int ising_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, in
         const int rc = zero_trace(trace_ME + 2 * i, 2 * (n_sweeps - i), s);
         if (rc) return rc;
     }
-    for (; i < n_sweeps; i += 2) {
+    // The rest (an even count) in passes that alternate between the two buffers and end in
+    // `spins`: two sweeps per pass when the option allows, in an even number of passes (an odd
+    // number of two-sweep passes gives one of them up for two one-sweep passes).
+    const int64_t rest = n_sweeps - i;
+    int64_t pairs = g_opt.fused_sweeps == 2 ? rest / 2 : 0;
+    if (pairs & 1) --pairs;
+    int8_t* bufs[2] = {spins, scratch};
+    int64_t pass = 0;
+    while (i < n_sweeps) {
+        const int k = pairs > 0 ? 2 : 1;
         const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
-        int rc = launch_fused_sweep(spins, scratch, L, th, seed, t, trace_ME ? trace_ME + 2 * i : nullptr, s);
+        const int rc = launch_fused_sweep(bufs[pass & 1], bufs[(pass + 1) & 1], L, th, seed, t,
+                                          trace_ME ? trace_ME + 2 * i : nullptr, s, k);
         if (rc) return rc;
-        rc = launch_fused_sweep(scratch, spins, L, th, seed, t + 1, trace_ME ? trace_ME + 2 * i + 2 : nullptr, s);
-        if (rc) return rc;
+        if (k == 2) --pairs;
+        i += k;
+        ++pass;
     }
     return ISING_OK;
 }
@@ -1697,6 +1884,24 @@ int ising_sweep_fused_step(const int8_t* src, int8_t* dst, int64_t L, double bet
         if (rc) return rc;
     }
     return launch_fused_sweep(src, dst, L, make_thresholds(beta, fmt), seed, (uint32_t)t, out_ME, s);
+}
+
+int ising_sweep_fused_pair(const int8_t* src, int8_t* dst, int64_t L, double beta, int fmt, uint64_t seed,
+                           uint64_t t, int64_t* out_ME, void* stream) {
+    if (!src || !dst || !valid_L(L) || !aligned16(src) || !aligned16(dst) || !valid_beta(beta) || fmt < 0 ||
+        fmt > 2 || t + 1 >= (uint64_t(1) << 32) || !disjoint(src, dst, (uint64_t)L * (uint64_t)L))
+        return ISING_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (L > kFusedMaxL) {  // a copy, then two sweeps in place on the copy
+        const hipError_t e = hipMemcpyAsync(dst, src, (size_t)L * (size_t)L, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_failed(e, "hipMemcpyAsync");
+        return ising_sweep_fmt(dst, L, beta, fmt, 2, seed, t, out_ME, stream);
+    }
+    if (out_ME) {
+        const int rc = zero_trace(out_ME, 4, s);
+        if (rc) return rc;
+    }
+    return launch_fused_sweep(src, dst, L, make_thresholds(beta, fmt), seed, (uint32_t)t, out_ME, s, 2);
 }
 
 int ising_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* stream) {
@@ -1831,6 +2036,9 @@ int ising_set_option(const char* name, int64_t value) {
     } else if (n == "fused_alternate") {
         if (value != 0 && value != 1) return ISING_EINVAL;
         g_opt.fused_alternate = value;
+    } else if (n == "fused_sweeps") {
+        if (value != 1 && value != 2) return ISING_EINVAL;
+        g_opt.fused_sweeps = value;
     } else if (n == "fused_rows") {
         if (value != 0 && (value < 2 || value > 256 || (value & (value - 1)) != 0)) return ISING_EINVAL;
         g_opt.fused_rows = value;
@@ -1853,6 +2061,7 @@ int ising_get_option(const char* name, int64_t* value) {
     else if (n == "batch_lists_per_cu") *value = g_opt.batch_lists_per_cu;
     else if (n == "fused_rows") *value = g_opt.fused_rows;
     else if (n == "fused_alternate") *value = g_opt.fused_alternate;
+    else if (n == "fused_sweeps") *value = g_opt.fused_sweeps;
     else if (n == "planes3") *value = g_opt.planes3;
     else return ISING_EINVAL;
     return ISING_OK;

@@ -63,6 +63,8 @@ _SIGNATURES = {
                           ctypes.c_int),
     "ising_sweep_fused_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising_sweep_fused_pair": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
+                                ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "ising3_init": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p], ctypes.c_int),
     "ising3_fill": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "ising3_sweep": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64,
@@ -248,6 +250,13 @@ def ising_sweep_fused_step(src, dst, L: int, beta: float, fmt, seed: int, t: int
     _check("ising_sweep_fused_step", library().ising_sweep_fused_step(
         _dev_ptr(src, "torch.int8", L * L), _dev_ptr(dst, "torch.int8", L * L), L, float(beta), _fmt(fmt), seed, t,
         _opt_ptr(out_ME, "torch.int64", 2), _stream(stream)))
+
+
+def ising_sweep_fused_pair(src, dst, L: int, beta: float, fmt, seed: int, t: int, out_ME=None,
+                           stream=None) -> None:
+    _check("ising_sweep_fused_pair", library().ising_sweep_fused_pair(
+        _dev_ptr(src, "torch.int8", L * L), _dev_ptr(dst, "torch.int8", L * L), L, float(beta), _fmt(fmt), seed, t,
+        _opt_ptr(out_ME, "torch.int64", 4), _stream(stream)))
 
 
 def ising3_init(spins, L: int, seed: int, stream=None) -> None:

@@ -102,6 +102,10 @@ def test_argument_checks_before_any_launch(lib):
     assert lib.ising_sweep_fused_step(fake, fake, 64, 0.4, 0, 1, 0, null, null) == EINVAL
     assert lib.ising_sweep_fused_step(fake, other, 64, 0.4, 0, 1, 2**32, null, null) == EINVAL
     assert lib.ising_sweep_fused_step(fake, other, 96, 0.4, 0, 1, 0, null, null) == EINVAL
+    assert lib.ising_sweep_fused_pair(fake, fake, 64, 0.4, 0, 1, 0, null, null) == EINVAL
+    assert lib.ising_sweep_fused_pair(fake, other, 64, 0.4, 0, 1, 2**32 - 1, null, null) == EINVAL
+    assert lib.ising_sweep_fused_pair(fake, other, 96, 0.4, 0, 1, 0, null, null) == EINVAL
+    assert lib.ising_sweep_fused_pair(fake, other, 64, -1.0, 0, 1, 0, null, null) == EINVAL
 
 
 @pytest.mark.parametrize("beta", [0.0, 0.1, 0.2216546, 0.35, 2.0, math.inf])
@@ -122,7 +126,7 @@ def test_options_round_trip(lib):
     from paper_1903_11714_amd import ising
     for name, good, bad in (("rows_per_lane", [0, 2, 64], [1, 3, 128, -2]), ("xcd_remap", [0, 1], [2]),
                             ("staged", [0, 1], [-1]), ("nt_store", [0, 1], [5]),
-                            ("fused_rows", [0, 2, 16, 256], [1, 6, 512, -4]), ("fused_alternate", [0, 1], [2]),
+                            ("fused_rows", [0, 2, 16, 256], [1, 6, 512, -4]), ("fused_alternate", [0, 1], [2]), ("fused_sweeps", [1, 2], [0, 3]),
                             ("planes3", [0, 2, 32, 256], [1, 3, 512]),
                             ("batch_threads", [0, 256, 512, 1024], [128, 2048, -1]),
                             ("batch_slab_sites", [0, -1, 1024, 65536, 262144], [512, 3000, 524288, -2]),

@@ -98,22 +98,65 @@ def test_fused_equals_two_half_sweeps_for_every_strip_height(dev, L):
     dev.ising_sweep_fmt(ref, L, BETA_C, "exact", 4, 17, 40, ref_tr)
     scratch = torch.empty_like(base)
     try:
-        for rows in (0, 2, 4, 8, 16, 32, 64, 128, 256):
-            if rows and (L % rows or rows > L):
-                continue
-            for remap, staged, alt in ((1, 1, 1), (0, 1, 1), (1, 0, 1), (1, 1, 0), (0, 0, 0)):
-                dev.ising_set_option("fused_rows", rows)
-                dev.ising_set_option("xcd_remap", remap)
-                dev.ising_set_option("staged", staged)
-                dev.ising_set_option("fused_alternate", alt)
-                s = base.clone()
-                tr = torch.empty((4, 2), dtype=torch.int64, device="cuda")
-                dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", 4, 17, 40, tr)
-                assert torch.equal(s, ref), (rows, remap, staged, alt)
-                assert torch.equal(tr, ref_tr), (rows, remap, staged, alt)
+        for sweeps in (1, 2):
+            dev.ising_set_option("fused_sweeps", sweeps)
+            for rows in (0, 2, 4, 8, 16, 32, 64, 128, 256):
+                if rows and (L % rows or rows > L):
+                    continue
+                for remap, staged, alt in ((1, 1, 1), (0, 1, 1), (1, 0, 1), (1, 1, 0), (0, 0, 0)):
+                    dev.ising_set_option("fused_rows", rows)
+                    dev.ising_set_option("xcd_remap", remap)
+                    dev.ising_set_option("staged", staged)
+                    dev.ising_set_option("fused_alternate", alt)
+                    s = base.clone()
+                    tr = torch.empty((4, 2), dtype=torch.int64, device="cuda")
+                    dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", 4, 17, 40, tr)
+                    assert torch.equal(s, ref), (sweeps, rows, remap, staged, alt)
+                    assert torch.equal(tr, ref_tr), (sweeps, rows, remap, staged, alt)
     finally:
-        for k, v in (("fused_rows", 0), ("xcd_remap", 1), ("staged", 1), ("fused_alternate", 1)):
+        for k, v in (("fused_rows", 0), ("xcd_remap", 1), ("staged", 1), ("fused_alternate", 1), ("fused_sweeps", 2)):
             dev.ising_set_option(k, v)
+
+
+@pytest.mark.parametrize("L", [192, 4096])
+def test_fused_sweep_counts_with_one_and_two_sweeps_per_pass(dev, L):
+    # every count splits into passes of one or two sweeps that end in the caller's buffer
+    _say("fused counts", L)
+    base = torch.empty((L, L), dtype=torch.int8, device="cuda")
+    dev.ising_init(base, L, 23)
+    scratch = torch.empty_like(base)
+    try:
+        for n in range(0, 8):
+            ref = base.clone()
+            ref_tr = torch.empty((max(n, 1), 2), dtype=torch.int64, device="cuda")
+            dev.ising_sweep_fmt(ref, L, 0.41, "exact", n, 23, 9, ref_tr[:n])
+            for sweeps in (1, 2):
+                dev.ising_set_option("fused_sweeps", sweeps)
+                s = base.clone()
+                tr = torch.empty((max(n, 1), 2), dtype=torch.int64, device="cuda")
+                dev.ising_sweep_fused(s, scratch, L, 0.41, "exact", n, 23, 9, tr[:n])
+                assert torch.equal(s, ref), (n, sweeps)
+                assert torch.equal(tr[:n], ref_tr[:n]), (n, sweeps)
+    finally:
+        dev.ising_set_option("fused_sweeps", 2)
+
+
+@pytest.mark.parametrize("L,fmt", [(64, "exact"), (192, "bf16"), (4096, "exact")])
+def test_fused_pair_is_two_sweeps_out_of_place(dev, oracle_lib, L, fmt):
+    _say("fused pair", L, fmt)
+    host = oracle_lib.init(L, 31)
+    src = _to_dev(host)
+    keep = src.clone()
+    dst = torch.empty_like(src)
+    me = torch.empty((2, 2), dtype=torch.int64, device="cuda")
+    dev.ising_sweep_fused_pair(src, dst, L, BETA_C, fmt, 31, 12, me)
+    if fmt == "exact":
+        ref = oracle_lib.sweep(host, BETA_C, 2, 31, 12, trace=True)
+    else:
+        ref = oracle_lib.sweep_fmt(host, BETA_C, fmt, 2, 31, 12, trace=True)
+    assert torch.equal(src, keep)
+    assert np.array_equal(dst.cpu().numpy(), host)
+    assert np.array_equal(me.cpu().numpy(), ref)
 
 
 def test_fused_full_size_16384_crops_and_trace(dev, oracle_lib):
