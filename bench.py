@@ -49,18 +49,41 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(layout: str, L: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
-    kernel source changed since the counters were taken."""
+def measured_counters(layout: str, L: int) -> dict:
+    """The committed rocprofv3 counter summary of this layout's kernel at this size (HBM bytes
+    and VALU instructions per launch), or {} when the kernel source changed since the counters
+    were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
     entry = rec.get(f"{layout}_L{L}")
     if not entry or entry.get("source_hash") != kernel_source_hash():
+        return {}
+    return entry
+
+
+def measured_traffic(layout: str, L: int):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    return measured_counters(layout, L).get("hbm_bytes_per_launch")
+
+
+# vector ALU issue peak for 32-bit integer work: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64
+# instruction takes 4 cycles on a 16-lane SIMD; integer ops have no packed two-per-lane form)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def alu_roofline(layout: str, L: int, avg_launch_ms: float):
+    """Lane operations per second of the kernel's VALU instructions (count from the committed
+    counters, time from this run) against the integer VALU peak, with rocprofv3's VALUBusy."""
+    c = measured_counters(layout, L)
+    if "valu_insts_per_launch" not in c:
         return None
-    return entry.get("hbm_bytes_per_launch")
+    achieved = c["valu_insts_per_launch"] * 64 / (avg_launch_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
+            "frac": achieved / VALU_PEAK_TOPS, "valu_busy": c.get("valu_busy_pct", 0.0) / 100.0,
+            "valu_insts_per_launch": c["valu_insts_per_launch"]}
 
 
 FUSED_MAX_L = 65536  # one workgroup thread per 64-column group, at most 1024 threads
@@ -419,12 +442,24 @@ def main() -> int:
         "gpu_event_ms": main["gpu_ms"],
         "final_ME": main["final_ME"],
     }
+    # The bound is the resource the kernel uses the larger share of: HBM (algorithmic bytes per
+    # launch over the launch time) or the vector ALU (its VALU instructions per launch, from the
+    # committed counters, over the launch time); the other one is reported beside it.
+    alu = alu_roofline(args.layout, L, main["avg_launch_ms"])
+    if alu is not None and alu["frac"] > result["roofline"]["frac"]:
+        hbm = {k: result["roofline"].pop(k) for k in ("bound", "achieved", "peak", "unit", "frac")}
+        rest = result["roofline"]
+        result["roofline"] = {**{k: alu[k] for k in ("bound", "achieved", "peak", "unit", "frac")}, **rest,
+                              "valu_busy": alu["valu_busy"], "valu_insts_per_launch": alu["valu_insts_per_launch"],
+                              "hbm": hbm}
+    elif alu is not None:
+        result["roofline"]["alu"] = alu
     # context for the roofline: a plain device-to-device copy of an L^2-byte buffer (out of place,
     # as the fused sweep moves its bytes) on the same GPU
     cb = copy_bandwidth(torch, L, stream)
     result["roofline"]["copy_GBs"] = cb
     result["roofline"]["copy_kind"] = "out of place"
-    result["roofline"]["frac_of_copy"] = achieved / cb if cb else None
+    result["roofline"]["hbm_frac_of_copy"] = achieved / cb if cb else None
     if args.compare and args.layout == "fused":
         # the same workload with the acceptance test in bfloat16 and in half (the chain differs:
         # u < p with both rounded to the format), on the same fused kernel
