@@ -217,6 +217,25 @@ def bench_3d(ising, torch, args, stream) -> dict:
                                 "kernel": "k_sweep3_packed (one colour per launch)",
                                 "avg_launch_us": ev0.elapsed_time(ev1) * 1e3 / (2 * kp)}
         del planes
+        # the same chain with both colours per pass, out of place (bit-identical spins)
+        kf = max(K // 4, 2) // 2 * 2
+        buf = torch.empty(2 * L ** 3, dtype=torch.int8, device=dev)
+        lat, scr = buf[:L ** 3].view(L, L, L), buf[L ** 3:].view(L, L, L)
+        ising.ising3_init(lat, L, seed, stream)
+        if W:
+            ising.ising3_sweep_fused(lat, scr, L, beta, W - W % 2, seed, 0, None, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        ising.ising3_sweep_fused(lat, scr, L, beta, kf, seed, W - W % 2, trace[:kf], stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        fw = time.perf_counter() - t0
+        fl_us = ev0.elapsed_time(ev1) * 1e3 / kf
+        res["fused_layout"] = {"value": float(L) ** 3 * kf / (fw * 1e9), "unit": "attempts/ns", "steps": kf,
+                               "kernel": "k_sweep3_fused (both colours per launch)", "avg_launch_us": fl_us,
+                               "hbm_GBs": 2.0 * L ** 3 / (fl_us * 1e-6) / 1e9}
+        del buf, lat, scr
     if args.copy_calibration:
         calibration_copies(torch, 16384 * 16384, args.copy_calibration)
     if not args.no_cpu_baseline:

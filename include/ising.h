@@ -124,6 +124,23 @@ int ising3_init(int8_t* spins, int64_t L, uint64_t seed, void* stream);
 int ising3_fill(int8_t* spins, int64_t L, int value, void* stream);
 int ising3_sweep(int8_t* spins, int64_t L, double beta, int64_t n_sweeps, uint64_t seed, uint64_t sweep_offset,
                  int64_t* trace_ME, void* stream);
+
+/* ising3_sweep with both colours of a sweep in ONE pass over the lattice, out of place (as
+ * ising_sweep_fused on the square lattice): each pass reads one L^3 buffer and writes the other.
+ *   scratch   device int8[L^3], 16-byte aligned, disjoint from spins; contents on return
+ *             unspecified; caller-owned.
+ * On return `spins` holds the lattice after n_sweeps sweeps, bit-identical to ising3_sweep, and
+ * so is trace_ME.  Sweeps go spins -> scratch -> spins in pairs; an odd count runs its first
+ * sweep in place.  ISING_EINVAL for the checks of ising3_sweep and a null, misaligned or
+ * overlapping scratch. */
+int ising3_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, int64_t n_sweeps, uint64_t seed,
+                       uint64_t sweep_offset, int64_t* trace_ME, void* stream);
+
+/* One sweep with index t (< 2^32) out of place: dst = the sweep of src (device int8[L^3] each,
+ * 16-byte aligned, disjoint; src unchanged).  out_ME: NULL or device int64[2] receiving (M, E)
+ * of dst. */
+int ising3_sweep_fused_step(const int8_t* src, int8_t* dst, int64_t L, double beta, uint64_t seed, uint64_t t,
+                            int64_t* out_ME, void* stream);
 int ising3_half_sweep(int8_t* spins, int64_t L, double beta, uint64_t seed, uint64_t t, int q, void* stream);
 int ising3_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* stream);
 /* out[0..2] = T_2, T_4, T_6 (host). */

@@ -437,7 +437,9 @@ __device__ __forceinline__ void fused2_strip(const FusedArgs& a, uint32_t strip,
     // onto the torus; prefetches past the last walk row are clamped to it
     auto vrow = [&](uint32_t k) {
         const uint32_t kk = k < R + 7 ? k : R + 7;
-        return (UP ? r0 + R + 3 + L - kk : r0 + L - 4 + kk) % L;
+        uint32_t v = UP ? r0 + R + 3 + L - kk : r0 + L - 4 + kk;  // in [L - 4, 2L + 4) since R <= L
+        v = v >= L ? v - L : v;
+        return v >= L ? v - L : v;
     };
     auto fetch = [&](Row& raw, uint32_t r) {
         if (STAGED) load_row_coalesced(raw, a.src + (size_t)r * L + col, lane);

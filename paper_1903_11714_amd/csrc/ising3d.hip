@@ -213,6 +213,174 @@ __global__ __launch_bounds__(512) void k_sweep3(Sweep3Args a) {
     if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, 1u, 64u * Rz, 3u);
 }
 
+// ---- Fused 3-D sweep: both colours of a sweep in one pass, out of place (src -> dst).
+//
+// A workgroup owns Y rows of every plane of a run of Rz planes and walks it in z.  At step k it
+// updates the white sites of plane z0 - 1 + k and then the black sites of the plane before it,
+// whose six neighbours (white sites of planes z - 1, z + 1 and of rows y - 1, y + 1, x - 1, x + 1
+// of plane z) are final by then (Sec. 3.1, in three dimensions).  A white update reads only values
+// the sweep has not changed, so the workgroup recomputes the white sites it needs outside its own
+// rows and planes: the planes just before and after its run (from the walk), and, when Y < L, the
+// rows just above and below its own in every plane -- one extra wave holds those two halo rows,
+// and each halo lane also reads the row beyond its halo row (its outer y neighbour).  One LDS
+// exchange per step gives every row its y and x neighbours: the plane being updated as it was,
+// and the plane before it after its white update.
+struct Fused3Args {
+    const int8_t* src;
+    int8_t* dst;
+    uint32_t L, G;        // G = L / 64 groups per row
+    uint32_t Y, ystrips;  // own rows per workgroup and L / Y
+    uint32_t Rz;          // planes per workgroup (even, divides L)
+    uint32_t t, key0, key1;
+    Thresholds3 th;
+    int64_t* obs;         // OBS: (M, E) accumulator, zeroed beforehand
+    uint32_t xcd_remap;
+};
+
+template <bool OBS, bool HALO>
+__global__ __launch_bounds__(576) void k_sweep3_fused(Fused3Args a) {
+    extern __shared__ uint4 f3_lds[];
+    const uint32_t tid = threadIdx.x, nt = blockDim.x, lane = tid & 63u;
+    const uint32_t L = a.L, G = a.G, Y = a.Y, Rz = a.Rz, own_n = Y * G;
+    uint4* const stage = f3_lds + (tid >> 6) * 256u;                          // own waves: 4 KiB each
+    uint4* const xch = f3_lds + (own_n >> 6) * 256u;                          // two slots of nt entries
+    const uint32_t b = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
+    const uint32_t y0 = (b % a.ystrips) * Y, z0 = (b / a.ystrips) * Rz;
+    const bool own = tid < own_n;
+    const uint32_t hh = own ? 0u : (tid - own_n) / G;   // halo lanes: 0 = row above, 1 = row below
+    const bool halo = HALO && !own && hh < 2u;          // lanes past the halo rows only shadow
+    const uint32_t g = own ? tid % G : (halo ? (tid - own_n) % G : 0u);
+    const uint32_t yy = own ? tid / G : 0u;
+    const uint32_t wrapy = L - 1u;  // L is a power of two
+    const uint32_t y = own ? y0 + yy : (hh == 0u ? (y0 + L - 1u) & wrapy : (y0 + Y) & wrapy);
+    const uint32_t yo = hh == 0u ? (y0 + L - 2u) & wrapy : (y0 + Y + 1u) & wrapy;  // halo lanes' outer row
+    const size_t plane = (size_t)L * L;
+    const size_t seg = (size_t)y0 * L + (size_t)(tid >> 6) * 4096u;          // own waves' rows in a plane
+    // plane of walk index k = 0 .. Rz + 3: z0 - 2 .. z0 + Rz + 1, wrapped; prefetches past the last
+    // one are clamped to it
+    auto zplane = [&](uint32_t k) { return (z0 + L - 2u + (k < Rz + 3u ? k : Rz + 3u)) & wrapy; };
+    auto fetch = [&](Row& raw, uint32_t z) {
+        if (own) load_row_coalesced(raw, a.src + z * plane + seg, lane);
+        else if (halo) load_row(raw, a.src + ((size_t)z * L + y) * L + (size_t)g * 64u);
+    };
+    auto bits = [&](const Row& raw) {
+        if (!own) return halo ? row_bits(raw) : RowBits{0u, 0u};
+        Row row;
+        regroup_to_owner(row, raw, stage, lane);
+        return row_bits(row);
+    };
+    auto fetch_outer = [&](Row& raw, uint32_t z) {
+        if (halo) load_row(raw, a.src + ((size_t)z * L + yo) * L + (size_t)g * 64u);
+    };
+    auto put = [&](uint32_t z, const RowBits& rb) {
+        Row row;
+        bits_to_row(row, rb);
+        if (own) store_row_coalesced(a.dst + z * plane + seg, row, stage, lane, false);
+    };
+    // neighbour entries: same row, next / previous group; rows above / below (own rows wrap when
+    // the workgroup holds whole planes; otherwise rows 0 and Y - 1 meet the halo lanes, and the
+    // halo lanes meet row 0 / Y - 1 on one side and their outer row on the other)
+    const bool shadow = !own && !halo;  // lanes past the halo rows read their own entry
+    const uint32_t ir = shadow ? tid : (g + 1 < G ? tid + 1 : tid + 1 - G);
+    const uint32_t il = shadow ? tid : (g > 0 ? tid - 1 : tid + G - 1);
+    uint32_t iym, iyp;
+    if (shadow) {
+        iym = iyp = tid;
+    } else if (own) {
+        iym = yy > 0 ? tid - G : (HALO ? own_n + g : tid + (Y - 1) * G);
+        iyp = yy + 1 < Y ? tid + G : (HALO ? own_n + G + g : tid - (Y - 1) * G);
+    } else {
+        iym = hh == 0u ? tid : (Y - 1) * G + g;   // hh == 0: the outer row stands in (below)
+        iyp = hh == 0u ? g : tid;                 // hh == 1: the outer row stands in
+    }
+    Counts cnt{0u, 0u};
+    // One step: white sites of plane zw (window p0), then black sites of plane zw - 1 (p1) when B.
+    // Planes: pn = zw + 1, p0 = zw, p1 = zw - 1, p2 = zw - 2; out = the halo lanes' outer row of
+    // plane zw (black sites as they were).
+    auto step = [&](bool B, uint32_t zw, uint32_t slot, const RowBits& pn, RowBits& p0, RowBits& p1, const RowBits& p2,
+                    const RowBits& out) {
+        uint4* const x = xch + slot * nt;
+        x[tid] = make_uint4(p0.e, p0.o, p1.e, p1.o);
+        workgroup_lds_sync();
+        const bool O = ((1u + y + zw) & 1u) != 0;  // column parity of the white sites of row y of plane zw,
+                                                   // and of the black sites of row y of plane zw - 1
+        {   // white sites of plane zw (neighbours: black sites as they were)
+            uint4 ym = x[iym], yp = x[iyp];
+            if (HALO && !own && hh == 0u) ym = make_uint4(out.e, out.o, 0u, 0u);
+            if (HALO && !own && hh == 1u) yp = make_uint4(out.e, out.o, 0u, 0u);
+            const uint32_t right_e = x[ir].x, left_o = x[il].y;
+            const uint32_t sites = O ? p0.o : p0.e, side = O ? p0.e : p0.o;
+            const uint32_t hs = O ? shift_next(p0.e, right_e & 1u) : shift_prev(p0.o, left_o >> 31);
+            const uint32_t nb[6] = {O ? ym.y : ym.x, O ? yp.y : yp.x, O ? p1.o : p1.e, O ? pn.o : pn.e, side, hs};
+            Counts none{0u, 0u};
+            const uint32_t F = decide3<false>(sites, nb, side, a.th, g, zw * L + y, a.t, 1u, a.key0, a.key1, none);
+            if (O) p0.o ^= F; else p0.e ^= F;
+        }
+        if (B && own) {   // black sites of plane zw - 1 (neighbours: white sites after this sweep)
+            const uint32_t z = (zw + L - 1u) & wrapy;
+            const uint4 ym = x[iym], yp = x[iyp];
+            const uint32_t right_e = x[ir].z, left_o = x[il].w;
+            const uint32_t sites = O ? p1.o : p1.e, side = O ? p1.e : p1.o;
+            const uint32_t hs = O ? shift_next(p1.e, right_e & 1u) : shift_prev(p1.o, left_o >> 31);
+            const uint32_t nb[6] = {O ? ym.w : ym.z, O ? yp.w : yp.z, O ? p2.o : p2.e, O ? p0.o : p0.e, side, hs};
+            const uint32_t F = decide3<OBS>(sites, nb, side, a.th, g, z * L + y, a.t, 0u, a.key0, a.key1, cnt);
+            if (O) p1.o ^= F; else p1.e ^= F;
+            put(z, p1);
+        }
+    };
+    // prologue: planes z0 - 2, z0 - 1, z0 in bits, z0 + 1, z0 + 2 in flight; outer rows of planes
+    // z0 - 1, z0 in bits, z0 + 1, z0 + 2 in flight
+    Row ra, rb, oa, ob;
+    fetch(ra, zplane(0));
+    fetch(rb, zplane(1));
+    RowBits p2{0u, 0u}, p1 = bits(ra), p0 = bits(rb);
+    fetch(ra, zplane(2));
+    RowBits pn = bits(ra), nx{0u, 0u};
+    fetch(ra, zplane(3));
+    fetch(rb, zplane(4));
+    RowBits o0{0u, 0u}, o1{0u, 0u};
+    if (HALO) {
+        fetch_outer(oa, zplane(1));
+        fetch_outer(ob, zplane(2));
+        o0 = halo ? row_bits(oa) : RowBits{0u, 0u};
+        o1 = halo ? row_bits(ob) : RowBits{0u, 0u};
+        fetch_outer(oa, zplane(3));
+        fetch_outer(ob, zplane(4));
+    }
+    // steps 0, 1: white sites of planes z0 - 1 and z0 only (plane z0 - 2, z0 - 1 are not this
+    // workgroup's to update)
+    step(false, zplane(1), 0u, pn, p0, p1, p2, o0);
+    p2 = p1; p1 = p0; p0 = pn; pn = bits(ra);
+    step(false, zplane(2), 1u, pn, p0, p1, p2, o1);
+    p2 = p1; p1 = p0; p0 = pn; pn = bits(rb);
+    fetch(ra, zplane(5));
+    fetch(rb, zplane(6));
+    if (HALO) {
+        o0 = halo ? row_bits(oa) : RowBits{0u, 0u};
+        o1 = halo ? row_bits(ob) : RowBits{0u, 0u};
+        fetch_outer(oa, zplane(5));
+        fetch_outer(ob, zplane(6));
+    }
+    // steps k = 2 .. Rz + 1: white sites of plane z0 - 1 + k, black sites of plane z0 - 2 + k
+#pragma unroll 1
+    for (uint32_t k = 2; k < Rz + 2; k += 2) {
+        step(true, zplane(k + 1), 0u, pn, p0, p1, p2, o0);
+        p2 = p1; p1 = p0; p0 = pn; pn = bits(ra);
+        step(true, zplane(k + 2), 1u, pn, p0, p1, p2, o1);
+        p2 = p1; p1 = p0; p0 = pn; pn = bits(rb);
+        fetch(ra, zplane(k + 5));
+        fetch(rb, zplane(k + 6));
+        if (HALO) {
+            o0 = halo ? row_bits(oa) : RowBits{0u, 0u};
+            o1 = halo ? row_bits(ob) : RowBits{0u, 0u};
+            fetch_outer(oa, zplane(k + 5));
+            fetch_outer(ob, zplane(k + 6));
+        }
+    }
+    (void)nx;
+    if (OBS) block_accumulate(a.obs, own ? cnt.anti : 0u, own ? cnt.neg : 0u, own ? 1u : 0u, 64u * Rz, 3u);
+}
+
 // (M, E) of a cubic lattice: each lane one 64-column group of one row; bonds to +x, +y, +z.
 __global__ __launch_bounds__(256) void k_observables3(const int8_t* spins, uint32_t L, uint32_t G, uint64_t n_lanes,
                                                       int64_t* out) {
@@ -514,6 +682,59 @@ dim3 grid3(uint64_t n_lanes) { return dim3((unsigned)((n_lanes + 255) / 256)); }
 
 }  // namespace
 
+namespace {
+
+// One fused sweep src -> dst: workgroups of Y own rows (W waves) plus, when Y < L, one wave with
+// the two halo rows; Rz planes each.
+// Planes per workgroup of the fused pass: it recomputes the planes on either side of its run, so
+// it takes the tallest run (up to 128, at least 8) that still leaves ~9 waves per compute unit
+// (256 CUs); option "planes3" overrides.
+Shape3 shape3_fused(int64_t L) {
+    Shape3 s = shape3(L);
+    if (ising_host::option("planes3") > 0) return s;
+    const uint32_t waves = s.W + ((int64_t)s.Y < L ? 1u : 0u);
+    uint32_t Rz = 128;
+    while (Rz > 8 && (L % Rz != 0 || (uint64_t)s.ystrips * (uint64_t)(L / Rz) * waves < 2304u)) Rz >>= 1;
+    if (L % Rz == 0) s.Rz = Rz;
+    return s;
+}
+
+int launch_sweep3_fused(const int8_t* src, int8_t* dst, int64_t L, const ising::Thresholds3& th, uint64_t seed,
+                        uint32_t t, int64_t* obs, hipStream_t stream) {
+    const Shape3 sh = shape3_fused(L);
+    ising::Fused3Args a;
+    a.src = src;
+    a.dst = dst;
+    a.L = (uint32_t)L;
+    a.G = (uint32_t)(L / 64);
+    a.Y = sh.Y;
+    a.ystrips = sh.ystrips;
+    a.Rz = sh.Rz;
+    a.t = t;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.th = th;
+    a.obs = obs;
+    a.xcd_remap = ising_host::xcd_remap() ? 1u : 0u;
+    const bool halo = (int64_t)sh.Y < L;
+    const uint32_t own = sh.W * 64u;
+    const uint32_t threads = halo ? (own + 2u * a.G + 63u) / 64u * 64u : own;
+    const size_t lds = (size_t)sh.W * 4096u + 2u * threads * sizeof(uint4);
+    const dim3 grid(sh.ystrips * (uint32_t)(L / sh.Rz)), block(threads);
+#define ISING_LAUNCH3F(OO, HH) hipLaunchKernelGGL((ising::k_sweep3_fused<OO, HH>), grid, block, lds, stream, a)
+    if (halo) { if (obs) ISING_LAUNCH3F(true, true); else ISING_LAUNCH3F(false, true); }
+    else { if (obs) ISING_LAUNCH3F(true, false); else ISING_LAUNCH3F(false, false); }
+#undef ISING_LAUNCH3F
+    return ising_host::check_launch("k_sweep3_fused");
+}
+
+bool disjoint3(const void* x, const void* y, uint64_t bytes) {
+    const uintptr_t p = reinterpret_cast<uintptr_t>(x), q = reinterpret_cast<uintptr_t>(y);
+    return p + bytes <= q || q + bytes <= p;
+}
+
+}  // namespace
+
 extern "C" {
 
 int ising3_pack(const int8_t* spins, int64_t L, uint32_t* planes, void* stream) {
@@ -607,6 +828,49 @@ int ising3_sweep(int8_t* spins, int64_t L, double beta, int64_t n_sweeps, uint64
         if (rc) return rc;
     }
     return ISING_OK;
+}
+
+int ising3_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, int64_t n_sweeps, uint64_t seed,
+                       uint64_t sweep_offset, int64_t* trace_ME, void* stream) {
+    if (!spins || !scratch || !valid_L3(L) || !ising_host::aligned16(spins) || !ising_host::aligned16(scratch) ||
+        !ising_host::valid_beta(beta) || n_sweeps < 0 || sweep_offset > (uint64_t(1) << 32) ||
+        (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset ||
+        !disjoint3(spins, scratch, (uint64_t)L * (uint64_t)L * (uint64_t)L))
+        return ISING_EINVAL;
+    const ising::Thresholds3 th = make_thresholds3(beta);
+    hipStream_t s = (hipStream_t)stream;
+    int64_t i = 0;
+    if (n_sweeps & 1) {  // an odd count: the first sweep in place, so that the pairs end in `spins`
+        const int rc = ising3_sweep(spins, L, beta, 1, seed, sweep_offset, trace_ME, stream);
+        if (rc) return rc;
+        i = 1;
+    }
+    if (trace_ME) {
+        const int rc = ising_host::zero_trace(trace_ME + 2 * i, 2 * (n_sweeps - i), s);
+        if (rc) return rc;
+    }
+    for (; i < n_sweeps; i += 2) {
+        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
+        int rc = launch_sweep3_fused(spins, scratch, L, th, seed, t, trace_ME ? trace_ME + 2 * i : nullptr, s);
+        if (rc) return rc;
+        rc = launch_sweep3_fused(scratch, spins, L, th, seed, t + 1, trace_ME ? trace_ME + 2 * i + 2 : nullptr, s);
+        if (rc) return rc;
+    }
+    return ISING_OK;
+}
+
+int ising3_sweep_fused_step(const int8_t* src, int8_t* dst, int64_t L, double beta, uint64_t seed, uint64_t t,
+                            int64_t* out_ME, void* stream) {
+    if (!src || !dst || !valid_L3(L) || !ising_host::aligned16(src) || !ising_host::aligned16(dst) ||
+        !ising_host::valid_beta(beta) || t >= (uint64_t(1) << 32) ||
+        !disjoint3(src, dst, (uint64_t)L * (uint64_t)L * (uint64_t)L))
+        return ISING_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (out_ME) {
+        const int rc = ising_host::zero_trace(out_ME, 2, s);
+        if (rc) return rc;
+    }
+    return launch_sweep3_fused(src, dst, L, make_thresholds3(beta), seed, (uint32_t)t, out_ME, s);
 }
 
 int ising3_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* stream) {

@@ -69,6 +69,10 @@ _SIGNATURES = {
     "ising3_fill": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "ising3_sweep": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64,
                       ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising3_sweep_fused": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int64,
+                            ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "ising3_sweep_fused_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
+                                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "ising3_half_sweep": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                            ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "ising3_observables": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
@@ -272,6 +276,19 @@ def ising3_sweep(spins, L: int, beta: float, n_sweeps: int, seed: int, sweep_off
     _check("ising3_sweep", library().ising3_sweep(
         _dev_ptr(spins, "torch.int8", L ** 3), L, float(beta), n_sweeps, seed, sweep_offset,
         _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
+
+
+def ising3_sweep_fused(spins, scratch, L: int, beta: float, n_sweeps: int, seed: int, sweep_offset: int = 0,
+                       trace_ME=None, stream=None) -> None:
+    _check("ising3_sweep_fused", library().ising3_sweep_fused(
+        _dev_ptr(spins, "torch.int8", L ** 3), _dev_ptr(scratch, "torch.int8", L ** 3), L, float(beta), n_sweeps,
+        seed, sweep_offset, _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
+
+
+def ising3_sweep_fused_step(src, dst, L: int, beta: float, seed: int, t: int, out_ME=None, stream=None) -> None:
+    _check("ising3_sweep_fused_step", library().ising3_sweep_fused_step(
+        _dev_ptr(src, "torch.int8", L ** 3), _dev_ptr(dst, "torch.int8", L ** 3), L, float(beta), seed, t,
+        _opt_ptr(out_ME, "torch.int64", 2), _stream(stream)))
 
 
 def ising3_half_sweep(spins, L: int, beta: float, seed: int, t: int, q: int, stream=None) -> None:

@@ -86,6 +86,14 @@ def test_argument_checks_before_any_launch(lib):
     assert lib.ising3_fill(fake, 64, 0, null) == EINVAL
     assert lib.ising3_sweep(fake, 64, float("nan"), 1, 1, 0, null, null) == EINVAL
     assert lib.ising3_sweep(fake, 64, 0.2, 2, 1, 2**32 - 1, null, null) == EINVAL
+    far = ctypes.c_void_p(4096 + 64 ** 3)
+    assert lib.ising3_sweep_fused(fake, fake, 64, 0.2, 2, 1, 0, null, null) == EINVAL           # overlap
+    assert lib.ising3_sweep_fused(fake, ctypes.c_void_p(4096 + 64 ** 3 - 16), 64, 0.2, 2, 1, 0, null,
+                                  null) == EINVAL
+    assert lib.ising3_sweep_fused(fake, far, 96, 0.2, 2, 1, 0, null, null) == EINVAL
+    assert lib.ising3_sweep_fused(fake, far, 64, -0.2, 2, 1, 0, null, null) == EINVAL
+    assert lib.ising3_sweep_fused_step(fake, far, 64, 0.2, 1, 2**32, null, null) == EINVAL
+    assert lib.ising3_sweep_fused_step(fake, fake, 64, 0.2, 1, 0, null, null) == EINVAL
     assert lib.ising3_half_sweep(fake, 64, 0.2, 1, 0, 2, null) == EINVAL
     assert lib.ising3_half_sweep(ctypes.c_void_p(4097), 64, 0.2, 1, 0, 0, null) == EINVAL
     assert lib.ising3_observables(fake, 64, null, null) == EINVAL

@@ -225,3 +225,69 @@ def test_packed3_equals_int8(dev, L, n):
     assert torch.equal(_unpacked3(dev, p, L), s)
     del s, p
     torch.cuda.empty_cache()
+
+
+# ---- both colours in one pass, out of place -----------------------------------------------------
+
+@pytest.mark.parametrize("L,beta,n,seed,offset", [(64, BETA_C3, 1, 1, 0), (64, BETA_C3, 6, 2, 5),
+                                                  (128, 0.25, 4, 3, 0), (256, BETA_C3, 3, 2**40 + 3, 11),
+                                                  (256, 0.0, 2, 9, 0), (128, math.inf, 2, 10, 2**32 - 2)])
+def test_fused3_sweeps_match_oracle(dev, oracle_lib, L, beta, n, seed, offset):
+    _say("fused3", L, beta, n)
+    host = _cube(L, L + n)
+    s, scratch = _to_dev(host), torch.empty((L, L, L), dtype=torch.int8, device="cuda")
+    tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising3_sweep_fused(s, scratch, L, beta, n, seed, offset, tr)
+    ref = oracle_lib.sweep3(host, beta, n, seed, offset, trace=True)
+    assert np.array_equal(s.cpu().numpy(), host)
+    assert np.array_equal(tr.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("L", [64, 256, 512])
+def test_fused3_step_is_one_sweep_out_of_place(dev, oracle_lib, L):
+    _say("fused3 step", L)
+    host = oracle_lib.init3(L, 21)
+    src = _to_dev(host)
+    keep = src.clone()
+    dst = torch.empty_like(src)
+    me = torch.empty(2, dtype=torch.int64, device="cuda")
+    dev.ising3_sweep_fused_step(src, dst, L, BETA_C3, 21, 7, me)
+    oracle_lib.sweep3(host, BETA_C3, 1, 21, 7)
+    assert torch.equal(src, keep)
+    assert np.array_equal(dst.cpu().numpy(), host)
+    assert tuple(me.tolist()) == oracle_lib.observables3(host)
+
+
+@pytest.mark.parametrize("L,n", [(512, 4), (1024, 3), (2048, 2)])
+def test_fused3_equals_two_pass_for_every_plane_count(dev, L, n):
+    # the two-pass sweep is pinned to the oracle at these sizes (light-cone blocks above); the fused
+    # pass must give the same lattice and trace for every plane count per workgroup
+    _say("fused3 == two-pass", L, n)
+    base = torch.empty((L, L, L), dtype=torch.int8, device="cuda")
+    dev.ising3_init(base, L, 5)
+    ref = base.clone()
+    ref_tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising3_sweep(ref, L, BETA_C3, n, 5, 30, ref_tr)
+    scratch = torch.empty_like(base)
+    try:
+        for rz in ((0, 2, 8, 32) if L <= 1024 else (0, 16)):
+            for remap in (1, 0):
+                dev.ising_set_option("planes3", rz)
+                dev.ising_set_option("xcd_remap", remap)
+                s = base.clone()
+                tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+                dev.ising3_sweep_fused(s, scratch, L, BETA_C3, n, 5, 30, tr)
+                assert torch.equal(s, ref), (rz, remap)
+                assert torch.equal(tr, ref_tr), (rz, remap)
+    finally:
+        dev.ising_set_option("planes3", 0)
+        dev.ising_set_option("xcd_remap", 1)
+    del base, ref, scratch
+    torch.cuda.empty_cache()
+
+
+def test_fused3_rejects_overlap(dev):
+    L = 64
+    s = torch.empty(2 * L ** 3, dtype=torch.int8, device="cuda")
+    with pytest.raises(dev.IsingError):
+        dev.ising3_sweep_fused(s[:L ** 3], s[L ** 3 - 16:2 * L ** 3 - 16], L, BETA_C3, 2, 1)
