@@ -14,6 +14,9 @@
  *   - Spin lattices hold +1 / -1 only (int8 layout) or the packed bit form of such a lattice.
  *     Other byte values give unspecified (but memory-safe) results.
  *   - L is the linear size of a square periodic lattice: L % 64 == 0, 64 <= L <= 2^20.
+ *   - Library state is process-wide and unguarded: the options below, and the batched form's
+ *     tuned schedules and captured graph.  Call the library from one host thread at a time
+ *     (ising_last_error is per thread).
  *
  * Lattice conventions (Sec. 3, Sec. 3.1, Sec. 3.2 of the paper):
  *   int8 layout: row-major L x L bytes, sigma[r][c] at offset r * L + c, periodic in r and c.

@@ -335,7 +335,7 @@ __global__ __launch_bounds__(576) void k_sweep3_fused(Fused3Args a) {
     fetch(rb, zplane(1));
     RowBits p2{0u, 0u}, p1 = bits(ra), p0 = bits(rb);
     fetch(ra, zplane(2));
-    RowBits pn = bits(ra), nx{0u, 0u};
+    RowBits pn = bits(ra);
     fetch(ra, zplane(3));
     fetch(rb, zplane(4));
     RowBits o0{0u, 0u}, o1{0u, 0u};
@@ -377,7 +377,6 @@ __global__ __launch_bounds__(576) void k_sweep3_fused(Fused3Args a) {
             fetch_outer(ob, zplane(k + 6));
         }
     }
-    (void)nx;
     if (OBS) block_accumulate(a.obs, own ? cnt.anti : 0u, own ? cnt.neg : 0u, own ? 1u : 0u, 64u * Rz, 3u);
 }
 
