@@ -534,6 +534,260 @@ __global__ __launch_bounds__(1024) void k_sweep_fused2(FusedArgs a) {
     }
 }
 
+// ---- Two sweeps per pass, with the ties of a step settled together.
+//
+// In the walk above each update needs the result of the one before it in the same step, so each
+// waits for the last undecided site of its wave: a word costs about 3.3 Philox blocks, where one
+// site needs about 1.07 on average (15 of 16 sites are decided by the first four bit planes).
+// This walk leaves two rows between consecutive updates: step s updates the white sites of walk
+// row s + 1 (sweep t), the black sites of s - 1 (t), the white sites of s - 3 (t + 1) and the
+// black sites of s - 5 (t + 1).  Every value an update reads was final at the end of step s - 1
+// and no update of the step writes it, so the four updates of a step are independent.  Each
+// takes its first two Philox blocks (eight bit planes) for all its sites; a word with sites still
+// tied after that goes to a queue in the wave's LDS, and the wave then settles the queued words
+// of all four updates at once, one word per lane.  About 25 words are queued per step, so the
+// planes after the eighth cost about two blocks per step instead of about 1.3 per update.  The
+// strip reads, recomputes and writes the same rows as the walk above, and every decision takes
+// the same uniform, so the result is the same two sweeps, bit for bit.
+
+// Per-wave LDS of a tie queue (5 KiB).  Entry j = one word with sites still tied: those sites,
+// the ones of them compared with T_2, the Philox row, and update | lane << 2 | group << 8.
+// res[lane] = the sites of the lane's updates 0 .. 3 that the queue accepted (zeroed before the
+// pushes).
+struct TieQueue {
+    uint32_t* task;  // [4][256]: tied, tied & sel2, row, meta
+    uint4* res;      // [64]
+};
+constexpr uint32_t kTieQueueBytes = 256u * 16u + 64u * 16u;
+
+// The four bit planes of one Philox block against the thresholds (as in accept_mask).
+__device__ __forceinline__ void compare_planes(uint32_t& acc, uint32_t& tied, uint32_t sel2, const Words4& blk,
+                                               const Thresholds& th, uint32_t m) {
+    const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t k = 4u * m + (uint32_t)w;
+        // threshold bit of every site: bit 31 - k of T_4, flipped on sel2 where T_2 differs (two
+        // instructions with uniform masks)
+        const uint32_t m4 = 0u - ((th.t4 >> (31u - k)) & 1u);
+        const uint32_t d = 0u - (((th.t2 ^ th.t4) >> (31u - k)) & 1u);
+        const uint32_t tbit = m4 ^ (sel2 & d);
+        const uint32_t x = planes[w];
+        acc |= tied & tbit & ~x;
+        tied &= ~(x ^ tbit);
+    }
+}
+
+// Appends the lane's word to the queue if it has tied sites (n = entries so far, uniform).
+__device__ __forceinline__ void tq_push(const TieQueue& q, uint32_t& n, uint32_t tied, uint32_t sel2, uint32_t row,
+                                        uint32_t meta) {
+    const uint64_t B = __builtin_amdgcn_ballot_w64(tied != 0u);
+    if (tied != 0u) {
+        const uint32_t pos =
+            n + __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, 0u));
+        q.task[pos] = tied;
+        q.task[256u + pos] = sel2 & tied;
+        q.task[512u + pos] = row;
+        q.task[768u + pos] = meta;
+    }
+    n += (uint32_t)__builtin_popcountll(B);
+}
+
+// One colour-Q update at column parity O (P = its pair in the edge words): the sites decided by
+// the first two Philox blocks flip at once, the word's remaining ties go to the queue (n entries,
+// uniform).  nbL / nbR = the edge words of the left / right neighbour group.
+template <int O, int Q, int P>
+__device__ __forceinline__ void tq_update(RowBits& own, const RowBits& v0, const RowBits& v1, uint32_t nbL,
+                                          uint32_t nbR, const Thresholds& th, uint32_t g, uint32_t row, uint32_t t,
+                                          uint32_t key0, uint32_t key1, const TieQueue& q, uint32_t& n,
+                                          uint32_t lane) {
+    const uint32_t side = O ? own.e : own.o;
+    const uint32_t hs = O ? shift_next(side, (nbR >> (2 * P)) & 1u) : shift_prev(side, (nbL >> (2 * P + 1)) & 1u);
+    const uint32_t a = O ? own.o : own.e;
+    const uint32_t x1 = a ^ (O ? v0.o : v0.e), x2 = a ^ (O ? v1.o : v1.e), x3 = a ^ side, x4 = a ^ hs;
+    const uint32_t o12 = x1 | x2, o34 = x3 | x4;
+    const uint32_t ge2 = (x1 & x2) | (x3 & x4) | (o12 & o34);  // s <= 0: always flips
+    const uint32_t any = o12 | o34;
+    uint32_t sel2 = any & ~ge2, sel4 = ~any;
+    uint32_t acc = ge2;
+    if (th.full2) { acc |= sel2; sel2 = 0u; }
+    if (th.full4) { acc |= sel4; sel4 = 0u; }
+    uint32_t tied = sel2 | sel4;
+#pragma unroll
+    for (uint32_t m = 0; m < 2; ++m) {
+        if (!wave_any(tied != 0u)) break;
+        compare_planes(acc, tied, sel2, philox4x32_10(g, row, t, 2u * m + (uint32_t)Q, key0, key1), th, m);
+    }
+    if (O) own.o ^= acc; else own.e ^= acc;
+    tq_push(q, n, tied, sel2, row, (uint32_t)P | (lane << 2) | (g << 8));
+}
+
+// Settles the n queued words (n <= 256), one per lane, with the planes of blocks 2 onwards.  The
+// uniform of a word of update u has sweep t + u / 2 and colour 1 - u % 2 when QC < 0 (the
+// two-sweep walk), sweep t and colour QC otherwise.
+template <int QC>
+__device__ __forceinline__ void tq_settle(const TieQueue& q, uint32_t n, const Thresholds& th, uint32_t t,
+                                          uint32_t key0, uint32_t key1, uint32_t lane) {
+    wave_lds_sync();
+#pragma unroll 1
+    for (uint32_t b = 0; b < n; b += 64u) {
+        const uint32_t j = b + lane;
+        const bool have = j < n;
+        uint4 tk = make_uint4(0u, 0u, 0u, 0u);
+        if (have) tk = make_uint4(q.task[j], q.task[256u + j], q.task[512u + j], q.task[768u + j]);
+        const uint32_t u = tk.w & 3u, src = (tk.w >> 2) & 63u, g = tk.w >> 8;
+        const uint32_t tu = QC < 0 ? t + (u >> 1) : t, qu = QC < 0 ? (u & 1u) ^ 1u : (uint32_t)QC;
+        uint32_t acc = 0u, tied = tk.x;
+#pragma unroll 1
+        for (uint32_t m = 2; m < th.blocks; ++m) {
+            if (!wave_any(tied != 0u)) break;
+            compare_planes(acc, tied, tk.y, philox4x32_10(g, tk.z, tu, 2u * m + qu, key0, key1), th, m);
+        }
+        if (have) reinterpret_cast<uint32_t*>(q.res)[4u * src + u] = acc;
+    }
+    wave_lds_sync();
+}
+
+// (M, E) contributions of the colour sites of `own` at parity O after their update (P as in
+// tq_update): their anti-aligned bonds, and the -1 spins of both colours of the row.
+template <int O, int P>
+__device__ __forceinline__ void tq_count(const RowBits& own, const RowBits& v0, const RowBits& v1, uint32_t nbL,
+                                         uint32_t nbR, Counts& cnt) {
+    const uint32_t side = O ? own.e : own.o;
+    const uint32_t hs = O ? shift_next(side, (nbR >> (2 * P)) & 1u) : shift_prev(side, (nbL >> (2 * P + 1)) & 1u);
+    const uint32_t a = O ? own.o : own.e;
+    cnt.anti += __builtin_popcount(a ^ (O ? v0.o : v0.e)) + __builtin_popcount(a ^ (O ? v1.o : v1.e)) +
+                __builtin_popcount(a ^ side) + __builtin_popcount(a ^ hs);
+    cnt.neg += __builtin_popcount(a) + __builtin_popcount(side);
+}
+
+// One step s of the walk: U1 (white, t) on w0 between wn and w1, U2 (black, t) on w2, U3 (white,
+// t + 1) on w4, U4 (black, t + 1) on w6.  U1 and U3 lie on columns of parity O, U2 and U4 on 1 - O.
+// rows[k] = global row of update k; act = which updates the step makes (bit k: update k);
+// count_t: U2's row is one the strip writes.
+template <int O, bool OBS>
+__device__ __forceinline__ void fused2q_step(RowBits& w0, RowBits& w2, RowBits& w4, RowBits& w6, const RowBits& wn,
+                                             const RowBits& w1, const RowBits& w3, const RowBits& w5,
+                                             const RowBits& w7, uint32_t nbL, uint32_t nbR, const Thresholds& th,
+                                             uint32_t g, const uint32_t (&rows)[4], uint32_t act, uint32_t t,
+                                             uint32_t key0, uint32_t key1, const TieQueue& q, uint32_t lane,
+                                             Counts& ct, Counts& ct1, bool count_t) {
+    constexpr int X = 1 - O;
+    q.res[lane] = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t n = 0u;
+    if (act & 1u) tq_update<O, 1, 0>(w0, wn, w1, nbL, nbR, th, g, rows[0], t, key0, key1, q, n, lane);
+    if (act & 2u) tq_update<X, 0, 1>(w2, w1, w3, nbL, nbR, th, g, rows[1], t, key0, key1, q, n, lane);
+    if (act & 4u) tq_update<O, 1, 2>(w4, w3, w5, nbL, nbR, th, g, rows[2], t + 1u, key0, key1, q, n, lane);
+    if (act & 8u) tq_update<X, 0, 3>(w6, w5, w7, nbL, nbR, th, g, rows[3], t + 1u, key0, key1, q, n, lane);
+    tq_settle<-1>(q, n, th, t, key0, key1, lane);
+    const uint4 r = q.res[lane];  // zero for the updates the step does not make
+    if (O) { w0.o ^= r.x; w4.o ^= r.z; w2.e ^= r.y; w6.e ^= r.w; }
+    else { w0.e ^= r.x; w4.e ^= r.z; w2.o ^= r.y; w6.o ^= r.w; }
+    if (OBS) {
+        if ((act & 2u) && count_t) tq_count<X, 1>(w2, w1, w3, nbL, nbR, ct);
+        if (act & 8u) tq_count<X, 3>(w6, w5, w7, nbL, nbR, ct1);
+    }
+}
+
+template <bool OBS, bool STAGED, bool UP>
+__device__ __forceinline__ void fused2q_strip(const FusedArgs& a, uint32_t strip, uint4* fused_lds, Counts& ct,
+                                              Counts& ct1) {
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t G = a.groups, L = a.L, R = a.rows;
+    // 5 KiB per wave: row staging (4 KiB) shared with the tie queue's entries, and its results
+    uint4* const stage = fused_lds + (tid >> 6) * (kTieQueueBytes / 16u);
+    uint32_t* const xch = reinterpret_cast<uint32_t*>(fused_lds + (nt >> 6) * (kTieQueueBytes / 16u));
+    const TieQueue q{reinterpret_cast<uint32_t*>(stage), stage + 256};
+    const bool active = tid < G;
+    const uint32_t g = active ? tid : G - 1;
+    const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
+    const uint32_t lane = tid & 63u;
+    const uint32_t r0 = strip * R;
+    const size_t col = (size_t)(STAGED ? g - lane : g) * 64u;
+    // walk row k = 0 .. R + 7: r0 - 4 .. r0 + R + 3 (down) or r0 + R + 3 .. r0 - 4 (up), wrapped
+    // onto the torus; prefetches past the last walk row are clamped to it
+    auto vrow = [&](uint32_t k) {
+        const uint32_t kk = k < R + 7 ? k : R + 7;
+        uint32_t v = UP ? r0 + R + 3 + L - kk : r0 + L - 4 + kk;  // in [L - 4, 2L + 4) since R <= L
+        v = v >= L ? v - L : v;
+        return v >= L ? v - L : v;
+    };
+    auto fetch = [&](Row& raw, uint32_t r) {
+        if (STAGED) load_row_coalesced(raw, a.src + (size_t)r * L + col, lane);
+        else load_row(raw, a.src + (size_t)r * L + col);
+    };
+    auto own = [&](const Row& raw) {
+        if (!STAGED) return row_bits(raw);
+        Row row;
+        regroup_to_owner(row, raw, stage, lane);
+        return row_bits(row);
+    };
+    auto put = [&](uint32_t r, const RowBits& b) {
+        Row row;
+        bits_to_row(row, b);
+        if (STAGED) store_row_coalesced(a.dst + (size_t)r * L + col, row, stage, lane, a.nt_store);
+        else if (active) store_row(a.dst + (size_t)r * L + col, row, a.nt_store);
+    };
+    // Step s (s = 0 .. R + 8) makes U1 for s <= R + 5 (walk rows 1 .. R + 6), U2 for 3 <= s <= R + 6
+    // (rows 2 .. R + 5), U3 for 6 <= s <= R + 7 (rows 3 .. R + 4) and U4 for 9 <= s <= R + 8 (rows
+    // 4 .. R + 3, the strip's own rows, written after their update).  U1 and U3 of an even step lie
+    // on columns of parity OA.  Step s reads edge-word slot s & 1 and publishes into the other.
+    constexpr int OA = UP ? 1 : 0, OB = 1 - OA;
+    const uint32_t t = a.t, k0 = a.key0, k1 = a.key1;
+    Row ra, rb;
+    fetch(ra, vrow(0));
+    fetch(rb, vrow(1));
+    RowBits w7{0u, 0u}, w6{0u, 0u}, w5{0u, 0u}, w4{0u, 0u}, w3{0u, 0u}, w2{0u, 0u};
+    RowBits w1 = own(ra), w0 = own(rb);
+    fetch(ra, vrow(2));
+    fetch(rb, vrow(3));
+    RowBits n0 = own(ra), n1 = own(rb);
+    fetch(ra, vrow(4));
+    fetch(rb, vrow(5));
+    xch[tid] = edge_word4(w0, w2, w4, w6);  // slot 0: walk row 1 (the other pairs are not read)
+    workgroup_lds_sync();
+#define ISING_FUSED2Q_STEP(O, S, NEXT)                                                                       \
+    do {                                                                                                     \
+        const uint32_t s_ = (S);                                                                             \
+        const uint32_t act = (s_ <= R + 5 ? 1u : 0u) | (s_ >= 3 && s_ <= R + 6 ? 2u : 0u) |                 \
+                             (s_ >= 6 && s_ <= R + 7 ? 4u : 0u) | (s_ >= 9 && s_ <= R + 8 ? 8u : 0u);        \
+        const uint32_t rw[4] = {vrow(s_ + 1), s_ >= 1 ? vrow(s_ - 1) : 0u, s_ >= 3 ? vrow(s_ - 3) : 0u,      \
+                                s_ >= 5 ? vrow(s_ - 5) : 0u};                                                \
+        const uint32_t sl = (s_ & 1u) * nt;                                                                  \
+        fused2q_step<O, OBS>(w0, w2, w4, w6, NEXT, w1, w3, w5, w7, xch[sl + gl], xch[sl + gr], a.th, g, rw,  \
+                             act, t, k0, k1, q, lane, ct, ct1, s_ >= 5 && s_ <= R + 4);                       \
+        if (act & 8u) put(rw[3], w6);                                                                        \
+        w7 = w6; w6 = w5; w5 = w4; w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = NEXT;                           \
+        xch[((s_ + 1) & 1u) * nt + tid] = edge_word4(w0, w2, w4, w6);                                        \
+        workgroup_lds_sync();                                                                                \
+    } while (0)
+#pragma unroll 1
+    for (uint32_t s = 0; s < R + 10; s += 2) {  // step R + 9 makes no update
+        ISING_FUSED2Q_STEP(OA, s, n0);
+        ISING_FUSED2Q_STEP(OB, s + 1, n1);
+        n0 = own(ra);  // walk rows s + 4, s + 5 for the next two steps
+        n1 = own(rb);
+        fetch(ra, vrow(s + 6));
+        fetch(rb, vrow(s + 7));
+    }
+#undef ISING_FUSED2Q_STEP
+}
+
+template <bool OBS, bool STAGED>
+__global__ __launch_bounds__(1024) void k_sweep_fused2q(FusedArgs a) {
+    extern __shared__ uint4 fused_lds[];
+    const uint32_t strip = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
+    Counts ct{0u, 0u}, ct1{0u, 0u};
+    if (a.alternate && (strip & 1u)) fused2q_strip<OBS, STAGED, true>(a, strip, fused_lds, ct, ct1);
+    else fused2q_strip<OBS, STAGED, false>(a, strip, fused_lds, ct, ct1);
+    const bool active = threadIdx.x < a.groups;
+    if (OBS) {
+        block_accumulate(a.obs, active ? ct.anti : 0u, active ? ct.neg : 0u, active ? 1u : 0u, 64u * a.rows);
+        __syncthreads();  // block_accumulate's LDS is reused
+        block_accumulate(a.obs + 2, active ? ct1.anti : 0u, active ? ct1.neg : 0u, active ? 1u : 0u, 64u * a.rows);
+    }
+}
+
 // ---- observables of an int8 lattice: M = sum of spins, E = -sum over bonds (right, down).
 struct ObsArgs {
     const int8_t* spins;
@@ -675,6 +929,97 @@ __global__ __launch_bounds__(256) void k_sweep_packed(PackedArgs a) {
         }
     }
     if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, active ? 1u : 0u, 64u * a.rows);
+}
+
+// Half-sweep on the packed layout with the ties of four rows settled together.  All colour-Q sites
+// of a half-sweep are independent, so a lane takes rows r .. r + 3 of its strip at a time, draws
+// the first two Philox blocks of each row's word, queues the words still holding tied sites and
+// settles them with the other lanes' (as in the two-sweep pass).  Same uniforms and results as
+// k_sweep_packed.  rows % 4 == 0; lanes past n_lanes shadow the last lane without storing.
+template <int Q, bool OBS>
+__global__ __launch_bounds__(256) void k_sweep_packed_q(PackedArgs a) {
+    extern __shared__ uint4 packed_lds[];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    uint4* const mine = packed_lds + (tid >> 6) * (kTieQueueBytes / 16u);
+    const TieQueue q{reinterpret_cast<uint32_t*>(mine), mine + 256};
+    const uint32_t raw_id = logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * blockDim.x + tid;
+    if (a.zero_slot && raw_id == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
+    const bool active = raw_id < a.n_lanes;
+    const uint32_t lane_id = active ? raw_id : a.n_lanes - 1u;
+    Counts cnt{0u, 0u};
+    const uint32_t W = a.groups, L = a.L, R = a.rows;
+    const uint32_t g = lane_id % W;
+    const uint32_t r0 = (lane_id / W) * R;
+    const uint32_t gl = g == 0 ? W - 1 : g - 1;
+    const uint32_t gr = g + 1 == W ? 0 : g + 1;
+    uint32_t* const pq = a.planes + (size_t)Q * L * W;              // sites being updated
+    const uint32_t* const po = a.planes + (size_t)(1 - Q) * L * W;  // other colour
+    // row r + i (r even): colour-Q sites at column parity Q for even i, 1 - Q for odd i; parity 1
+    // takes the right group's site 0 as the far horizontal neighbour, parity 0 the left group's
+    // site 31
+    uint32_t bprev = po[(size_t)(r0 == 0 ? L - 1 : r0 - 1) * W + g];
+    uint32_t bcur = po[(size_t)r0 * W + g];
+#pragma unroll 1
+    for (uint32_t s = 0; s < R; s += 4) {
+        const uint32_t r = r0 + s;
+        uint32_t b[6], w[4], e[4];
+        b[0] = bprev;
+        b[1] = bcur;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t ri = r + (uint32_t)i, rn = ri + 1u >= L ? ri + 1u - L : ri + 1u;
+            b[i + 2] = po[(size_t)rn * W + g];
+            w[i] = pq[(size_t)ri * W + g];
+            const bool right = (Q == 1) == ((i & 1) == 0);
+            e[i] = po[(size_t)ri * W + (right ? gr : gl)];
+        }
+        q.res[lane] = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t n = 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const bool right = (Q == 1) == ((i & 1) == 0);
+            const uint32_t side = b[i + 1];
+            const uint32_t hs = right ? shift_next(side, e[i] & 1u) : shift_prev(side, e[i] >> 31);
+            const uint32_t x1 = w[i] ^ b[i], x2 = w[i] ^ b[i + 2], x3 = w[i] ^ side, x4 = w[i] ^ hs;
+            const uint32_t o12 = x1 | x2, o34 = x3 | x4;
+            const uint32_t ge2 = (x1 & x2) | (x3 & x4) | (o12 & o34);
+            const uint32_t any = o12 | o34;
+            uint32_t sel2 = any & ~ge2, sel4 = ~any;
+            uint32_t acc = ge2;
+            if (a.th.full2) { acc |= sel2; sel2 = 0u; }
+            if (a.th.full4) { acc |= sel4; sel4 = 0u; }
+            uint32_t tied = sel2 | sel4;
+#pragma unroll
+            for (uint32_t m = 0; m < 2; ++m) {
+                if (!wave_any(tied != 0u)) break;
+                compare_planes(acc, tied, sel2, philox4x32_10(g, r + (uint32_t)i, a.t, 2u * m + (uint32_t)Q, a.key0, a.key1),
+                               a.th, m);
+            }
+            w[i] ^= acc;
+            tq_push(q, n, tied, sel2, r + (uint32_t)i, (uint32_t)i | (lane << 2) | (g << 8));
+        }
+        tq_settle<Q>(q, n, a.th, a.t, a.key0, a.key1, lane);
+        const uint4 res = q.res[lane];
+        w[0] ^= res.x;
+        w[1] ^= res.y;
+        w[2] ^= res.z;
+        w[3] ^= res.w;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (active) pq[(size_t)(r + (uint32_t)i) * W + g] = w[i];
+            if (OBS) {
+                const bool right = (Q == 1) == ((i & 1) == 0);
+                const uint32_t side = b[i + 1];
+                const uint32_t hs = right ? shift_next(side, e[i] & 1u) : shift_prev(side, e[i] >> 31);
+                cnt.anti += __builtin_popcount(w[i] ^ b[i]) + __builtin_popcount(w[i] ^ b[i + 2]) +
+                            __builtin_popcount(w[i] ^ side) + __builtin_popcount(w[i] ^ hs);
+                cnt.neg += __builtin_popcount(w[i]) + __builtin_popcount(side);
+            }
+        }
+        bprev = b[4];
+        bcur = b[5];
+    }
+    if (OBS) block_accumulate(a.obs, active ? cnt.anti : 0u, active ? cnt.neg : 0u, active ? 1u : 0u, 64u * a.rows);
 }
 
 // (M, E) of a packed lattice: every bond has exactly one black (q = 0) end, so the black sites'
@@ -1203,6 +1548,8 @@ struct Options {
     int64_t fused_rows = 0;     // rows per strip of the fused sweep; 0 = choose from L
     int64_t fused_alternate = 1;  // fused sweep: odd strips walk upwards
     int64_t fused_sweeps = 2;     // fused sweep: sweeps per pass over the lattice (1 or 2)
+    int64_t fused_ties = 1;       // two-sweep pass: settle the ties of a step's four updates together
+    int64_t packed_ties = 1;      // packed half-sweep: settle the ties of four rows together
     int64_t planes3 = 0;          // 3-D sweep: planes per workgroup; 0 = choose from L
 };
 Options g_opt;
@@ -1376,7 +1723,9 @@ int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::T
     a.alternate = g_opt.fused_alternate ? 1u : 0u;
     const uint32_t threads = (a.groups + 63u) / 64u * 64u;
     const bool staged = g_opt.staged && a.groups % 64u == 0;
-    const size_t lds = (staged ? (size_t)(threads / 64u) * 4096u : 0u) + 2u * threads * sizeof(uint32_t);
+    const bool ties = sweeps == 2 && g_opt.fused_ties;
+    const size_t per_wave = ties ? ising::kTieQueueBytes : staged ? 4096u : 0u;
+    const size_t lds = (size_t)(threads / 64u) * per_wave + 2u * threads * sizeof(uint32_t);
     const dim3 grid(a.L / a.rows), block(threads);
 #define ISING_LAUNCH_FUSED(K, OO, SS)                                                                    \
     do {                                                                                                 \
@@ -1387,6 +1736,11 @@ int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::T
         }                                                                                                \
         hipLaunchKernelGGL((ising::K<OO, SS>), grid, block, lds, stream, a);                            \
     } while (0)
+    if (ties) {
+        if (staged) { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused2q, true, true); else ISING_LAUNCH_FUSED(k_sweep_fused2q, false, true); }
+        else { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused2q, true, false); else ISING_LAUNCH_FUSED(k_sweep_fused2q, false, false); }
+        return check_launch("k_sweep_fused2q");
+    }
     if (sweeps == 2) {
         if (staged) { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused2, true, true); else ISING_LAUNCH_FUSED(k_sweep_fused2, false, true); }
         else { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused2, true, false); else ISING_LAUNCH_FUSED(k_sweep_fused2, false, false); }
@@ -1711,6 +2065,17 @@ int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Threshold
     a.zero_slot = zero_slot;
     a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
     const dim3 grid((a.n_lanes + 255u) / 256u), block(256);
+    if (g_opt.packed_ties && a.rows % 4u == 0) {
+        const size_t lds = 4u * ising::kTieQueueBytes;  // four waves per workgroup
+        if (q == 1) {
+            if (obs) hipLaunchKernelGGL((ising::k_sweep_packed_q<1, true>), grid, block, lds, stream, a);
+            else hipLaunchKernelGGL((ising::k_sweep_packed_q<1, false>), grid, block, lds, stream, a);
+        } else {
+            if (obs) hipLaunchKernelGGL((ising::k_sweep_packed_q<0, true>), grid, block, lds, stream, a);
+            else hipLaunchKernelGGL((ising::k_sweep_packed_q<0, false>), grid, block, lds, stream, a);
+        }
+        return check_launch("k_sweep_packed_q");
+    }
     if (q == 1) {
         if (obs) hipLaunchKernelGGL((ising::k_sweep_packed<1, true>), grid, block, 0, stream, a);
         else hipLaunchKernelGGL((ising::k_sweep_packed<1, false>), grid, block, 0, stream, a);
@@ -2041,6 +2406,12 @@ int ising_set_option(const char* name, int64_t value) {
     } else if (n == "fused_sweeps") {
         if (value != 1 && value != 2) return ISING_EINVAL;
         g_opt.fused_sweeps = value;
+    } else if (n == "fused_ties") {
+        if (value != 0 && value != 1) return ISING_EINVAL;
+        g_opt.fused_ties = value;
+    } else if (n == "packed_ties") {
+        if (value != 0 && value != 1) return ISING_EINVAL;
+        g_opt.packed_ties = value;
     } else if (n == "fused_rows") {
         if (value != 0 && (value < 2 || value > 256 || (value & (value - 1)) != 0)) return ISING_EINVAL;
         g_opt.fused_rows = value;
@@ -2064,6 +2435,8 @@ int ising_get_option(const char* name, int64_t* value) {
     else if (n == "fused_rows") *value = g_opt.fused_rows;
     else if (n == "fused_alternate") *value = g_opt.fused_alternate;
     else if (n == "fused_sweeps") *value = g_opt.fused_sweeps;
+    else if (n == "fused_ties") *value = g_opt.fused_ties;
+    else if (n == "packed_ties") *value = g_opt.packed_ties;
     else if (n == "planes3") *value = g_opt.planes3;
     else return ISING_EINVAL;
     return ISING_OK;

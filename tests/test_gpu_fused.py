@@ -39,16 +39,23 @@ def _to_dev(a: np.ndarray):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
+@pytest.mark.parametrize("ties", [1, 0])
 @pytest.mark.parametrize("fmt", ["exact", "bf16", "fp16"])
 @pytest.mark.parametrize("L,beta,n,seed,offset", [
     (64, BETA_C, 1, 1, 0), (64, BETA_C, 6, 2, 5), (128, 0.3, 4, 3, 0), (192, 0.7, 5, 2**40 + 3, 11),
     (320, 1 / 2.6, 2, 8, 1000), (256, 0.0, 3, 9, 0), (128, math.inf, 4, 10, 2**32 - 4)])
-def test_fused_sweeps_match_oracle(dev, oracle_lib, L, beta, n, seed, offset, fmt):
-    _say("fused", L, beta, n, seed, offset, fmt)
+def test_fused_sweeps_match_oracle(dev, oracle_lib, L, beta, n, seed, offset, fmt, ties):
+    # ties: the two-sweep pass settles the still-tied words of a step's four updates together (1)
+    # or each update finishes its own words (0)
+    _say("fused", L, beta, n, seed, offset, fmt, ties)
     host = inputs.random_lattice(L, seed=L + n)
     s, scratch = _to_dev(host), torch.empty((L, L), dtype=torch.int8, device="cuda")
     trace = torch.empty((n, 2), dtype=torch.int64, device="cuda")
-    dev.ising_sweep_fused(s, scratch, L, beta, fmt, n, seed, offset, trace)
+    dev.ising_set_option("fused_ties", ties)
+    try:
+        dev.ising_sweep_fused(s, scratch, L, beta, fmt, n, seed, offset, trace)
+    finally:
+        dev.ising_set_option("fused_ties", 1)
     if fmt == "exact":
         ref = oracle_lib.sweep(host, beta, n, seed, offset, trace=True)
     else:
@@ -98,8 +105,9 @@ def test_fused_equals_two_half_sweeps_for_every_strip_height(dev, L):
     dev.ising_sweep_fmt(ref, L, BETA_C, "exact", 4, 17, 40, ref_tr)
     scratch = torch.empty_like(base)
     try:
-        for sweeps in (1, 2):
+        for sweeps, ties in ((1, 1), (2, 0), (2, 1)):
             dev.ising_set_option("fused_sweeps", sweeps)
+            dev.ising_set_option("fused_ties", ties)
             for rows in (0, 2, 4, 8, 16, 32, 64, 128, 256):
                 if rows and (L % rows or rows > L):
                     continue
@@ -111,10 +119,11 @@ def test_fused_equals_two_half_sweeps_for_every_strip_height(dev, L):
                     s = base.clone()
                     tr = torch.empty((4, 2), dtype=torch.int64, device="cuda")
                     dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", 4, 17, 40, tr)
-                    assert torch.equal(s, ref), (sweeps, rows, remap, staged, alt)
-                    assert torch.equal(tr, ref_tr), (sweeps, rows, remap, staged, alt)
+                    assert torch.equal(s, ref), (sweeps, ties, rows, remap, staged, alt)
+                    assert torch.equal(tr, ref_tr), (sweeps, ties, rows, remap, staged, alt)
     finally:
-        for k, v in (("fused_rows", 0), ("xcd_remap", 1), ("staged", 1), ("fused_alternate", 1), ("fused_sweeps", 2)):
+        for k, v in (("fused_rows", 0), ("xcd_remap", 1), ("staged", 1), ("fused_alternate", 1), ("fused_sweeps", 2),
+                     ("fused_ties", 1)):
             dev.ising_set_option(k, v)
 
 
@@ -130,15 +139,17 @@ def test_fused_sweep_counts_with_one_and_two_sweeps_per_pass(dev, L):
             ref = base.clone()
             ref_tr = torch.empty((max(n, 1), 2), dtype=torch.int64, device="cuda")
             dev.ising_sweep_fmt(ref, L, 0.41, "exact", n, 23, 9, ref_tr[:n])
-            for sweeps in (1, 2):
+            for sweeps, ties in ((1, 1), (2, 0), (2, 1)):
                 dev.ising_set_option("fused_sweeps", sweeps)
+                dev.ising_set_option("fused_ties", ties)
                 s = base.clone()
                 tr = torch.empty((max(n, 1), 2), dtype=torch.int64, device="cuda")
                 dev.ising_sweep_fused(s, scratch, L, 0.41, "exact", n, 23, 9, tr[:n])
-                assert torch.equal(s, ref), (n, sweeps)
-                assert torch.equal(tr[:n], ref_tr[:n]), (n, sweeps)
+                assert torch.equal(s, ref), (n, sweeps, ties)
+                assert torch.equal(tr[:n], ref_tr[:n]), (n, sweeps, ties)
     finally:
         dev.ising_set_option("fused_sweeps", 2)
+        dev.ising_set_option("fused_ties", 1)
 
 
 @pytest.mark.parametrize("L,fmt", [(64, "exact"), (192, "bf16"), (4096, "exact")])

@@ -109,6 +109,32 @@ def test_sweep_packed_matches_oracle(dev, oracle_lib, L, beta, n, seed, offset):
     assert np.array_equal(trace.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("ties", [1, 0])
+@pytest.mark.parametrize("L,beta,n", [(192, BETA_C, 6), (1024, 0.41, 3), (256, 0.0, 2), (128, math.inf, 2)])
+def test_packed_rows_per_lane_and_tie_queue_match_oracle(dev, oracle_lib, L, beta, n, ties):
+    # ties = 1: a lane decides four rows' words with two Philox blocks each and the wave settles
+    # the words left with tied sites together (needs rows per lane % 4 == 0); 0: row by row
+    _say("packed rows/ties", L, beta, n, ties)
+    host = oracle_lib.init(L, 7)
+    ref_host = host.copy()
+    ref = oracle_lib.sweep(ref_host, beta, n, 7, 21, trace=True)
+    try:
+        dev.ising_set_option("packed_ties", ties)
+        for rows in (2, 4, 8, 16, 32, 64):
+            if L % rows:
+                continue
+            dev.ising_set_option("rows_per_lane", rows)
+            p = _planes(L)
+            dev.ising_pack(torch.from_numpy(host).cuda(), L, p)
+            trace = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+            dev.ising_sweep_packed(p, L, beta, n, 7, 21, trace)
+            assert np.array_equal(_unpacked(dev, p, L).cpu().numpy(), ref_host), rows
+            assert np.array_equal(trace.cpu().numpy(), ref), rows
+    finally:
+        dev.ising_set_option("rows_per_lane", 0)
+        dev.ising_set_option("packed_ties", 1)
+
+
 @pytest.mark.parametrize("L,n", [(4096, 5), (16384, 8)])
 def test_packed_equals_int8(dev, L, n):
     _say("packed == int8", L, n)
