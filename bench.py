@@ -89,9 +89,9 @@ def alu_roofline(layout: str, L: int, avg_launch_ms: float):
 FUSED_MAX_L = 65536  # one workgroup thread per 64-column group, at most 1024 threads
 
 KERNEL_NAME = {
-    "fused": "k_sweep_fused2 (two sweeps per launch)",
+    "fused": "k_sweep_fused2q (two sweeps per launch, tie queue)",
     "int8": "k_sweep_int8 (one colour per launch)",
-    "packed": "k_sweep_packed (one colour per launch)",
+    "packed": "k_sweep_packed_q (one colour per launch, tie queue)",
 }
 
 
@@ -214,7 +214,7 @@ def bench_3d(ising, torch, args, stream) -> dict:
         torch.cuda.synchronize()
         pw = time.perf_counter() - t0
         res["packed_layout"] = {"value": float(L) ** 3 * kp / (pw * 1e9), "unit": "attempts/ns", "steps": kp,
-                                "kernel": "k_sweep3_packed (one colour per launch)",
+                                "kernel": "k_sweep3_packed_q (one colour per launch, tie queue)",
                                 "avg_launch_us": ev0.elapsed_time(ev1) * 1e3 / (2 * kp)}
         del planes
         # the same chain with both colours per pass, out of place (bit-identical spins)

@@ -550,49 +550,6 @@ __global__ __launch_bounds__(1024) void k_sweep_fused2(FusedArgs a) {
 // strip reads, recomputes and writes the same rows as the walk above, and every decision takes
 // the same uniform, so the result is the same two sweeps, bit for bit.
 
-// Per-wave LDS of a tie queue (5 KiB).  Entry j = one word with sites still tied: those sites,
-// the ones of them compared with T_2, the Philox row, and update | lane << 2 | group << 8.
-// res[lane] = the sites of the lane's updates 0 .. 3 that the queue accepted (zeroed before the
-// pushes).
-struct TieQueue {
-    uint32_t* task;  // [4][256]: tied, tied & sel2, row, meta
-    uint4* res;      // [64]
-};
-constexpr uint32_t kTieQueueBytes = 256u * 16u + 64u * 16u;
-
-// The four bit planes of one Philox block against the thresholds (as in accept_mask).
-__device__ __forceinline__ void compare_planes(uint32_t& acc, uint32_t& tied, uint32_t sel2, const Words4& blk,
-                                               const Thresholds& th, uint32_t m) {
-    const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const uint32_t k = 4u * m + (uint32_t)w;
-        // threshold bit of every site: bit 31 - k of T_4, flipped on sel2 where T_2 differs (two
-        // instructions with uniform masks)
-        const uint32_t m4 = 0u - ((th.t4 >> (31u - k)) & 1u);
-        const uint32_t d = 0u - (((th.t2 ^ th.t4) >> (31u - k)) & 1u);
-        const uint32_t tbit = m4 ^ (sel2 & d);
-        const uint32_t x = planes[w];
-        acc |= tied & tbit & ~x;
-        tied &= ~(x ^ tbit);
-    }
-}
-
-// Appends the lane's word to the queue if it has tied sites (n = entries so far, uniform).
-__device__ __forceinline__ void tq_push(const TieQueue& q, uint32_t& n, uint32_t tied, uint32_t sel2, uint32_t row,
-                                        uint32_t meta) {
-    const uint64_t B = __builtin_amdgcn_ballot_w64(tied != 0u);
-    if (tied != 0u) {
-        const uint32_t pos =
-            n + __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, 0u));
-        q.task[pos] = tied;
-        q.task[256u + pos] = sel2 & tied;
-        q.task[512u + pos] = row;
-        q.task[768u + pos] = meta;
-    }
-    n += (uint32_t)__builtin_popcountll(B);
-}
-
 // One colour-Q update at column parity O (P = its pair in the edge words): the sites decided by
 // the first two Philox blocks flip at once, the word's remaining ties go to the queue (n entries,
 // uniform).  nbL / nbR = the edge words of the left / right neighbour group.
@@ -620,32 +577,6 @@ __device__ __forceinline__ void tq_update(RowBits& own, const RowBits& v0, const
     }
     if (O) own.o ^= acc; else own.e ^= acc;
     tq_push(q, n, tied, sel2, row, (uint32_t)P | (lane << 2) | (g << 8));
-}
-
-// Settles the n queued words (n <= 256), one per lane, with the planes of blocks 2 onwards.  The
-// uniform of a word of update u has sweep t + u / 2 and colour 1 - u % 2 when QC < 0 (the
-// two-sweep walk), sweep t and colour QC otherwise.
-template <int QC>
-__device__ __forceinline__ void tq_settle(const TieQueue& q, uint32_t n, const Thresholds& th, uint32_t t,
-                                          uint32_t key0, uint32_t key1, uint32_t lane) {
-    wave_lds_sync();
-#pragma unroll 1
-    for (uint32_t b = 0; b < n; b += 64u) {
-        const uint32_t j = b + lane;
-        const bool have = j < n;
-        uint4 tk = make_uint4(0u, 0u, 0u, 0u);
-        if (have) tk = make_uint4(q.task[j], q.task[256u + j], q.task[512u + j], q.task[768u + j]);
-        const uint32_t u = tk.w & 3u, src = (tk.w >> 2) & 63u, g = tk.w >> 8;
-        const uint32_t tu = QC < 0 ? t + (u >> 1) : t, qu = QC < 0 ? (u & 1u) ^ 1u : (uint32_t)QC;
-        uint32_t acc = 0u, tied = tk.x;
-#pragma unroll 1
-        for (uint32_t m = 2; m < th.blocks; ++m) {
-            if (!wave_any(tied != 0u)) break;
-            compare_planes(acc, tied, tk.y, philox4x32_10(g, tk.z, tu, 2u * m + qu, key0, key1), th, m);
-        }
-        if (have) reinterpret_cast<uint32_t*>(q.res)[4u * src + u] = acc;
-    }
-    wave_lds_sync();
 }
 
 // (M, E) contributions of the colour sites of `own` at parity O after their update (P as in
@@ -734,19 +665,19 @@ __device__ __forceinline__ void fused2q_strip(const FusedArgs& a, uint32_t strip
     // on columns of parity OA.  Step s reads edge-word slot s & 1 and publishes into the other.
     constexpr int OA = UP ? 1 : 0, OB = 1 - OA;
     const uint32_t t = a.t, k0 = a.key0, k1 = a.key1;
-    Row ra, rb;
-    fetch(ra, vrow(0));
-    fetch(rb, vrow(1));
+    // one prefetched row in flight: the row a step needs next is requested a step ahead
+    Row raw;
+    fetch(raw, vrow(0));
     RowBits w7{0u, 0u}, w6{0u, 0u}, w5{0u, 0u}, w4{0u, 0u}, w3{0u, 0u}, w2{0u, 0u};
-    RowBits w1 = own(ra), w0 = own(rb);
-    fetch(ra, vrow(2));
-    fetch(rb, vrow(3));
-    RowBits n0 = own(ra), n1 = own(rb);
-    fetch(ra, vrow(4));
-    fetch(rb, vrow(5));
+    RowBits w1 = own(raw);
+    fetch(raw, vrow(1));
+    RowBits w0 = own(raw);
+    fetch(raw, vrow(2));
+    RowBits nx = own(raw);
+    fetch(raw, vrow(3));
     xch[tid] = edge_word4(w0, w2, w4, w6);  // slot 0: walk row 1 (the other pairs are not read)
     workgroup_lds_sync();
-#define ISING_FUSED2Q_STEP(O, S, NEXT)                                                                       \
+#define ISING_FUSED2Q_STEP(O, S)                                                                             \
     do {                                                                                                     \
         const uint32_t s_ = (S);                                                                             \
         const uint32_t act = (s_ <= R + 5 ? 1u : 0u) | (s_ >= 3 && s_ <= R + 6 ? 2u : 0u) |                 \
@@ -754,21 +685,19 @@ __device__ __forceinline__ void fused2q_strip(const FusedArgs& a, uint32_t strip
         const uint32_t rw[4] = {vrow(s_ + 1), s_ >= 1 ? vrow(s_ - 1) : 0u, s_ >= 3 ? vrow(s_ - 3) : 0u,      \
                                 s_ >= 5 ? vrow(s_ - 5) : 0u};                                                \
         const uint32_t sl = (s_ & 1u) * nt;                                                                  \
-        fused2q_step<O, OBS>(w0, w2, w4, w6, NEXT, w1, w3, w5, w7, xch[sl + gl], xch[sl + gr], a.th, g, rw,  \
+        fused2q_step<O, OBS>(w0, w2, w4, w6, nx, w1, w3, w5, w7, xch[sl + gl], xch[sl + gr], a.th, g, rw,    \
                              act, t, k0, k1, q, lane, ct, ct1, s_ >= 5 && s_ <= R + 4);                       \
         if (act & 8u) put(rw[3], w6);                                                                        \
-        w7 = w6; w6 = w5; w5 = w4; w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = NEXT;                           \
+        w7 = w6; w6 = w5; w5 = w4; w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = nx;                              \
         xch[((s_ + 1) & 1u) * nt + tid] = edge_word4(w0, w2, w4, w6);                                        \
+        nx = own(raw);  /* walk row s + 3 */                                                                 \
+        fetch(raw, vrow(s_ + 4));                                                                            \
         workgroup_lds_sync();                                                                                \
     } while (0)
 #pragma unroll 1
     for (uint32_t s = 0; s < R + 10; s += 2) {  // step R + 9 makes no update
-        ISING_FUSED2Q_STEP(OA, s, n0);
-        ISING_FUSED2Q_STEP(OB, s + 1, n1);
-        n0 = own(ra);  // walk rows s + 4, s + 5 for the next two steps
-        n1 = own(rb);
-        fetch(ra, vrow(s + 6));
-        fetch(rb, vrow(s + 7));
+        ISING_FUSED2Q_STEP(OA, s);
+        ISING_FUSED2Q_STEP(OB, s + 1);
     }
 #undef ISING_FUSED2Q_STEP
 }

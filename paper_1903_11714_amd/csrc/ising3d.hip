@@ -526,6 +526,169 @@ __global__ __launch_bounds__(256) void k_sweep3_packed(Packed3Args a) {
     if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, active ? 1u : 0u, 64u * a.Rz, 3u);
 }
 
+// ---- Tie queue with three thresholds (as the square lattice's, see rows.hpp): entry j = the
+// word's tied sites, those of them compared with T_2 and with T_4 (the rest with T_6), its Philox
+// row, and plane | lane << 2 | group << 8.  6 KiB per wave.
+struct TieQueue3 {
+    uint32_t* task;  // [5][256]
+    uint4* res;      // [64]
+};
+constexpr uint32_t kTieQueue3Bytes = 5u * 256u * 4u + 64u * 16u;
+
+// The four bit planes of one Philox block against T_2 / T_4 / T_6: the threshold bit is bit
+// 31 - k of T_6, flipped on s2 where T_2 differs from it and on s4 where T_4 does.
+__device__ __forceinline__ void compare_planes3(uint32_t& acc, uint32_t& tied, uint32_t s2, uint32_t s4,
+                                                const Words4& blk, const Thresholds3& th, uint32_t m) {
+    const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t k = 4u * m + (uint32_t)w;
+        const uint32_t m6 = 0u - ((th.t[2] >> (31u - k)) & 1u);
+        const uint32_t d2 = 0u - (((th.t[0] ^ th.t[2]) >> (31u - k)) & 1u);
+        const uint32_t d4 = 0u - (((th.t[1] ^ th.t[2]) >> (31u - k)) & 1u);
+        const uint32_t tbit = m6 ^ (s2 & d2) ^ (s4 & d4);
+        const uint32_t x = planes[w];
+        acc |= tied & tbit & ~x;
+        tied &= ~(x ^ tbit);
+    }
+}
+
+// Half-sweep of colour Q on the packed cubic layout with the ties of four planes settled together:
+// a lane takes planes z .. z + 3 of its column at a time (all colour-Q sites of a half-sweep are
+// independent), draws the first two Philox blocks of each word, queues the words still holding tied
+// sites and settles them with the other lanes'.  Same uniforms and results as k_sweep3_packed.
+// Rz % 4 == 0; lanes past n_lanes shadow the last lane without storing.
+template <int Q, bool OBS>
+__global__ __launch_bounds__(256) void k_sweep3_packed_q(Packed3Args a) {
+    extern __shared__ uint4 packed3_lds[];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    uint4* const mine = packed3_lds + (tid >> 6) * (kTieQueue3Bytes / 16u);
+    uint32_t* const task = reinterpret_cast<uint32_t*>(mine);
+    uint4* const res = mine + 5u * 64u;
+    const uint64_t raw = (uint64_t)logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * blockDim.x + tid;
+    if (a.zero_slot && blockIdx.x == 0 && tid == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
+    const bool active = raw < a.n_lanes;
+    const uint64_t id = active ? raw : a.n_lanes - 1u;
+    Counts cnt{0u, 0u};
+    const uint32_t L = a.L, G = a.G, Rz = a.Rz;
+    const uint32_t g = (uint32_t)(id % G);
+    const uint64_t zy = id / G;
+    const uint32_t y = (uint32_t)(zy % L), z0 = (uint32_t)(zy / L) * Rz;
+    const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
+    const uint32_t ym = y == 0 ? L - 1 : y - 1, yp = y + 1 == L ? 0 : y + 1;
+    const size_t rows = (size_t)L * L;
+    uint32_t* const pq = a.planes + (size_t)Q * rows * G;
+    const uint32_t* const po = a.planes + (size_t)(1 - Q) * rows * G;
+    auto at = [&](uint32_t z, uint32_t yy, uint32_t gg) { return ((size_t)z * L + yy) * G + gg; };
+    uint32_t zprev = po[at(z0 == 0 ? L - 1 : z0 - 1, y, g)];
+    uint32_t zcur = po[at(z0, y, g)];
+    const Thresholds3& th = a.th;
+#pragma unroll 1
+    for (uint32_t k0 = 0; k0 < Rz; k0 += 4) {
+        uint32_t zw[6], w[4], up[4], dn[4], ed[4];
+        zw[0] = zprev;
+        zw[1] = zcur;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t z = z0 + k0 + (uint32_t)i, zn = z + 1 == L ? 0 : z + 1;
+            const bool O = ((Q + y + z) & 1u) != 0;  // column parity of the colour-Q sites of row (z, y)
+            zw[i + 2] = po[at(zn, y, g)];
+            w[i] = pq[at(z, y, g)];
+            up[i] = po[at(z, ym, g)];
+            dn[i] = po[at(z, yp, g)];
+            ed[i] = po[at(z, y, O ? gr : gl)];
+        }
+        res[lane] = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t n = 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t z = z0 + k0 + (uint32_t)i;
+            const bool O = ((Q + y + z) & 1u) != 0;
+            const uint32_t side = zw[i + 1];
+            const uint32_t hs = O ? shift_next(side, ed[i] & 1u) : shift_prev(side, ed[i] >> 31);
+            const uint32_t nb[6] = {up[i], dn[i], zw[i], zw[i + 2], side, hs};
+            uint32_t x[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) x[j] = w[i] ^ nb[j];
+            const uint32_t s1 = x[0] ^ x[1] ^ x[2], c1 = (x[0] & x[1]) | (x[2] & (x[0] ^ x[1]));
+            const uint32_t s2 = x[3] ^ x[4] ^ x[5], c2 = (x[3] & x[4]) | (x[5] & (x[3] ^ x[4]));
+            const uint32_t b0 = s1 ^ s2, kk = s1 & s2;
+            const uint32_t b1 = c1 ^ c2 ^ kk, b2 = (c1 & c2) | (kk & (c1 ^ c2));  // c = b0 + 2 b1 + 4 b2
+            uint32_t sel2 = b1 & ~b0 & ~b2, sel4 = b0 & ~b1 & ~b2, sel6 = ~(b0 | b1 | b2);
+            uint32_t acc = b2 | (b1 & b0);  // c >= 3: s <= 0
+            if (th.full[0]) { acc |= sel2; sel2 = 0u; }
+            if (th.full[1]) { acc |= sel4; sel4 = 0u; }
+            if (th.full[2]) { acc |= sel6; sel6 = 0u; }
+            uint32_t tied = sel2 | sel4 | sel6;
+            const uint32_t r = z * L + y;
+#pragma unroll
+            for (uint32_t m = 0; m < 2; ++m) {
+                if (!wave_any(tied != 0u)) break;
+                compare_planes3(acc, tied, sel2, sel4, philox4x32_10(g, r, a.t, 2u * m + (uint32_t)Q, a.key0, a.key1),
+                                th, m);
+            }
+            w[i] ^= acc;
+            const uint64_t B = __builtin_amdgcn_ballot_w64(tied != 0u);
+            if (tied != 0u) {
+                const uint32_t pos =
+                    n + __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, 0u));
+                task[pos] = tied;
+                task[256u + pos] = sel2 & tied;
+                task[512u + pos] = sel4 & tied;
+                task[768u + pos] = r;
+                task[1024u + pos] = (uint32_t)i | (lane << 2) | (g << 8);
+            }
+            n += (uint32_t)__builtin_popcountll(B);
+        }
+        // settle the queued words, one per lane, with the planes of blocks 2 onwards
+        wave_lds_sync();
+#pragma unroll 1
+        for (uint32_t b = 0; b < n; b += 64u) {
+            const uint32_t j = b + lane;
+            const bool have = j < n;
+            uint32_t tied = 0u, t2 = 0u, t4 = 0u, r = 0u, meta = 0u;
+            if (have) {
+                tied = task[j];
+                t2 = task[256u + j];
+                t4 = task[512u + j];
+                r = task[768u + j];
+                meta = task[1024u + j];
+            }
+            uint32_t acc = 0u;
+#pragma unroll 1
+            for (uint32_t m = 2; m < th.blocks; ++m) {
+                if (!wave_any(tied != 0u)) break;
+                compare_planes3(acc, tied, t2, t4,
+                                philox4x32_10(meta >> 8, r, a.t, 2u * m + (uint32_t)Q, a.key0, a.key1), th, m);
+            }
+            if (have) reinterpret_cast<uint32_t*>(res)[4u * ((meta >> 2) & 63u) + (meta & 3u)] = acc;
+        }
+        wave_lds_sync();
+        const uint4 rr = res[lane];
+        w[0] ^= rr.x;
+        w[1] ^= rr.y;
+        w[2] ^= rr.z;
+        w[3] ^= rr.w;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t z = z0 + k0 + (uint32_t)i;
+            if (active) pq[at(z, y, g)] = w[i];
+            if (OBS) {
+                const bool O = ((Q + y + z) & 1u) != 0;
+                const uint32_t side = zw[i + 1];
+                const uint32_t hs = O ? shift_next(side, ed[i] & 1u) : shift_prev(side, ed[i] >> 31);
+                cnt.anti += __builtin_popcount(w[i] ^ up[i]) + __builtin_popcount(w[i] ^ dn[i]) +
+                            __builtin_popcount(w[i] ^ zw[i]) + __builtin_popcount(w[i] ^ zw[i + 2]) +
+                            __builtin_popcount(w[i] ^ side) + __builtin_popcount(w[i] ^ hs);
+                cnt.neg += __builtin_popcount(w[i]) + __builtin_popcount(side);
+            }
+        }
+        zprev = zw[4];
+        zcur = zw[5];
+    }
+    if (OBS) block_accumulate(a.obs, active ? cnt.anti : 0u, active ? cnt.neg : 0u, active ? 1u : 0u, 64u * a.Rz, 3u);
+}
+
 // (M, E) of a packed cubic lattice: every bond has one black end, so the black sites' anti-aligned
 // neighbour counts cover all 3 L^3 bonds once.
 __global__ __launch_bounds__(256) void k_observables3_packed(const uint32_t* planes, uint32_t L, uint32_t G,
@@ -668,6 +831,14 @@ int launch_half_sweep3_packed(uint32_t* planes, int64_t L, const ising::Threshol
     a.zero_slot = zero_slot;
     a.xcd_remap = ising_host::xcd_remap() ? 1u : 0u;
     const dim3 grid((unsigned)((a.n_lanes + 255) / 256)), block(256);
+    if (ising_host::option("packed_ties") && a.Rz % 4u == 0) {
+        const size_t lds = 4u * ising::kTieQueue3Bytes;  // four waves per workgroup
+#define ISING_LAUNCH3PQ(QQ, OO) hipLaunchKernelGGL((ising::k_sweep3_packed_q<QQ, OO>), grid, block, lds, stream, a)
+        if (q == 1) { if (obs) ISING_LAUNCH3PQ(1, true); else ISING_LAUNCH3PQ(1, false); }
+        else { if (obs) ISING_LAUNCH3PQ(0, true); else ISING_LAUNCH3PQ(0, false); }
+#undef ISING_LAUNCH3PQ
+        return ising_host::check_launch("k_sweep3_packed_q");
+    }
 #define ISING_LAUNCH3P(QQ, OO) hipLaunchKernelGGL((ising::k_sweep3_packed<QQ, OO>), grid, block, 0, stream, a)
     if (q == 1) { if (obs) ISING_LAUNCH3P(1, true); else ISING_LAUNCH3P(1, false); }
     else { if (obs) ISING_LAUNCH3P(0, true); else ISING_LAUNCH3P(0, false); }

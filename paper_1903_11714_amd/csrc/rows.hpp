@@ -267,6 +267,82 @@ __device__ __forceinline__ void bits_to_row(Row& row, const RowBits& b) {
     }
 }
 
+// ---- Tie queue.  A wave decides a word's sites with as many Philox blocks as its least
+// decided site needs, though 15 of 16 sites are decided by the first block.  Where a lane has
+// several independent words to decide (rows of one colour update, or updates of one step that do
+// not read each other), each word takes its first two blocks at once and the words still holding
+// tied sites go to a per-wave queue in LDS; the wave then settles the queue one word per lane, so
+// the later planes cost a block per 64 queued words instead of one per word position.
+
+// Per-wave LDS of a tie queue (5 KiB).  Entry j = one word with sites still tied: those sites,
+// the ones of them compared with T_2, the Philox row, and update | lane << 2 | group << 8.
+// res[lane] = the sites of the lane's updates 0 .. 3 that the queue accepted (zeroed before the
+// pushes).
+struct TieQueue {
+    uint32_t* task;  // [4][256]: tied, tied & sel2, row, meta
+    uint4* res;      // [64]
+};
+constexpr uint32_t kTieQueueBytes = 256u * 16u + 64u * 16u;
+
+// The four bit planes of one Philox block against the thresholds (as in accept_mask).
+__device__ __forceinline__ void compare_planes(uint32_t& acc, uint32_t& tied, uint32_t sel2, const Words4& blk,
+                                               const Thresholds& th, uint32_t m) {
+    const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t k = 4u * m + (uint32_t)w;
+        // threshold bit of every site: bit 31 - k of T_4, flipped on sel2 where T_2 differs (two
+        // instructions with uniform masks; branching on the uniform bits instead measured slower)
+        const uint32_t m4 = 0u - ((th.t4 >> (31u - k)) & 1u);
+        const uint32_t d = 0u - (((th.t2 ^ th.t4) >> (31u - k)) & 1u);
+        const uint32_t tbit = m4 ^ (sel2 & d);
+        const uint32_t x = planes[w];
+        acc |= tied & tbit & ~x;
+        tied &= ~(x ^ tbit);
+    }
+}
+
+// Appends the lane's word to the queue if it has tied sites (n = entries so far, uniform).
+__device__ __forceinline__ void tq_push(const TieQueue& q, uint32_t& n, uint32_t tied, uint32_t sel2, uint32_t row,
+                                        uint32_t meta) {
+    const uint64_t B = __builtin_amdgcn_ballot_w64(tied != 0u);
+    if (tied != 0u) {
+        const uint32_t pos =
+            n + __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, 0u));
+        q.task[pos] = tied;
+        q.task[256u + pos] = sel2 & tied;
+        q.task[512u + pos] = row;
+        q.task[768u + pos] = meta;
+    }
+    n += (uint32_t)__builtin_popcountll(B);
+}
+
+// Settles the n queued words (n <= 256), one per lane, with the planes of blocks 2 onwards.  The
+// uniform of a word of update u has sweep t + u / 2 and colour 1 - u % 2 when QC < 0 (the
+// two-sweep walk), sweep t and colour QC otherwise.
+template <int QC>
+__device__ __forceinline__ void tq_settle(const TieQueue& q, uint32_t n, const Thresholds& th, uint32_t t,
+                                          uint32_t key0, uint32_t key1, uint32_t lane) {
+    wave_lds_sync();
+#pragma unroll 1
+    for (uint32_t b = 0; b < n; b += 64u) {
+        const uint32_t j = b + lane;
+        const bool have = j < n;
+        uint4 tk = make_uint4(0u, 0u, 0u, 0u);
+        if (have) tk = make_uint4(q.task[j], q.task[256u + j], q.task[512u + j], q.task[768u + j]);
+        const uint32_t u = tk.w & 3u, src = (tk.w >> 2) & 63u, g = tk.w >> 8;
+        const uint32_t tu = QC < 0 ? t + (u >> 1) : t, qu = QC < 0 ? (u & 1u) ^ 1u : (uint32_t)QC;
+        uint32_t acc = 0u, tied = tk.x;
+#pragma unroll 1
+        for (uint32_t m = 2; m < th.blocks; ++m) {
+            if (!wave_any(tied != 0u)) break;
+            compare_planes(acc, tied, tk.y, philox4x32_10(g, tk.z, tu, 2u * m + qu, key0, key1), th, m);
+        }
+        if (have) reinterpret_cast<uint32_t*>(q.res)[4u * src + u] = acc;
+    }
+    wave_lds_sync();
+}
+
 __device__ __forceinline__ void workgroup_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();

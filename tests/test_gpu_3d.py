@@ -210,6 +210,30 @@ def test_sweeps3_packed_match_oracle(dev, oracle_lib, L, beta, n, seed, offset):
     assert np.array_equal(tr.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("ties", [1, 0])
+@pytest.mark.parametrize("L,beta,n", [(64, BETA_C3, 3), (128, 0.15, 2), (64, 0.0, 1), (64, math.inf, 2)])
+def test_packed3_planes_and_tie_queue_match_oracle(dev, oracle_lib, L, beta, n, ties):
+    # ties = 1: a lane decides four planes' words with two Philox blocks each and the wave settles
+    # the words left with tied sites together (needs planes per lane % 4 == 0); 0: plane by plane
+    _say("packed3 planes/ties", L, beta, n, ties)
+    host = oracle_lib.init3(L, 5)
+    ref_host = host.copy()
+    ref = oracle_lib.sweep3(ref_host, beta, n, 5, 9, trace=True)
+    try:
+        dev.ising_set_option("packed_ties", ties)
+        for rz in (2, 4, 8, 16, 32):
+            dev.ising_set_option("planes3", rz)
+            p = _planes3(L)
+            dev.ising3_pack(_to_dev(host), L, p)
+            tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+            dev.ising3_sweep_packed(p, L, beta, n, 5, 9, tr)
+            assert np.array_equal(_unpacked3(dev, p, L).cpu().numpy(), ref_host), rz
+            assert np.array_equal(tr.cpu().numpy(), ref), rz
+    finally:
+        dev.ising_set_option("planes3", 0)
+        dev.ising_set_option("packed_ties", 1)
+
+
 @pytest.mark.parametrize("L,n", [(256, 3), (1024, 2)])
 def test_packed3_equals_int8(dev, L, n):
     _say("packed3 == int8", L, n)
