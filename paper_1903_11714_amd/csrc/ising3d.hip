@@ -37,6 +37,24 @@ struct Thresholds3 {
     uint32_t blocks;  // Philox blocks (4 bit planes each) that can decide
 };
 
+// The four bit planes of one Philox block against T_2 / T_4 / T_6: the threshold bit is bit
+// 31 - k of T_6, flipped on s2 where T_2 differs from it and on s4 where T_4 does.
+__device__ __forceinline__ void compare_planes3(uint32_t& acc, uint32_t& tied, uint32_t s2, uint32_t s4,
+                                                const Words4& blk, const Thresholds3& th, uint32_t m) {
+    const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t k = 4u * m + (uint32_t)w;
+        const uint32_t m6 = 0u - ((th.t[2] >> (31u - k)) & 1u);
+        const uint32_t d2 = 0u - (((th.t[0] ^ th.t[2]) >> (31u - k)) & 1u);
+        const uint32_t d4 = 0u - (((th.t[1] ^ th.t[2]) >> (31u - k)) & 1u);
+        const uint32_t tbit = m6 ^ (s2 & d2) ^ (s4 & d4);
+        const uint32_t x = planes[w];
+        acc |= tied & tbit & ~x;
+        tied &= ~(x ^ tbit);
+    }
+}
+
 // Exact x < T_s for the sites of sel2 / sel4 / sel6, bit plane by bit plane (as accept_mask).
 __device__ __forceinline__ uint32_t accept_mask3(uint32_t sel2, uint32_t sel4, uint32_t sel6, const Thresholds3& th,
                                                  uint32_t g, uint32_t r, uint32_t t, uint32_t q, uint32_t key0,
@@ -49,19 +67,7 @@ __device__ __forceinline__ uint32_t accept_mask3(uint32_t sel2, uint32_t sel4, u
 #pragma unroll 1
     for (uint32_t m = 0; m < th.blocks; ++m) {
         if (!wave_any(tied != 0)) break;
-        const Words4 blk = philox4x32_10(g, r, t, 2u * m + q, key0, key1);
-        const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const uint32_t k = 4u * m + (uint32_t)w;
-            const uint32_t m2 = 0u - ((th.t[0] >> (31u - k)) & 1u);
-            const uint32_t m4 = 0u - ((th.t[1] >> (31u - k)) & 1u);
-            const uint32_t m6 = 0u - ((th.t[2] >> (31u - k)) & 1u);
-            const uint32_t tbit = (sel2 & m2) | (sel4 & m4) | (sel6 & m6);  // the site's threshold bit
-            const uint32_t x = planes[w];
-            acc |= tied & tbit & ~x;
-            tied &= ~(x ^ tbit);
-        }
+        compare_planes3(acc, tied, sel2, sel4, philox4x32_10(g, r, t, 2u * m + q, key0, key1), th, m);
     }
     return acc;
 }
@@ -534,24 +540,6 @@ struct TieQueue3 {
     uint4* res;      // [64]
 };
 constexpr uint32_t kTieQueue3Bytes = 5u * 256u * 4u + 64u * 16u;
-
-// The four bit planes of one Philox block against T_2 / T_4 / T_6: the threshold bit is bit
-// 31 - k of T_6, flipped on s2 where T_2 differs from it and on s4 where T_4 does.
-__device__ __forceinline__ void compare_planes3(uint32_t& acc, uint32_t& tied, uint32_t s2, uint32_t s4,
-                                                const Words4& blk, const Thresholds3& th, uint32_t m) {
-    const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const uint32_t k = 4u * m + (uint32_t)w;
-        const uint32_t m6 = 0u - ((th.t[2] >> (31u - k)) & 1u);
-        const uint32_t d2 = 0u - (((th.t[0] ^ th.t[2]) >> (31u - k)) & 1u);
-        const uint32_t d4 = 0u - (((th.t[1] ^ th.t[2]) >> (31u - k)) & 1u);
-        const uint32_t tbit = m6 ^ (s2 & d2) ^ (s4 & d4);
-        const uint32_t x = planes[w];
-        acc |= tied & tbit & ~x;
-        tied &= ~(x ^ tbit);
-    }
-}
 
 // Half-sweep of colour Q on the packed cubic layout with the ties of four planes settled together:
 // a lane takes planes z .. z + 3 of its column at a time (all colour-Q sites of a half-sweep are

@@ -181,6 +181,26 @@ struct Thresholds {
                             // both thresholds are multiples of 2^16 (16-bit uniforms)
 };
 
+// The four bit planes of one Philox block (planes 4m .. 4m + 3) against the thresholds: a tied site
+// whose uniform has 0 where its threshold has 1 is accepted (x < T), one that differs the other way
+// is decided against, one that agrees stays tied.
+__device__ __forceinline__ void compare_planes(uint32_t& acc, uint32_t& tied, uint32_t sel2, const Words4& blk,
+                                               const Thresholds& th, uint32_t m) {
+    const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t k = 4u * m + (uint32_t)w;
+        // threshold bit of every site: bit 31 - k of T_4, flipped on sel2 where T_2 differs (two
+        // instructions with uniform masks; branching on the uniform bits instead measured slower)
+        const uint32_t m4 = 0u - ((th.t4 >> (31u - k)) & 1u);
+        const uint32_t d = 0u - (((th.t2 ^ th.t4) >> (31u - k)) & 1u);
+        const uint32_t tbit = m4 ^ (sel2 & d);
+        const uint32_t x = planes[w];
+        acc |= tied & tbit & ~x;
+        tied &= ~(x ^ tbit);
+    }
+}
+
 // Exact x < T for every site in sel2 (threshold T_2) or sel4 (T_4), bit plane by bit plane.
 // Returns the accepted sites.  Planes come four per Philox block with counter
 // (g, r, t, 2m + q), plane k = 4m + w is bit 31 - k of each site's uniform.
@@ -197,20 +217,7 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t sel2, uint32_t sel4, co
         // a site still tied after the last deciding plane has x >= T (the remaining bits of T
         // are zero), so it is rejected
         if (!wave_any(tied != 0)) break;
-        const Words4 blk = philox4x32_10(g, r, t, 2u * m + q, key0, key1);
-        const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const uint32_t k = 4u * m + (uint32_t)w;
-            // threshold bit of every site: bit 31 - k of T_2 on sel2, of T_4 elsewhere (the
-            // value outside sel2 | sel4 is never used because those sites are not tied)
-            const uint32_t m2 = 0u - ((th.t2 >> (31u - k)) & 1u);
-            const uint32_t m4 = 0u - ((th.t4 >> (31u - k)) & 1u);
-            const uint32_t tbit = (sel2 & m2) | (~sel2 & m4);
-            const uint32_t x = planes[w];
-            acc |= tied & tbit & ~x;   // first difference: x has 0 where T has 1 -> x < T
-            tied &= ~(x ^ tbit);       // still equal so far
-        }
+        compare_planes(acc, tied, sel2, philox4x32_10(g, r, t, 2u * m + q, key0, key1), th, m);
     }
     return acc;
 }
@@ -283,24 +290,6 @@ struct TieQueue {
     uint4* res;      // [64]
 };
 constexpr uint32_t kTieQueueBytes = 256u * 16u + 64u * 16u;
-
-// The four bit planes of one Philox block against the thresholds (as in accept_mask).
-__device__ __forceinline__ void compare_planes(uint32_t& acc, uint32_t& tied, uint32_t sel2, const Words4& blk,
-                                               const Thresholds& th, uint32_t m) {
-    const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const uint32_t k = 4u * m + (uint32_t)w;
-        // threshold bit of every site: bit 31 - k of T_4, flipped on sel2 where T_2 differs (two
-        // instructions with uniform masks; branching on the uniform bits instead measured slower)
-        const uint32_t m4 = 0u - ((th.t4 >> (31u - k)) & 1u);
-        const uint32_t d = 0u - (((th.t2 ^ th.t4) >> (31u - k)) & 1u);
-        const uint32_t tbit = m4 ^ (sel2 & d);
-        const uint32_t x = planes[w];
-        acc |= tied & tbit & ~x;
-        tied &= ~(x ^ tbit);
-    }
-}
 
 // Appends the lane's word to the queue if it has tied sites (n = entries so far, uniform).
 __device__ __forceinline__ void tq_push(const TieQueue& q, uint32_t& n, uint32_t tied, uint32_t sel2, uint32_t row,
