@@ -866,7 +866,7 @@ __global__ __launch_bounds__(256) void k_sweep_packed(PackedArgs a) {
 // settles them with the other lanes' (as in the two-sweep pass).  Same uniforms and results as
 // k_sweep_packed.  rows % 4 == 0; lanes past n_lanes shadow the last lane without storing.
 template <int Q, bool OBS>
-__global__ __launch_bounds__(256) void k_sweep_packed_q(PackedArgs a) {
+__global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
     extern __shared__ uint4 packed_lds[];
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     uint4* const mine = packed_lds + (tid >> 6) * (kTieQueueBytes / 16u);
@@ -1995,13 +1995,17 @@ int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Threshold
     a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
     const dim3 grid((a.n_lanes + 255u) / 256u), block(256);
     if (g_opt.packed_ties && a.rows % 4u == 0) {
-        const size_t lds = 4u * ising::kTieQueueBytes;  // four waves per workgroup
+        // a counting launch ends every workgroup with atomics on the same two words: 512 threads
+        // per workgroup halve them (the others keep 256, which leaves more waves per CU)
+        const uint32_t threads = obs ? 512u : 256u;
+        const dim3 qgrid((a.n_lanes + threads - 1u) / threads), qblock(threads);
+        const size_t lds = (threads / 64u) * ising::kTieQueueBytes;
         if (q == 1) {
-            if (obs) hipLaunchKernelGGL((ising::k_sweep_packed_q<1, true>), grid, block, lds, stream, a);
-            else hipLaunchKernelGGL((ising::k_sweep_packed_q<1, false>), grid, block, lds, stream, a);
+            if (obs) hipLaunchKernelGGL((ising::k_sweep_packed_q<1, true>), qgrid, qblock, lds, stream, a);
+            else hipLaunchKernelGGL((ising::k_sweep_packed_q<1, false>), qgrid, qblock, lds, stream, a);
         } else {
-            if (obs) hipLaunchKernelGGL((ising::k_sweep_packed_q<0, true>), grid, block, lds, stream, a);
-            else hipLaunchKernelGGL((ising::k_sweep_packed_q<0, false>), grid, block, lds, stream, a);
+            if (obs) hipLaunchKernelGGL((ising::k_sweep_packed_q<0, true>), qgrid, qblock, lds, stream, a);
+            else hipLaunchKernelGGL((ising::k_sweep_packed_q<0, false>), qgrid, qblock, lds, stream, a);
         }
         return check_launch("k_sweep_packed_q");
     }
