@@ -289,9 +289,13 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
  *   "fused_ties"     two-sweep pass: 1 = its four updates of a step are independent and the
  *                    words still tied after two Philox blocks are settled together (default),
  *                    0 = each update settles its own words before the next one.
- *   "packed_ties"    ising_sweep_packed / ising_half_sweep_packed: 1 = each lane takes four rows
- *                    at a time and their still-tied words are settled together (default; used
- *                    when the rows per lane are a multiple of 4), 0 = row by row.
+ *   "packed_ties"    ising_sweep_packed / ising_half_sweep_packed (and the 3-D packed sweep, four
+ *                    planes): 1 = each lane takes four rows at a time and their still-tied words are
+ *                    settled together (default; used when the rows per lane are a multiple of 4),
+ *                    0 = row by row.
+ *   "ties3"          ising3_sweep / ising3_half_sweep: 1 = the two planes of each step share one
+ *                    row exchange and their still-tied words are settled together (default),
+ *                    0 = plane by plane.
  *   "planes3"        planes each workgroup of ising3_sweep (each lane of ising3_sweep_packed)
  *                    walks: 0 = automatic, else a power of two in [2, 256] (ignored for lattices it
  *                    does not divide). */

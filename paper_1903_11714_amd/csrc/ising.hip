@@ -1479,6 +1479,7 @@ struct Options {
     int64_t fused_sweeps = 2;     // fused sweep: sweeps per pass over the lattice (1 or 2)
     int64_t fused_ties = 1;       // two-sweep pass: settle the ties of a step's four updates together
     int64_t packed_ties = 1;      // packed half-sweep: settle the ties of four rows together
+    int64_t ties3 = 1;            // 3-D int8 half-sweep: two planes per exchange, ties settled together
     int64_t planes3 = 0;          // 3-D sweep: planes per workgroup; 0 = choose from L
 };
 Options g_opt;
@@ -2345,6 +2346,9 @@ int ising_set_option(const char* name, int64_t value) {
     } else if (n == "packed_ties") {
         if (value != 0 && value != 1) return ISING_EINVAL;
         g_opt.packed_ties = value;
+    } else if (n == "ties3") {
+        if (value != 0 && value != 1) return ISING_EINVAL;
+        g_opt.ties3 = value;
     } else if (n == "fused_rows") {
         if (value != 0 && (value < 2 || value > 256 || (value & (value - 1)) != 0)) return ISING_EINVAL;
         g_opt.fused_rows = value;
@@ -2370,6 +2374,7 @@ int ising_get_option(const char* name, int64_t* value) {
     else if (n == "fused_sweeps") *value = g_opt.fused_sweeps;
     else if (n == "fused_ties") *value = g_opt.fused_ties;
     else if (n == "packed_ties") *value = g_opt.packed_ties;
+    else if (n == "ties3") *value = g_opt.ties3;
     else if (n == "planes3") *value = g_opt.planes3;
     else return ISING_EINVAL;
     return ISING_OK;

@@ -55,6 +55,87 @@ __device__ __forceinline__ void compare_planes3(uint32_t& acc, uint32_t& tied, u
     }
 }
 
+// ---- Tie queue with three thresholds (as the square lattice's in rows.hpp): entry j = the word's
+// tied sites, those of them compared with T_2 and with T_4 (the rest with T_6), its Philox row, and
+// update | lane << 2 | group << 8; res[lane] = the sites of the lane's updates 0 .. 3 that the queue
+// accepted (zeroed before the pushes).  6 KiB per wave.
+struct TieQueue3 {
+    uint32_t* task;  // [5][256]
+    uint4* res;      // [64]
+};
+constexpr uint32_t kTieQueue3Bytes = 5u * 256u * 4u + 64u * 16u;
+
+// The start of decide3 for one word: returns the sites decided by the neighbour count and the first
+// two Philox blocks (to flip at once); tied, s2, s4 = the sites still tied and which of them
+// compare with T_2 / T_4.
+__device__ __forceinline__ uint32_t decide3_head(uint32_t a, const uint32_t (&nb)[6], const Thresholds3& th,
+                                                 uint32_t g, uint32_t r, uint32_t t, uint32_t q, uint32_t key0,
+                                                 uint32_t key1, uint32_t& tied, uint32_t& s2, uint32_t& s4) {
+    uint32_t x[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) x[k] = a ^ nb[k];
+    const uint32_t sa = x[0] ^ x[1] ^ x[2], ca = (x[0] & x[1]) | (x[2] & (x[0] ^ x[1]));
+    const uint32_t sb = x[3] ^ x[4] ^ x[5], cb = (x[3] & x[4]) | (x[5] & (x[3] ^ x[4]));
+    const uint32_t b0 = sa ^ sb, kk = sa & sb;
+    const uint32_t b1 = ca ^ cb ^ kk, b2 = (ca & cb) | (kk & (ca ^ cb));  // c = b0 + 2 b1 + 4 b2
+    uint32_t sel2 = b1 & ~b0 & ~b2, sel4 = b0 & ~b1 & ~b2, sel6 = ~(b0 | b1 | b2);
+    uint32_t acc = b2 | (b1 & b0);  // c >= 3: s <= 0
+    if (th.full[0]) { acc |= sel2; sel2 = 0u; }
+    if (th.full[1]) { acc |= sel4; sel4 = 0u; }
+    if (th.full[2]) { acc |= sel6; sel6 = 0u; }
+    tied = sel2 | sel4 | sel6;
+#pragma unroll
+    for (uint32_t m = 0; m < 2; ++m) {
+        if (!wave_any(tied != 0u)) break;
+        compare_planes3(acc, tied, sel2, sel4, philox4x32_10(g, r, t, 2u * m + q, key0, key1), th, m);
+    }
+    s2 = sel2;
+    s4 = sel4;
+    return acc;
+}
+
+__device__ __forceinline__ void tq3_push(const TieQueue3& q, uint32_t& n, uint32_t tied, uint32_t s2, uint32_t s4,
+                                         uint32_t row, uint32_t meta) {
+    const uint64_t B = __builtin_amdgcn_ballot_w64(tied != 0u);
+    if (tied != 0u) {
+        const uint32_t pos =
+            n + __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, 0u));
+        q.task[pos] = tied;
+        q.task[256u + pos] = s2 & tied;
+        q.task[512u + pos] = s4 & tied;
+        q.task[768u + pos] = row;
+        q.task[1024u + pos] = meta;
+    }
+    n += (uint32_t)__builtin_popcountll(B);
+}
+
+// Settles the n (<= 256) queued words of colour Q and sweep t, one per lane, from block 2 onwards.
+__device__ __forceinline__ void tq3_settle(const TieQueue3& q, uint32_t n, const Thresholds3& th, uint32_t t,
+                                           uint32_t Q, uint32_t key0, uint32_t key1, uint32_t lane) {
+    wave_lds_sync();
+#pragma unroll 1
+    for (uint32_t b = 0; b < n; b += 64u) {
+        const uint32_t j = b + lane;
+        const bool have = j < n;
+        uint32_t tied = 0u, t2 = 0u, t4 = 0u, r = 0u, meta = 0u;
+        if (have) {
+            tied = q.task[j];
+            t2 = q.task[256u + j];
+            t4 = q.task[512u + j];
+            r = q.task[768u + j];
+            meta = q.task[1024u + j];
+        }
+        uint32_t acc = 0u;
+#pragma unroll 1
+        for (uint32_t m = 2; m < th.blocks; ++m) {
+            if (!wave_any(tied != 0u)) break;
+            compare_planes3(acc, tied, t2, t4, philox4x32_10(meta >> 8, r, t, 2u * m + Q, key0, key1), th, m);
+        }
+        if (have) reinterpret_cast<uint32_t*>(q.res)[4u * ((meta >> 2) & 63u) + (meta & 3u)] = acc;
+    }
+    wave_lds_sync();
+}
+
 // Exact x < T_s for the sites of sel2 / sel4 / sel6, bit plane by bit plane (as accept_mask).
 __device__ __forceinline__ uint32_t accept_mask3(uint32_t sel2, uint32_t sel4, uint32_t sel6, const Thresholds3& th,
                                                  uint32_t g, uint32_t r, uint32_t t, uint32_t q, uint32_t key0,
@@ -114,12 +195,20 @@ struct Sweep3Args {
 
 // HALO: Y < L, so the first and last row of the workgroup take their outer y neighbour from the
 // adjacent strip's row in memory; otherwise the workgroup holds whole planes and y wraps inside.
-template <int Q, bool OBS, bool HALO>
+// TQ: the two planes of a loop iteration are updated together -- one exchange and one barrier for
+// both, and the words left with tied sites after two Philox blocks settled by the wave at once
+// (the planes' colour-Q sites are independent: their z neighbours in each other are the other
+// colour).  Same uniforms and results either way.
+template <int Q, bool OBS, bool HALO, bool TQ>
 __global__ __launch_bounds__(512) void k_sweep3(Sweep3Args a) {
     extern __shared__ uint4 s3_lds[];
     const uint32_t tid = threadIdx.x, nt = blockDim.x, lane = tid & 63u;
-    uint4* const stage = s3_lds + (tid >> 6) * 256u;                            // 4 KiB per wave
-    uint2* const xch = reinterpret_cast<uint2*>(s3_lds + (nt >> 6) * 256u);  // two slots of nt words
+    // per wave: row staging (4 KiB), with TQ shared with the tie queue (6 KiB)
+    constexpr uint32_t kWave = TQ ? kTieQueue3Bytes / 16u : 256u;
+    uint4* const stage = s3_lds + (tid >> 6) * kWave;
+    uint2* const xch = reinterpret_cast<uint2*>(s3_lds + (nt >> 6) * kWave);  // two slots of nt words
+    uint4* const xch4 = s3_lds + (nt >> 6) * kWave;                           // TQ: two slots of nt entries
+    const TieQueue3 q{reinterpret_cast<uint32_t*>(stage), stage + 5u * 64u};
     const uint32_t b = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
     const uint32_t L = a.L, G = a.G, Y = a.Y, Rz = a.Rz;
     const uint32_t y0 = (b % a.ystrips) * Y, z0 = (b / a.ystrips) * Rz;
@@ -176,6 +265,50 @@ __global__ __launch_bounds__(512) void k_sweep3(Sweep3Args a) {
         if (O) cur.o ^= F; else cur.e ^= F;
         put(z, cur);
     };
+    // TQ: planes za and zb = za + 1 (walk order; prev = za - 1, next = zb + 1) in one exchange
+    auto step2 = [&](uint32_t za, uint32_t zb, const RowBits& prev, RowBits& ca, RowBits& cb, const RowBits& next,
+                     const RowBits& hba, const RowBits& hbb, uint32_t slot) {
+        uint4* const x = xch4 + slot * nt;
+        x[tid] = make_uint4(ca.e, ca.o, cb.e, cb.o);
+        workgroup_lds_sync();
+        uint4 ym = x[iym], yp = x[iyp];
+        if (HALO && yy == 0) ym = make_uint4(hba.e, hba.o, hbb.e, hbb.o);
+        if (HALO && yy + 1 == Y) yp = make_uint4(hba.e, hba.o, hbb.e, hbb.o);
+        const uint4 xr = x[ir], xl = x[il];
+        const bool Oa = ((Q + y + za) & 1u) != 0, Ob = !Oa;  // L is even, so zb has the other parity
+        const uint32_t sa = Oa ? ca.e : ca.o, sb = Ob ? cb.e : cb.o;   // the other colour of each row
+        const uint32_t ha = Oa ? shift_next(ca.e, xr.x & 1u) : shift_prev(ca.o, xl.y >> 31);
+        const uint32_t hb = Ob ? shift_next(cb.e, xr.z & 1u) : shift_prev(cb.o, xl.w >> 31);
+        const uint32_t nba[6] = {Oa ? ym.y : ym.x, Oa ? yp.y : yp.x, Oa ? prev.o : prev.e, Oa ? cb.o : cb.e, sa, ha};
+        const uint32_t nbb[6] = {Ob ? ym.w : ym.z, Ob ? yp.w : yp.z, Ob ? ca.o : ca.e, Ob ? next.o : next.e, sb, hb};
+        q.res[lane] = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t n = 0u, tied, s2, s4;
+        uint32_t acc = decide3_head(Oa ? ca.o : ca.e, nba, a.th, g, za * L + y, a.t, (uint32_t)Q, a.key0, a.key1,
+                                    tied, s2, s4);
+        ca.o ^= Oa ? acc : 0u;  // both fields, with selects: the parity is a runtime value
+        ca.e ^= Oa ? 0u : acc;
+        tq3_push(q, n, tied, s2, s4, za * L + y, 0u | (lane << 2) | (g << 8));
+        acc = decide3_head(Ob ? cb.o : cb.e, nbb, a.th, g, zb * L + y, a.t, (uint32_t)Q, a.key0, a.key1, tied, s2,
+                           s4);
+        cb.o ^= Ob ? acc : 0u;
+        cb.e ^= Ob ? 0u : acc;
+        tq3_push(q, n, tied, s2, s4, zb * L + y, 1u | (lane << 2) | (g << 8));
+        tq3_settle(q, n, a.th, a.t, (uint32_t)Q, a.key0, a.key1, lane);
+        const uint4 r = q.res[lane];
+        ca.o ^= Oa ? r.x : 0u;
+        ca.e ^= Oa ? 0u : r.x;
+        cb.o ^= Ob ? r.y : 0u;
+        cb.e ^= Ob ? 0u : r.y;
+        if (OBS) {
+            const uint32_t ma = Oa ? ~0u : 0u;  // masks, not selects of fields
+            const uint32_t fa = (ca.o & ma) | (ca.e & ~ma), fb = (cb.o & ~ma) | (cb.e & ma);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) cnt.anti += __builtin_popcount(fa ^ nba[k]) + __builtin_popcount(fb ^ nbb[k]);
+            cnt.neg += __builtin_popcount(fa) + __builtin_popcount(sa) + __builtin_popcount(fb) + __builtin_popcount(sb);
+        }
+        put(za, ca);
+        put(zb, cb);
+    };
     // prologue: planes z0 - 1 .. z0 + 2 in bits, z0 + 3, z0 + 4 in flight; halo rows of planes
     // z0, z0 + 1 in bits, z0 + 2, z0 + 3 in flight
     Row ra, rb, ha, hb;
@@ -199,12 +332,18 @@ __global__ __launch_bounds__(512) void k_sweep3(Sweep3Args a) {
 #pragma unroll 1
     for (uint32_t k = 0; k < Rz; k += 2) {
         const uint32_t z = zplane(k + 1);
-        step(z, p, c, n0, h0, 0);
-        p = c;
-        c = n0;
-        step(zplane(k + 2), p, c, n1, h1, 1);
-        p = c;
-        c = n1;
+        if (TQ) {
+            step2(z, zplane(k + 2), p, c, n0, n1, h0, h1, (k >> 1) & 1u);
+            p = n0;
+            c = n1;
+        } else {
+            step(z, p, c, n0, h0, 0);
+            p = c;
+            c = n0;
+            step(zplane(k + 2), p, c, n1, h1, 1);
+            p = c;
+            c = n1;
+        }
         n0 = own(ra);  // planes of walk steps k + 4, k + 5
         n1 = own(rb);
         fetch(ra, zplane(k + 6));
@@ -532,15 +671,6 @@ __global__ __launch_bounds__(256) void k_sweep3_packed(Packed3Args a) {
     if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, active ? 1u : 0u, 64u * a.Rz, 3u);
 }
 
-// ---- Tie queue with three thresholds (as the square lattice's, see rows.hpp): entry j = the
-// word's tied sites, those of them compared with T_2 and with T_4 (the rest with T_6), its Philox
-// row, and plane | lane << 2 | group << 8.  6 KiB per wave.
-struct TieQueue3 {
-    uint32_t* task;  // [5][256]
-    uint4* res;      // [64]
-};
-constexpr uint32_t kTieQueue3Bytes = 5u * 256u * 4u + 64u * 16u;
-
 // Half-sweep of colour Q on the packed cubic layout with the ties of four planes settled together:
 // a lane takes planes z .. z + 3 of its column at a time (all colour-Q sites of a half-sweep are
 // independent), draws the first two Philox blocks of each word, queues the words still holding tied
@@ -551,8 +681,7 @@ __global__ __launch_bounds__(256) void k_sweep3_packed_q(Packed3Args a) {
     extern __shared__ uint4 packed3_lds[];
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     uint4* const mine = packed3_lds + (tid >> 6) * (kTieQueue3Bytes / 16u);
-    uint32_t* const task = reinterpret_cast<uint32_t*>(mine);
-    uint4* const res = mine + 5u * 64u;
+    const TieQueue3 q{reinterpret_cast<uint32_t*>(mine), mine + 5u * 64u};
     const uint64_t raw = (uint64_t)logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * blockDim.x + tid;
     if (a.zero_slot && blockIdx.x == 0 && tid == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
     const bool active = raw < a.n_lanes;
@@ -586,7 +715,7 @@ __global__ __launch_bounds__(256) void k_sweep3_packed_q(Packed3Args a) {
             dn[i] = po[at(z, yp, g)];
             ed[i] = po[at(z, y, O ? gr : gl)];
         }
-        res[lane] = make_uint4(0u, 0u, 0u, 0u);
+        q.res[lane] = make_uint4(0u, 0u, 0u, 0u);
         uint32_t n = 0u;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -595,64 +724,12 @@ __global__ __launch_bounds__(256) void k_sweep3_packed_q(Packed3Args a) {
             const uint32_t side = zw[i + 1];
             const uint32_t hs = O ? shift_next(side, ed[i] & 1u) : shift_prev(side, ed[i] >> 31);
             const uint32_t nb[6] = {up[i], dn[i], zw[i], zw[i + 2], side, hs};
-            uint32_t x[6];
-#pragma unroll
-            for (int j = 0; j < 6; ++j) x[j] = w[i] ^ nb[j];
-            const uint32_t s1 = x[0] ^ x[1] ^ x[2], c1 = (x[0] & x[1]) | (x[2] & (x[0] ^ x[1]));
-            const uint32_t s2 = x[3] ^ x[4] ^ x[5], c2 = (x[3] & x[4]) | (x[5] & (x[3] ^ x[4]));
-            const uint32_t b0 = s1 ^ s2, kk = s1 & s2;
-            const uint32_t b1 = c1 ^ c2 ^ kk, b2 = (c1 & c2) | (kk & (c1 ^ c2));  // c = b0 + 2 b1 + 4 b2
-            uint32_t sel2 = b1 & ~b0 & ~b2, sel4 = b0 & ~b1 & ~b2, sel6 = ~(b0 | b1 | b2);
-            uint32_t acc = b2 | (b1 & b0);  // c >= 3: s <= 0
-            if (th.full[0]) { acc |= sel2; sel2 = 0u; }
-            if (th.full[1]) { acc |= sel4; sel4 = 0u; }
-            if (th.full[2]) { acc |= sel6; sel6 = 0u; }
-            uint32_t tied = sel2 | sel4 | sel6;
-            const uint32_t r = z * L + y;
-#pragma unroll
-            for (uint32_t m = 0; m < 2; ++m) {
-                if (!wave_any(tied != 0u)) break;
-                compare_planes3(acc, tied, sel2, sel4, philox4x32_10(g, r, a.t, 2u * m + (uint32_t)Q, a.key0, a.key1),
-                                th, m);
-            }
-            w[i] ^= acc;
-            const uint64_t B = __builtin_amdgcn_ballot_w64(tied != 0u);
-            if (tied != 0u) {
-                const uint32_t pos =
-                    n + __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, 0u));
-                task[pos] = tied;
-                task[256u + pos] = sel2 & tied;
-                task[512u + pos] = sel4 & tied;
-                task[768u + pos] = r;
-                task[1024u + pos] = (uint32_t)i | (lane << 2) | (g << 8);
-            }
-            n += (uint32_t)__builtin_popcountll(B);
+            uint32_t tied, s2, s4;
+            w[i] ^= decide3_head(w[i], nb, th, g, z * L + y, a.t, (uint32_t)Q, a.key0, a.key1, tied, s2, s4);
+            tq3_push(q, n, tied, s2, s4, z * L + y, (uint32_t)i | (lane << 2) | (g << 8));
         }
-        // settle the queued words, one per lane, with the planes of blocks 2 onwards
-        wave_lds_sync();
-#pragma unroll 1
-        for (uint32_t b = 0; b < n; b += 64u) {
-            const uint32_t j = b + lane;
-            const bool have = j < n;
-            uint32_t tied = 0u, t2 = 0u, t4 = 0u, r = 0u, meta = 0u;
-            if (have) {
-                tied = task[j];
-                t2 = task[256u + j];
-                t4 = task[512u + j];
-                r = task[768u + j];
-                meta = task[1024u + j];
-            }
-            uint32_t acc = 0u;
-#pragma unroll 1
-            for (uint32_t m = 2; m < th.blocks; ++m) {
-                if (!wave_any(tied != 0u)) break;
-                compare_planes3(acc, tied, t2, t4,
-                                philox4x32_10(meta >> 8, r, a.t, 2u * m + (uint32_t)Q, a.key0, a.key1), th, m);
-            }
-            if (have) reinterpret_cast<uint32_t*>(res)[4u * ((meta >> 2) & 63u) + (meta & 3u)] = acc;
-        }
-        wave_lds_sync();
-        const uint4 rr = res[lane];
+        tq3_settle(q, n, th, a.t, (uint32_t)Q, a.key0, a.key1, lane);
+        const uint4 rr = q.res[lane];
         w[0] ^= rr.x;
         w[1] ^= rr.y;
         w[2] ^= rr.z;
@@ -777,10 +854,16 @@ int launch_half_sweep3(int8_t* spins, int64_t L, const ising::Thresholds3& th, u
     a.zero_slot = zero_slot;
     a.xcd_remap = ising_host::xcd_remap() ? 1u : 0u;
     const uint32_t threads = sh.W * 64u;
-    const size_t lds = (size_t)sh.W * 4096u + 2u * threads * sizeof(uint2);
+    const bool tq = ising_host::option("ties3") != 0;
+    const size_t lds = tq ? (size_t)sh.W * ising::kTieQueue3Bytes + 2u * threads * sizeof(uint4)
+                          : (size_t)sh.W * 4096u + 2u * threads * sizeof(uint2);
     const dim3 grid(sh.ystrips * (uint32_t)(L / sh.Rz)), block(threads);
     const bool halo = (int64_t)sh.Y < L;
-#define ISING_LAUNCH3(QQ, OO, HH) hipLaunchKernelGGL((ising::k_sweep3<QQ, OO, HH>), grid, block, lds, stream, a)
+#define ISING_LAUNCH3(QQ, OO, HH)                                                                         \
+    do {                                                                                                  \
+        if (tq) hipLaunchKernelGGL((ising::k_sweep3<QQ, OO, HH, true>), grid, block, lds, stream, a);    \
+        else hipLaunchKernelGGL((ising::k_sweep3<QQ, OO, HH, false>), grid, block, lds, stream, a);      \
+    } while (0)
     if (q == 1) {
         if (halo) { if (obs) ISING_LAUNCH3(1, true, true); else ISING_LAUNCH3(1, false, true); }
         else { if (obs) ISING_LAUNCH3(1, true, false); else ISING_LAUNCH3(1, false, false); }

@@ -135,7 +135,7 @@ def test_options_round_trip(lib):
     for name, good, bad in (("rows_per_lane", [0, 2, 64], [1, 3, 128, -2]), ("xcd_remap", [0, 1], [2]),
                             ("staged", [0, 1], [-1]), ("nt_store", [0, 1], [5]),
                             ("fused_rows", [0, 2, 16, 256], [1, 6, 512, -4]), ("fused_alternate", [0, 1], [2]), ("fused_sweeps", [1, 2], [0, 3]),
-                            ("fused_ties", [0, 1], [2, -1]), ("packed_ties", [0, 1], [2]),
+                            ("fused_ties", [0, 1], [2, -1]), ("packed_ties", [0, 1], [2]), ("ties3", [0, 1], [2]),
                             ("planes3", [0, 2, 32, 256], [1, 3, 512]),
                             ("batch_threads", [0, 256, 512, 1024], [128, 2048, -1]),
                             ("batch_slab_sites", [0, -1, 1024, 65536, 262144], [512, 3000, 524288, -2]),

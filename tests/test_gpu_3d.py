@@ -77,14 +77,21 @@ def test_half_sweep3_matches_oracle(dev, oracle_lib, L, beta, q):
     assert np.array_equal(s.cpu().numpy(), host)
 
 
+@pytest.mark.parametrize("ties", [1, 0])
 @pytest.mark.parametrize("L,beta,n,seed,offset", [(64, BETA_C3, 10, 1, 0), (128, 0.25, 4, 2**33 + 1, 7),
-                                                  (256, BETA_C3, 2, 5, 2**32 - 2)])
-def test_sweeps3_match_oracle(dev, oracle_lib, L, beta, n, seed, offset):
-    _say("sweep3", L, beta, n)
+                                                  (256, BETA_C3, 2, 5, 2**32 - 2), (128, 0.0, 2, 3, 0),
+                                                  (64, math.inf, 2, 4, 1)])
+def test_sweeps3_match_oracle(dev, oracle_lib, L, beta, n, seed, offset, ties):
+    # ties = 1: the two planes of each step share one exchange and one tie queue; 0: plane by plane
+    _say("sweep3", L, beta, n, ties)
     s = torch.empty((L, L, L), dtype=torch.int8, device="cuda")
     dev.ising3_init(s, L, seed)
     tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
-    dev.ising3_sweep(s, L, beta, n, seed, offset, tr)
+    dev.ising_set_option("ties3", ties)
+    try:
+        dev.ising3_sweep(s, L, beta, n, seed, offset, tr)
+    finally:
+        dev.ising_set_option("ties3", 1)
     host = oracle_lib.init3(L, seed)
     ref = oracle_lib.sweep3(host, beta, n, seed, offset, trace=True)
     assert np.array_equal(s.cpu().numpy(), host)
@@ -134,20 +141,22 @@ def test_every_plane_count_gives_identical_lattices(dev, L):
     ref = None
     try:
         for rz in (0, 2, 4, 8, 16, 32, 64):
-            for remap in (1, 0):
+            for remap, ties in ((1, 1), (0, 1), (1, 0)):
                 dev.ising_set_option("planes3", rz)
                 dev.ising_set_option("xcd_remap", remap)
+                dev.ising_set_option("ties3", ties)
                 s = base.clone()
                 tr = torch.empty((3, 2), dtype=torch.int64, device="cuda")
                 dev.ising3_sweep(s, L, BETA_C3, 3, 17, 40, tr)
                 if ref is None:
                     ref = (s, tr)
                 else:
-                    assert torch.equal(s, ref[0]), (rz, remap)
-                    assert torch.equal(tr, ref[1]), (rz, remap)
+                    assert torch.equal(s, ref[0]), (rz, remap, ties)
+                    assert torch.equal(tr, ref[1]), (rz, remap, ties)
     finally:
         dev.ising_set_option("planes3", 0)
         dev.ising_set_option("xcd_remap", 1)
+        dev.ising_set_option("ties3", 1)
 
 
 def test_invalid_3d_arguments_raise(dev):
