@@ -39,11 +39,12 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "spin-flip attempts/ns (L=16384², T_c) + % HBM peak, exact vs bf16 accept"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_11714_amd", "csrc", f) for f in ("ising.hip", "philox.hpp", "rows.hpp")]
+KERNEL_SOURCES_3D = KERNEL_SOURCES + [os.path.join(ROOT, "paper_1903_11714_amd", "csrc", "ising3d.hip")]
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources or KERNEL_SOURCES:
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -59,7 +60,8 @@ def measured_counters(layout: str, L: int) -> dict:
     except (OSError, ValueError):
         return {}
     entry = rec.get(f"{layout}_L{L}")
-    if not entry or entry.get("source_hash") != kernel_source_hash():
+    sources = KERNEL_SOURCES_3D if layout.endswith("3d") else KERNEL_SOURCES
+    if not entry or entry.get("source_hash") != kernel_source_hash(sources):
         return {}
     return entry
 
@@ -193,7 +195,8 @@ def bench_3d(ising, torch, args, stream) -> dict:
                                f"exact-threshold checkerboard Metropolis, int8 ({L ** 3 / 2 ** 20:.0f} MiB), one "
                                "launch per colour, (M,E) traced every sweep", "L": L, "beta": beta},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sweep3 (one colour per launch)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("int8_3d", L),
+                     "kernel": "k_sweep3 (one colour per launch, two planes per exchange)",
                      "avg_launch_us": launch_us, "alg_bytes_per_launch": alg, "copy_GBs": cb,
                      "copy_kind": "in place", "frac_of_copy": achieved / cb if cb else None},
         "final_ME": trace[K - 1].tolist() if K else None,
