@@ -1628,7 +1628,8 @@ uint32_t fused_rows(int64_t L, int sweeps = 1) {
     if (g_opt.fused_rows > 0 && L % g_opt.fused_rows == 0 && g_opt.fused_rows <= L) return (uint32_t)g_opt.fused_rows;
     const uint64_t waves = (uint64_t)(L / 64 + 63) / 64;
     uint32_t R = sweeps == 2 ? 128 : 64;
-    while (R > 8 && (uint64_t)(L / R) * waves < 4096ull) R >>= 1;
+    // R must divide L (64 always does): L = 64 (2k + 1) takes at most 64 rows
+    while (R > 8 && ((uint64_t)(L / R) * waves < 4096ull || L % R != 0)) R >>= 1;
     return R;
 }
 

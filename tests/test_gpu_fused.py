@@ -218,6 +218,25 @@ def test_fused_largest_lattice_and_in_place_above_it(dev):
         torch.cuda.empty_cache()
 
 
+def test_fused_strip_height_divides_odd_multiple_of_64(dev):
+    # L = 64 * 769: the tallest two-sweep strip that leaves enough waves (128 rows) does not divide L,
+    # so the strips must be 64 rows tall; every row of the lattice must still be swept
+    L, n = 64 * 769, 2
+    _say("fused odd multiple of 64", L)
+    base = torch.empty((L, L), dtype=torch.int8, device="cuda")
+    dev.ising_init(base, L, 5)
+    ref = base.clone()
+    ref_tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising_sweep_fmt(ref, L, BETA_C, "exact", n, 5, 0, ref_tr)
+    scratch = torch.empty_like(base)
+    tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising_sweep_fused(base, scratch, L, BETA_C, "exact", n, 5, 0, tr)
+    assert torch.equal(base, ref)
+    assert torch.equal(tr, ref_tr)
+    del base, ref, scratch
+    torch.cuda.empty_cache()
+
+
 def test_fused_rejects_overlap(dev):
     s = torch.empty((128, 128), dtype=torch.int8, device="cuda")
     with pytest.raises(dev.IsingError):
