@@ -286,9 +286,9 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
  *                    of two in [2, 256] (ignored for lattices it does not divide).
  *   "fused_alternate" 1 = odd strips of ising_sweep_fused walk upwards (default), 0 = all down.
  *   "fused_sweeps"   sweeps per pass of ising_sweep_fused: 2 (default) or 1.
- *   "fused_ties"     two-sweep pass: 1 = its four updates of a step are independent and the
- *                    words still tied after two Philox blocks are settled together (default),
- *                    0 = each update settles its own words before the next one.
+ *   "fused_ties"     fused passes (two sweeps or one): 1 = the updates of a step are independent
+ *                    and the words still tied after two Philox blocks are settled together
+ *                    (default), 0 = each update settles its own words before the next one.
  *   "packed_ties"    ising_sweep_packed / ising_half_sweep_packed (and the 3-D packed sweep, four
  *                    planes): 1 = each lane takes four rows at a time and their still-tied words are
  *                    settled together (default; used when the rows per lane are a multiple of 4),

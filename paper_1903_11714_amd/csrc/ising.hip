@@ -717,6 +717,107 @@ __global__ __launch_bounds__(1024) void k_sweep_fused2q(FusedArgs a) {
     }
 }
 
+// ---- One sweep per pass with the ties of a step settled together: the one-sweep walk with two
+// rows between its updates.  Step s updates the white sites of walk row s + 1 and the black sites
+// of walk row s - 1; neither reads what the other writes, so the two are independent and share
+// the tie queue (as in the two-sweep pass).  Same rows read and written as k_sweep_fused, same
+// uniforms, same result.
+template <bool OBS, bool STAGED, bool UP>
+__device__ __forceinline__ void fusedq_strip(const FusedArgs& a, uint32_t strip, uint4* fused_lds, Counts& ct) {
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t G = a.groups, L = a.L, R = a.rows;
+    uint4* const stage = fused_lds + (tid >> 6) * (kTieQueueBytes / 16u);
+    uint32_t* const xch = reinterpret_cast<uint32_t*>(fused_lds + (nt >> 6) * (kTieQueueBytes / 16u));
+    const TieQueue q{reinterpret_cast<uint32_t*>(stage), stage + 256};
+    const bool active = tid < G;
+    const uint32_t g = active ? tid : G - 1;
+    const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
+    const uint32_t lane = tid & 63u;
+    const uint32_t r0 = strip * R;
+    const size_t col = (size_t)(STAGED ? g - lane : g) * 64u;
+    // walk row k = 0 .. R + 3: r0 - 2 .. r0 + R + 1 (down) or r0 + R + 1 .. r0 - 2 (up), wrapped;
+    // prefetches past the last walk row are clamped to it
+    auto vrow = [&](uint32_t k) {
+        const uint32_t kk = k < R + 3 ? k : R + 3;
+        const uint32_t v = UP ? r0 + R + 1 + L - kk : r0 + L + kk - 2;  // in [L - 2, 2L + 2)
+        return v >= 2 * L ? v - 2 * L : v >= L ? v - L : v;
+    };
+    auto fetch = [&](Row& raw, uint32_t r) {
+        if (STAGED) load_row_coalesced(raw, a.src + (size_t)r * L + col, lane);
+        else load_row(raw, a.src + (size_t)r * L + col);
+    };
+    auto own = [&](const Row& raw) {
+        if (!STAGED) return row_bits(raw);
+        Row row;
+        regroup_to_owner(row, raw, stage, lane);
+        return row_bits(row);
+    };
+    auto put = [&](uint32_t r, const RowBits& b) {
+        Row row;
+        bits_to_row(row, b);
+        if (STAGED) store_row_coalesced(a.dst + (size_t)r * L + col, row, stage, lane, a.nt_store);
+        else if (active) store_row(a.dst + (size_t)r * L + col, row, a.nt_store);
+    };
+    // Step s makes the white update for s <= R + 1 (walk rows 1 .. R + 2) and the black one for
+    // 3 <= s <= R + 2 (walk rows 2 .. R + 1, the strip's own rows, written after their update).
+    // The white update of an even step lies on columns of parity OA, the black one on 1 - OA.
+    constexpr int OA = UP ? 1 : 0, OB = 1 - OA;
+    const uint32_t t = a.t, k0 = a.key0, k1 = a.key1;
+    Row raw;
+    fetch(raw, vrow(0));
+    RowBits w3{0u, 0u}, w2{0u, 0u};
+    RowBits w1 = own(raw);
+    fetch(raw, vrow(1));
+    RowBits w0 = own(raw);
+    fetch(raw, vrow(2));
+    RowBits nx = own(raw);
+    fetch(raw, vrow(3));
+    xch[tid] = edge_word4(w0, w2, w0, w0);  // slot 0: walk row 1 (pair 0), pair 1 unused yet
+    workgroup_lds_sync();
+#define ISING_FUSEDQ_STEP(O, S)                                                                              \
+    do {                                                                                                     \
+        constexpr int X_ = 1 - (O);                                                                          \
+        const uint32_t s_ = (S);                                                                             \
+        const bool a1 = s_ <= R + 1, a2 = s_ >= 3 && s_ <= R + 2;                                            \
+        const uint32_t sl = (s_ & 1u) * nt;                                                                  \
+        const uint32_t nbL = xch[sl + gl], nbR = xch[sl + gr];                                               \
+        const uint32_t rw1 = vrow(s_ + 1), rw2 = s_ >= 1 ? vrow(s_ - 1) : 0u;                                \
+        q.res[lane] = make_uint4(0u, 0u, 0u, 0u);                                                            \
+        uint32_t n = 0u;                                                                                     \
+        if (a1) tq_update<(O), 1, 0>(w0, nx, w1, nbL, nbR, a.th, g, rw1, t, k0, k1, q, n, lane);             \
+        if (a2) tq_update<X_, 0, 1>(w2, w1, w3, nbL, nbR, a.th, g, rw2, t, k0, k1, q, n, lane);              \
+        tq_settle<-1>(q, n, a.th, t, k0, k1, lane);                                                          \
+        const uint4 r_ = q.res[lane];                                                                        \
+        if (O) { w0.o ^= r_.x; w2.e ^= r_.y; } else { w0.e ^= r_.x; w2.o ^= r_.y; }                          \
+        if (a2) {                                                                                            \
+            if (OBS) tq_count<X_, 1>(w2, w1, w3, nbL, nbR, ct);                                              \
+            put(rw2, w2);                                                                                    \
+        }                                                                                                    \
+        w3 = w2; w2 = w1; w1 = w0; w0 = nx;                                                                  \
+        xch[((s_ + 1) & 1u) * nt + tid] = edge_word4(w0, w2, w0, w0);                                        \
+        nx = own(raw); /* walk row s + 3 */                                                                  \
+        fetch(raw, vrow(s_ + 4));                                                                            \
+        workgroup_lds_sync();                                                                                \
+    } while (0)
+#pragma unroll 1
+    for (uint32_t s = 0; s < R + 4; s += 2) {  // step R + 3 makes no update
+        ISING_FUSEDQ_STEP(OA, s);
+        ISING_FUSEDQ_STEP(OB, s + 1);
+    }
+#undef ISING_FUSEDQ_STEP
+}
+
+template <bool OBS, bool STAGED>
+__global__ __launch_bounds__(1024) void k_sweep_fusedq(FusedArgs a) {
+    extern __shared__ uint4 fused_lds[];
+    const uint32_t strip = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
+    Counts ct{0u, 0u};
+    if (a.alternate && (strip & 1u)) fusedq_strip<OBS, STAGED, true>(a, strip, fused_lds, ct);
+    else fusedq_strip<OBS, STAGED, false>(a, strip, fused_lds, ct);
+    const bool active = threadIdx.x < a.groups;
+    if (OBS) block_accumulate(a.obs, active ? ct.anti : 0u, active ? ct.neg : 0u, active ? 1u : 0u, 64u * a.rows);
+}
+
 // ---- observables of an int8 lattice: M = sum of spins, E = -sum over bonds (right, down).
 struct ObsArgs {
     const int8_t* spins;
@@ -1654,7 +1755,7 @@ int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::T
     a.alternate = g_opt.fused_alternate ? 1u : 0u;
     const uint32_t threads = (a.groups + 63u) / 64u * 64u;
     const bool staged = g_opt.staged && a.groups % 64u == 0;
-    const bool ties = sweeps == 2 && g_opt.fused_ties;
+    const bool ties = g_opt.fused_ties != 0;
     const size_t per_wave = ties ? ising::kTieQueueBytes : staged ? 4096u : 0u;
     const size_t lds = (size_t)(threads / 64u) * per_wave + 2u * threads * sizeof(uint32_t);
     const dim3 grid(a.L / a.rows), block(threads);
@@ -1667,10 +1768,15 @@ int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::T
         }                                                                                                \
         hipLaunchKernelGGL((ising::K<OO, SS>), grid, block, lds, stream, a);                            \
     } while (0)
-    if (ties) {
+    if (ties && sweeps == 2) {
         if (staged) { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused2q, true, true); else ISING_LAUNCH_FUSED(k_sweep_fused2q, false, true); }
         else { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused2q, true, false); else ISING_LAUNCH_FUSED(k_sweep_fused2q, false, false); }
         return check_launch("k_sweep_fused2q");
+    }
+    if (ties) {
+        if (staged) { if (obs) ISING_LAUNCH_FUSED(k_sweep_fusedq, true, true); else ISING_LAUNCH_FUSED(k_sweep_fusedq, false, true); }
+        else { if (obs) ISING_LAUNCH_FUSED(k_sweep_fusedq, true, false); else ISING_LAUNCH_FUSED(k_sweep_fusedq, false, false); }
+        return check_launch("k_sweep_fusedq");
     }
     if (sweeps == 2) {
         if (staged) { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused2, true, true); else ISING_LAUNCH_FUSED(k_sweep_fused2, false, true); }

@@ -45,8 +45,8 @@ def _to_dev(a: np.ndarray):
     (64, BETA_C, 1, 1, 0), (64, BETA_C, 6, 2, 5), (128, 0.3, 4, 3, 0), (192, 0.7, 5, 2**40 + 3, 11),
     (320, 1 / 2.6, 2, 8, 1000), (256, 0.0, 3, 9, 0), (128, math.inf, 4, 10, 2**32 - 4)])
 def test_fused_sweeps_match_oracle(dev, oracle_lib, L, beta, n, seed, offset, fmt, ties):
-    # ties: the two-sweep pass settles the still-tied words of a step's four updates together (1)
-    # or each update finishes its own words (0)
+    # ties: the fused passes settle the still-tied words of a step's updates together (1) or each
+    # update finishes its own words (0)
     _say("fused", L, beta, n, seed, offset, fmt, ties)
     host = inputs.random_lattice(L, seed=L + n)
     s, scratch = _to_dev(host), torch.empty((L, L), dtype=torch.int8, device="cuda")
@@ -105,7 +105,7 @@ def test_fused_equals_two_half_sweeps_for_every_strip_height(dev, L):
     dev.ising_sweep_fmt(ref, L, BETA_C, "exact", 4, 17, 40, ref_tr)
     scratch = torch.empty_like(base)
     try:
-        for sweeps, ties in ((1, 1), (2, 0), (2, 1)):
+        for sweeps, ties in ((1, 0), (1, 1), (2, 0), (2, 1)):
             dev.ising_set_option("fused_sweeps", sweeps)
             dev.ising_set_option("fused_ties", ties)
             for rows in (0, 2, 4, 8, 16, 32, 64, 128, 256):
@@ -139,7 +139,7 @@ def test_fused_sweep_counts_with_one_and_two_sweeps_per_pass(dev, L):
             ref = base.clone()
             ref_tr = torch.empty((max(n, 1), 2), dtype=torch.int64, device="cuda")
             dev.ising_sweep_fmt(ref, L, 0.41, "exact", n, 23, 9, ref_tr[:n])
-            for sweeps, ties in ((1, 1), (2, 0), (2, 1)):
+            for sweeps, ties in ((1, 0), (1, 1), (2, 0), (2, 1)):
                 dev.ising_set_option("fused_sweeps", sweeps)
                 dev.ising_set_option("fused_ties", ties)
                 s = base.clone()
