@@ -236,7 +236,7 @@ def bench_3d(ising, torch, args, stream) -> dict:
         fw = time.perf_counter() - t0
         fl_us = ev0.elapsed_time(ev1) * 1e3 / kf
         res["fused_layout"] = {"value": float(L) ** 3 * kf / (fw * 1e9), "unit": "attempts/ns", "steps": kf,
-                               "kernel": "k_sweep3_fused (both colours per launch)", "avg_launch_us": fl_us,
+                               "kernel": "k_sweep3_fusedq (both colours per launch, tie queue)", "avg_launch_us": fl_us,
                                "hbm_GBs": 2.0 * L ** 3 / (fl_us * 1e-6) / 1e9}
         del buf, lat, scr
     if args.copy_calibration:

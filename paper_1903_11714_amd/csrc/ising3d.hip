@@ -109,9 +109,11 @@ __device__ __forceinline__ void tq3_push(const TieQueue3& q, uint32_t& n, uint32
     n += (uint32_t)__builtin_popcountll(B);
 }
 
-// Settles the n (<= 256) queued words of colour Q and sweep t, one per lane, from block 2 onwards.
+// Settles the n (<= 256) queued words of sweep t, one per lane, from block 2 onwards: all of colour
+// QC, or (QC < 0) update u of colour 1 - u % 2 (white first, as in the fused pass).
+template <int QC>
 __device__ __forceinline__ void tq3_settle(const TieQueue3& q, uint32_t n, const Thresholds3& th, uint32_t t,
-                                           uint32_t Q, uint32_t key0, uint32_t key1, uint32_t lane) {
+                                           uint32_t key0, uint32_t key1, uint32_t lane) {
     wave_lds_sync();
 #pragma unroll 1
     for (uint32_t b = 0; b < n; b += 64u) {
@@ -125,11 +127,12 @@ __device__ __forceinline__ void tq3_settle(const TieQueue3& q, uint32_t n, const
             r = q.task[768u + j];
             meta = q.task[1024u + j];
         }
+        const uint32_t qc = QC < 0 ? (meta & 1u) ^ 1u : (uint32_t)QC;
         uint32_t acc = 0u;
 #pragma unroll 1
         for (uint32_t m = 2; m < th.blocks; ++m) {
             if (!wave_any(tied != 0u)) break;
-            compare_planes3(acc, tied, t2, t4, philox4x32_10(meta >> 8, r, t, 2u * m + Q, key0, key1), th, m);
+            compare_planes3(acc, tied, t2, t4, philox4x32_10(meta >> 8, r, t, 2u * m + qc, key0, key1), th, m);
         }
         if (have) reinterpret_cast<uint32_t*>(q.res)[4u * ((meta >> 2) & 63u) + (meta & 3u)] = acc;
     }
@@ -293,7 +296,7 @@ __global__ __launch_bounds__(512) void k_sweep3(Sweep3Args a) {
         cb.o ^= Ob ? acc : 0u;
         cb.e ^= Ob ? 0u : acc;
         tq3_push(q, n, tied, s2, s4, zb * L + y, 1u | (lane << 2) | (g << 8));
-        tq3_settle(q, n, a.th, a.t, (uint32_t)Q, a.key0, a.key1, lane);
+        tq3_settle<Q>(q, n, a.th, a.t, a.key0, a.key1, lane);
         const uint4 r = q.res[lane];
         ca.o ^= Oa ? r.x : 0u;
         ca.e ^= Oa ? 0u : r.x;
@@ -525,6 +528,161 @@ __global__ __launch_bounds__(576) void k_sweep3_fused(Fused3Args a) {
     if (OBS) block_accumulate(a.obs, own ? cnt.anti : 0u, own ? cnt.neg : 0u, own ? 1u : 0u, 64u * Rz, 3u);
 }
 
+// ---- The fused 3-D sweep with two planes between its updates.  Step k updates the white sites of
+// plane z0 - 1 + k and the black sites of plane z0 - 3 + k: the black update's neighbours are white
+// sites of planes updated at least one step earlier, and the white update reads black sites the
+// step does not change, so the two are independent and share the wave's tie queue (as the square
+// lattice's passes do).  The exchange of a step carries each row's plane being white-updated as it
+// was and the plane being black-updated after its white update.  Same rows read and written as
+// k_sweep3_fused, same uniforms, same result.  One row (and outer row) is prefetched a step ahead.
+template <bool OBS, bool HALO>
+__global__ __launch_bounds__(576) void k_sweep3_fusedq(Fused3Args a) {
+    extern __shared__ uint4 f3q_lds[];
+    const uint32_t tid = threadIdx.x, nt = blockDim.x, lane = tid & 63u;
+    const uint32_t L = a.L, G = a.G, Y = a.Y, Rz = a.Rz, own_n = Y * G;
+    // per wave: row staging (own waves) shared with the tie queue; then two exchange slots
+    uint4* const mine = f3q_lds + (tid >> 6) * (kTieQueue3Bytes / 16u);
+    uint4* const stage = mine;
+    const TieQueue3 q{reinterpret_cast<uint32_t*>(mine), mine + 5u * 64u};
+    uint4* const xch = f3q_lds + (nt >> 6) * (kTieQueue3Bytes / 16u);
+    const uint32_t b = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
+    const uint32_t y0 = (b % a.ystrips) * Y, z0 = (b / a.ystrips) * Rz;
+    const bool own = tid < own_n;                        // uniform per wave (own_n is a multiple of 64)
+    const uint32_t hh = own ? 0u : (tid - own_n) / G;   // halo lanes: 0 = row above, 1 = row below
+    const bool halo = HALO && !own && hh < 2u;          // lanes past the halo rows only shadow
+    const uint32_t g = own ? tid % G : (halo ? (tid - own_n) % G : 0u);
+    const uint32_t yy = own ? tid / G : 0u;
+    const uint32_t wrapy = L - 1u;  // L is a power of two
+    const uint32_t y = own ? y0 + yy : (hh == 0u ? (y0 + L - 1u) & wrapy : (y0 + Y) & wrapy);
+    const uint32_t yo = hh == 0u ? (y0 + L - 2u) & wrapy : (y0 + Y + 1u) & wrapy;  // halo lanes' outer row
+    const size_t plane = (size_t)L * L;
+    const size_t seg = (size_t)y0 * L + (size_t)(tid >> 6) * 4096u;
+    // plane of walk index k = 0 .. Rz + 3: z0 - 2 .. z0 + Rz + 1, wrapped; later ones are clamped
+    auto zplane = [&](uint32_t k) { return (z0 + L - 2u + (k < Rz + 3u ? k : Rz + 3u)) & wrapy; };
+    auto fetch = [&](Row& raw, uint32_t z) {
+        if (own) load_row_coalesced(raw, a.src + z * plane + seg, lane);
+        else if (halo) load_row(raw, a.src + ((size_t)z * L + y) * L + (size_t)g * 64u);
+    };
+    auto bits = [&](const Row& raw) {
+        if (!own) return halo ? row_bits(raw) : RowBits{0u, 0u};
+        Row row;
+        regroup_to_owner(row, raw, stage, lane);
+        return row_bits(row);
+    };
+    auto fetch_outer = [&](Row& raw, uint32_t z) {
+        if (halo) load_row(raw, a.src + ((size_t)z * L + yo) * L + (size_t)g * 64u);
+    };
+    auto put = [&](uint32_t z, const RowBits& rb) {
+        Row row;
+        bits_to_row(row, rb);
+        if (own) store_row_coalesced(a.dst + z * plane + seg, row, stage, lane, false);
+    };
+    const bool shadow = !own && !halo;
+    const uint32_t ir = shadow ? tid : (g + 1 < G ? tid + 1 : tid + 1 - G);
+    const uint32_t il = shadow ? tid : (g > 0 ? tid - 1 : tid + G - 1);
+    uint32_t iym, iyp;
+    if (shadow) {
+        iym = iyp = tid;
+    } else if (own) {
+        iym = yy > 0 ? tid - G : (HALO ? own_n + g : tid + (Y - 1) * G);
+        iyp = yy + 1 < Y ? tid + G : (HALO ? own_n + G + g : tid - (Y - 1) * G);
+    } else {
+        iym = hh == 0u ? tid : (Y - 1) * G + g;   // hh == 0: the outer row stands in (below)
+        iyp = hh == 0u ? g : tid;                 // hh == 1: the outer row stands in
+    }
+    Counts cnt{0u, 0u};
+    // Step k: white sites of plane zw = z0 - 1 + k (window p0; when WH) and black sites of plane
+    // zw - 2 (p2; when BL, own lanes).  pn = zw + 1, p1 = zw - 1, p3 = zw - 3; out = the halo lanes'
+    // outer row of plane zw (black sites as they were).
+    auto step = [&](bool WH, bool BL, uint32_t zw, uint32_t slot, const RowBits& pn, RowBits& p0, const RowBits& p1,
+                    RowBits& p2, const RowBits& p3, const RowBits& out) {
+        uint4* const x = xch + slot * nt;
+        x[tid] = make_uint4(p0.e, p0.o, p2.e, p2.o);
+        workgroup_lds_sync();
+        const bool O = ((1u + y + zw) & 1u) != 0;  // column parity of the white sites of row y of plane zw;
+                                                   // the black sites of row y of plane zw - 2 lie on 1 - O
+        const uint4 ym = x[iym], yp = x[iyp], xr = x[ir], xl = x[il];
+        q.res[lane] = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t n = 0u;
+        if (WH) {
+            uint32_t ymw = O ? ym.y : ym.x, ypw = O ? yp.y : yp.x;
+            if (HALO && !own && hh == 0u) ymw = O ? out.o : out.e;
+            if (HALO && !own && hh == 1u) ypw = O ? out.o : out.e;
+            const uint32_t side = O ? p0.e : p0.o;
+            const uint32_t hs = O ? shift_next(p0.e, xr.x & 1u) : shift_prev(p0.o, xl.y >> 31);
+            const uint32_t nb[6] = {ymw, ypw, O ? p1.o : p1.e, O ? pn.o : pn.e, side, hs};
+            uint32_t tied, s2, s4;
+            const uint32_t acc =
+                decide3_head(O ? p0.o : p0.e, nb, a.th, g, zw * L + y, a.t, 1u, a.key0, a.key1, tied, s2, s4);
+            p0.o ^= O ? acc : 0u;
+            p0.e ^= O ? 0u : acc;
+            tq3_push(q, n, tied, s2, s4, zw * L + y, 0u | (lane << 2) | (g << 8));
+        }
+        const uint32_t zb = (zw + L - 2u) & wrapy;
+        const bool Ob = !O;
+        const uint32_t sideb = Ob ? p2.e : p2.o;
+        const uint32_t hsb = Ob ? shift_next(p2.e, xr.z & 1u) : shift_prev(p2.o, xl.w >> 31);
+        const uint32_t nbb[6] = {Ob ? ym.w : ym.z, Ob ? yp.w : yp.z, Ob ? p3.o : p3.e, Ob ? p1.o : p1.e, sideb, hsb};
+        if (BL && own) {
+            uint32_t tied, s2, s4;
+            const uint32_t acc =
+                decide3_head(Ob ? p2.o : p2.e, nbb, a.th, g, zb * L + y, a.t, 0u, a.key0, a.key1, tied, s2, s4);
+            p2.o ^= Ob ? acc : 0u;
+            p2.e ^= Ob ? 0u : acc;
+            tq3_push(q, n, tied, s2, s4, zb * L + y, 1u | (lane << 2) | (g << 8));
+        }
+        tq3_settle<-1>(q, n, a.th, a.t, a.key0, a.key1, lane);
+        const uint4 r = q.res[lane];  // zero for an update the step does not make
+        p0.o ^= O ? r.x : 0u;
+        p0.e ^= O ? 0u : r.x;
+        p2.o ^= Ob ? r.y : 0u;
+        p2.e ^= Ob ? 0u : r.y;
+        if (BL && own) {
+            if (OBS) {
+                const uint32_t mb = Ob ? ~0u : 0u;  // masks, not selects of fields
+                const uint32_t f = (p2.o & mb) | (p2.e & ~mb);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) cnt.anti += __builtin_popcount(f ^ nbb[k]);
+                cnt.neg += __builtin_popcount(f) + __builtin_popcount(sideb);
+            }
+            put(zb, p2);
+        }
+    };
+    // prologue: planes z0 - 2, z0 - 1, z0 in bits, z0 + 1 in flight; the outer row of plane z0 - 1
+    // in bits, of plane z0 in flight
+    Row raw, oraw;
+    fetch(raw, zplane(0));
+    RowBits p3{0u, 0u}, p2{0u, 0u}, p1 = bits(raw);
+    fetch(raw, zplane(1));
+    RowBits p0 = bits(raw);
+    fetch(raw, zplane(2));
+    RowBits pn = bits(raw);
+    fetch(raw, zplane(3));
+    RowBits o{0u, 0u};
+    if (HALO) {
+        fetch_outer(oraw, zplane(1));
+        o = halo ? row_bits(oraw) : RowBits{0u, 0u};
+        fetch_outer(oraw, zplane(2));
+    }
+    // steps k = 0 .. Rz + 2: white sites of plane z0 - 1 + k for k <= Rz + 1, black sites of plane
+    // z0 - 3 + k for k >= 3
+#pragma unroll 1
+    for (uint32_t k = 0; k < Rz + 3u; ++k) {
+        step(k <= Rz + 1u, k >= 3u, zplane(k + 1), k & 1u, pn, p0, p1, p2, p3, o);
+        p3 = p2;
+        p2 = p1;
+        p1 = p0;
+        p0 = pn;
+        pn = bits(raw);  // plane of walk index k + 3
+        fetch(raw, zplane(k + 4));
+        if (HALO) {
+            o = halo ? row_bits(oraw) : RowBits{0u, 0u};  // outer row of plane z0 + k
+            fetch_outer(oraw, zplane(k + 3));
+        }
+    }
+    if (OBS) block_accumulate(a.obs, own ? cnt.anti : 0u, own ? cnt.neg : 0u, own ? 1u : 0u, 64u * Rz, 3u);
+}
+
 // (M, E) of a cubic lattice: each lane one 64-column group of one row; bonds to +x, +y, +z.
 __global__ __launch_bounds__(256) void k_observables3(const int8_t* spins, uint32_t L, uint32_t G, uint64_t n_lanes,
                                                       int64_t* out) {
@@ -728,7 +886,7 @@ __global__ __launch_bounds__(256) void k_sweep3_packed_q(Packed3Args a) {
             w[i] ^= decide3_head(w[i], nb, th, g, z * L + y, a.t, (uint32_t)Q, a.key0, a.key1, tied, s2, s4);
             tq3_push(q, n, tied, s2, s4, z * L + y, (uint32_t)i | (lane << 2) | (g << 8));
         }
-        tq3_settle(q, n, th, a.t, (uint32_t)Q, a.key0, a.key1, lane);
+        tq3_settle<Q>(q, n, th, a.t, a.key0, a.key1, lane);
         const uint4 rr = q.res[lane];
         w[0] ^= rr.x;
         w[1] ^= rr.y;
@@ -960,8 +1118,24 @@ int launch_sweep3_fused(const int8_t* src, int8_t* dst, int64_t L, const ising::
     const bool halo = (int64_t)sh.Y < L;
     const uint32_t own = sh.W * 64u;
     const uint32_t threads = halo ? (own + 2u * a.G + 63u) / 64u * 64u : own;
-    const size_t lds = (size_t)sh.W * 4096u + 2u * threads * sizeof(uint4);
     const dim3 grid(sh.ystrips * (uint32_t)(L / sh.Rz)), block(threads);
+    if (ising_host::option("ties3")) {
+        const size_t lds = (size_t)(threads / 64u) * ising::kTieQueue3Bytes + 2u * threads * sizeof(uint4);
+#define ISING_LAUNCH3FQ(OO, HH)                                                                            \
+    do {                                                                                                   \
+        if (lds > 65536) {                                                                                 \
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ising::k_sweep3_fusedq<OO, HH>), \
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+            if (e != hipSuccess) return ising_host::hip_failed(e, "hipFuncSetAttribute(k_sweep3_fusedq)"); \
+        }                                                                                                  \
+        hipLaunchKernelGGL((ising::k_sweep3_fusedq<OO, HH>), grid, block, lds, stream, a);                \
+    } while (0)
+        if (halo) { if (obs) ISING_LAUNCH3FQ(true, true); else ISING_LAUNCH3FQ(false, true); }
+        else { if (obs) ISING_LAUNCH3FQ(true, false); else ISING_LAUNCH3FQ(false, false); }
+#undef ISING_LAUNCH3FQ
+        return ising_host::check_launch("k_sweep3_fusedq");
+    }
+    const size_t lds = (size_t)sh.W * 4096u + 2u * threads * sizeof(uint4);
 #define ISING_LAUNCH3F(OO, HH) hipLaunchKernelGGL((ising::k_sweep3_fused<OO, HH>), grid, block, lds, stream, a)
     if (halo) { if (obs) ISING_LAUNCH3F(true, true); else ISING_LAUNCH3F(false, true); }
     else { if (obs) ISING_LAUNCH3F(true, false); else ISING_LAUNCH3F(false, false); }

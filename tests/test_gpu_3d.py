@@ -265,12 +265,19 @@ def test_packed3_equals_int8(dev, L, n):
 @pytest.mark.parametrize("L,beta,n,seed,offset", [(64, BETA_C3, 1, 1, 0), (64, BETA_C3, 6, 2, 5),
                                                   (128, 0.25, 4, 3, 0), (256, BETA_C3, 3, 2**40 + 3, 11),
                                                   (256, 0.0, 2, 9, 0), (128, math.inf, 2, 10, 2**32 - 2)])
-def test_fused3_sweeps_match_oracle(dev, oracle_lib, L, beta, n, seed, offset):
-    _say("fused3", L, beta, n)
+@pytest.mark.parametrize("ties", [1, 0])
+def test_fused3_sweeps_match_oracle(dev, oracle_lib, L, beta, n, seed, offset, ties):
+    # ties = 1: the pass that updates white sites of plane z and black sites of plane z - 2 in one
+    # step and settles their tied words together; ties = 0: one plane apart, each word on its own
+    _say("fused3", L, beta, n, ties)
     host = _cube(L, L + n)
     s, scratch = _to_dev(host), torch.empty((L, L, L), dtype=torch.int8, device="cuda")
     tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
-    dev.ising3_sweep_fused(s, scratch, L, beta, n, seed, offset, tr)
+    try:
+        dev.ising_set_option("ties3", ties)
+        dev.ising3_sweep_fused(s, scratch, L, beta, n, seed, offset, tr)
+    finally:
+        dev.ising_set_option("ties3", 1)
     ref = oracle_lib.sweep3(host, beta, n, seed, offset, trace=True)
     assert np.array_equal(s.cpu().numpy(), host)
     assert np.array_equal(tr.cpu().numpy(), ref)
@@ -304,17 +311,19 @@ def test_fused3_equals_two_pass_for_every_plane_count(dev, L, n):
     scratch = torch.empty_like(base)
     try:
         for rz in ((0, 2, 8, 32) if L <= 1024 else (0, 16)):
-            for remap in (1, 0):
+            for remap, ties in ((1, 1), (0, 1), (1, 0)):
                 dev.ising_set_option("planes3", rz)
                 dev.ising_set_option("xcd_remap", remap)
+                dev.ising_set_option("ties3", ties)
                 s = base.clone()
                 tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
                 dev.ising3_sweep_fused(s, scratch, L, BETA_C3, n, 5, 30, tr)
-                assert torch.equal(s, ref), (rz, remap)
-                assert torch.equal(tr, ref_tr), (rz, remap)
+                assert torch.equal(s, ref), (rz, remap, ties)
+                assert torch.equal(tr, ref_tr), (rz, remap, ties)
     finally:
         dev.ising_set_option("planes3", 0)
         dev.ising_set_option("xcd_remap", 1)
+        dev.ising_set_option("ties3", 1)
     del base, ref, scratch
     torch.cuda.empty_cache()
 
