@@ -534,9 +534,12 @@ __global__ __launch_bounds__(576) void k_sweep3_fused(Fused3Args a) {
 // step does not change, so the two are independent and share the wave's tie queue (as the square
 // lattice's passes do).  The exchange of a step carries each row's plane being white-updated as it
 // was and the plane being black-updated after its white update.  Same rows read and written as
-// k_sweep3_fused, same uniforms, same result.  One row (and outer row) is prefetched a step ahead.
+// k_sweep3_fused, same uniforms, same result.  When Y < L the lanes after the own rows hold the
+// halo rows y0 - 1, y0 + Y (white updates only) and then the rows beyond them, y0 - 2 and y0 + Y + 1,
+// which are only read: the halo lanes take those rows' old black sites from the exchange like any
+// other row.  One row is prefetched a step ahead.
 template <bool OBS, bool HALO>
-__global__ __launch_bounds__(576) void k_sweep3_fusedq(Fused3Args a) {
+__global__ __launch_bounds__(640) __attribute__((amdgpu_waves_per_eu(HALO ? 5 : 1))) void k_sweep3_fusedq(Fused3Args a) {
     extern __shared__ uint4 f3q_lds[];
     const uint32_t tid = threadIdx.x, nt = blockDim.x, lane = tid & 63u;
     const uint32_t L = a.L, G = a.G, Y = a.Y, Rz = a.Rz, own_n = Y * G;
@@ -548,54 +551,56 @@ __global__ __launch_bounds__(576) void k_sweep3_fusedq(Fused3Args a) {
     const uint32_t b = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
     const uint32_t y0 = (b % a.ystrips) * Y, z0 = (b / a.ystrips) * Rz;
     const bool own = tid < own_n;                        // uniform per wave (own_n is a multiple of 64)
-    const uint32_t hh = own ? 0u : (tid - own_n) / G;   // halo lanes: 0 = row above, 1 = row below
-    const bool halo = HALO && !own && hh < 2u;          // lanes past the halo rows only shadow
-    const uint32_t g = own ? tid % G : (halo ? (tid - own_n) % G : 0u);
+    // lanes after the own rows: 0 = row y0 - 1, 1 = row y0 + Y (halo), 2 = row y0 - 2, 3 = row
+    // y0 + Y + 1 (outer: read only); lanes past those only shadow
+    const uint32_t hh = own ? 0u : (tid - own_n) / G;
+    const bool halo = HALO && !own && hh < 2u;
+    const bool ld = HALO && !own && hh < 4u;             // halo and outer lanes load their row
+    const bool act = own || halo;                        // lanes whose white updates are kept
+    const uint32_t g = own ? tid % G : (ld ? (tid - own_n) % G : 0u);
     const uint32_t yy = own ? tid / G : 0u;
     const uint32_t wrapy = L - 1u;  // L is a power of two
-    const uint32_t y = own ? y0 + yy : (hh == 0u ? (y0 + L - 1u) & wrapy : (y0 + Y) & wrapy);
-    const uint32_t yo = hh == 0u ? (y0 + L - 2u) & wrapy : (y0 + Y + 1u) & wrapy;  // halo lanes' outer row
+    const uint32_t yoff[4] = {L - 1u, Y, L - 2u, Y + 1u};
+    const uint32_t y = own ? y0 + yy : (y0 + yoff[ld ? hh : 1u]) & wrapy;
     const size_t plane = (size_t)L * L;
     const size_t seg = (size_t)y0 * L + (size_t)(tid >> 6) * 4096u;
     // plane of walk index k = 0 .. Rz + 3: z0 - 2 .. z0 + Rz + 1, wrapped; later ones are clamped
     auto zplane = [&](uint32_t k) { return (z0 + L - 2u + (k < Rz + 3u ? k : Rz + 3u)) & wrapy; };
     auto fetch = [&](Row& raw, uint32_t z) {
         if (own) load_row_coalesced(raw, a.src + z * plane + seg, lane);
-        else if (halo) load_row(raw, a.src + ((size_t)z * L + y) * L + (size_t)g * 64u);
+        else if (ld) load_row(raw, a.src + ((size_t)z * L + y) * L + (size_t)g * 64u);
     };
     auto bits = [&](const Row& raw) {
-        if (!own) return halo ? row_bits(raw) : RowBits{0u, 0u};
+        if (!own) return ld ? row_bits(raw) : RowBits{0u, 0u};
         Row row;
         regroup_to_owner(row, raw, stage, lane);
         return row_bits(row);
-    };
-    auto fetch_outer = [&](Row& raw, uint32_t z) {
-        if (halo) load_row(raw, a.src + ((size_t)z * L + yo) * L + (size_t)g * 64u);
     };
     auto put = [&](uint32_t z, const RowBits& rb) {
         Row row;
         bits_to_row(row, rb);
         if (own) store_row_coalesced(a.dst + z * plane + seg, row, stage, lane, false);
     };
-    const bool shadow = !own && !halo;
-    const uint32_t ir = shadow ? tid : (g + 1 < G ? tid + 1 : tid + 1 - G);
-    const uint32_t il = shadow ? tid : (g > 0 ? tid - 1 : tid + G - 1);
+    // neighbour entries (own rows wrap when the workgroup holds whole planes); outer and shadow
+    // lanes read their own entry
+    const uint32_t ir = !act ? tid : (g + 1 < G ? tid + 1 : tid + 1 - G);
+    const uint32_t il = !act ? tid : (g > 0 ? tid - 1 : tid + G - 1);
     uint32_t iym, iyp;
-    if (shadow) {
+    if (!act) {
         iym = iyp = tid;
     } else if (own) {
         iym = yy > 0 ? tid - G : (HALO ? own_n + g : tid + (Y - 1) * G);
         iyp = yy + 1 < Y ? tid + G : (HALO ? own_n + G + g : tid - (Y - 1) * G);
     } else {
-        iym = hh == 0u ? tid : (Y - 1) * G + g;   // hh == 0: the outer row stands in (below)
-        iyp = hh == 0u ? g : tid;                 // hh == 1: the outer row stands in
+        iym = hh == 0u ? own_n + 2u * G + g : (Y - 1) * G + g;
+        iyp = hh == 0u ? g : own_n + 3u * G + g;
     }
+    const uint32_t keep = act ? ~0u : 0u;
     Counts cnt{0u, 0u};
     // Step k: white sites of plane zw = z0 - 1 + k (window p0; when WH) and black sites of plane
-    // zw - 2 (p2; when BL, own lanes).  pn = zw + 1, p1 = zw - 1, p3 = zw - 3; out = the halo lanes'
-    // outer row of plane zw (black sites as they were).
+    // zw - 2 (p2; when BL, own lanes).  pn = zw + 1, p1 = zw - 1, p3 = zw - 3.
     auto step = [&](bool WH, bool BL, uint32_t zw, uint32_t slot, const RowBits& pn, RowBits& p0, const RowBits& p1,
-                    RowBits& p2, const RowBits& p3, const RowBits& out) {
+                    RowBits& p2, const RowBits& p3) {
         uint4* const x = xch + slot * nt;
         x[tid] = make_uint4(p0.e, p0.o, p2.e, p2.o);
         workgroup_lds_sync();
@@ -605,18 +610,15 @@ __global__ __launch_bounds__(576) void k_sweep3_fusedq(Fused3Args a) {
         q.res[lane] = make_uint4(0u, 0u, 0u, 0u);
         uint32_t n = 0u;
         if (WH) {
-            uint32_t ymw = O ? ym.y : ym.x, ypw = O ? yp.y : yp.x;
-            if (HALO && !own && hh == 0u) ymw = O ? out.o : out.e;
-            if (HALO && !own && hh == 1u) ypw = O ? out.o : out.e;
             const uint32_t side = O ? p0.e : p0.o;
             const uint32_t hs = O ? shift_next(p0.e, xr.x & 1u) : shift_prev(p0.o, xl.y >> 31);
-            const uint32_t nb[6] = {ymw, ypw, O ? p1.o : p1.e, O ? pn.o : pn.e, side, hs};
+            const uint32_t nb[6] = {O ? ym.y : ym.x, O ? yp.y : yp.x, O ? p1.o : p1.e, O ? pn.o : pn.e, side, hs};
             uint32_t tied, s2, s4;
-            const uint32_t acc =
-                decide3_head(O ? p0.o : p0.e, nb, a.th, g, zw * L + y, a.t, 1u, a.key0, a.key1, tied, s2, s4);
+            const uint32_t acc = keep & decide3_head(O ? p0.o : p0.e, nb, a.th, g, zw * L + y, a.t, 1u, a.key0,
+                                                     a.key1, tied, s2, s4);
             p0.o ^= O ? acc : 0u;
             p0.e ^= O ? 0u : acc;
-            tq3_push(q, n, tied, s2, s4, zw * L + y, 0u | (lane << 2) | (g << 8));
+            tq3_push(q, n, keep & tied, s2, s4, zw * L + y, 0u | (lane << 2) | (g << 8));
         }
         const uint32_t zb = (zw + L - 2u) & wrapy;
         const bool Ob = !O;
@@ -648,9 +650,8 @@ __global__ __launch_bounds__(576) void k_sweep3_fusedq(Fused3Args a) {
             put(zb, p2);
         }
     };
-    // prologue: planes z0 - 2, z0 - 1, z0 in bits, z0 + 1 in flight; the outer row of plane z0 - 1
-    // in bits, of plane z0 in flight
-    Row raw, oraw;
+    // prologue: planes z0 - 2, z0 - 1, z0 in bits, z0 + 1 in flight
+    Row raw;
     fetch(raw, zplane(0));
     RowBits p3{0u, 0u}, p2{0u, 0u}, p1 = bits(raw);
     fetch(raw, zplane(1));
@@ -658,27 +659,17 @@ __global__ __launch_bounds__(576) void k_sweep3_fusedq(Fused3Args a) {
     fetch(raw, zplane(2));
     RowBits pn = bits(raw);
     fetch(raw, zplane(3));
-    RowBits o{0u, 0u};
-    if (HALO) {
-        fetch_outer(oraw, zplane(1));
-        o = halo ? row_bits(oraw) : RowBits{0u, 0u};
-        fetch_outer(oraw, zplane(2));
-    }
     // steps k = 0 .. Rz + 2: white sites of plane z0 - 1 + k for k <= Rz + 1, black sites of plane
     // z0 - 3 + k for k >= 3
 #pragma unroll 1
     for (uint32_t k = 0; k < Rz + 3u; ++k) {
-        step(k <= Rz + 1u, k >= 3u, zplane(k + 1), k & 1u, pn, p0, p1, p2, p3, o);
+        step(k <= Rz + 1u, k >= 3u, zplane(k + 1), k & 1u, pn, p0, p1, p2, p3);
         p3 = p2;
         p2 = p1;
         p1 = p0;
         p0 = pn;
         pn = bits(raw);  // plane of walk index k + 3
         fetch(raw, zplane(k + 4));
-        if (HALO) {
-            o = halo ? row_bits(oraw) : RowBits{0u, 0u};  // outer row of plane z0 + k
-            fetch_outer(oraw, zplane(k + 3));
-        }
     }
     if (OBS) block_accumulate(a.obs, own ? cnt.anti : 0u, own ? cnt.neg : 0u, own ? 1u : 0u, 64u * Rz, 3u);
 }
@@ -1120,7 +1111,10 @@ int launch_sweep3_fused(const int8_t* src, int8_t* dst, int64_t L, const ising::
     const uint32_t threads = halo ? (own + 2u * a.G + 63u) / 64u * 64u : own;
     const dim3 grid(sh.ystrips * (uint32_t)(L / sh.Rz)), block(threads);
     if (ising_host::option("ties3")) {
-        const size_t lds = (size_t)(threads / 64u) * ising::kTieQueue3Bytes + 2u * threads * sizeof(uint4);
+        // own rows, then the two halo rows and the two rows beyond them
+        const uint32_t nq = halo ? (own + 4u * a.G + 63u) / 64u * 64u : own;
+        const dim3 blockq(nq);
+        const size_t lds = (size_t)(nq / 64u) * ising::kTieQueue3Bytes + 2u * nq * sizeof(uint4);
 #define ISING_LAUNCH3FQ(OO, HH)                                                                            \
     do {                                                                                                   \
         if (lds > 65536) {                                                                                 \
@@ -1128,7 +1122,7 @@ int launch_sweep3_fused(const int8_t* src, int8_t* dst, int64_t L, const ising::
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
             if (e != hipSuccess) return ising_host::hip_failed(e, "hipFuncSetAttribute(k_sweep3_fusedq)"); \
         }                                                                                                  \
-        hipLaunchKernelGGL((ising::k_sweep3_fusedq<OO, HH>), grid, block, lds, stream, a);                \
+        hipLaunchKernelGGL((ising::k_sweep3_fusedq<OO, HH>), grid, blockq, lds, stream, a);               \
     } while (0)
         if (halo) { if (obs) ISING_LAUNCH3FQ(true, true); else ISING_LAUNCH3FQ(false, true); }
         else { if (obs) ISING_LAUNCH3FQ(true, false); else ISING_LAUNCH3FQ(false, false); }
