@@ -528,22 +528,25 @@ __global__ __launch_bounds__(576) void k_sweep3_fused(Fused3Args a) {
     if (OBS) block_accumulate(a.obs, own ? cnt.anti : 0u, own ? cnt.neg : 0u, own ? 1u : 0u, 64u * Rz, 3u);
 }
 
-// ---- The fused 3-D sweep with two planes between its updates.  Step k updates the white sites of
-// plane z0 - 1 + k and the black sites of plane z0 - 3 + k: the black update's neighbours are white
-// sites of planes updated at least one step earlier, and the white update reads black sites the
-// step does not change, so the two are independent and share the wave's tie queue (as the square
-// lattice's passes do).  The exchange of a step carries each row's plane being white-updated as it
-// was and the plane being black-updated after its white update.  Same rows read and written as
-// k_sweep3_fused, same uniforms, same result.  When Y < L the lanes after the own rows hold the
-// halo rows y0 - 1, y0 + Y (white updates only) and then the rows beyond them, y0 - 2 and y0 + Y + 1,
-// which are only read: the halo lanes take those rows' old black sites from the exchange like any
-// other row.  One row is prefetched a step ahead.
+// ---- The fused 3-D sweep, four independent plane updates per step.  Step j updates the white
+// sites of planes w = z0 - 1 + 2j and w + 1 and the black sites of planes w - 3 and w - 2.  The black
+// updates' neighbours are white sites of planes the walk finished in earlier steps; the white updates
+// read black sites no step has changed yet; and no update reads what another one of its step writes
+// (the two white planes meet only at black sites, the two black planes only at white ones).  So one
+// exchange and one settle of the wave's tie queue serve all four (as in the square lattice's
+// two-sweep pass).  The exchange carries each row's planes w and w + 1 as they were and w - 3, w - 2
+// after their white updates.  Same rows read and written as k_sweep3_fused, same uniforms, same
+// result.  When Y < L the lanes after the own rows hold the halo rows y0 - 1, y0 + Y (white updates
+// only) and then the rows beyond them, y0 - 2 and y0 + Y + 1, which are only read: the halo lanes take
+// those rows' old black sites from the exchange like any other row.  Two rows are prefetched a step
+// ahead.  Rz must be even.
 template <bool OBS, bool HALO>
-__global__ __launch_bounds__(640) __attribute__((amdgpu_waves_per_eu(HALO ? 5 : 1))) void k_sweep3_fusedq(Fused3Args a) {
+__global__ __launch_bounds__(640) void k_sweep3_fusedq(Fused3Args a) {
     extern __shared__ uint4 f3q_lds[];
     const uint32_t tid = threadIdx.x, nt = blockDim.x, lane = tid & 63u;
     const uint32_t L = a.L, G = a.G, Y = a.Y, Rz = a.Rz, own_n = Y * G;
-    // per wave: row staging (own waves) shared with the tie queue; then two exchange slots
+    // per wave: row staging (own waves) shared with the tie queue; then two exchange slots of two
+    // entries per lane
     uint4* const mine = f3q_lds + (tid >> 6) * (kTieQueue3Bytes / 16u);
     uint4* const stage = mine;
     const TieQueue3 q{reinterpret_cast<uint32_t*>(mine), mine + 5u * 64u};
@@ -597,79 +600,97 @@ __global__ __launch_bounds__(640) __attribute__((amdgpu_waves_per_eu(HALO ? 5 : 
     }
     const uint32_t keep = act ? ~0u : 0u;
     Counts cnt{0u, 0u};
-    // Step k: white sites of plane zw = z0 - 1 + k (window p0; when WH) and black sites of plane
-    // zw - 2 (p2; when BL, own lanes).  pn = zw + 1, p1 = zw - 1, p3 = zw - 3.
-    auto step = [&](bool WH, bool BL, uint32_t zw, uint32_t slot, const RowBits& pn, RowBits& p0, const RowBits& p1,
-                    RowBits& p2, const RowBits& p3) {
-        uint4* const x = xch + slot * nt;
-        x[tid] = make_uint4(p0.e, p0.o, p2.e, p2.o);
+    // One white or black update of the sites of parity P (1 = odd columns) of row word pair c;
+    // lo, hi = the planes below and above, u = the update's slot in the queue.
+    auto update = [&](bool P, RowBits& c, const RowBits& lo, const RowBits& hi, uint32_t ymw, uint32_t ypw,
+                      uint32_t re, uint32_t lo_o, uint32_t z, uint32_t colour, uint32_t u, uint32_t mask,
+                      uint32_t& n) {
+        const uint32_t side = P ? c.e : c.o;
+        const uint32_t hs = P ? shift_next(c.e, re & 1u) : shift_prev(c.o, lo_o >> 31);
+        const uint32_t nb[6] = {ymw, ypw, P ? lo.o : lo.e, P ? hi.o : hi.e, side, hs};
+        uint32_t tied, s2, s4;
+        const uint32_t acc = mask & decide3_head(P ? c.o : c.e, nb, a.th, g, z * L + y, a.t, colour, a.key0,
+                                                 a.key1, tied, s2, s4);
+        c.o ^= P ? acc : 0u;
+        c.e ^= P ? 0u : acc;
+        tq3_push(q, n, mask & tied, s2, s4, z * L + y, u | (lane << 2) | (g << 8));
+    };
+    // black-update (M, E) terms of the final sites of parity P of c
+    auto count = [&](bool P, const RowBits& c, const RowBits& lo, const RowBits& hi, uint32_t ymw, uint32_t ypw,
+                     uint32_t re, uint32_t lo_o) {
+        const uint32_t mp = P ? ~0u : 0u;  // masks, not selects of fields
+        const uint32_t f = (c.o & mp) | (c.e & ~mp), side = (c.e & mp) | (c.o & ~mp);
+        const uint32_t hs = P ? shift_next(c.e, re & 1u) : shift_prev(c.o, lo_o >> 31);
+        const uint32_t nb[6] = {ymw, ypw, (lo.o & mp) | (lo.e & ~mp), (hi.o & mp) | (hi.e & ~mp), side, hs};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) cnt.anti += __builtin_popcount(f ^ nb[k]);
+        cnt.neg += __builtin_popcount(f) + __builtin_popcount(side);
+    };
+    // window: q0 .. q6 = planes w - 4 .. w + 2
+    Row ra, rb;
+    fetch(ra, zplane(0));
+    fetch(rb, zplane(1));
+    RowBits q0{0u, 0u}, q1{0u, 0u}, q2{0u, 0u}, q3 = bits(ra), q4 = bits(rb);
+    fetch(ra, zplane(2));
+    fetch(rb, zplane(3));
+    RowBits q5 = bits(ra), q6 = bits(rb);
+    fetch(ra, zplane(4));
+    fetch(rb, zplane(5));
+    const uint32_t steps = Rz / 2u + 2u;
+#pragma unroll 1
+    for (uint32_t j = 0; j < steps; ++j) {
+        const bool WH = j <= Rz / 2u, BL = j >= 2u && own;
+        const uint32_t w = zplane(2u * j + 1u);
+        uint4* const x = xch + (j & 1u) * 2u * nt;
+        x[2u * tid] = make_uint4(q4.e, q4.o, q5.e, q5.o);
+        x[2u * tid + 1u] = make_uint4(q1.e, q1.o, q2.e, q2.o);
         workgroup_lds_sync();
-        const bool O = ((1u + y + zw) & 1u) != 0;  // column parity of the white sites of row y of plane zw;
-                                                   // the black sites of row y of plane zw - 2 lie on 1 - O
-        const uint4 ym = x[iym], yp = x[iyp], xr = x[ir], xl = x[il];
+        const bool O = ((1u + y + w) & 1u) != 0;  // column parity of the white sites of row y of plane w
+                                                   // and of the black sites of row y of plane w - 3
         q.res[lane] = make_uint4(0u, 0u, 0u, 0u);
         uint32_t n = 0u;
         if (WH) {
-            const uint32_t side = O ? p0.e : p0.o;
-            const uint32_t hs = O ? shift_next(p0.e, xr.x & 1u) : shift_prev(p0.o, xl.y >> 31);
-            const uint32_t nb[6] = {O ? ym.y : ym.x, O ? yp.y : yp.x, O ? p1.o : p1.e, O ? pn.o : pn.e, side, hs};
-            uint32_t tied, s2, s4;
-            const uint32_t acc = keep & decide3_head(O ? p0.o : p0.e, nb, a.th, g, zw * L + y, a.t, 1u, a.key0,
-                                                     a.key1, tied, s2, s4);
-            p0.o ^= O ? acc : 0u;
-            p0.e ^= O ? 0u : acc;
-            tq3_push(q, n, keep & tied, s2, s4, zw * L + y, 0u | (lane << 2) | (g << 8));
+            const uint4 ym = x[2u * iym], yp = x[2u * iyp], xr = x[2u * ir], xl = x[2u * il];
+            update(O, q4, q3, q5, O ? ym.y : ym.x, O ? yp.y : yp.x, xr.x, xl.y, w, 1u, 0u, keep, n);
+            update(!O, q5, q4, q6, O ? ym.z : ym.w, O ? yp.z : yp.w, xr.z, xl.w, (w + 1u) & wrapy, 1u, 2u, keep, n);
         }
-        const uint32_t zb = (zw + L - 2u) & wrapy;
-        const bool Ob = !O;
-        const uint32_t sideb = Ob ? p2.e : p2.o;
-        const uint32_t hsb = Ob ? shift_next(p2.e, xr.z & 1u) : shift_prev(p2.o, xl.w >> 31);
-        const uint32_t nbb[6] = {Ob ? ym.w : ym.z, Ob ? yp.w : yp.z, Ob ? p3.o : p3.e, Ob ? p1.o : p1.e, sideb, hsb};
-        if (BL && own) {
-            uint32_t tied, s2, s4;
-            const uint32_t acc =
-                decide3_head(Ob ? p2.o : p2.e, nbb, a.th, g, zb * L + y, a.t, 0u, a.key0, a.key1, tied, s2, s4);
-            p2.o ^= Ob ? acc : 0u;
-            p2.e ^= Ob ? 0u : acc;
-            tq3_push(q, n, tied, s2, s4, zb * L + y, 1u | (lane << 2) | (g << 8));
+        const uint32_t zb = (w + L - 3u) & wrapy;
+        uint4 ym{}, yp{}, xr{}, xl{};
+        if (BL) {
+            ym = x[2u * iym + 1u];
+            yp = x[2u * iyp + 1u];
+            xr = x[2u * ir + 1u];
+            xl = x[2u * il + 1u];
+            update(O, q1, q0, q2, O ? ym.y : ym.x, O ? yp.y : yp.x, xr.x, xl.y, zb, 0u, 1u, ~0u, n);
+            update(!O, q2, q1, q3, O ? ym.z : ym.w, O ? yp.z : yp.w, xr.z, xl.w, (zb + 1u) & wrapy, 0u, 3u, ~0u, n);
         }
         tq3_settle<-1>(q, n, a.th, a.t, a.key0, a.key1, lane);
         const uint4 r = q.res[lane];  // zero for an update the step does not make
-        p0.o ^= O ? r.x : 0u;
-        p0.e ^= O ? 0u : r.x;
-        p2.o ^= Ob ? r.y : 0u;
-        p2.e ^= Ob ? 0u : r.y;
-        if (BL && own) {
+        q4.o ^= O ? r.x : 0u;
+        q4.e ^= O ? 0u : r.x;
+        q5.o ^= O ? 0u : r.z;
+        q5.e ^= O ? r.z : 0u;
+        if (BL) {
+            q1.o ^= O ? r.y : 0u;
+            q1.e ^= O ? 0u : r.y;
+            q2.o ^= O ? 0u : r.w;
+            q2.e ^= O ? r.w : 0u;
             if (OBS) {
-                const uint32_t mb = Ob ? ~0u : 0u;  // masks, not selects of fields
-                const uint32_t f = (p2.o & mb) | (p2.e & ~mb);
-#pragma unroll
-                for (int k = 0; k < 6; ++k) cnt.anti += __builtin_popcount(f ^ nbb[k]);
-                cnt.neg += __builtin_popcount(f) + __builtin_popcount(sideb);
+                count(O, q1, q0, q2, O ? ym.y : ym.x, O ? yp.y : yp.x, xr.x, xl.y);
+                count(!O, q2, q1, q3, O ? ym.z : ym.w, O ? yp.z : yp.w, xr.z, xl.w);
             }
-            put(zb, p2);
+            put(zb, q1);
+            put((zb + 1u) & wrapy, q2);
         }
-    };
-    // prologue: planes z0 - 2, z0 - 1, z0 in bits, z0 + 1 in flight
-    Row raw;
-    fetch(raw, zplane(0));
-    RowBits p3{0u, 0u}, p2{0u, 0u}, p1 = bits(raw);
-    fetch(raw, zplane(1));
-    RowBits p0 = bits(raw);
-    fetch(raw, zplane(2));
-    RowBits pn = bits(raw);
-    fetch(raw, zplane(3));
-    // steps k = 0 .. Rz + 2: white sites of plane z0 - 1 + k for k <= Rz + 1, black sites of plane
-    // z0 - 3 + k for k >= 3
-#pragma unroll 1
-    for (uint32_t k = 0; k < Rz + 3u; ++k) {
-        step(k <= Rz + 1u, k >= 3u, zplane(k + 1), k & 1u, pn, p0, p1, p2, p3);
-        p3 = p2;
-        p2 = p1;
-        p1 = p0;
-        p0 = pn;
-        pn = bits(raw);  // plane of walk index k + 3
-        fetch(raw, zplane(k + 4));
+        q0 = q2;
+        q1 = q3;
+        q2 = q4;
+        q3 = q5;
+        q4 = q6;
+        q5 = bits(ra);  // planes of walk index 2j + 4, 2j + 5
+        q6 = bits(rb);
+        fetch(ra, zplane(2u * j + 6u));
+        fetch(rb, zplane(2u * j + 7u));
     }
     if (OBS) block_accumulate(a.obs, own ? cnt.anti : 0u, own ? cnt.neg : 0u, own ? 1u : 0u, 64u * Rz, 3u);
 }
@@ -1110,11 +1131,11 @@ int launch_sweep3_fused(const int8_t* src, int8_t* dst, int64_t L, const ising::
     const uint32_t own = sh.W * 64u;
     const uint32_t threads = halo ? (own + 2u * a.G + 63u) / 64u * 64u : own;
     const dim3 grid(sh.ystrips * (uint32_t)(L / sh.Rz)), block(threads);
-    if (ising_host::option("ties3")) {
+    if (ising_host::option("ties3") && sh.Rz % 2u == 0u) {
         // own rows, then the two halo rows and the two rows beyond them
         const uint32_t nq = halo ? (own + 4u * a.G + 63u) / 64u * 64u : own;
         const dim3 blockq(nq);
-        const size_t lds = (size_t)(nq / 64u) * ising::kTieQueue3Bytes + 2u * nq * sizeof(uint4);
+        const size_t lds = (size_t)(nq / 64u) * ising::kTieQueue3Bytes + 4u * nq * sizeof(uint4);
 #define ISING_LAUNCH3FQ(OO, HH)                                                                            \
     do {                                                                                                   \
         if (lds > 65536) {                                                                                 \
