@@ -296,9 +296,9 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
  *   "ties3"          ising3_sweep / ising3_half_sweep: 1 = the two planes of each step share one
  *                    row exchange and their still-tied words are settled together (default),
  *                    0 = plane by plane.  ising3_sweep_fused / ising3_sweep_fused_step: 1 = each
- *                    step updates the white sites of plane z and the black sites of plane z - 2
- *                    and settles their still-tied words together (default), 0 = the white sites
- *                    of plane z, then the black sites of plane z - 1, each on its own.
+ *                    step updates the white sites of planes z, z + 1 and the black sites of planes
+ *                    z - 3, z - 2 and settles their still-tied words together (default), 0 = the
+ *                    white sites of plane z, then the black sites of plane z - 1, each on its own.
  *   "planes3"        planes each workgroup of ising3_sweep (each lane of ising3_sweep_packed)
  *                    walks: 0 = automatic, else a power of two in [2, 256] (ignored for lattices it
  *                    does not divide). */

@@ -267,8 +267,9 @@ def test_packed3_equals_int8(dev, L, n):
                                                   (256, 0.0, 2, 9, 0), (128, math.inf, 2, 10, 2**32 - 2)])
 @pytest.mark.parametrize("ties", [1, 0])
 def test_fused3_sweeps_match_oracle(dev, oracle_lib, L, beta, n, seed, offset, ties):
-    # ties = 1: the pass that updates white sites of plane z and black sites of plane z - 2 in one
-    # step and settles their tied words together; ties = 0: one plane apart, each word on its own
+    # ties = 1: the pass that updates the white sites of planes z, z + 1 and the black sites of
+    # planes z - 3, z - 2 in one step and settles their tied words together; ties = 0: white sites of
+    # plane z, then black sites of plane z - 1, each word on its own
     _say("fused3", L, beta, n, ties)
     host = _cube(L, L + n)
     s, scratch = _to_dev(host), torch.empty((L, L, L), dtype=torch.int8, device="cuda")
