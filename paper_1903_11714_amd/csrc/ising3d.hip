@@ -546,7 +546,7 @@ __global__ __launch_bounds__(640) void k_sweep3_fusedq(Fused3Args a) {
     const uint32_t tid = threadIdx.x, nt = blockDim.x, lane = tid & 63u;
     const uint32_t L = a.L, G = a.G, Y = a.Y, Rz = a.Rz, own_n = Y * G;
     // per wave: row staging (own waves) shared with the tie queue; then two exchange slots of two
-    // entries per lane
+    // arrays of one entry per lane
     uint4* const mine = f3q_lds + (tid >> 6) * (kTieQueue3Bytes / 16u);
     uint4* const stage = mine;
     const TieQueue3 q{reinterpret_cast<uint32_t*>(mine), mine + 5u * 64u};
@@ -641,26 +641,27 @@ __global__ __launch_bounds__(640) void k_sweep3_fusedq(Fused3Args a) {
     for (uint32_t j = 0; j < steps; ++j) {
         const bool WH = j <= Rz / 2u, BL = j >= 2u && own;
         const uint32_t w = zplane(2u * j + 1u);
-        uint4* const x = xch + (j & 1u) * 2u * nt;
-        x[2u * tid] = make_uint4(q4.e, q4.o, q5.e, q5.o);
-        x[2u * tid + 1u] = make_uint4(q1.e, q1.o, q2.e, q2.o);
+        uint4* const xw = xch + (j & 1u) * 2u * nt;  // planes w, w + 1 as they were
+        uint4* const xb = xw + nt;                      // planes w - 3, w - 2 after their white updates
+        xw[tid] = make_uint4(q4.e, q4.o, q5.e, q5.o);
+        xb[tid] = make_uint4(q1.e, q1.o, q2.e, q2.o);
         workgroup_lds_sync();
         const bool O = ((1u + y + w) & 1u) != 0;  // column parity of the white sites of row y of plane w
                                                    // and of the black sites of row y of plane w - 3
         q.res[lane] = make_uint4(0u, 0u, 0u, 0u);
         uint32_t n = 0u;
         if (WH) {
-            const uint4 ym = x[2u * iym], yp = x[2u * iyp], xr = x[2u * ir], xl = x[2u * il];
+            const uint4 ym = xw[iym], yp = xw[iyp], xr = xw[ir], xl = xw[il];
             update(O, q4, q3, q5, O ? ym.y : ym.x, O ? yp.y : yp.x, xr.x, xl.y, w, 1u, 0u, keep, n);
             update(!O, q5, q4, q6, O ? ym.z : ym.w, O ? yp.z : yp.w, xr.z, xl.w, (w + 1u) & wrapy, 1u, 2u, keep, n);
         }
         const uint32_t zb = (w + L - 3u) & wrapy;
         uint4 ym{}, yp{}, xr{}, xl{};
         if (BL) {
-            ym = x[2u * iym + 1u];
-            yp = x[2u * iyp + 1u];
-            xr = x[2u * ir + 1u];
-            xl = x[2u * il + 1u];
+            ym = xb[iym];
+            yp = xb[iyp];
+            xr = xb[ir];
+            xl = xb[il];
             update(O, q1, q0, q2, O ? ym.y : ym.x, O ? yp.y : yp.x, xr.x, xl.y, zb, 0u, 1u, ~0u, n);
             update(!O, q2, q1, q3, O ? ym.z : ym.w, O ? yp.z : yp.w, xr.z, xl.w, (zb + 1u) & wrapy, 0u, 3u, ~0u, n);
         }
