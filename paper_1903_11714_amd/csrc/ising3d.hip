@@ -539,8 +539,9 @@ __global__ __launch_bounds__(576) void k_sweep3_fused(Fused3Args a) {
 // result.  When Y < L the lanes after the own rows hold the halo rows y0 - 1, y0 + Y (white updates
 // only) and then the rows beyond them, y0 - 2 and y0 + Y + 1, which are only read: the halo lanes take
 // those rows' old black sites from the exchange like any other row.  Two rows are prefetched a step
-// ahead.  Rz must be even.
-template <bool OBS, bool HALO>
+// ahead.  Rz must be even.  DIRECT: every lane loads and stores its own 64 bytes (no regroup through
+// LDS), which is faster where a wave's 4 KiB span eight or more rows (L <= 512).
+template <bool OBS, bool HALO, bool DIRECT>
 __global__ __launch_bounds__(640) void k_sweep3_fusedq(Fused3Args a) {
     extern __shared__ uint4 f3q_lds[];
     const uint32_t tid = threadIdx.x, nt = blockDim.x, lane = tid & 63u;
@@ -570,11 +571,11 @@ __global__ __launch_bounds__(640) void k_sweep3_fusedq(Fused3Args a) {
     // plane of walk index k = 0 .. Rz + 3: z0 - 2 .. z0 + Rz + 1, wrapped; later ones are clamped
     auto zplane = [&](uint32_t k) { return (z0 + L - 2u + (k < Rz + 3u ? k : Rz + 3u)) & wrapy; };
     auto fetch = [&](Row& raw, uint32_t z) {
-        if (own) load_row_coalesced(raw, a.src + z * plane + seg, lane);
-        else if (ld) load_row(raw, a.src + ((size_t)z * L + y) * L + (size_t)g * 64u);
+        if (own && !DIRECT) load_row_coalesced(raw, a.src + z * plane + seg, lane);
+        else if (own || ld) load_row(raw, a.src + ((size_t)z * L + y) * L + (size_t)g * 64u);
     };
     auto bits = [&](const Row& raw) {
-        if (!own) return ld ? row_bits(raw) : RowBits{0u, 0u};
+        if (DIRECT || !own) return (own || ld) ? row_bits(raw) : RowBits{0u, 0u};
         Row row;
         regroup_to_owner(row, raw, stage, lane);
         return row_bits(row);
@@ -582,7 +583,8 @@ __global__ __launch_bounds__(640) void k_sweep3_fusedq(Fused3Args a) {
     auto put = [&](uint32_t z, const RowBits& rb) {
         Row row;
         bits_to_row(row, rb);
-        if (own) store_row_coalesced(a.dst + z * plane + seg, row, stage, lane, false);
+        if (own && DIRECT) store_row(a.dst + ((size_t)z * L + y) * L + (size_t)g * 64u, row, false);
+        else if (own) store_row_coalesced(a.dst + z * plane + seg, row, stage, lane, false);
     };
     // neighbour entries (own rows wrap when the workgroup holds whole planes); outer and shadow
     // lanes read their own entry
@@ -1140,14 +1142,22 @@ int launch_sweep3_fused(const int8_t* src, int8_t* dst, int64_t L, const ising::
 #define ISING_LAUNCH3FQ(OO, HH)                                                                            \
     do {                                                                                                   \
         if (lds > 65536) {                                                                                 \
-            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ising::k_sweep3_fusedq<OO, HH>), \
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ising::k_sweep3_fusedq<OO, HH, DD>), \
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
             if (e != hipSuccess) return ising_host::hip_failed(e, "hipFuncSetAttribute(k_sweep3_fusedq)"); \
         }                                                                                                  \
-        hipLaunchKernelGGL((ising::k_sweep3_fusedq<OO, HH>), grid, blockq, lds, stream, a);               \
+        hipLaunchKernelGGL((ising::k_sweep3_fusedq<OO, HH, DD>), grid, blockq, lds, stream, a);           \
     } while (0)
-        if (halo) { if (obs) ISING_LAUNCH3FQ(true, true); else ISING_LAUNCH3FQ(false, true); }
-        else { if (obs) ISING_LAUNCH3FQ(true, false); else ISING_LAUNCH3FQ(false, false); }
+        // a wave's 4 KiB hold 4096 / L rows: direct row I/O from eight rows per wave (L <= 512) on
+        if (L <= 512) {
+            constexpr bool DD = true;
+            if (halo) { if (obs) ISING_LAUNCH3FQ(true, true); else ISING_LAUNCH3FQ(false, true); }
+            else { if (obs) ISING_LAUNCH3FQ(true, false); else ISING_LAUNCH3FQ(false, false); }
+        } else {
+            constexpr bool DD = false;
+            if (halo) { if (obs) ISING_LAUNCH3FQ(true, true); else ISING_LAUNCH3FQ(false, true); }
+            else { if (obs) ISING_LAUNCH3FQ(true, false); else ISING_LAUNCH3FQ(false, false); }
+        }
 #undef ISING_LAUNCH3FQ
         return ising_host::check_launch("k_sweep3_fusedq");
     }
