@@ -284,6 +284,31 @@ def test_fused3_sweeps_match_oracle(dev, oracle_lib, L, beta, n, seed, offset, t
     assert np.array_equal(tr.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("L,n", [(128, 3), (256, 2)])
+def test_fused3_short_walks_match_oracle(dev, oracle_lib, L, n):
+    # walks of 2, 4 and 16 planes per workgroup: the first and last steps of a walk make only some of
+    # their plane updates, and with 2 planes no step has all of them (128^3: whole planes per
+    # workgroup; 256^3: row strips with halo rows)
+    host0 = _cube(L, 3 * L + n)
+    ref = host0.copy()
+    ref_tr = oracle_lib.sweep3(ref, BETA_C3, n, 77, 9, trace=True)
+    scratch = torch.empty((L, L, L), dtype=torch.int8, device="cuda")
+    try:
+        for rz in (2, 4, 16):
+            for ties in (1, 0):
+                _say("fused3 short walk", L, n, rz, ties)
+                dev.ising_set_option("planes3", rz)
+                dev.ising_set_option("ties3", ties)
+                s = _to_dev(host0)
+                tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+                dev.ising3_sweep_fused(s, scratch, L, BETA_C3, n, 77, 9, tr)
+                assert np.array_equal(s.cpu().numpy(), ref), (rz, ties)
+                assert np.array_equal(tr.cpu().numpy(), ref_tr), (rz, ties)
+    finally:
+        dev.ising_set_option("planes3", 0)
+        dev.ising_set_option("ties3", 1)
+
+
 @pytest.mark.parametrize("L", [64, 256, 512])
 def test_fused3_step_is_one_sweep_out_of_place(dev, oracle_lib, L):
     _say("fused3 step", L)
