@@ -23,15 +23,28 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle into ``oracle/liboracle.so`` (gcc, OpenMP, no -march)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+def build(force: bool = True, out: str | None = None, native: bool = False) -> str:
+    """Compile the oracle.  Default: ``oracle/liboracle.so`` with -O2 and no -march, so the library
+    built once runs on whichever host runs the tests.  native=True: -O3 -march=native into ``out``
+    (a copy for timing on the host that builds it; same source, same results)."""
+    lib = out or _LIB
+    if force or not os.path.exists(lib):
+        tmp = lib + ".tmp%d" % os.getpid()
+        opt = ["-O3", "-march=native"] if native else ["-O2"]
+        cmd = ["gcc", *opt, "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
                "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
+
+
+def load_native(directory: str) -> str:
+    """Build the -O3 -march=native copy into `directory` and use it for every later call (the CPU
+    baseline's timing).  Returns the compiler flags used."""
+    global _lib
+    path = build(force=True, out=os.path.join(directory, "liboracle_native.so"), native=True)
+    _lib = _configure(ctypes.CDLL(path))
+    return "gcc -O3 -march=native -fopenmp"
 
 
 def _load():
@@ -40,7 +53,11 @@ def _load():
         return _lib
     if not os.path.exists(_LIB):
         build(force=True)
-    lib = ctypes.CDLL(_LIB)
+    _lib = _configure(ctypes.CDLL(_LIB))
+    return _lib
+
+
+def _configure(lib):
     u32p = ctypes.POINTER(ctypes.c_uint32)
     u64p = ctypes.POINTER(ctypes.c_uint64)
     i64p = ctypes.POINTER(ctypes.c_int64)
@@ -81,6 +98,10 @@ def _load():
     lib.oracle_sweep_fmt.restype = None
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
+    lib.oracle_moments.argtypes = [i64p, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+    lib.oracle_moments.restype = None
     lib.oracle3_thresholds.argtypes = [ctypes.c_double, u64p]
     lib.oracle3_thresholds.restype = None
     lib.oracle3_init.argtypes = [i8p, ctypes.c_int64, ctypes.c_uint64]
@@ -98,7 +119,6 @@ def _load():
                                  ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                  ctypes.c_int64, i8p]
     lib.oracle3_crop.restype = None
-    _lib = lib
     return lib
 
 
@@ -265,3 +285,15 @@ def crop3(L: int, seed: int, beta: float, n: int, offset: int, z0: int, y0: int,
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    _load().oracle_set_num_threads(int(n))
+
+
+def moments(trace: np.ndarray, n_sites: int) -> np.ndarray:
+    """(<|m|>, <m^2>, <m^4>, <e>, <e^2>) of an (n, 2) int64 (M, E) trace, FP64 sums in sweep order."""
+    tr = np.ascontiguousarray(trace, dtype=np.int64)
+    out = np.zeros(5, dtype=np.float64)
+    _load().oracle_moments(_ptr(tr, ctypes.c_int64), tr.shape[0], int(n_sites), _ptr(out, ctypes.c_double))
+    return out

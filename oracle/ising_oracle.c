@@ -427,3 +427,32 @@ int oracle_num_threads(void) {
     return 1;
 #endif
 }
+
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* Moments of a traced chain (Sec. 4.1: the magnetisation m = M / N and, for the Binder cumulant,
+ * its second and fourth powers; the energy per site e = E / N): out = (<|m|>, <m^2>, <m^4>, <e>, <e^2>)
+ * over the n sweeps of trace (M, E pairs), each a plain sum in sweep order divided by n. */
+void oracle_moments(const int64_t* trace, int64_t n, int64_t n_sites, double out[5]) {
+    double s_abs = 0.0, s_m2 = 0.0, s_m4 = 0.0, s_e = 0.0, s_e2 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double m = (double)trace[2 * i] / (double)n_sites;
+        double e = (double)trace[2 * i + 1] / (double)n_sites;
+        s_abs += fabs(m);
+        s_m2 += m * m;
+        s_m4 += (m * m) * (m * m);
+        s_e += e;
+        s_e2 += e * e;
+    }
+    out[0] = s_abs / (double)n;
+    out[1] = s_m2 / (double)n;
+    out[2] = s_m4 / (double)n;
+    out[3] = s_e / (double)n;
+    out[4] = s_e2 / (double)n;
+}

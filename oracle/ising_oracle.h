@@ -111,6 +111,13 @@ void oracle3_crop(int64_t L, uint64_t seed, double beta, int64_t n, uint64_t off
 /* Number of OpenMP threads the oracle's parallel loops use (1 without OpenMP). */
 int oracle_num_threads(void);
 
+/* Threads of the OpenMP loops from now on (n > 0). */
+void oracle_set_num_threads(int n);
+
+/* (<|m|>, <m^2>, <m^4>, <e>, <e^2>) of a traced chain, m = M / n_sites, e = E / n_sites, plain FP64
+ * sums in sweep order (Sec. 4.1). */
+void oracle_moments(const int64_t* trace, int64_t n, int64_t n_sites, double out[5]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,5 +1,6 @@
-"""Pin the exact-results helpers (enumeration, Kaufman, Onsager, Yang) against each other and
-against closed forms.  These are what the oracle's Markov chain is later judged against.
+"""Pin the exact finite-lattice results (enumeration, Kaufman) against each other and against closed
+forms.  These are what the oracle's Markov chain is later judged against (the infinite-lattice
+closed forms are pinned in tests/test_analysis.py).
 """
 import math
 
@@ -60,16 +61,3 @@ def test_energy_derivative_of_log_z():
         h = 1e-5
         dlz = (X.kaufman_log_z(beta + h, 4, 4) - X.kaufman_log_z(beta - h, 4, 4)) / (2 * h)
         assert X.boltzmann_moments(4, beta)["e"] * 16 == pytest.approx(-dlz, rel=1e-7)
-
-
-def test_onsager_and_yang_special_values():
-    assert X.onsager_energy(X.BETA_C) == pytest.approx(-math.sqrt(2), rel=1e-14)
-    assert X.onsager_energy(20.0) == pytest.approx(-2.0, abs=1e-12)      # ground state
-    assert X.onsager_energy(1e-4) == pytest.approx(-2 * math.tanh(1e-4), rel=1e-3)  # high-T
-    # continuity across T_c
-    assert X.onsager_energy(X.BETA_C * (1 + 1e-7)) == pytest.approx(-math.sqrt(2), abs=1e-4)
-    assert X.yang_magnetisation(X.BETA_C * 0.999) == 0.0
-    assert X.yang_magnetisation(10.0) == pytest.approx(1.0, abs=1e-12)
-    assert 0 < X.yang_magnetisation(X.BETA_C * 1.001) < 0.6
-    # large-L limit of the 4x4 energy at low temperature: both go to -2
-    assert X.boltzmann_moments(4, 3.0)["e"] == pytest.approx(X.onsager_energy(3.0), abs=1e-9)

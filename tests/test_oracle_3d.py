@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from oracle import exact as X
-from oracle import stats
+from paper_1903_11714_amd import analysis as A
 
 Z_MAX = 4.5
 
@@ -157,7 +157,7 @@ def test_l2_chain_matches_enumeration(oracle_lib, beta):
     m, e = tr[:, 0] / N, tr[:, 1] / N
     exact = X.boltzmann_moments3(L, beta)
     for series, key in ((e, "e"), (np.abs(m), "abs_m"), (m * m, "m2"), (m ** 4, "m4")):
-        mean, err, _ = stats.mean_and_error(series)
+        mean, err, _ = A.mean_err(series)
         assert abs(mean - exact[key]) < Z_MAX * err, (key, mean, exact[key], err)
 
 

@@ -230,3 +230,29 @@ def test_init_is_balanced_and_seeded(oracle_lib):
     assert abs(int(a.sum())) < 5 * 128                    # 5 sigma of a fair +-1 sum
     assert (a != b).mean() > 0.45
     assert oracle_lib.init_site(1, 5, 77) == a[5, 77]
+
+
+def test_init_has_no_repeated_rows_or_columns(oracle_lib):
+    # The hot start draws every site's bit from its own (row, 128-column chunk, word, bit) position of
+    # the init stream; a mapping that reused a counter or a word would repeat rows or columns.  Among
+    # 512 random rows (or columns) of 512 spins, two equal ones have probability ~2^-494.
+    a = oracle_lib.init(512, seed=9)
+    assert len({row.tobytes() for row in a}) == 512
+    assert len({col.tobytes() for col in a.T}) == 512
+    # neighbouring columns across a word (32) and chunk (128) boundary are uncorrelated
+    for d in (1, 32, 128):
+        corr = float((a[:, :-d].astype(np.int64) * a[:, d:]).mean())
+        assert abs(corr) < 5 / math.sqrt(a[:, d:].size), d
+
+
+def test_init_site_uses_the_init_stream(oracle_lib):
+    # sigma0(r, c) = -1 iff bit c & 31 of word (c >> 5) & 3 of Philox(key, (c >> 7, r, 0, 2^31)); the
+    # generator itself is pinned against rocRAND (test_oracle_philox.py)
+    seed = 0x1234_5678_9ABC_DEF0
+    rng = np.random.default_rng(5)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for _ in range(200):
+        r, c = int(rng.integers(0, 1 << 20)), int(rng.integers(0, 1 << 20))
+        blk = oracle_lib.philox4x32_10([c >> 7, r, 0, 0x80000000], key)
+        bit = (int(blk[(c >> 5) & 3]) >> (c & 31)) & 1
+        assert oracle_lib.init_site(seed, r, c) == (-1 if bit else 1)

@@ -77,3 +77,18 @@ def test_uniform_depends_on_sweep_and_colour(oracle_lib):
     assert base != oracle_lib.uniform(1, 10, 21, 6, 1)
     assert base != oracle_lib.uniform(2, 10, 21, 5, 1)
     assert base != oracle_lib.uniform(1, 12, 21, 5, 1)
+    assert base != oracle_lib.uniform(1, 10, 21, 5, 0)
+
+
+def test_colours_draw_independent_uniforms(oracle_lib):
+    # The same site (r, c) with the same sweep index under the two colour labels: a counter that
+    # dropped the colour would give equal uniforms, a shared word correlated ones.
+    rng = np.random.default_rng(8)
+    xs = []
+    for _ in range(4000):
+        r, c, t = int(rng.integers(0, 4096)), int(rng.integers(0, 4096)), int(rng.integers(0, 1 << 20))
+        xs.append((oracle_lib.uniform(5, r, c, t, 0), oracle_lib.uniform(5, r, c, t, 1)))
+    x = np.array(xs, dtype=np.float64)
+    assert (x[:, 0] != x[:, 1]).all()
+    corr = np.corrcoef(x[:, 0], x[:, 1])[0, 1]
+    assert abs(corr) < 5 / math.sqrt(len(x))
