@@ -27,6 +27,7 @@ import hashlib
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -88,32 +89,58 @@ def alu_roofline(layout: str, L: int, avg_launch_ms: float):
             "valu_insts_per_launch": c["valu_insts_per_launch"]}
 
 
-FUSED_MAX_L = 65536  # one workgroup thread per 64-column group, at most 1024 threads
+FUSED_MAX_L = 65536  # above this the two-sweep pass runs as column bands of one wave each
 
 KERNEL_NAME = {
     "fused": "k_sweep_fused2q (two sweeps per launch, tie queue)",
+    "bands": "k_sweep_fused2b (two sweeps per launch in column bands of one wave, tie queue)",
     "int8": "k_sweep_int8 (one colour per launch)",
     "packed": "k_sweep_packed_q (one colour per launch, tie queue)",
 }
 
 
+def kernel_name(layout: str, L: int) -> str:
+    return KERNEL_NAME["bands" if layout == "fused" and L > FUSED_MAX_L else layout]
+
+
 FUSED_SWEEPS_PER_LAUNCH = 2
+
+# Bytes each attempt must move at minimum for the schedule of each layout (one read and one write of
+# every spin per pass): int8 with one launch per colour 4 B per sweep (read L^2 and write L^2 per
+# half-sweep); int8 with both colours of a sweep in one pass 2 B (the minimum for one sweep per pass;
+# the default pass makes two sweeps and so needs only 1 B, but the 2 B figure is the one a one-sweep
+# schedule would be held to); 1-bit colour-split 0.375 B (both planes read, one written, per half-sweep).
+BYTES_PER_ATTEMPT = {"fused": 2.0, "int8": 4.0, "packed": 0.375}
+
+
+def attempts_per_launch(layout: str, L: int) -> float:
+    """Site updates one launch of the layout's dominant kernel makes: two sweeps of L^2 sites for the
+    two-sweep pass, one colour (L^2 / 2 sites) for the one-launch-per-colour kernels."""
+    return 2.0 * L * L if layout == "fused" else 0.5 * L * L
 
 
 def algorithmic_bytes(layout: str, L: int) -> float:
-    """Bytes one launch must move: fused reads the L^2-byte lattice and writes the other buffer
-    (for its two sweeps); int8 reads and writes the lattice for one colour; packed reads both
-    colour planes (L^2 / 8 bytes) and writes one (L^2 / 16 bytes)."""
+    """Algorithmic bytes per launch: bytes per attempt x attempts per launch."""
+    return BYTES_PER_ATTEMPT[layout] * attempts_per_launch(layout, L)
+
+
+def moved_bytes(layout: str, L: int) -> float:
+    """Bytes one launch reads and writes when every spin moves exactly once each way: the two-sweep
+    pass reads the L^2-byte lattice and writes the other buffer; the int8 half-sweep reads and writes
+    the lattice; the packed half-sweep reads both colour planes (L^2 / 8) and writes one (L^2 / 16)."""
     return 3.0 * L * L / 16.0 if layout == "packed" else 2.0 * L * L
 
 
-def fused_launches(n: int) -> int:
-    """Passes ising_sweep_fused makes for an even count n: two sweeps each, in an even number of
-    passes (an odd number of two-sweep passes gives one up for two one-sweep passes)."""
-    pairs = n // 2
-    if pairs % 2:
+def fused_passes(n: int) -> tuple[int, int, int]:
+    """(two-sweep passes, one-sweep passes, in-place sweeps) that ising_sweep_fused makes for n sweeps:
+    an odd n runs its first sweep in place; the even rest goes in passes of two sweeps, an even number of
+    passes in all (an odd number of two-sweep passes gives one up for two one-sweep passes)."""
+    in_place = n & 1
+    rest = n - in_place
+    pairs = rest // 2
+    if pairs & 1:
         pairs -= 1
-    return pairs + (n - 2 * pairs)
+    return pairs, rest - 2 * pairs, in_place
 
 
 def copy_bandwidth(torch, L: int, stream, reps: int = 20, in_place: bool = False) -> float:
@@ -255,29 +282,65 @@ def bench_3d(ising, torch, args, stream) -> dict:
     return res
 
 
-def cpu_baseline(L: int, beta: float, seed: int, sweeps: int):
-    """The oracle on `sweeps` sweeps of the same lattice (at most 16384^2, so the sample stays
-    around ten seconds of host time)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(L: int, beta: float, seed: int, sweeps: int, one_core_L: int = 8192, one_core_sweeps: int = 2):
+    """The oracle, built -O3 -march=native on this host, timed on `sweeps` sweeps of the lattice (at most
+    16384^2) with every OpenMP thread, and on `one_core_sweeps` sweeps of a one_core_L^2 lattice with
+    one thread; each sample is 10-20 s of host time."""
+    import tempfile
+
     import oracle
+    tmp = tempfile.mkdtemp(prefix="oracle_native_")
+    flags = oracle.load_native(tmp)
     L = min(L, 16384)
+    threads = oracle.num_threads()
     spins = oracle.init(L, seed)
     t0 = time.perf_counter()
     oracle.sweep(spins, beta, sweeps, seed, 0)
     dt = time.perf_counter() - t0
+    del spins
+    oracle.set_num_threads(1)
+    Lc = min(L, one_core_L)
+    spins = oracle.init(Lc, seed)
+    t0 = time.perf_counter()
+    oracle.sweep(spins, beta, one_core_sweeps, seed, 0)
+    dt1 = time.perf_counter() - t0
+    oracle.set_num_threads(threads)
     return {
         "value": L * L * sweeps / (dt * 1e9),
         "unit": "attempts/ns",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"{sweeps} sweeps of the full {L}x{L} lattice at T_c from the seed-{seed} hot start "
-                  f"({dt:.1f} s; plain C oracle, OpenMP over the rows of each half-sweep)",
+        "sample": f"{sweeps} sweeps of the full {L}x{L} lattice at beta={beta:.6g} from the seed-{seed} hot start "
+                  f"({dt:.1f} s; plain C oracle, {flags}, OpenMP over the rows of each half-sweep, {threads} threads)",
+        "one_core": {"value": Lc * Lc * one_core_sweeps / (dt1 * 1e9), "unit": "attempts/ns", "cores": 1,
+                     "sample": f"{one_core_sweeps} sweeps of a {Lc}x{Lc} lattice, same start and beta ({dt1:.1f} s)"},
+        "nproc": os.cpu_count(),
+        "cpu_model": cpu_model(),
+        "build": flags,
     }
 
 
-def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream, fmt="exact"):
-    """Hot start, W warm-up sweeps, K timed sweeps with the (M, E) trace, then `kernel_sweeps`
-    sweeps with every launch bracketed by events (one launch per two sweeps for "fused", per
-    colour otherwise).  `fmt` is the acceptance format of the fused layout (exact, bf16 or fp16)."""
+WARM_FLOOR_S = 0.3   # GPU seconds of sweeps before anything is timed, whatever --warmup asks
+
+
+def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream, fmt="exact", repeats=5,
+               warm_floor=WARM_FLOOR_S):
+    """Hot start; W warm-up sweeps and more until `warm_floor` seconds of GPU time have gone into
+    sweeps; then `repeats` timed runs of exactly K sweeps with the (M, E) trace, each bracketed by a
+    device synchronisation and by events on the launch stream; then `kernel_sweeps` sweeps with every
+    launch bracketed by events (one launch per two sweeps for "fused", per colour otherwise).  `fmt`
+    is the acceptance format (exact, bf16 or fp16; the fused layout only)."""
     assert fmt == "exact" or layout == "fused"
     dev = torch.device("cuda:0")
     if layout in ("int8", "fused"):
@@ -297,30 +360,46 @@ def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream,
         lat = torch.empty(L * L // 32, dtype=torch.int32, device=dev)
         ising.ising_init_packed(lat, L, seed, stream)
         sweep = ising.ising_sweep_packed
-    warm_trace = torch.empty((max(W, 1), 2), dtype=torch.int64, device=dev)
-    trace = torch.empty((max(K, 1), 2), dtype=torch.int64, device=dev)
-    if W:
-        sweep(lat, L, beta, W, seed, 0, warm_trace[:W], stream)
-    torch.cuda.synchronize()
-    print(f"bench: {layout} ({fmt}) L={L} warmup={W} done", file=sys.stderr, flush=True)
-
+    trace = torch.empty((max(K, W, 1), 2), dtype=torch.int64, device=dev)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    sweep(lat, L, beta, K, seed, W, trace[:K], stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    print(f"bench: {layout} timed {K} sweeps in {wall:.3f} s wall, {gpu_ms:.1f} ms events", file=sys.stderr,
+
+    def run(n, off, tr):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        sweep(lat, L, beta, n, seed, off, tr, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, ev0.elapsed_time(ev1)
+
+    t = 0
+    warm_ms, warm_n = 0.0, 0
+    if W:
+        warm_ms += run(W, t, trace[:W])[1]
+        t += W
+        warm_n += W
+    chunk = max(K, 2)
+    while warm_ms < warm_floor * 1e3 and warm_n < 100000:
+        warm_ms += run(chunk, t, trace[:chunk])[1]
+        t += chunk
+        warm_n += chunk
+    print(f"bench: {layout} ({fmt}) L={L} warm-up {warm_n} sweeps, {warm_ms:.0f} ms of GPU time", file=sys.stderr,
           flush=True)
+    walls, gpus = [], []
+    for _ in range(repeats):
+        w, g = run(K, t, trace[:K])
+        t += K
+        walls.append(w)
+        gpus.append(g)
+    wall = statistics.median(walls)
+    gpu_ms = statistics.median(gpus)
+    print(f"bench: {layout} timed {repeats} x {K} sweeps: median {wall * 1e3:.3f} ms wall, {gpu_ms:.3f} ms events",
+          file=sys.stderr, flush=True)
     final_ME = trace[K - 1].tolist() if K else None
 
-    # dominant kernel: each launch bracketed by events on the launch stream
+    # the dominant kernel launch by launch, each bracketed by events on the launch stream (untraced)
     nk = kernel_sweeps + (kernel_sweeps & 1)
-    t = W + K
     if layout == "fused":
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(nk // 2 + 1)]
         evs[0].record(stream)
@@ -341,35 +420,76 @@ def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream,
     torch.cuda.synchronize()
     durs = [evs[k].elapsed_time(evs[k + 1]) for k in range(len(evs) - 1)]
     del lat
-    launches = fused_launches(K) if layout == "fused" else 2 * K
+    if layout == "fused":
+        pairs, singles, in_place = fused_passes(K)
+        # the timed region holds only two-sweep passes (and the trace's zeroing) when K % 4 == 0
+        launches = pairs if (singles == 0 and in_place == 0) else 0
+    else:
+        launches = 2 * K
     return {
         "value": float(L) * L * K / (wall * 1e9),
         "wall_s": wall,
         "gpu_ms": gpu_ms,
+        "repeats": [float(L) * L * K / (w * 1e9) for w in walls],
+        "warmup_sweeps": warm_n,
         # the timed region's launches (with the traced (M, E) reduction): events on the launch
         # stream around the whole region, divided by the number of sweep launches in it
-        "avg_launch_ms": gpu_ms / launches if launches else float("nan"),
+        "avg_launch_ms": gpu_ms / launches if launches else sum(durs) / len(durs),
+        "avg_launch_from": "timed region" if launches else "untraced launches (K not a multiple of 4)",
         # launch by launch, without the trace
         "untraced_launch_ms": sum(durs) / len(durs),
         "final_ME": final_ME,
     }
 
 
+def roofline(layout: str, L: int, avg_launch_ms: float, untraced_launch_ms: float, copy_gbs: float) -> dict:
+    """HBM roofline of the dominant kernel at the algorithmic bytes per launch (bytes per attempt x
+    attempts per launch), with the measured HBM traffic (committed counters, while the kernel source
+    is unchanged), the bytes a pass moves when every spin goes once each way, and the vector-ALU
+    roofline beside it."""
+    alg = algorithmic_bytes(layout, L)
+    sec = avg_launch_ms * 1e-3
+    achieved = alg / sec / 1e9
+    traffic = measured_traffic(layout, L)
+    moved = moved_bytes(layout, L)
+    roof = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "kernel": kernel_name(layout, L), "avg_launch_us": avg_launch_ms * 1e3,
+        "untraced_launch_us": untraced_launch_ms * 1e3,
+        "bytes_per_attempt": BYTES_PER_ATTEMPT[layout], "attempts_per_launch": attempts_per_launch(layout, L),
+        "alg_bytes_per_launch": alg,
+        "moved": {"bytes_per_launch": moved, "achieved": moved / sec / 1e9, "frac": moved / sec / 1e9 / HBM_PEAK_GBS},
+        "measured_traffic": None if traffic is None else
+        {"achieved": traffic / sec / 1e9, "frac": traffic / sec / 1e9 / HBM_PEAK_GBS},
+        "alu": alu_roofline(layout, L, avg_launch_ms),
+        "copy_GBs": copy_gbs,
+        "copy_kind": "out of place" if layout == "fused" else "in place",
+        "moved_frac_of_copy": (moved / sec / 1e9) / copy_gbs if copy_gbs else None,
+    }
+    return roof
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000, help="timed sweeps")
-    ap.add_argument("--warmup", type=int, default=20, help="untimed sweeps first")
+    ap.add_argument("--steps", type=int, default=1000, help="timed sweeps per repeat")
+    ap.add_argument("--warmup", type=int, default=20,
+                    help="untimed sweeps first (more follow until %.1f s of GPU time has gone into sweeps)" % WARM_FLOOR_S)
+    ap.add_argument("--repeats", type=int, default=5, help="timed runs of --steps sweeps; the median is reported")
     ap.add_argument("--L", type=int, default=16384)
     ap.add_argument("--beta", type=float, default=BETA_C)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--kernel-sweeps", type=int, default=50, help="sweeps timed launch by launch")
-    ap.add_argument("--cpu-sweeps", type=int, default=8, help="sweeps in the CPU-oracle sample")
+    ap.add_argument("--cpu-sweeps", type=int, default=8, help="sweeps in the CPU-oracle sample (all threads)")
     ap.add_argument("--layout", choices=["fused", "int8", "packed"], default="fused",
                     help="fused: int8, both colours per launch, two buffers (default); int8: one launch "
                          "per colour, in place; packed: 1-bit spins, one launch per colour")
     ap.add_argument("--compare", type=int, default=1,
-                    help="with the fused layout, also time the other two layouts on the same workload")
+                    help="with the fused layout, also time the other formats and layouts on the same workload")
+    ap.add_argument("--largest", type=int, default=1,
+                    help="with the fused layout, also time the largest lattice (L = 131072, 100-sweep workload) on "
+                         "both layouts at T = 2.0, T_c and 2.6")
     ap.add_argument("--form", choices=["plain", "precision", "batch", "3d"], default="plain",
                     help="plain: the timed sweep (default); precision: bfloat16/half vs exact chains on "
                          "the --L lattice; batch: the 255-replica Binder-crossing run in one launch; "
@@ -377,6 +497,10 @@ def main() -> int:
     ap.add_argument("--L3", type=int, default=1024, help="edge of the cubic lattice for --form 3d")
     ap.add_argument("--meas", type=int, default=None, help="measurement sweeps of the precision/batch forms")
     ap.add_argument("--therm", type=int, default=None, help="thermalisation sweeps of the precision/batch forms")
+    ap.add_argument("--seeds", type=int, default=8, help="seeds per temperature and format (precision form)")
+    ap.add_argument("--record", default=None,
+                    help="precision/batch forms: write the full JSON record to this path and a markdown "
+                         "table beside it (.md)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run this many plain device copies of an L^2-byte buffer (counter calibration)")
@@ -385,6 +509,9 @@ def main() -> int:
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(one periodic lattice per GPU, no sharding).", file=sys.stderr)
+        return 2
+    if args.steps < 1 or args.repeats < 1:
+        print("bench.py: --steps and --repeats must be positive", file=sys.stderr)
         return 2
 
     import torch
@@ -402,33 +529,40 @@ def main() -> int:
         return 0
     if args.form != "plain":
         from paper_1903_11714_amd import studies
+
+        def log(msg):
+            print("bench: " + msg, file=sys.stderr, flush=True)
         if args.form == "precision":
             res = studies.precision_study(L=L, n_therm=args.therm if args.therm is not None else 1000,
-                                          n_meas=args.meas if args.meas is not None else 10000, seed=seed)
+                                          n_meas=args.meas if args.meas is not None else 10000,
+                                          seeds=tuple(range(seed, seed + args.seeds)), log=log)
+            table = studies.precision_table(res)
         else:
             res = studies.batch_study(n_therm=args.therm if args.therm is not None else 2000,
                                       n_meas=args.meas if args.meas is not None else 20000)
-        print(json.dumps({"form": args.form, **res}), flush=True)
+            table = studies.batch_table(res)
+        res = {"form": args.form, "command": "python bench.py " + " ".join(sys.argv[1:]), **res}
+        if args.record:
+            os.makedirs(os.path.dirname(os.path.abspath(args.record)), exist_ok=True)
+            with open(args.record, "w") as f:
+                json.dump(res, f, indent=1)
+            with open(os.path.splitext(args.record)[0] + ".md", "w") as f:
+                f.write(f"Command: `{res['command']}`\n\n{table}\n")
+        print(table, file=sys.stderr, flush=True)
+        print(json.dumps({k: v for k, v in res.items() if k not in ("runs", "curves")}), flush=True)
         return 0
 
-    if args.layout == "fused" and K % 2:
-        K += 1  # whole two-sweep passes
-        print(f"bench: fused layout times an even number of sweeps: {K}", file=sys.stderr, flush=True)
-    if args.layout == "fused" and L > FUSED_MAX_L:
-        print(f"bench: L={L} is above the fused sweep's limit ({FUSED_MAX_L}); timing the int8 layout",
-              file=sys.stderr, flush=True)
-        args.layout = "int8"
-    main = run_layout(ising, torch, args.layout, L, beta, seed, K, W, args.kernel_sweeps, stream)
+    main = run_layout(ising, torch, args.layout, L, beta, seed, K, W, args.kernel_sweeps, stream,
+                      repeats=args.repeats)
     lat_bytes = L * L // 8 if args.layout == "packed" else L * L
-    alg_bytes = algorithmic_bytes(args.layout, L)
-    achieved = alg_bytes / (main["avg_launch_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(args.layout, L)
     layout_text = {
         "fused": f"int8 layout, two sweeps per launch, lattice + scratch buffer ({2 * lat_bytes / 2**20:.0f} MiB)",
         "int8": f"int8 layout, one launch per colour, in place ({lat_bytes / 2**20:.0f} MiB)",
         "packed": f"1-bit layout, one launch per colour ({lat_bytes / 2**20:.0f} MiB)",
     }[args.layout]
-
+    # context for the roofline: a plain pass over an L^2-byte buffer on the same GPU (out of place, as
+    # the fused sweep moves its bytes; in place for the one-launch-per-colour kernels)
+    cb = copy_bandwidth(torch, L, stream, in_place=args.layout != "fused")
     result = {
         "metric": METRIC,
         "value": main["value"],
@@ -448,61 +582,37 @@ def main() -> int:
                         f"exact-threshold checkerboard Metropolis, {layout_text}, (M,E) traced every sweep",
             "L": L, "beta": beta, "layout": args.layout, "sweeps_timed": K,
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": KERNEL_NAME[args.layout],
-            "avg_launch_us": main["avg_launch_ms"] * 1e3,
-            "untraced_launch_us": main["untraced_launch_ms"] * 1e3,
-            "alg_bytes_per_launch": alg_bytes,
-            "sweeps_per_launch": FUSED_SWEEPS_PER_LAUNCH if args.layout == "fused" else 0.5,
-        },
+        "timing": {"repeats": args.repeats, "per_repeat_attempts_per_ns": main["repeats"],
+                   "statistic": "median of the repeats", "warmup_sweeps_run": main["warmup_sweeps"],
+                   "warmup_floor_gpu_s": WARM_FLOOR_S, "avg_launch_from": main["avg_launch_from"]},
+        "roofline": roofline(args.layout, L, main["avg_launch_ms"], main["untraced_launch_ms"], cb),
         "gpu_event_ms": main["gpu_ms"],
         "final_ME": main["final_ME"],
     }
-    # The bound is the resource the kernel uses the larger share of: HBM (algorithmic bytes per
-    # launch over the launch time) or the vector ALU (its VALU instructions per launch, from the
-    # committed counters, over the launch time); the other one is reported beside it.
-    alu = alu_roofline(args.layout, L, main["avg_launch_ms"])
-    if alu is not None and alu["frac"] > result["roofline"]["frac"]:
-        hbm = {k: result["roofline"].pop(k) for k in ("bound", "achieved", "peak", "unit", "frac")}
-        rest = result["roofline"]
-        result["roofline"] = {**{k: alu[k] for k in ("bound", "achieved", "peak", "unit", "frac")}, **rest,
-                              "valu_busy": alu["valu_busy"], "valu_insts_per_launch": alu["valu_insts_per_launch"],
-                              "hbm": hbm}
-    elif alu is not None:
-        result["roofline"]["alu"] = alu
-    # context for the roofline: a plain device-to-device copy of an L^2-byte buffer (out of place,
-    # as the fused sweep moves its bytes) on the same GPU
-    cb = copy_bandwidth(torch, L, stream)
-    result["roofline"]["copy_GBs"] = cb
-    result["roofline"]["copy_kind"] = "out of place"
-    result["roofline"]["hbm_frac_of_copy"] = achieved / cb if cb else None
     if args.compare and args.layout == "fused":
         # the same workload with the acceptance test in bfloat16 and in half (the chain differs:
         # u < p with both rounded to the format), on the same fused kernel
         for fmt in ("bf16", "fp16"):
-            low = run_layout(ising, torch, "fused", L, beta, seed, K, W, args.kernel_sweeps, stream, fmt=fmt)
-            gbs = alg_bytes / (low["avg_launch_ms"] * 1e-3) / 1e9
+            low = run_layout(ising, torch, "fused", L, beta, seed, K, W, args.kernel_sweeps, stream, fmt=fmt,
+                             repeats=3)
+            r = roofline("fused", L, low["avg_launch_ms"], low["untraced_launch_ms"], cb)
             result[f"{fmt}_accept"] = {
                 "value": low["value"], "unit": "attempts/ns", "steps": K, "kernel": KERNEL_NAME["fused"],
-                "avg_launch_us": low["avg_launch_ms"] * 1e3, "hbm_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                "avg_launch_us": low["avg_launch_ms"] * 1e3, "hbm_GBs": r["achieved"], "hbm_frac": r["frac"],
                 "vs_exact": low["value"] / main["value"], "final_ME": low["final_ME"],
             }
         # the same workload on the other layouts (same chain, bit-identical spins), for reference
         ks = max(K // 4, 1)
         for lay in ("int8", "packed"):
-            other = run_layout(ising, torch, lay, L, beta, seed, ks, W, args.kernel_sweeps, stream)
-            gbs = algorithmic_bytes(lay, L) / (other["avg_launch_ms"] * 1e-3) / 1e9
+            other = run_layout(ising, torch, lay, L, beta, seed, ks, W, args.kernel_sweeps, stream, repeats=3)
+            r = roofline(lay, L, other["avg_launch_ms"], other["untraced_launch_ms"], 0.0)
             result[f"{lay}_layout"] = {
                 "value": other["value"], "unit": "attempts/ns", "steps": ks, "kernel": KERNEL_NAME[lay],
-                "avg_launch_us": other["avg_launch_ms"] * 1e3,
-                "hbm_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                "avg_launch_us": other["avg_launch_ms"] * 1e3, "hbm_GBs": r["achieved"], "hbm_frac": r["frac"],
+                "bytes_per_attempt": BYTES_PER_ATTEMPT[lay],
             }
+    if args.largest and args.layout == "fused" and L != LARGEST_L:
+        result["largest"] = bench_largest(ising, torch, stream, seed)
     if args.copy_calibration:
         calibration_copies(torch, L * L, args.copy_calibration)
     if not args.no_cpu_baseline:
@@ -510,6 +620,28 @@ def main() -> int:
         result["cpu_baseline"] = cpu_baseline(L, beta, seed, args.cpu_sweeps)
     print(json.dumps(result), flush=True)
     return 0
+
+
+LARGEST_L = 131072
+
+
+def bench_largest(ising, torch, stream, seed: int, temps=(2.0, 1.0 / BETA_C, 2.6), K: int = 8) -> dict:
+    """The largest single-GPU lattice (L = 131072: 16 GiB int8, 2 GiB 1-bit), hot start, at three
+    temperatures on both layouts: throughput over 3 x K timed sweeps (after the warm-up floor) and the
+    roofline of each layout's dominant kernel."""
+    out = {"L": LARGEST_L, "sweeps_timed": K, "runs": []}
+    layouts = ("fused", "packed")
+    for T in temps:
+        for lay in layouts:
+            r = run_layout(ising, torch, lay, LARGEST_L, 1.0 / T, seed, K, 0, 4, stream, repeats=3)
+            roof = roofline(lay, LARGEST_L, r["avg_launch_ms"], r["untraced_launch_ms"], 0.0)
+            out["runs"].append({"T": T, "layout": lay, "value": r["value"], "unit": "attempts/ns",
+                                "per_repeat": r["repeats"], "kernel": kernel_name(lay, LARGEST_L),
+                                "avg_launch_us": roof["avg_launch_us"], "hbm_GBs": roof["achieved"],
+                                "hbm_frac": roof["frac"], "bytes_per_attempt": roof["bytes_per_attempt"],
+                                "moved_frac": roof["moved"]["frac"], "final_ME": r["final_ME"]})
+            torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":
