@@ -13,10 +13,13 @@
  *     ISING_EHIP means a HIP call failed; ising_last_error() returns its text.
  *   - Spin lattices hold +1 / -1 only (int8 layout) or the packed bit form of such a lattice.
  *     Other byte values give unspecified (but memory-safe) results.
- *   - L is the linear size of a square periodic lattice: L % 64 == 0, 64 <= L <= 2^20.
- *   - Library state is process-wide and unguarded: the options below, and the batched form's
- *     tuned schedules and captured graph.  Call the library from one host thread at a time
- *     (ising_last_error is per thread).
+ *   - L is the linear size of a square periodic lattice: L % 32 == 0, 32 <= L <= 2^20 (Sec. 3:
+ *     any L x L torus; the kernels take 64-column groups, and a row whose length is an odd multiple
+ *     of 32 ends in a half group of 32 columns).
+ *   - Library state is process-wide: the options below (each an atomic value; every valid setting
+ *     gives the same results, so a setting that races a launch is harmless) and the batched form's
+ *     tuned schedules and captured graphs (guarded by a mutex held for the whole of each batch
+ *     call).  ising_last_error is per thread.
  *
  * Lattice conventions (Sec. 3, Sec. 3.1, Sec. 3.2 of the paper):
  *   int8 layout: row-major L x L bytes, sigma[r][c] at offset r * L + c, periodic in r and c.
@@ -84,23 +87,27 @@ int ising_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sw
  * On return `spins` holds the lattice after n_sweeps sweeps, bit-identical to ising_sweep_fmt
  * with the same arguments, and so is trace_ME.  Passes alternate spins -> scratch -> spins, an
  * even number of them; an odd count runs its first sweep in place.  Option "fused_sweeps" sets
- * the sweeps per pass (2 by default, 1).  Above L = 65536 every sweep runs in place as in
- * ising_sweep_fmt (scratch unused).  Returns ISING_EINVAL for the checks of ising_sweep_fmt,
- * for a null, misaligned or overlapping scratch. */
+ * the sweeps per pass (2 by default, 1).  Up to L = 65536 a pass gives each row to one workgroup
+ * (one thread per 64-column group); above, the two-sweep pass runs in column bands of one wave each
+ * (62 own groups and one recomputed group on either side), and the one-sweep pass is not available
+ * (fused_sweeps = 1 then sweeps in place as ising_sweep_fmt).  When L % 64 != 0 every sweep runs in
+ * place as in ising_sweep_fmt (scratch unused).  Returns ISING_EINVAL for the checks of
+ * ising_sweep_fmt, for a null, misaligned or overlapping scratch. */
 int ising_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, int fmt, int64_t n_sweeps,
                       uint64_t seed, uint64_t sweep_offset, int64_t* trace_ME, void* stream);
 
 /* One sweep with sweep index t (< 2^32) out of place: dst = the sweep of src (both device
  * int8[L * L], 16-byte aligned, disjoint; src is not modified).  out_ME: NULL or device int64[2]
  * receiving (M, E) of dst.  For a caller that manages its own pair of buffers (a captured graph
- * of alternating steps, say).  Above L = 65536: a device copy, then the two half-sweeps on dst. */
+ * of alternating steps, say).  Above L = 65536, or when L % 64 != 0: a device copy, then the two
+ * half-sweeps on dst. */
 int ising_sweep_fused_step(const int8_t* src, int8_t* dst, int64_t L, double beta, int fmt, uint64_t seed,
                            uint64_t t, int64_t* out_ME, void* stream);
 
 /* Two sweeps, t and t + 1 (t + 1 < 2^32), in one pass out of place: dst = src after both (same
  * buffers and conventions as ising_sweep_fused_step).  out_ME: NULL or device int64[4] receiving
- * (M, E) after sweep t, then after sweep t + 1.  Above L = 65536: a device copy, then the four
- * half-sweeps on dst. */
+ * (M, E) after sweep t, then after sweep t + 1.  Above L = 65536 the pass runs in column bands;
+ * when L % 64 != 0: a device copy, then the four half-sweeps on dst. */
 int ising_sweep_fused_pair(const int8_t* src, int8_t* dst, int64_t L, double beta, int fmt, uint64_t seed,
                            uint64_t t, int64_t* out_ME, void* stream);
 
@@ -164,10 +171,16 @@ int ising3_half_sweep_packed(uint32_t* planes, int64_t L, double beta, uint64_t 
 int ising3_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME, void* stream);
 
 /* ---- 1-bit packed layout -----------------------------------------------------------------
- * planes: device uint32[L * L / 32], two colour planes of L rows x (L / 64) words each:
- * word (q * L + r) * (L / 64) + g holds the colour-q sites of row r with j = c >> 1 in
- * [32 g, 32 g + 32); site i = j & 31 sits at bit 8 * (0, 2, 1, 3)[i & 3] + (i >> 2) (the bit
- * position its uniform uses); a set bit is spin -1. */
+ * planes: device uint32[ising_packed_words(L)] = uint32[2 L G], G = ceil(L / 64): two colour
+ * planes of L rows x G words each (L * L / 32 words when L % 64 == 0).  Word (q * L + r) * G + g
+ * holds the colour-q sites of row r with j = c >> 1 in [32 g, 32 g + 32); site i = j & 31 sits at
+ * bit 8 * (0, 2, 1, 3)[i & 3] + (i >> 2) (the bit position its uniform uses); a set bit is spin -1.
+ * When L % 64 == 32 the last word of each row holds sites 0 .. 15 only (bits 0 .. 3 of each byte);
+ * its other bits are zero. */
+
+/* Number of uint32 words of the packed layout for L (2 L ceil(L / 64)), or ISING_EINVAL. */
+int64_t ising_packed_words(int64_t L);
+
 int ising_pack(const int8_t* spins, int64_t L, uint32_t* planes, void* stream);
 int ising_unpack(const uint32_t* planes, int64_t L, int8_t* spins, void* stream);
 
@@ -232,7 +245,12 @@ int64_t ising_batch_workspace_bytes(const ising_replica_t* replicas, int64_t n);
  * sizes by timing the candidates on the table itself (options "batch_threads",
  * "batch_slab_sites", "batch_depth" and "batch_lists_per_cu" fix them);
  * every schedule gives identical results.  The first call for a new set of sizes synchronises
- * for that timing.  A split schedule is used only if all its workgroups fit on the GPU at once
+ * for that timing; every other call returns without synchronising.  The run is captured once per
+ * plan (workspace address and layout, schedule) into a hipGraph; the per-call values (start mode,
+ * sweep counts, trace and moments pointers) are written into the workspace by a small kernel on
+ * `stream` ahead of the graph, so repeated calls replay one graph.  At most 8 plans stay captured;
+ * making a ninth waits for the latest run of the least recently used one (that run only, not the
+ * device) before releasing it.  A split schedule is used only if all its workgroups fit on the GPU at once
  * (slabs wait for their neighbours' rows); its waits are bounded, and a run in which one gave up
  * (possible only if other work keeps its workgroups off the GPU, e.g. two batch runs at once on
  * different streams) writes NaN moments for the replicas concerned. */

@@ -27,6 +27,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <atomic>
 #include <queue>
 #include <string>
 #include <vector>
@@ -71,17 +73,21 @@ __device__ __forceinline__ uint32_t decide(uint32_t a, uint32_t up, uint32_t dow
 // One row of the int8 half-sweep for colour Q.  O = column parity of the colour-Q sites of this
 // row.  bprev: row r-1 sites at parity O (vertical neighbours), bcur: row r sites at parity 1-O
 // (horizontal neighbours).  Returns row r+1's sites at parity O (the next row's bcur).
+// `half`: this group is a half group (16 sites per colour, the last group of a row whose length is an
+// odd multiple of 32).
 template <int Q, int O, bool OBS>
 __device__ __forceinline__ uint32_t sweep_row(Row& cur, const Row& nxt, uint32_t bprev, uint32_t bcur,
                                               uint32_t halo, const Thresholds& th, uint32_t g,
                                               uint32_t r, uint32_t t, uint32_t key0, uint32_t key1,
-                                              Counts& cnt) {
+                                              Counts& cnt, bool half = false) {
     const uint32_t bnext = site_bits<O>(nxt);
     const uint32_t a = site_bits<O>(cur);
     // horizontal neighbour that lies in the adjacent group: byte 0 of the right halo dword
     // (O = 1) or byte 3 of the left halo dword (O = 0); bit 1 of a byte is its sign
-    const uint32_t hs = O == 1 ? shift_next(bcur, (halo >> 1) & 1u) : shift_prev(bcur, (halo >> 25) & 1u);
-    const uint32_t F = decide<Q, OBS>(a, bprev, bnext, bcur, hs, bcur, th, g, r, t, key0, key1, cnt);
+    const uint32_t hs = O == 1 ? (half ? shift_next_half(bcur, (halo >> 1) & 1u) : shift_next(bcur, (halo >> 1) & 1u))
+                               : shift_prev(bcur, (halo >> 25) & 1u);
+    const uint32_t F = decide<Q, OBS>(a, bprev, bnext, bcur, hs, bcur, th, g, r, t, key0, key1, cnt,
+                                      half ? kHalfSites : 0xFFFFFFFFu);
     apply_flips<O>(cur, F);
     return bnext;
 }
@@ -98,8 +104,9 @@ struct SweepArgs {
 };
 
 // STAGED: the wave's lanes own 64 consecutive groups of one row (groups % 64 == 0); rows move
-// through LDS with coalesced loads and stores.  Otherwise every lane reads its own 64 bytes.
-template <int Q, bool OBS, bool STAGED>
+// through LDS with coalesced loads and stores.  Otherwise every lane reads its own 64 bytes, or 32 in
+// the half group that ends each row when HALF (L an odd multiple of 32; never STAGED).
+template <int Q, bool OBS, bool STAGED, bool HALF = false>
 __global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
     __shared__ uint4 lds_all[4][256];
     const uint32_t lane_id = logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * blockDim.x + threadIdx.x;
@@ -114,12 +121,15 @@ __global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
         const uint32_t gl = g == 0 ? a.groups - 1 : g - 1;
         const uint32_t gr = g + 1 == a.groups ? 0 : g + 1;
         const uint32_t lane = threadIdx.x & 63u;
+        const bool half = HALF && g + 1 == a.groups;          // this lane's group is a half group
+        const uint32_t left_last = HALF && gl + 1 == a.groups ? 28u : 60u;  // last dword of the left group
         uint4* const lds = lds_all[threadIdx.x >> 6];
         // first byte of this lane's group (unstaged) or of the wave's 64 groups (staged)
         int8_t* const col = a.spins + (size_t)(STAGED ? g - lane : g) * 64u;
         auto rowp = [&](uint32_t r) { return col + (size_t)r * L; };
         auto fetch = [&](Row& raw, uint32_t r) {
             if (STAGED) load_row_coalesced(raw, rowp(r), lane);
+            else if (half) load_row_half(raw, rowp(r));
             else load_row(raw, rowp(r));
         };
         auto own = [&](Row& row, const Row& raw) {
@@ -128,10 +138,11 @@ __global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
         };
         auto put = [&](uint32_t r, const Row& row) {
             if (STAGED) store_row_coalesced(rowp(r), row, lds, lane, a.nt_store);
+            else if (half) store_row_half(rowp(r), row);
             else store_row(rowp(r), row, a.nt_store);
         };
         auto halo_left = [&](uint32_t r) {
-            return *reinterpret_cast<const uint32_t*>(a.spins + (size_t)r * L + (size_t)gl * 64u + 60u);
+            return *reinterpret_cast<const uint32_t*>(a.spins + (size_t)r * L + (size_t)gl * 64u + left_last);
         };
         auto halo_right = [&](uint32_t r) {
             return *reinterpret_cast<const uint32_t*>(a.spins + (size_t)r * L + (size_t)gr * 64u);
@@ -181,11 +192,11 @@ __global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
             fetch(ra, ahead(r + 4));
             fetch(rb, ahead(r + 5));
             const uint32_t h2 = halo_of(pa, ahead(r + 2), O0), h3 = halo_of(pb, ahead(r + 3), O1);
-            uint32_t bn = sweep_row<Q, O0, OBS>(cur, nxt, bprev, bcur, h0, a.th, g, r, a.t, a.key0, a.key1, cnt);
+            uint32_t bn = sweep_row<Q, O0, OBS>(cur, nxt, bprev, bcur, h0, a.th, g, r, a.t, a.key0, a.key1, cnt, half);
             put(r, cur);
             bprev = bcur;
             bcur = bn;
-            bn = sweep_row<Q, O1, OBS>(nxt, pa, bprev, bcur, h1, a.th, g, r + 1, a.t, a.key0, a.key1, cnt);
+            bn = sweep_row<Q, O1, OBS>(nxt, pa, bprev, bcur, h1, a.th, g, r + 1, a.t, a.key0, a.key1, cnt, half);
             put(r + 1, nxt);
             bprev = bcur;
             bcur = bn;
@@ -195,7 +206,9 @@ __global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
             h1 = h3;
         }
     }
-    if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, active ? 1u : 0u, 64u * a.rows);
+    // sites in units of 32: a lane covers two per row, one in a half group
+    const uint32_t units = !active ? 0u : (HALF && lane_id % a.groups + 1 == a.groups) ? 1u : 2u;
+    if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, units, 32u * a.rows);
 }
 
 // ---- Fused sweep: both colours of one sweep in one pass over the lattice, out of place.
@@ -717,6 +730,141 @@ __global__ __launch_bounds__(1024) void k_sweep_fused2q(FusedArgs a) {
     }
 }
 
+// ---- Two sweeps per pass in column bands of one wave.
+//
+// The pass above puts a whole row in one workgroup, one thread per 64-column group, so it stops at
+// L = 65536.  Here (L >= 4096) a band of one wave walks a strip of R rows instead, over 64 consecutive groups
+// (modulo the row) of which the middle ones are its own: lane l takes group b0 - 1 + l, lanes
+// 1 .. n of them (n <= 62) are the band's groups, and lane 0 and the lanes past n only recompute their
+// groups so that the band's own sites see correct neighbours.  The group-edge neighbours come from the
+// adjacent lanes by a lane shift (no LDS exchange, no workgroup barrier: every wave is independent).
+// The shift brings nothing into lane 0 from the left or into lane 63 from the right; a wrong value at
+// a band's edge spreads by at most one column per colour update, four columns over the pass, so it
+// never reaches the neighbour group of an own one (the light cone of Sec. 3.1's colour updates).  Rows
+// are recomputed four deep above and below the strip as in the full-row pass.  The walk, the
+// uniforms and the tie queue are those of the full-row pass, so the result is the same two sweeps,
+// bit for bit.
+struct BandArgs {
+    const int8_t* src;
+    int8_t* dst;
+    uint32_t L, groups, rows;  // rows = R, even, divides L
+    uint32_t bands;            // bands per row; band b owns groups [b G / bands, (b + 1) G / bands)
+    uint32_t units;            // bands x strips
+    uint32_t t, key0, key1;
+    Thresholds th;
+    int64_t* obs;        // OBS: (M, E) after sweep t, then after t + 1, zeroed beforehand
+    uint32_t xcd_remap;  // renumber blocks per XCD (see logical_block)
+    uint32_t nt_store;   // non-temporal stores of the output rows
+    uint32_t alternate;  // walk odd strips upwards
+};
+
+// lane l's value of v from lane l - 1 (to the left; lane 0 gets 0) and from lane l + 1 (lane 63 gets 0)
+__device__ __forceinline__ uint32_t from_left_lane(uint32_t v) {
+    return __builtin_amdgcn_update_dpp(0u, v, 0x138, 0xF, 0xF, false);  // wave_shr:1
+}
+__device__ __forceinline__ uint32_t from_right_lane(uint32_t v) {
+    return __builtin_amdgcn_update_dpp(0u, v, 0x130, 0xF, 0xF, false);  // wave_shl:1
+}
+
+// Band b's first own group and its number of own groups (at most 62; uniform).
+__device__ __forceinline__ uint32_t band_first(const BandArgs& a, uint32_t band) {
+    return (uint32_t)((uint64_t)band * a.groups / a.bands);
+}
+__device__ __forceinline__ uint32_t band_width(const BandArgs& a, uint32_t band) {
+    return (uint32_t)((uint64_t)(band + 1) * a.groups / a.bands) - band_first(a, band);
+}
+
+template <bool OBS, bool UP>
+__device__ __forceinline__ void fused2b_strip(const BandArgs& a, uint32_t band, uint32_t strip, uint4* stage,
+                                              uint32_t lane, Counts& ct, Counts& ct1) {
+    const uint32_t G = a.groups, L = a.L, R = a.rows;
+    const TieQueue q{reinterpret_cast<uint32_t*>(stage), stage + 256};
+    const uint32_t b0 = band_first(a, band), n_own = band_width(a, band);
+    // b0 + G - 1 + lane < 3G since G >= 64
+    uint32_t g = b0 + G - 1u + lane;
+    g = g >= G ? g - G : g;
+    g = g >= G ? g - G : g;
+    // the row group of the band group lane / 4 (the lane's coalesced chunks are in band groups
+    // lane / 4 + 16 k; those in band groups 1 .. n_own are stored)
+    uint32_t gbase = b0 + G - 1u + (lane >> 2);
+    gbase = gbase >= G ? gbase - G : gbase;
+    gbase = gbase >= G ? gbase - G : gbase;
+    const uint32_t r0 = strip * R;
+    auto vrow = [&](uint32_t k) {
+        const uint32_t kk = k < R + 7 ? k : R + 7;
+        uint32_t v = UP ? r0 + R + 3 + L - kk : r0 + L - 4 + kk;  // in [L - 4, 2L + 4) since R <= L
+        v = v >= L ? v - L : v;
+        return v >= L ? v - L : v;
+    };
+    auto fetch = [&](Row& raw, uint32_t r) { load_row_chunks(raw, a.src + (size_t)r * L, gbase, G, lane); };
+    auto own = [&](const Row& raw) {
+        Row row;
+        regroup_to_owner(row, raw, stage, lane);
+        return row_bits(row);
+    };
+    auto put = [&](uint32_t r, const RowBits& b) {
+        Row row;
+        bits_to_row(row, b);
+        store_row_chunks(a.dst + (size_t)r * L, row, stage, lane, gbase, G, n_own, a.nt_store);
+    };
+    constexpr int OA = UP ? 1 : 0, OB = 1 - OA;
+    const uint32_t t = a.t, k0 = a.key0, k1 = a.key1;
+    Row raw;
+    fetch(raw, vrow(0));
+    RowBits w7{0u, 0u}, w6{0u, 0u}, w5{0u, 0u}, w4{0u, 0u}, w3{0u, 0u}, w2{0u, 0u};
+    RowBits w1 = own(raw);
+    fetch(raw, vrow(1));
+    RowBits w0 = own(raw);
+    fetch(raw, vrow(2));
+    RowBits nx = own(raw);
+    fetch(raw, vrow(3));
+    uint32_t e = edge_word4(w0, w2, w4, w6);
+#define ISING_FUSED2B_STEP(O, S)                                                                             \
+    do {                                                                                                     \
+        const uint32_t s_ = (S);                                                                             \
+        const uint32_t act = (s_ <= R + 5 ? 1u : 0u) | (s_ >= 3 && s_ <= R + 6 ? 2u : 0u) |                 \
+                             (s_ >= 6 && s_ <= R + 7 ? 4u : 0u) | (s_ >= 9 && s_ <= R + 8 ? 8u : 0u);        \
+        const uint32_t rw[4] = {vrow(s_ + 1), s_ >= 1 ? vrow(s_ - 1) : 0u, s_ >= 3 ? vrow(s_ - 3) : 0u,      \
+                                s_ >= 5 ? vrow(s_ - 5) : 0u};                                                \
+        fused2q_step<O, OBS>(w0, w2, w4, w6, nx, w1, w3, w5, w7, from_left_lane(e), from_right_lane(e), a.th,  \
+                             g, rw, act, t, k0, k1, q, lane, ct, ct1, s_ >= 5 && s_ <= R + 4);                \
+        if (act & 8u) put(rw[3], w6);                                                                        \
+        w7 = w6; w6 = w5; w5 = w4; w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = nx;                              \
+        e = edge_word4(w0, w2, w4, w6);                                                                      \
+        nx = own(raw);  /* walk row s + 3 */                                                                 \
+        fetch(raw, vrow(s_ + 4));                                                                            \
+    } while (0)
+#pragma unroll 1
+    for (uint32_t s = 0; s < R + 10; s += 2) {  // step R + 9 makes no update
+        ISING_FUSED2B_STEP(OA, s);
+        ISING_FUSED2B_STEP(OB, s + 1);
+    }
+#undef ISING_FUSED2B_STEP
+}
+
+// One wave per (band, strip) unit; units are numbered band-fastest within a strip, and the XCD
+// renumbering hands each XCD a contiguous range of them (vertically adjacent strips share rows).
+template <bool OBS>
+__global__ __launch_bounds__(256, 4) void k_sweep_fused2b(BandArgs a) {
+    extern __shared__ uint4 band_lds[];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t unit = logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * (blockDim.x >> 6) + wave;
+    uint4* const stage = band_lds + wave * (kTieQueueBytes / 16u);
+    Counts ct{0u, 0u}, ct1{0u, 0u};
+    const bool live = unit < a.units;  // uniform per wave
+    const uint32_t band = live ? unit % a.bands : 0u, strip = live ? unit / a.bands : 0u;
+    if (live) {
+        if (a.alternate && (strip & 1u)) fused2b_strip<OBS, true>(a, band, strip, stage, lane, ct, ct1);
+        else fused2b_strip<OBS, false>(a, band, strip, stage, lane, ct, ct1);
+    }
+    if (OBS) {
+        const bool own = live && lane >= 1u && lane <= band_width(a, band);
+        block_accumulate(a.obs, own ? ct.anti : 0u, own ? ct.neg : 0u, own ? 1u : 0u, 64u * a.rows);
+        __syncthreads();  // block_accumulate's LDS is reused
+        block_accumulate(a.obs + 2, own ? ct1.anti : 0u, own ? ct1.neg : 0u, own ? 1u : 0u, 64u * a.rows);
+    }
+}
+
 // ---- One sweep per pass with the ties of a step settled together: the one-sweep walk with two
 // rows between its updates.  Step s updates the white sites of walk row s + 1 and the black sites
 // of walk row s - 1; neither reads what the other writes, so the two are independent and share
@@ -828,34 +976,43 @@ struct ObsArgs {
 __global__ __launch_bounds__(256) void k_observables_int8(ObsArgs a) {
     const uint32_t lane_id = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = lane_id < a.n_lanes;
-    uint32_t anti = 0, neg = 0;
+    uint32_t anti = 0, neg = 0, units = 0;
     if (active) {
         const uint32_t g = lane_id % a.groups;
         const uint32_t strip = lane_id / a.groups;
         const uint32_t L = a.L;
         const uint32_t gr = g + 1 == a.groups ? 0 : g + 1;
+        // a half group (the last 32 columns of a row whose length is an odd multiple of 32) has 8
+        // dwords; its right neighbour is column 0 of the row
+        const bool half = (L & 63u) != 0 && gr == 0;
+        const uint32_t nd = half ? 8u : 16u;
+        units = half ? 1u : 2u;
         const int8_t* col = a.spins + (size_t)g * 64u;
         Row cur, dn;
         uint32_t r = strip * a.rows;
-        load_row(cur, col + (size_t)r * L);
+        if (half) load_row_half(cur, col + (size_t)r * L);
+        else load_row(cur, col + (size_t)r * L);
 #pragma unroll 1
         for (uint32_t s = 0; s < a.rows; ++s, ++r) {
             const uint32_t rd = r + 1 == L ? 0 : r + 1;
-            load_row(dn, col + (size_t)rd * L);
+            if (half) load_row_half(dn, col + (size_t)rd * L);
+            else load_row(dn, col + (size_t)rd * L);
             const uint32_t right = *reinterpret_cast<const uint32_t*>(a.spins + (size_t)r * L + (size_t)gr * 64u);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const uint32_t nb = k < 15 ? cur.d[k + 1] : right;
-                const uint32_t rn = __builtin_amdgcn_alignbyte(nb, cur.d[k], 1);  // right neighbours
-                neg += __builtin_popcount(cur.d[k] & 0x80808080u);
-                anti += __builtin_popcount((cur.d[k] ^ rn) & 0x80808080u);
-                anti += __builtin_popcount((cur.d[k] ^ dn.d[k]) & 0x80808080u);
+            for (uint32_t k = 0; k < 16; ++k) {
+                if (k < nd) {
+                    const uint32_t nb = k + 1 < nd ? cur.d[(k + 1) & 15u] : right;
+                    const uint32_t rn = __builtin_amdgcn_alignbyte(nb, cur.d[k], 1);  // right neighbours
+                    neg += __builtin_popcount(cur.d[k] & 0x80808080u);
+                    anti += __builtin_popcount((cur.d[k] ^ rn) & 0x80808080u);
+                    anti += __builtin_popcount((cur.d[k] ^ dn.d[k]) & 0x80808080u);
+                }
             }
             cur = dn;
         }
     }
-    // every site contributes 2 bonds; block_accumulate converts counts to (M, E)
-    block_accumulate(a.out, anti, neg, active ? 1u : 0u, 64u * a.rows);
+    // every site contributes 2 bonds; block_accumulate converts counts to (M, E) (sites in units of 32)
+    block_accumulate(a.out, anti, neg, units, 32u * a.rows);
 }
 
 __global__ void k_zero_n(int64_t* p, int64_t n) {
@@ -872,16 +1029,18 @@ __device__ __forceinline__ uint32_t nibble_to_bytes(uint32_t nib) {
     return 0x01010101u | (t * 0xFEu);                         // 0x01 for +1, 0xFF for -1
 }
 
+// A grid-stride loop over (row, 128-column chunk): a dispatch holds fewer than 2^32 work-items.
 __global__ __launch_bounds__(256) void k_init_int8(int8_t* spins, uint32_t L, uint32_t chunks,
                                                    uint64_t n_lanes, uint32_t key0, uint32_t key1) {
-    const uint64_t lane_id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (lane_id >= n_lanes) return;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t lane_id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; lane_id < n_lanes; lane_id += stride) {
     const uint32_t cb = (uint32_t)(lane_id % chunks);
     const uint32_t r = (uint32_t)(lane_id / chunks);
     const Words4 w = philox4x32_10(cb, r, 0u, 0x80000000u, key0, key1);
     const uint32_t words[4] = {w.w0, w.w1, w.w2, w.w3};
     int8_t* p = spins + (size_t)r * L + (size_t)cb * 128u;
-    const uint32_t n_words = (cb * 128u + 128u <= L) ? 4u : 2u;  // L % 64 == 0
+    const uint32_t left = L - cb * 128u;                              // columns from this chunk on
+    const uint32_t n_words = left >= 128u ? 4u : left / 32u;          // L % 32 == 0
     for (uint32_t i = 0; i < n_words; ++i) {
         uint4* v = reinterpret_cast<uint4*>(p + 32u * i);
         const uint32_t x = words[i];
@@ -889,6 +1048,7 @@ __global__ __launch_bounds__(256) void k_init_int8(int8_t* spins, uint32_t L, ui
                           nibble_to_bytes((x >> 8) & 15u), nibble_to_bytes((x >> 12) & 15u));
         v[1] = make_uint4(nibble_to_bytes((x >> 16) & 15u), nibble_to_bytes((x >> 20) & 15u),
                           nibble_to_bytes((x >> 24) & 15u), nibble_to_bytes(x >> 28));
+    }
     }
 }
 
@@ -916,7 +1076,7 @@ struct PackedArgs {
 // down it.  Vertical neighbours of row r's colour-Q sites are the other plane's words of rows
 // r +- 1 (same group); horizontal ones are the other plane's word of row r and its shift by one
 // site, whose edge bit comes from the adjacent group's word.
-template <int Q, bool OBS>
+template <int Q, bool OBS, bool HALF = false>
 __global__ __launch_bounds__(256) void k_sweep_packed(PackedArgs a) {
     const uint32_t lane_id = logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * blockDim.x + threadIdx.x;
     if (a.zero_slot && lane_id == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
@@ -928,6 +1088,9 @@ __global__ __launch_bounds__(256) void k_sweep_packed(PackedArgs a) {
         const uint32_t r0 = (lane_id / W) * R;
         const uint32_t gl = g == 0 ? W - 1 : g - 1;
         const uint32_t gr = g + 1 == W ? 0 : g + 1;
+        // HALF: the last word of each row holds a half group (sites 0 .. 15)
+        const bool half = HALF && gr == 0, left_half = HALF && gl + 1 == W;
+        const uint32_t valid = half ? kHalfSites : 0xFFFFFFFFu;
         uint32_t* const pq = a.planes + (size_t)Q * L * W;        // sites being updated
         const uint32_t* const po = a.planes + (size_t)(1 - Q) * L * W;  // other colour
         auto wrapr = [&](uint32_t r) { return r >= L ? r - L : r; };
@@ -947,18 +1110,22 @@ __global__ __launch_bounds__(256) void k_sweep_packed(PackedArgs a) {
             // parity 1 (Q = 1 on even rows): right neighbour is site j + 1 -> shift_next with the
             // next group's site 0 (bit 0); parity 0: left neighbour j - 1 -> shift_prev with the
             // previous group's site 31 (bit 31)
-            const uint32_t hs0 = Q == 1 ? shift_next(bcur, e0 & 1u) : shift_prev(bcur, e0 >> 31);
-            uint32_t F = decide<Q, OBS>(acur, bprev, bn, bcur, hs0, bcur, a.th, g, r, a.t, a.key0, a.key1, cnt);
+            const uint32_t hs0 = Q == 1 ? (half ? shift_next_half(bcur, e0 & 1u) : shift_next(bcur, e0 & 1u))
+                                        : shift_prev(bcur, last_site_bit(e0, left_half));
+            uint32_t F = decide<Q, OBS>(acur, bprev, bn, bcur, hs0, bcur, a.th, g, r, a.t, a.key0, a.key1, cnt, valid);
             pq[(size_t)r * W + g] = acur ^ F;
-            const uint32_t hs1 = Q == 1 ? shift_prev(bn, e1 >> 31) : shift_next(bn, e1 & 1u);
-            F = decide<Q, OBS>(a1, bcur, bn2, bn, hs1, bn, a.th, g, r1, a.t, a.key0, a.key1, cnt);
+            const uint32_t hs1 = Q == 1 ? shift_prev(bn, last_site_bit(e1, left_half))
+                                        : (half ? shift_next_half(bn, e1 & 1u) : shift_next(bn, e1 & 1u));
+            F = decide<Q, OBS>(a1, bcur, bn2, bn, hs1, bn, a.th, g, r1, a.t, a.key0, a.key1, cnt, valid);
             pq[(size_t)r1 * W + g] = a1 ^ F;
             bprev = bn;
             bcur = bn2;
             acur = a2;
         }
     }
-    if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, active ? 1u : 0u, 64u * a.rows);
+    // sites in units of 32: a lane covers two per row, one in a half group
+    const uint32_t units = !active ? 0u : (HALF && lane_id % a.groups + 1 == a.groups) ? 1u : 2u;
+    if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, units, 32u * a.rows);
 }
 
 // Half-sweep on the packed layout with the ties of four rows settled together.  All colour-Q sites
@@ -966,7 +1133,7 @@ __global__ __launch_bounds__(256) void k_sweep_packed(PackedArgs a) {
 // the first two Philox blocks of each row's word, queues the words still holding tied sites and
 // settles them with the other lanes' (as in the two-sweep pass).  Same uniforms and results as
 // k_sweep_packed.  rows % 4 == 0; lanes past n_lanes shadow the last lane without storing.
-template <int Q, bool OBS>
+template <int Q, bool OBS, bool HALF = false>
 __global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
     extern __shared__ uint4 packed_lds[];
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
@@ -982,6 +1149,9 @@ __global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
     const uint32_t r0 = (lane_id / W) * R;
     const uint32_t gl = g == 0 ? W - 1 : g - 1;
     const uint32_t gr = g + 1 == W ? 0 : g + 1;
+    // HALF: the last word of each row holds a half group (sites 0 .. 15)
+    const bool half = HALF && gr == 0, left_half = HALF && gl + 1 == W;
+    const uint32_t valid = half ? kHalfSites : 0xFFFFFFFFu;
     uint32_t* const pq = a.planes + (size_t)Q * L * W;              // sites being updated
     const uint32_t* const po = a.planes + (size_t)(1 - Q) * L * W;  // other colour
     // row r + i (r even): colour-Q sites at column parity Q for even i, 1 - Q for odd i; parity 1
@@ -1009,12 +1179,13 @@ __global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
         for (int i = 0; i < 4; ++i) {
             const bool right = (Q == 1) == ((i & 1) == 0);
             const uint32_t side = b[i + 1];
-            const uint32_t hs = right ? shift_next(side, e[i] & 1u) : shift_prev(side, e[i] >> 31);
+            const uint32_t hs = right ? (half ? shift_next_half(side, e[i] & 1u) : shift_next(side, e[i] & 1u))
+                                      : shift_prev(side, last_site_bit(e[i], left_half));
             const uint32_t x1 = w[i] ^ b[i], x2 = w[i] ^ b[i + 2], x3 = w[i] ^ side, x4 = w[i] ^ hs;
             const uint32_t o12 = x1 | x2, o34 = x3 | x4;
-            const uint32_t ge2 = (x1 & x2) | (x3 & x4) | (o12 & o34);
+            const uint32_t ge2 = ((x1 & x2) | (x3 & x4) | (o12 & o34)) & valid;
             const uint32_t any = o12 | o34;
-            uint32_t sel2 = any & ~ge2, sel4 = ~any;
+            uint32_t sel2 = any & ~ge2 & valid, sel4 = ~any & valid;
             uint32_t acc = ge2;
             if (a.th.full2) { acc |= sel2; sel2 = 0u; }
             if (a.th.full4) { acc |= sel4; sel4 = 0u; }
@@ -1040,64 +1211,90 @@ __global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
             if (OBS) {
                 const bool right = (Q == 1) == ((i & 1) == 0);
                 const uint32_t side = b[i + 1];
-                const uint32_t hs = right ? shift_next(side, e[i] & 1u) : shift_prev(side, e[i] >> 31);
-                cnt.anti += __builtin_popcount(w[i] ^ b[i]) + __builtin_popcount(w[i] ^ b[i + 2]) +
-                            __builtin_popcount(w[i] ^ side) + __builtin_popcount(w[i] ^ hs);
-                cnt.neg += __builtin_popcount(w[i]) + __builtin_popcount(side);
+                const uint32_t hs = right ? (half ? shift_next_half(side, e[i] & 1u) : shift_next(side, e[i] & 1u))
+                                          : shift_prev(side, last_site_bit(e[i], left_half));
+                cnt.anti += __builtin_popcount((w[i] ^ b[i]) & valid) + __builtin_popcount((w[i] ^ b[i + 2]) & valid) +
+                            __builtin_popcount((w[i] ^ side) & valid) + __builtin_popcount((w[i] ^ hs) & valid);
+                cnt.neg += __builtin_popcount(w[i] & valid) + __builtin_popcount(side & valid);
             }
         }
         bprev = b[4];
         bcur = b[5];
     }
-    if (OBS) block_accumulate(a.obs, active ? cnt.anti : 0u, active ? cnt.neg : 0u, active ? 1u : 0u, 64u * a.rows);
+    // sites in units of 32: a lane covers two per row, one in a half group
+    const uint32_t units = !active ? 0u : half ? 1u : 2u;
+    if (OBS) block_accumulate(a.obs, active ? cnt.anti : 0u, active ? cnt.neg : 0u, units, 32u * a.rows);
 }
 
 // (M, E) of a packed lattice: every bond has exactly one black (q = 0) end, so the black sites'
-// anti-aligned neighbour counts cover all 2 L^2 bonds once.
+// anti-aligned neighbour counts cover all 2 L^2 bonds once.  A grid-stride loop over (row, group)
+// words: a bounded grid keeps the final atomics few at any L.
 __global__ __launch_bounds__(256) void k_observables_packed(const uint32_t* planes, uint32_t L, uint32_t groups,
-                                                            uint32_t n_lanes, int64_t* out) {
-    const uint32_t lane_id = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = lane_id < n_lanes;
-    uint32_t anti = 0, neg = 0;
-    if (active) {
+                                                            uint64_t n_lanes, int64_t* out) {
+    uint32_t anti = 0, neg = 0, words = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t lane_id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; lane_id < n_lanes; lane_id += stride) {
         const uint32_t W = groups;
-        const uint32_t g = lane_id % W, r = lane_id / W;
+        const uint32_t g = (uint32_t)(lane_id % W), r = (uint32_t)(lane_id / W);
         const uint32_t gl = g == 0 ? W - 1 : g - 1, gr = g + 1 == W ? 0 : g + 1;
+        // a half group (16 sites) ends each row when L is an odd multiple of 32
+        const bool odd32 = (L & 63u) != 0, half = odd32 && gr == 0, left_half = odd32 && gl + 1 == W;
+        const uint32_t valid = half ? kHalfSites : 0xFFFFFFFFu;
         const uint32_t* p0 = planes;
         const uint32_t* p1 = planes + (size_t)L * W;
         const uint32_t up = r == 0 ? L - 1 : r - 1, dn = r + 1 == L ? 0 : r + 1;
         const uint32_t b = p0[(size_t)r * W + g];
         const uint32_t w = p1[(size_t)r * W + g];
         // black sites of row r sit at column parity r & 1
-        const uint32_t hs = (r & 1u) ? shift_next(w, p1[(size_t)r * W + gr] & 1u)
-                                     : shift_prev(w, p1[(size_t)r * W + gl] >> 31);
-        anti = __builtin_popcount(b ^ p1[(size_t)up * W + g]) + __builtin_popcount(b ^ p1[(size_t)dn * W + g]) +
-               __builtin_popcount(b ^ w) + __builtin_popcount(b ^ hs);
-        neg = __builtin_popcount(b) + __builtin_popcount(w);
+        const uint32_t right0 = p1[(size_t)r * W + gr] & 1u;
+        const uint32_t hs = (r & 1u) ? (half ? shift_next_half(w, right0) : shift_next(w, right0))
+                                     : shift_prev(w, last_site_bit(p1[(size_t)r * W + gl], left_half));
+        anti += __builtin_popcount((b ^ p1[(size_t)up * W + g]) & valid) +
+                __builtin_popcount((b ^ p1[(size_t)dn * W + g]) & valid) + __builtin_popcount((b ^ w) & valid) +
+                __builtin_popcount((b ^ hs) & valid);
+        neg += __builtin_popcount(b & valid) + __builtin_popcount(w & valid);
+        words += half ? 1u : 2u;
     }
-    block_accumulate(out, anti, neg, active ? 1u : 0u, 64u);
+    // `words` counts 32-site units (two per word, one per half word).  With the grid capped at 16384
+    // blocks of 256 threads a thread takes at most 2^12 words (L = 2^20), so its counts stay below 2^19
+    // and a wave's below 2^25 (32-bit sums)
+    block_accumulate(out, anti, neg, words, 32u);
 }
 
 // int8 -> packed: lane per (row, group)
 __global__ __launch_bounds__(256) void k_pack(const int8_t* spins, uint32_t* planes, uint32_t L, uint32_t groups,
-                                              uint32_t n_lanes) {
-    const uint32_t lane_id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (lane_id >= n_lanes) return;
-    const uint32_t g = lane_id % groups, r = lane_id / groups;
+                                              uint64_t n_lanes) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t lane_id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; lane_id < n_lanes; lane_id += stride) {
+    const uint32_t g = (uint32_t)(lane_id % groups), r = (uint32_t)(lane_id / groups);
+    // the last group of a row whose length is an odd multiple of 32 is a half group (sites 0 .. 15);
+    // its other bits are kept zero
+    const bool half = (L & 63u) != 0 && g + 1 == groups;
     Row row;
-    load_row(row, spins + (size_t)r * L + (size_t)g * 64u);
-    const uint32_t even = site_bits<0>(row), odd = site_bits<1>(row);
+    if (half) load_row_half(row, spins + (size_t)r * L + (size_t)g * 64u);
+    else load_row(row, spins + (size_t)r * L + (size_t)g * 64u);
+    const uint32_t valid = half ? kHalfSites : 0xFFFFFFFFu;
+    const uint32_t even = site_bits<0>(row) & valid, odd = site_bits<1>(row) & valid;
     // colour q of row r sits at column parity (r + q) & 1
     planes[(size_t)r * groups + g] = (r & 1u) ? odd : even;                          // q = 0
     planes[((size_t)L + r) * groups + g] = (r & 1u) ? even : odd;                    // q = 1
+    }
+}
+
+// cold start in the packed layout: every word `word`, masked to its sites in a half group
+__global__ __launch_bounds__(256) void k_fill_packed(uint32_t* planes, uint64_t n, uint32_t groups, uint32_t half,
+                                                     uint32_t word) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        planes[i] = half && i % groups + 1 == groups ? word & kHalfSites : word;
 }
 
 // packed -> int8
 __global__ __launch_bounds__(256) void k_unpack(const uint32_t* planes, int8_t* spins, uint32_t L, uint32_t groups,
-                                                uint32_t n_lanes) {
-    const uint32_t lane_id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (lane_id >= n_lanes) return;
-    const uint32_t g = lane_id % groups, r = lane_id / groups;
+                                                uint64_t n_lanes) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t lane_id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; lane_id < n_lanes; lane_id += stride) {
+    const uint32_t g = (uint32_t)(lane_id % groups), r = (uint32_t)(lane_id / groups);
     const uint32_t q0 = planes[(size_t)r * groups + g], q1 = planes[((size_t)L + r) * groups + g];
     const uint32_t even = (r & 1u) ? q1 : q0, odd = (r & 1u) ? q0 : q1;
     Row row;
@@ -1112,15 +1309,17 @@ __global__ __launch_bounds__(256) void k_unpack(const uint32_t* planes, int8_t* 
             row.d[2 * k + h] = perm(odd << sh, even << sh, 0x0B090A08u) | 0x01010101u;
         }
     }
-    store_row(spins + (size_t)r * L + (size_t)g * 64u, row, false);
+    if ((L & 63u) != 0 && g + 1 == groups) store_row_half(spins + (size_t)r * L + (size_t)g * 64u, row);
+    else store_row(spins + (size_t)r * L + (size_t)g * 64u, row, false);
+    }
 }
 
 // packed hot start: the int8 hot start's bits for one group, regrouped by colour
-__global__ __launch_bounds__(256) void k_init_packed(uint32_t* planes, uint32_t L, uint32_t groups, uint32_t n_lanes,
+__global__ __launch_bounds__(256) void k_init_packed(uint32_t* planes, uint32_t L, uint32_t groups, uint64_t n_lanes,
                                                      uint32_t key0, uint32_t key1) {
-    const uint32_t lane_id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (lane_id >= n_lanes) return;
-    const uint32_t g = lane_id % groups, r = lane_id / groups;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t lane_id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; lane_id < n_lanes; lane_id += stride) {
+    const uint32_t g = (uint32_t)(lane_id % groups), r = (uint32_t)(lane_id / groups);
     const Words4 w = philox4x32_10(g >> 1, r, 0u, 0x80000000u, key0, key1);
     const uint32_t lo = (g & 1u) ? w.w2 : w.w0, hi = (g & 1u) ? w.w3 : w.w1;  // columns 0-31, 32-63
     Row row;
@@ -1129,9 +1328,11 @@ __global__ __launch_bounds__(256) void k_init_packed(uint32_t* planes, uint32_t 
         const uint32_t src = d < 8 ? lo : hi;
         row.d[d] = nibble_to_bytes((src >> (4 * (d & 7))) & 15u);
     }
-    const uint32_t even = site_bits<0>(row), odd = site_bits<1>(row);
+    const uint32_t valid = (L & 63u) != 0 && g + 1 == groups ? kHalfSites : 0xFFFFFFFFu;  // half group
+    const uint32_t even = site_bits<0>(row) & valid, odd = site_bits<1>(row) & valid;
     planes[(size_t)r * groups + g] = (r & 1u) ? odd : even;
     planes[((size_t)L + r) * groups + g] = (r & 1u) ? even : odd;
+    }
 }
 
 // ==========================================================================================
@@ -1366,10 +1567,10 @@ __device__ __forceinline__ bool batch_exchange(uint32_t* lds, const BatchUnit* u
 
 // FP64 moment sums of one sample, each operation rounded as written (no fused multiply-add), so
 // the sums equal a plain sequential evaluation in the same order.
-__device__ __forceinline__ void accumulate_moments(int64_t M, int64_t E, double inv, double& s_abs, double& s_m2,
+__device__ __forceinline__ void accumulate_moments(int64_t M, int64_t E, double n_sites, double& s_abs, double& s_m2,
                                                    double& s_m4, double& s_e, double& s_e2) {
 #pragma clang fp contract(off)
-    const double m = (double)M * inv, e = (double)E * inv, m2 = m * m;
+    const double m = (double)M / n_sites, e = (double)E / n_sites, m2 = m * m;
     s_abs += fabs(m);
     s_m2 += m2;
     s_m4 += m2 * m2;
@@ -1380,12 +1581,12 @@ __device__ __forceinline__ void accumulate_moments(int64_t M, int64_t E, double 
 __device__ __forceinline__ void store_moments(double* mo, uint32_t n, double s_abs, double s_m2, double s_m4,
                                               double s_e, double s_e2) {
 #pragma clang fp contract(off)
-    const double k = 1.0 / (double)n;
-    mo[0] = s_abs * k;
-    mo[1] = s_m2 * k;
-    mo[2] = s_m4 * k;
-    mo[3] = s_e * k;
-    mo[4] = s_e2 * k;
+    const double k = (double)n;
+    mo[0] = s_abs / k;
+    mo[1] = s_m2 / k;
+    mo[2] = s_m4 / k;
+    mo[3] = s_e / k;
+    mo[4] = s_e2 / k;
 }
 
 // start: 0 = hot start from the seed, 1 = cold start (all +1), 2 = continue from `state`,
@@ -1394,11 +1595,25 @@ __device__ __forceinline__ void store_moments(double* mo, uint32_t n, double s_a
 // `depth`: colour updates between exchanges when the list has split units (0 when none does).  A
 // split replica's (M, E) of a measurement sweep is the sum of its slabs' counts, combined by its
 // slab 0 `lag` sweeps later (or at the end); a run in which a wait gave up leaves NaN moments.
+// Per-call values of a batch run.  k_batch reads them from the workspace, so that one captured graph
+// serves every call with the same plan; k_batch_set_run writes them on the caller's stream first.
+struct BatchRun {
+    uint32_t start, n_therm, n_meas, pad;
+    int64_t* trace;    // (M, E) of every measurement sweep, replica-major, or NULL
+    double* moments;   // FP64 moments per replica, or NULL
+};
+
+__global__ void k_batch_set_run(BatchRun* run, BatchRun v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *run = v;
+}
+
 __global__ __launch_bounds__(1024) void k_batch(const BatchReplica* table, const BatchGroup* groups,
                                                 const BatchUnit* units, uint32_t* state, uint64_t* exchange,
-                                                uint32_t depth, uint32_t start, uint32_t n_therm, uint32_t n_meas,
-                                                int64_t* trace, double* moments) {
+                                                uint32_t depth, const BatchRun* run) {
     extern __shared__ uint32_t lds[];
+    const uint32_t start = run->start, n_therm = run->n_therm, n_meas = run->n_meas;
+    int64_t* const trace = run->trace;
+    double* const moments = run->moments;
     __shared__ BatchUnit us[kMaxUnits];
     __shared__ BatchReplica rs[kMaxUnits];
     __shared__ uint32_t cnt[kMaxUnits][2];
@@ -1442,7 +1657,7 @@ __global__ __launch_bounds__(1024) void k_batch(const BatchReplica* table, const
             tr[0] = M;
             tr[1] = E;
         }
-        accumulate_moments(M, E, 1.0 / ((double)rp.L * (double)rp.L), acc[u][0], acc[u][1], acc[u][2], acc[u][3],
+        accumulate_moments(M, E, (double)rp.L * (double)rp.L, acc[u][0], acc[u][1], acc[u][2], acc[u][3],
                            acc[u][4]);
     };
     auto combine = [&](uint32_t u, uint32_t j) {
@@ -1535,12 +1750,12 @@ __global__ void k_batch_unpack(const BatchReplica* table, const uint32_t* state,
 // depend on scheduling: out = (<|m|>, <m^2>, <m^4>, <e>, <e^2>) with m = M / N, e = E / N.
 __global__ void k_moments(const int64_t* trace, int64_t n, int64_t n_sites, double* out) {
 #pragma clang fp contract(off)
-    // separate multiplies and adds (no fused multiply-add), each rounded as written
+    // separate divides, multiplies and adds (no fused multiply-add), each rounded as written
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double inv = 1.0 / (double)n_sites;
+    const double N = (double)n_sites;
     double s_abs = 0.0, s_m2 = 0.0, s_m4 = 0.0, s_e = 0.0, s_e2 = 0.0;
     for (int64_t i = 0; i < n; ++i) {
-        const double m = (double)trace[2 * i] * inv, e = (double)trace[2 * i + 1] * inv;
+        const double m = (double)trace[2 * i] / N, e = (double)trace[2 * i + 1] / N;
         const double m2 = m * m;
         s_abs += fabs(m);
         s_m2 += m2;
@@ -1548,12 +1763,12 @@ __global__ void k_moments(const int64_t* trace, int64_t n, int64_t n_sites, doub
         s_e += e;
         s_e2 += e * e;
     }
-    const double k = 1.0 / (double)n;
-    out[0] = s_abs * k;
-    out[1] = s_m2 * k;
-    out[2] = s_m4 * k;
-    out[3] = s_e * k;
-    out[4] = s_e2 * k;
+    const double k = (double)n;
+    out[0] = s_abs / k;
+    out[1] = s_m2 / k;
+    out[2] = s_m4 / k;
+    out[3] = s_e / k;
+    out[4] = s_e2 / k;
 }
 
 }  // namespace ising
@@ -1564,24 +1779,28 @@ namespace {
 
 thread_local std::string g_last_error;
 
-// Launch-shape options (ising_set_option).  Every valid setting gives bit-identical results.
+// Launch-shape options (ising_set_option).  Every valid setting gives bit-identical results.  Each
+// one is an atomic, so a setting made on one thread while another launches is race-free (the launch
+// sees the old or the new value, with the same results).
 struct Options {
-    int64_t rows_per_lane = 0;  // 0 = choose from L
-    int64_t xcd_remap = 1;
-    int64_t nt_store = 0;
-    int64_t staged = 1;
-    int64_t batch_threads = 0;  // 0 = autotune
-    int64_t batch_slab_sites = 0;  // batch: split replicas into slabs of at most this many sites;
+    std::atomic<int64_t> rows_per_lane = 0;  // 0 = choose from L
+    std::atomic<int64_t> xcd_remap = 1;
+    std::atomic<int64_t> nt_store = 0;
+    std::atomic<int64_t> staged = 1;
+    std::atomic<int64_t> batch_threads = 0;  // 0 = autotune
+    std::atomic<int64_t> batch_slab_sites = 0;  // batch: split replicas into slabs of at most this many sites;
                                    // 0 = autotune, -1 = never split
-    int64_t batch_depth = 0;       // batch: colour updates between exchanges of split replicas; 0 = autotune
-    int64_t batch_lists_per_cu = 0;  // batch: work lists per compute unit of a split schedule; 0 = autotune
-    int64_t fused_rows = 0;     // rows per strip of the fused sweep; 0 = choose from L
-    int64_t fused_alternate = 1;  // fused sweep: odd strips walk upwards
-    int64_t fused_sweeps = 2;     // fused sweep: sweeps per pass over the lattice (1 or 2)
-    int64_t fused_ties = 1;       // two-sweep pass: settle the ties of a step's four updates together
-    int64_t packed_ties = 1;      // packed half-sweep: settle the ties of four rows together
-    int64_t ties3 = 1;            // 3-D int8 half-sweep: two planes per exchange, ties settled together
-    int64_t planes3 = 0;          // 3-D sweep: planes per workgroup; 0 = choose from L
+    std::atomic<int64_t> batch_depth = 0;       // batch: colour updates between exchanges of split replicas; 0 = autotune
+    std::atomic<int64_t> batch_lists_per_cu = 0;  // batch: work lists per compute unit of a split schedule; 0 = autotune
+    std::atomic<int64_t> fused_rows = 0;     // rows per strip of the fused sweep; 0 = choose from L
+    std::atomic<int64_t> fused_alternate = 1;  // fused sweep: odd strips walk upwards
+    std::atomic<int64_t> fused_sweeps = 2;     // fused sweep: sweeps per pass over the lattice (1 or 2)
+    std::atomic<int64_t> fused_ties = 1;       // two-sweep pass: settle the ties of a step's four updates together
+    std::atomic<int64_t> fused_bands = 0;      // two-sweep pass in column bands of one wave: 0 = above L = 65536, 1 = always
+    std::atomic<int64_t> band_rows = 0;        // rows per strip of the band pass; 0 = choose from L
+    std::atomic<int64_t> packed_ties = 1;      // packed half-sweep: settle the ties of four rows together
+    std::atomic<int64_t> ties3 = 1;            // 3-D int8 half-sweep: two planes per exchange, ties settled together
+    std::atomic<int64_t> planes3 = 0;          // 3-D sweep: planes per workgroup; 0 = choose from L
 };
 Options g_opt;
 
@@ -1595,9 +1814,14 @@ int check_launch(const char* what) {
     return e == hipSuccess ? ISING_OK : hip_failed(e, what);
 }
 
-bool valid_L(int64_t L) { return L >= 64 && L % 64 == 0 && L <= (int64_t(1) << 20); }
+// square lattices: L a multiple of 32 (an odd multiple ends every row in a half group), 32 .. 2^20
+bool valid_L(int64_t L) { return L >= 32 && L % 32 == 0 && L <= (int64_t(1) << 20); }
 
 bool valid_beta(double beta) { return !std::isnan(beta) && beta >= 0.0; }
+
+// Blocks of 256 threads for a grid-stride loop over n items: a dispatch holds fewer than 2^32
+// work-items, and a million threads keep every compute unit busy.
+unsigned grid_blocks(uint64_t n) { return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 4096)); }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
@@ -1675,13 +1899,17 @@ ising::Thresholds make_thresholds(double beta, int fmt = 0) {
     return th;
 }
 
-// rows per lane for the streaming kernels: even, divides L (L % 64 == 0)
+// Column groups of a row: 64 columns each, the last one a half group of 32 when L is an odd multiple
+// of 32.
+uint32_t groups_of(int64_t L) { return (uint32_t)((L + 63) / 64); }
+
+// rows per lane for the streaming kernels: even, divides L (L % 32 == 0)
 uint32_t rows_per_lane(int64_t L) {
     if (g_opt.rows_per_lane > 0 && L % g_opt.rows_per_lane == 0) return (uint32_t)g_opt.rows_per_lane;
-    const uint32_t groups = (uint32_t)(L / 64);
+    const uint32_t groups = groups_of(L);
     // tall strips re-read fewer boundary rows; keep at least ~1024 workgroups' worth of lanes
     uint32_t R = 32;
-    while (R > 2 && (uint64_t)groups * (uint64_t)(L / R) < 1024ull * 256ull) R >>= 1;
+    while (R > 2 && ((uint64_t)groups * (uint64_t)(L / R) < 1024ull * 256ull || L % R != 0)) R >>= 1;
     return R;
 }
 
@@ -1690,7 +1918,7 @@ int launch_half_sweep(int8_t* spins, int64_t L, const ising::Thresholds& th, uin
     ising::SweepArgs a;
     a.spins = spins;
     a.L = (uint32_t)L;
-    a.groups = (uint32_t)(L / 64);
+    a.groups = groups_of(L);
     a.rows = rows_per_lane(L);
     a.n_lanes = a.groups * (uint32_t)(L / a.rows);
     a.t = t;
@@ -1702,16 +1930,20 @@ int launch_half_sweep(int8_t* spins, int64_t L, const ising::Thresholds& th, uin
     a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
     a.nt_store = g_opt.nt_store ? 1u : 0u;
     const dim3 grid((a.n_lanes + 255u) / 256u), block(256);
-    // coalesced LDS-staged row I/O needs whole waves on 64 consecutive groups of one row
-    const bool staged = g_opt.staged && a.groups % 64u == 0;
-#define ISING_LAUNCH_SWEEP(QQ, OO, SS) \
-    hipLaunchKernelGGL((ising::k_sweep_int8<QQ, OO, SS>), grid, block, 0, stream, a)
-    if (q == 1) {
-        if (staged) { if (obs) ISING_LAUNCH_SWEEP(1, true, true); else ISING_LAUNCH_SWEEP(1, false, true); }
-        else { if (obs) ISING_LAUNCH_SWEEP(1, true, false); else ISING_LAUNCH_SWEEP(1, false, false); }
+    // coalesced LDS-staged row I/O needs whole waves on 64 consecutive whole groups of one row
+    const bool half = L % 64 != 0;
+    const bool staged = g_opt.staged && a.groups % 64u == 0 && !half;
+#define ISING_LAUNCH_SWEEP(QQ, OO, SS, HH) \
+    hipLaunchKernelGGL((ising::k_sweep_int8<QQ, OO, SS, HH>), grid, block, 0, stream, a)
+    if (half) {
+        if (q == 1) { if (obs) ISING_LAUNCH_SWEEP(1, true, false, true); else ISING_LAUNCH_SWEEP(1, false, false, true); }
+        else { if (obs) ISING_LAUNCH_SWEEP(0, true, false, true); else ISING_LAUNCH_SWEEP(0, false, false, true); }
+    } else if (q == 1) {
+        if (staged) { if (obs) ISING_LAUNCH_SWEEP(1, true, true, false); else ISING_LAUNCH_SWEEP(1, false, true, false); }
+        else { if (obs) ISING_LAUNCH_SWEEP(1, true, false, false); else ISING_LAUNCH_SWEEP(1, false, false, false); }
     } else {
-        if (staged) { if (obs) ISING_LAUNCH_SWEEP(0, true, true); else ISING_LAUNCH_SWEEP(0, false, true); }
-        else { if (obs) ISING_LAUNCH_SWEEP(0, true, false); else ISING_LAUNCH_SWEEP(0, false, false); }
+        if (staged) { if (obs) ISING_LAUNCH_SWEEP(0, true, true, false); else ISING_LAUNCH_SWEEP(0, false, true, false); }
+        else { if (obs) ISING_LAUNCH_SWEEP(0, true, false, false); else ISING_LAUNCH_SWEEP(0, false, false, false); }
     }
 #undef ISING_LAUNCH_SWEEP
     return check_launch("k_sweep_int8");
@@ -1789,6 +2021,51 @@ int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::T
     return check_launch("k_sweep_fused");
 }
 
+// The two-sweep pass runs in column bands (k_sweep_fused2b) above kFusedMaxL, and with option
+// "fused_bands" from L = 4096 (a band's 64 lanes then take 64 distinct groups).
+bool use_bands(int64_t L) { return L > kFusedMaxL || (g_opt.fused_bands != 0 && L >= 4096); }
+
+// Bands per row: each owns at most 62 groups (its wave has one recomputed group on either side).
+uint32_t band_count(int64_t L) { return (uint32_t)((L / 64 + 61) / 62); }
+
+// Rows per strip of the band pass: even, divides L; the tallest up to 128 that still leaves 8192
+// waves (two rounds of four waves per SIMD), 8 at least.
+uint32_t band_rows(int64_t L) {
+    if (g_opt.band_rows > 0 && L % g_opt.band_rows == 0 && g_opt.band_rows <= L) return (uint32_t)g_opt.band_rows;
+    const uint64_t bands = band_count(L);
+    uint32_t R = 128;
+    while (R > 8 && ((uint64_t)(L / R) * bands < 8192ull || L % R != 0)) R >>= 1;
+    return R;
+}
+
+// One two-sweep pass in column bands: sweeps t, t + 1 from src to dst; obs: NULL or 4 int64, zeroed
+// beforehand.
+int launch_band_pass(const int8_t* src, int8_t* dst, int64_t L, const ising::Thresholds& th, uint64_t seed,
+                     uint32_t t, int64_t* obs, hipStream_t stream) {
+    ising::BandArgs a;
+    a.src = src;
+    a.dst = dst;
+    a.L = (uint32_t)L;
+    a.groups = (uint32_t)(L / 64);
+    a.rows = band_rows(L);
+    a.bands = band_count(L);
+    a.units = a.bands * (a.L / a.rows);
+    a.t = t;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.th = th;
+    a.obs = obs;
+    a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
+    a.nt_store = g_opt.nt_store ? 1u : 0u;
+    a.alternate = g_opt.fused_alternate ? 1u : 0u;
+    constexpr uint32_t waves = 4;
+    const dim3 grid((a.units + waves - 1) / waves), block(64 * waves);
+    const size_t lds = waves * ising::kTieQueueBytes;
+    if (obs) hipLaunchKernelGGL((ising::k_sweep_fused2b<true>), grid, block, lds, stream, a);
+    else hipLaunchKernelGGL((ising::k_sweep_fused2b<false>), grid, block, lds, stream, a);
+    return check_launch("k_sweep_fused2b");
+}
+
 bool disjoint(const void* a, const void* b, uint64_t bytes) {
     const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
     return x + bytes <= y || y + bytes <= x;
@@ -1821,15 +2098,19 @@ uint32_t batch_W(int64_t L) { return L >= 64 ? (uint32_t)(L / 64) : 1u; }
 
 uint64_t batch_words(int64_t L) { return 2ull * (uint64_t)L * batch_W(L); }
 
-// Workspace: replica table | both colour planes of every replica | work lists | units |
-// exchange areas.
+// Workspace: replica table | per-call values | both colour planes of every replica | work lists |
+// units | exchange areas.
 struct BatchLayout {
-    size_t state, groups, units, exchange, total;
+    size_t params, state, groups, units, exchange, total;
 };
+
+size_t batch_params_offset(int64_t n) { return align_up((size_t)n * sizeof(ising::BatchReplica)); }
+size_t batch_state_offset(int64_t n) { return align_up(batch_params_offset(n) + sizeof(ising::BatchRun)); }
 
 BatchLayout batch_layout(const ising_replica_t* reps, int64_t n) {
     BatchLayout b{};
-    b.state = align_up((size_t)n * sizeof(ising::BatchReplica));
+    b.params = batch_params_offset(n);
+    b.state = batch_state_offset(n);
     uint64_t words = 0, xwords = 0;
     for (int64_t i = 0; i < n; ++i) {
         words += batch_words(reps[i].L);
@@ -1945,12 +2226,19 @@ BatchPlan plan_batch(const ising_replica_t* reps, int64_t n, int64_t target, uin
     return plan;
 }
 
-struct BatchGraph {
+// Captured batch runs, one per plan (workspace address, layout and schedule; the per-call values
+// live in the workspace), least recently used dropped first.  Guarded by g_batch_mu, which every
+// batch entry point holds for its whole call (the tuned schedules below too).
+struct BatchExec {
     hipGraphExec_t exec = nullptr;
-    hipStream_t capture = nullptr;
-    std::string key;
+    hipEvent_t done = nullptr;  // recorded after the exec's latest launch
+    uint64_t used = 0;
 };
-BatchGraph g_batch_graph;
+constexpr size_t kMaxBatchExecs = 8;
+std::map<std::string, BatchExec> g_batch_execs;
+hipStream_t g_batch_capture = nullptr;
+uint64_t g_batch_clock = 0;
+std::mutex g_batch_mu;
 
 struct BatchSchedule {
     int threads;
@@ -1989,6 +2277,7 @@ bool plan_fits(const BatchPlan& plan, int threads, int cus) {
 }
 
 struct BatchBuffers {
+    ising::BatchRun* run;
     const ising::BatchReplica* table;
     ising::BatchGroup* groups;
     ising::BatchUnit* units;
@@ -2009,16 +2298,22 @@ int upload_plan(const BatchBuffers& b, const BatchPlan& plan, hipStream_t stream
     return ISING_OK;
 }
 
+// The per-call values of a run, written into the workspace on `stream` ahead of the run.
+int set_batch_run(const BatchBuffers& b, uint32_t start, uint32_t n_therm, uint32_t n_meas, int64_t* trace,
+                  double* moments, hipStream_t stream) {
+    ising::BatchRun v{start, n_therm, n_meas, 0u, trace, moments};
+    hipLaunchKernelGGL(ising::k_batch_set_run, dim3(1), dim3(64), 0, stream, b.run, v);
+    return check_launch("k_batch_set_run");
+}
+
 // The exchange area is cleared by a kernel (tags start at 0 for every run), then the run.
-int launch_batch(const BatchBuffers& b, const BatchPlan& plan, int threads, uint32_t start, uint32_t n_therm,
-                 uint32_t n_meas, int64_t* trace, double* moments, hipStream_t stream) {
+int launch_batch(const BatchBuffers& b, const BatchPlan& plan, int threads, hipStream_t stream) {
     if (plan.depth > 0) {
         const int rc = zero_trace(reinterpret_cast<int64_t*>(b.exchange), b.exchange_words, stream);
         if (rc) return rc;
     }
     hipLaunchKernelGGL(ising::k_batch, dim3((unsigned)plan.groups.size()), dim3((unsigned)threads), plan.lds, stream,
-                       b.table, b.groups, b.units, b.state, b.exchange, plan.depth, start, n_therm, n_meas, trace,
-                       moments);
+                       b.table, b.groups, b.units, b.state, b.exchange, plan.depth, b.run);
     return check_launch("k_batch");
 }
 
@@ -2063,8 +2358,10 @@ int autotune_batch(const ising_replica_t* reps, int64_t n, const BatchBuffers& b
         rc = upload_plan(b, plan, stream);
         // the fastest of three 32-sweep runs, after one untimed run
         for (int rep = 0; rep < 4 && rc == ISING_OK; ++rep) {
+            rc = set_batch_run(b, start, 32u, 0u, nullptr, nullptr, stream);
+            if (rc) break;
             (void)hipEventRecord(e0, stream);
-            rc = launch_batch(b, plan, c.threads, start, 32u, 0u, nullptr, nullptr, stream);
+            rc = launch_batch(b, plan, c.threads, stream);
             (void)hipEventRecord(e1, stream);
             if (rc) break;
             e = hipEventSynchronize(e1);
@@ -2091,7 +2388,7 @@ int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Threshold
     ising::PackedArgs a;
     a.planes = planes;
     a.L = (uint32_t)L;
-    a.groups = (uint32_t)(L / 64);
+    a.groups = groups_of(L);
     a.rows = rows_per_lane(L);
     a.n_lanes = a.groups * (uint32_t)(L / a.rows);
     a.t = t;
@@ -2101,7 +2398,13 @@ int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Threshold
     a.obs = obs;
     a.zero_slot = zero_slot;
     a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
+    const bool half = L % 64 != 0;  // each row ends in a half group
     const dim3 grid((a.n_lanes + 255u) / 256u), block(256);
+#define ISING_LAUNCH_PACKED(K, QQ, OO, G, B, LDS)                                                  \
+    do {                                                                                           \
+        if (half) hipLaunchKernelGGL((ising::K<QQ, OO, true>), G, B, LDS, stream, a);              \
+        else hipLaunchKernelGGL((ising::K<QQ, OO, false>), G, B, LDS, stream, a);                  \
+    } while (0)
     if (g_opt.packed_ties && a.rows % 4u == 0) {
         // a counting launch ends every workgroup with atomics on the same two words: 512 threads
         // per workgroup halve them (the others keep 256, which leaves more waves per CU)
@@ -2109,21 +2412,22 @@ int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Threshold
         const dim3 qgrid((a.n_lanes + threads - 1u) / threads), qblock(threads);
         const size_t lds = (threads / 64u) * ising::kTieQueueBytes;
         if (q == 1) {
-            if (obs) hipLaunchKernelGGL((ising::k_sweep_packed_q<1, true>), qgrid, qblock, lds, stream, a);
-            else hipLaunchKernelGGL((ising::k_sweep_packed_q<1, false>), qgrid, qblock, lds, stream, a);
+            if (obs) ISING_LAUNCH_PACKED(k_sweep_packed_q, 1, true, qgrid, qblock, lds);
+            else ISING_LAUNCH_PACKED(k_sweep_packed_q, 1, false, qgrid, qblock, lds);
         } else {
-            if (obs) hipLaunchKernelGGL((ising::k_sweep_packed_q<0, true>), qgrid, qblock, lds, stream, a);
-            else hipLaunchKernelGGL((ising::k_sweep_packed_q<0, false>), qgrid, qblock, lds, stream, a);
+            if (obs) ISING_LAUNCH_PACKED(k_sweep_packed_q, 0, true, qgrid, qblock, lds);
+            else ISING_LAUNCH_PACKED(k_sweep_packed_q, 0, false, qgrid, qblock, lds);
         }
         return check_launch("k_sweep_packed_q");
     }
     if (q == 1) {
-        if (obs) hipLaunchKernelGGL((ising::k_sweep_packed<1, true>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((ising::k_sweep_packed<1, false>), grid, block, 0, stream, a);
+        if (obs) ISING_LAUNCH_PACKED(k_sweep_packed, 1, true, grid, block, 0);
+        else ISING_LAUNCH_PACKED(k_sweep_packed, 1, false, grid, block, 0);
     } else {
-        if (obs) hipLaunchKernelGGL((ising::k_sweep_packed<0, true>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((ising::k_sweep_packed<0, false>), grid, block, 0, stream, a);
+        if (obs) ISING_LAUNCH_PACKED(k_sweep_packed, 0, true, grid, block, 0);
+        else ISING_LAUNCH_PACKED(k_sweep_packed, 0, false, grid, block, 0);
     }
+#undef ISING_LAUNCH_PACKED
     return check_launch("k_sweep_packed");
 }
 }  // namespace
@@ -2166,7 +2470,7 @@ int ising_init(int8_t* spins, int64_t L, uint64_t seed, void* stream) {
     if (!spins || !valid_L(L) || !aligned16(spins)) return ISING_EINVAL;
     const uint32_t chunks = (uint32_t)((L + 127) / 128);
     const uint64_t n_lanes = (uint64_t)chunks * (uint64_t)L;
-    const dim3 grid((unsigned)((n_lanes + 255) / 256)), block(256);
+    const dim3 grid(grid_blocks(n_lanes)), block(256);
     hipLaunchKernelGGL(ising::k_init_int8, grid, block, 0, (hipStream_t)stream, spins, (uint32_t)L, chunks,
                        n_lanes, (uint32_t)seed, (uint32_t)(seed >> 32));
     return check_launch("k_init_int8");
@@ -2242,7 +2546,12 @@ int ising_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, in
         n_sweeps < 0 || fmt < 0 || fmt > 2 || sweep_offset > (uint64_t(1) << 32) ||
         (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset || !disjoint(spins, scratch, (uint64_t)L * (uint64_t)L))
         return ISING_EINVAL;
-    if (L > kFusedMaxL) return ising_sweep_fmt(spins, L, beta, fmt, n_sweeps, seed, sweep_offset, trace_ME, stream);
+    // the passes take whole 64-column groups: a row that ends in a half group sweeps in place
+    if (L % 64 != 0) return ising_sweep_fmt(spins, L, beta, fmt, n_sweeps, seed, sweep_offset, trace_ME, stream);
+    const bool bands = use_bands(L);
+    const bool single_passes = L <= kFusedMaxL;  // the one-sweep pass needs a whole row per workgroup
+    if (!single_passes && g_opt.fused_sweeps != 2)
+        return ising_sweep_fmt(spins, L, beta, fmt, n_sweeps, seed, sweep_offset, trace_ME, stream);
     const ising::Thresholds th = make_thresholds(beta, fmt);
     hipStream_t s = (hipStream_t)stream;
     int64_t i = 0;
@@ -2256,22 +2565,33 @@ int ising_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, in
         if (rc) return rc;
     }
     // The rest (an even count) in passes that alternate between the two buffers and end in
-    // `spins`: two sweeps per pass when the option allows, in an even number of passes (an odd
-    // number of two-sweep passes gives one of them up for two one-sweep passes).
+    // `spins`: two sweeps per pass when the option allows, in an even number of passes.  An odd
+    // number of two-sweep passes gives one of them up for two one-sweep passes, or, where there is no
+    // one-sweep pass (above L = 65536), for two sweeps in place at the end.
     const int64_t rest = n_sweeps - i;
     int64_t pairs = g_opt.fused_sweeps == 2 ? rest / 2 : 0;
     if (pairs & 1) --pairs;
     int8_t* bufs[2] = {spins, scratch};
     int64_t pass = 0;
     while (i < n_sweeps) {
-        const int k = pairs > 0 ? 2 : 1;
         const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
-        const int rc = launch_fused_sweep(bufs[pass & 1], bufs[(pass + 1) & 1], L, th, seed, t,
-                                          trace_ME ? trace_ME + 2 * i : nullptr, s, k);
+        int64_t* obs = trace_ME ? trace_ME + 2 * i : nullptr;
+        int rc;
+        if (pairs > 0) {
+            rc = bands ? launch_band_pass(bufs[pass & 1], bufs[(pass + 1) & 1], L, th, seed, t, obs, s)
+                       : launch_fused_sweep(bufs[pass & 1], bufs[(pass + 1) & 1], L, th, seed, t, obs, s, 2);
+            --pairs;
+            i += 2;
+            ++pass;
+        } else if (single_passes) {
+            rc = launch_fused_sweep(bufs[pass & 1], bufs[(pass + 1) & 1], L, th, seed, t, obs, s, 1);
+            i += 1;
+            ++pass;
+        } else {
+            rc = ising_sweep_fmt(spins, L, beta, fmt, n_sweeps - i, seed, t, obs, stream);
+            i = n_sweeps;
+        }
         if (rc) return rc;
-        if (k == 2) --pairs;
-        i += k;
-        ++pass;
     }
     return ISING_OK;
 }
@@ -2282,7 +2602,7 @@ int ising_sweep_fused_step(const int8_t* src, int8_t* dst, int64_t L, double bet
         fmt > 2 || t >= (uint64_t(1) << 32) || !disjoint(src, dst, (uint64_t)L * (uint64_t)L))
         return ISING_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    if (L > kFusedMaxL) {  // a copy, then the two half-sweeps in place on the copy
+    if (L > kFusedMaxL || L % 64 != 0) {  // a copy, then the two half-sweeps in place on the copy
         const hipError_t e = hipMemcpyAsync(dst, src, (size_t)L * (size_t)L, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_failed(e, "hipMemcpyAsync");
         return ising_sweep_fmt(dst, L, beta, fmt, 1, seed, t, out_ME, stream);
@@ -2300,7 +2620,7 @@ int ising_sweep_fused_pair(const int8_t* src, int8_t* dst, int64_t L, double bet
         fmt > 2 || t + 1 >= (uint64_t(1) << 32) || !disjoint(src, dst, (uint64_t)L * (uint64_t)L))
         return ISING_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    if (L > kFusedMaxL) {  // a copy, then two sweeps in place on the copy
+    if (L % 64 != 0) {  // rows that end in a half group: a copy, then two sweeps in place on the copy
         const hipError_t e = hipMemcpyAsync(dst, src, (size_t)L * (size_t)L, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_failed(e, "hipMemcpyAsync");
         return ising_sweep_fmt(dst, L, beta, fmt, 2, seed, t, out_ME, stream);
@@ -2309,6 +2629,7 @@ int ising_sweep_fused_pair(const int8_t* src, int8_t* dst, int64_t L, double bet
         const int rc = zero_trace(out_ME, 4, s);
         if (rc) return rc;
     }
+    if (use_bands(L)) return launch_band_pass(src, dst, L, make_thresholds(beta, fmt), seed, (uint32_t)t, out_ME, s);
     return launch_fused_sweep(src, dst, L, make_thresholds(beta, fmt), seed, (uint32_t)t, out_ME, s, 2);
 }
 
@@ -2321,7 +2642,7 @@ int ising_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* str
     ising::ObsArgs a;
     a.spins = spins;
     a.L = (uint32_t)L;
-    a.groups = (uint32_t)(L / 64);
+    a.groups = groups_of(L);
     a.rows = rows_per_lane(L);
     a.n_lanes = a.groups * (uint32_t)(L / a.rows);
     a.out = out_ME;
@@ -2331,36 +2652,43 @@ int ising_observables(const int8_t* spins, int64_t L, int64_t* out_ME, void* str
 
 int ising_pack(const int8_t* spins, int64_t L, uint32_t* planes, void* stream) {
     if (!spins || !planes || !valid_L(L) || !aligned16(spins) || !aligned16(planes)) return ISING_EINVAL;
-    const uint32_t groups = (uint32_t)(L / 64), n = groups * (uint32_t)L;
-    hipLaunchKernelGGL(ising::k_pack, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, spins, planes,
-                       (uint32_t)L, groups, n);
+    const uint32_t groups = groups_of(L);
+    const uint64_t n = (uint64_t)groups * (uint64_t)L;  // up to 2^34 lanes at L = 2^20
+    hipLaunchKernelGGL(ising::k_pack, dim3(grid_blocks(n)), dim3(256), 0, (hipStream_t)stream, spins,
+                       planes, (uint32_t)L, groups, n);
     return check_launch("k_pack");
 }
 
 int ising_unpack(const uint32_t* planes, int64_t L, int8_t* spins, void* stream) {
     if (!spins || !planes || !valid_L(L) || !aligned16(spins) || !aligned16(planes)) return ISING_EINVAL;
-    const uint32_t groups = (uint32_t)(L / 64), n = groups * (uint32_t)L;
-    hipLaunchKernelGGL(ising::k_unpack, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, planes, spins,
-                       (uint32_t)L, groups, n);
+    const uint32_t groups = groups_of(L);
+    const uint64_t n = (uint64_t)groups * (uint64_t)L;
+    hipLaunchKernelGGL(ising::k_unpack, dim3(grid_blocks(n)), dim3(256), 0, (hipStream_t)stream, planes,
+                       spins, (uint32_t)L, groups, n);
     return check_launch("k_unpack");
+}
+
+int64_t ising_packed_words(int64_t L) {
+    if (!valid_L(L)) return ISING_EINVAL;
+    return 2 * L * (int64_t)groups_of(L);
 }
 
 int ising_fill_packed(uint32_t* planes, int64_t L, int value, void* stream) {
     if (!planes || !valid_L(L) || !aligned16(planes) || (value != 1 && value != -1)) return ISING_EINVAL;
-    // both planes together are L^2 / 8 bytes = L^2 / 128 16-byte chunks; a set bit is spin -1
-    const uint64_t n16 = (uint64_t)L * (uint64_t)L / 128u;
-    uint64_t blocks = (n16 + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(ising::k_fill_int8, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
-                       reinterpret_cast<int8_t*>(planes), n16, value == 1 ? 0u : 0xFFFFFFFFu);
-    return check_launch("k_fill_int8");
+    // a set bit is spin -1; both planes are 2 L G words (the bits past a half group stay zero)
+    const uint32_t groups = groups_of(L);
+    const uint64_t n = 2ull * (uint64_t)L * groups;
+    hipLaunchKernelGGL(ising::k_fill_packed, dim3(grid_blocks(n)), dim3(256), 0, (hipStream_t)stream, planes, n,
+                       groups, (uint32_t)(L % 64 != 0), value == 1 ? 0u : 0xFFFFFFFFu);
+    return check_launch("k_fill_packed");
 }
 
 int ising_init_packed(uint32_t* planes, int64_t L, uint64_t seed, void* stream) {
     if (!planes || !valid_L(L) || !aligned16(planes)) return ISING_EINVAL;
-    const uint32_t groups = (uint32_t)(L / 64), n = groups * (uint32_t)L;
-    hipLaunchKernelGGL(ising::k_init_packed, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, planes,
-                       (uint32_t)L, groups, n, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint32_t groups = groups_of(L);
+    const uint64_t n = (uint64_t)groups * (uint64_t)L;
+    hipLaunchKernelGGL(ising::k_init_packed, dim3(grid_blocks(n)), dim3(256), 0, (hipStream_t)stream,
+                       planes, (uint32_t)L, groups, n, (uint32_t)seed, (uint32_t)(seed >> 32));
     return check_launch("k_init_packed");
 }
 
@@ -2404,8 +2732,10 @@ int ising_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME,
     hipLaunchKernelGGL(ising::k_zero2, dim3(1), dim3(64), 0, s, out_ME);
     int rc = check_launch("k_zero2");
     if (rc) return rc;
-    const uint32_t groups = (uint32_t)(L / 64), n = groups * (uint32_t)L;
-    hipLaunchKernelGGL(ising::k_observables_packed, dim3((n + 255) / 256), dim3(256), 0, s, planes, (uint32_t)L,
+    const uint32_t groups = groups_of(L);
+    const uint64_t n = (uint64_t)groups * (uint64_t)L;
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(ising::k_observables_packed, dim3((unsigned)blocks), dim3(256), 0, s, planes, (uint32_t)L,
                        groups, n, out_ME);
     return check_launch("k_observables_packed");
 }
@@ -2456,6 +2786,12 @@ int ising_set_option(const char* name, int64_t value) {
     } else if (n == "ties3") {
         if (value != 0 && value != 1) return ISING_EINVAL;
         g_opt.ties3 = value;
+    } else if (n == "fused_bands") {
+        if (value != 0 && value != 1) return ISING_EINVAL;
+        g_opt.fused_bands = value;
+    } else if (n == "band_rows") {
+        if (value != 0 && (value < 2 || value > 1024 || (value & (value - 1)) != 0)) return ISING_EINVAL;
+        g_opt.band_rows = value;
     } else if (n == "fused_rows") {
         if (value != 0 && (value < 2 || value > 256 || (value & (value - 1)) != 0)) return ISING_EINVAL;
         g_opt.fused_rows = value;
@@ -2477,6 +2813,8 @@ int ising_get_option(const char* name, int64_t* value) {
     else if (n == "batch_depth") *value = g_opt.batch_depth;
     else if (n == "batch_lists_per_cu") *value = g_opt.batch_lists_per_cu;
     else if (n == "fused_rows") *value = g_opt.fused_rows;
+    else if (n == "fused_bands") *value = g_opt.fused_bands;
+    else if (n == "band_rows") *value = g_opt.band_rows;
     else if (n == "fused_alternate") *value = g_opt.fused_alternate;
     else if (n == "fused_sweeps") *value = g_opt.fused_sweeps;
     else if (n == "fused_ties") *value = g_opt.fused_ties;
@@ -2504,6 +2842,7 @@ int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm,
         return ISING_EINVAL;
     for (int64_t i = 0; i < n; ++i)
         if (!valid_beta(replicas[i].beta)) return ISING_EINVAL;
+    std::lock_guard<std::mutex> lock(g_batch_mu);
     const BatchLayout lay = batch_layout(replicas, n);
     // replica table (host) -> workspace head (device)
     std::vector<ising::BatchReplica> table((size_t)n);
@@ -2524,6 +2863,7 @@ int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm,
     hipStream_t s = (hipStream_t)stream;
     char* ws = reinterpret_cast<char*>(workspace);
     BatchBuffers bufs{};
+    bufs.run = reinterpret_cast<ising::BatchRun*>(ws + lay.params);
     bufs.table = reinterpret_cast<const ising::BatchReplica*>(ws);
     bufs.groups = reinterpret_cast<ising::BatchGroup*>(ws + lay.groups);
     bufs.units = reinterpret_cast<ising::BatchUnit*>(ws + lay.units);
@@ -2561,44 +2901,64 @@ int ising_batch_run(const ising_replica_t* replicas, int64_t n, int64_t n_therm,
     if (!plan.ok) return ISING_EINVAL;
     int rc = upload_plan(bufs, plan, s);
     if (rc) return rc;
-    // One persistent launch (after the clearing of the exchange area), captured once into a
-    // hipGraph and replayed on the caller's stream.
+    rc = set_batch_run(bufs, (uint32_t)start, (uint32_t)n_therm, (uint32_t)n_meas, trace_ME, moments, s);
+    if (rc) return rc;
+    // One persistent launch (after the clearing of the exchange area), captured once per plan into a
+    // hipGraph and replayed on the caller's stream.  The graph holds only what the plan fixes (the
+    // workspace's layout, the launch shape); the per-call values come from the workspace.
     char keybuf[320];
-    std::snprintf(keybuf, sizeof keybuf, "%p|%p|%p|%lld|%d|%lld|%d|%d|%zu|%u|%d|%lld|%lld|%zu", workspace,
-                  (void*)trace_ME, (void*)moments, (long long)n, sched.threads, (long long)sched.target, sched.depth,
-                  plan.per_cu, plan.groups.size(), plan.depth, start, (long long)n_therm, (long long)n_meas, plan.lds);
+    std::snprintf(keybuf, sizeof keybuf, "%p|%zu|%zu|%zu|%zu|%zu|%lld|%d|%zu|%u|%zu", workspace, lay.params, lay.state,
+                  lay.groups, lay.units, lay.exchange, (long long)bufs.exchange_words, sched.threads,
+                  plan.groups.size(), plan.depth, plan.lds);
     const std::string key(keybuf);
-    if (g_batch_graph.key != key || !g_batch_graph.exec) {
-        if (g_batch_graph.exec) {
-            (void)hipDeviceSynchronize();
-            (void)hipGraphExecDestroy(g_batch_graph.exec);
-            g_batch_graph.exec = nullptr;
+    auto it = g_batch_execs.find(key);
+    if (it == g_batch_execs.end()) {
+        if (g_batch_execs.size() >= kMaxBatchExecs) {
+            // drop the least recently used exec once its latest launch has completed (a wait on that
+            // launch alone, not on the device)
+            auto lru = g_batch_execs.begin();
+            for (auto j = g_batch_execs.begin(); j != g_batch_execs.end(); ++j)
+                if (j->second.used < lru->second.used) lru = j;
+            e = hipEventSynchronize(lru->second.done);
+            if (e != hipSuccess) return hip_failed(e, "hipEventSynchronize");
+            (void)hipGraphExecDestroy(lru->second.exec);
+            (void)hipEventDestroy(lru->second.done);
+            g_batch_execs.erase(lru);
         }
-        if (!g_batch_graph.capture) {
-            e = hipStreamCreateWithFlags(&g_batch_graph.capture, hipStreamNonBlocking);
+        if (!g_batch_capture) {
+            e = hipStreamCreateWithFlags(&g_batch_capture, hipStreamNonBlocking);
             if (e != hipSuccess) return hip_failed(e, "hipStreamCreateWithFlags");
         }
-        hipStream_t cs = g_batch_graph.capture;
+        BatchExec x;
+        e = hipEventCreateWithFlags(&x.done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_failed(e, "hipEventCreateWithFlags");
+        hipStream_t cs = g_batch_capture;
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_failed(e, "hipStreamBeginCapture");
-        const int launch_rc = launch_batch(bufs, plan, sched.threads, (uint32_t)start, (uint32_t)n_therm,
-                                           (uint32_t)n_meas, trace_ME, moments, cs);
+        if (e != hipSuccess) { (void)hipEventDestroy(x.done); return hip_failed(e, "hipStreamBeginCapture"); }
+        const int launch_rc = launch_batch(bufs, plan, sched.threads, cs);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(cs, &graph);
-        if (launch_rc) { if (graph) (void)hipGraphDestroy(graph); return launch_rc; }
-        if (e != hipSuccess) return hip_failed(e, "hipStreamEndCapture");
-        e = hipGraphInstantiate(&g_batch_graph.exec, graph, nullptr, nullptr, 0);
+        if (launch_rc || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipEventDestroy(x.done);
+            return launch_rc ? launch_rc : hip_failed(e, "hipStreamEndCapture");
+        }
+        e = hipGraphInstantiate(&x.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) { g_batch_graph.exec = nullptr; return hip_failed(e, "hipGraphInstantiate"); }
-        g_batch_graph.key = key;
+        if (e != hipSuccess) { (void)hipEventDestroy(x.done); return hip_failed(e, "hipGraphInstantiate"); }
+        it = g_batch_execs.emplace(key, x).first;
     }
-    e = hipGraphLaunch(g_batch_graph.exec, s);
+    it->second.used = ++g_batch_clock;
+    e = hipGraphLaunch(it->second.exec, s);
     if (e != hipSuccess) return hip_failed(e, "hipGraphLaunch");
+    e = hipEventRecord(it->second.done, s);
+    if (e != hipSuccess) return hip_failed(e, "hipEventRecord");
     return ISING_OK;
 }
 
 int ising_batch_schedule(const ising_replica_t* replicas, int64_t n, int64_t out[4]) {
     if (!replicas || n <= 0 || !out) return ISING_EINVAL;
+    std::lock_guard<std::mutex> lock(g_batch_mu);
     auto it = g_batch_tuned.find(batch_signature(replicas, n));
     if (it == g_batch_tuned.end()) return ISING_EINVAL;
     out[0] = it->second.threads;
@@ -2612,8 +2972,7 @@ int ising_batch_unpack(const void* workspace, int64_t n, int64_t j, int8_t* spin
     if (!workspace || !spins || n <= 0 || j < 0 || j >= n || !aligned16(workspace)) return ISING_EINVAL;
     const auto* dtable = reinterpret_cast<const ising::BatchReplica*>(workspace);
     const auto* state =
-        reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(workspace) +
-                                          align_up((size_t)n * sizeof(ising::BatchReplica)));
+        reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(workspace) + batch_state_offset(n));
     hipLaunchKernelGGL(ising::k_batch_unpack, dim3(16), dim3(256), 0, (hipStream_t)stream, dtable, state,
                        (uint32_t)j, spins);
     return check_launch("k_batch_unpack");

@@ -121,6 +121,52 @@ __device__ __forceinline__ void store_row_coalesced(int8_t* seg, const Row& row,
     wave_lds_sync();
 }
 
+// ---- Row I/O of a column band: a wave whose 64 lanes own 64 consecutive groups of a row modulo the
+// row length G >= 64 (a band can wrap round the torus seam, so the groups need not be contiguous in
+// memory).  Lane l moves the 16-byte chunks c = l + 64 k of the band's 64 groups: chunk c is quarter
+// c % 4 of the band's group c / 4 = l / 4 + 16 k, i.e. of row group (gbase + 16 k) mod G with gbase =
+// the row group of band group l / 4.  The chunks are regrouped per lane through the wave's 4 KiB of
+// LDS exactly as for a contiguous segment.
+__device__ __forceinline__ uint32_t band_chunk_offset(uint32_t gbase, uint32_t k, uint32_t G, uint32_t lane) {
+    uint32_t gk = gbase + 16u * k;  // < G + 48 <= 2G
+    gk = gk >= G ? gk - G : gk;
+    return gk * 64u + (lane & 3u) * 16u;
+}
+
+__device__ __forceinline__ void load_row_chunks(Row& raw, const int8_t* row, uint32_t gbase, uint32_t G,
+                                                uint32_t lane) {
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint4 x = *reinterpret_cast<const uint4*>(row + band_chunk_offset(gbase, k, G, lane));
+        raw.d[4 * k + 0] = x.x;
+        raw.d[4 * k + 1] = x.y;
+        raw.d[4 * k + 2] = x.z;
+        raw.d[4 * k + 3] = x.w;
+    }
+}
+
+// this lane's own 64 bytes -> the band's chunks; only the chunks of band groups 1 .. n_own are stored
+__device__ __forceinline__ void store_row_chunks(int8_t* row, const Row& own, uint4* lds, uint32_t lane,
+                                                 uint32_t gbase, uint32_t G, uint32_t n_own, bool streaming) {
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q)
+        lds[lds_slot(lane, q)] = make_uint4(own.d[4 * q], own.d[4 * q + 1], own.d[4 * q + 2], own.d[4 * q + 3]);
+    wave_lds_sync();
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t c = lane + 64u * k;
+        const uint4 x = lds[lds_slot(c >> 2, c & 3u)];
+        const u32x4 y = {x.x, x.y, x.z, x.w};
+        u32x4* v = reinterpret_cast<u32x4*>(row + band_chunk_offset(gbase, k, G, lane));
+        const uint32_t owner = (lane >> 2) + 16u * k;
+        if (owner >= 1u && owner <= n_own) {
+            if (streaming) __builtin_nontemporal_store(y, v);
+            else *v = y;
+        }
+    }
+    wave_lds_sync();
+}
+
 // Workgroups are dispatched to the eight XCDs round robin (block b runs on XCD b mod 8).
 // Renumbering them so that each XCD receives one contiguous range of logical blocks keeps
 // neighbouring row strips, which read each other's boundary rows, inside one L2.
@@ -152,6 +198,42 @@ __device__ __forceinline__ uint32_t shift_next(uint32_t y, uint32_t bit0) {
 __device__ __forceinline__ uint32_t shift_prev(uint32_t y, uint32_t bit31) {
     const uint32_t low = ((y >> 23) & 0xFEu) | bit31;
     return perm(y, low, 0x05040600u);
+}
+
+// ---- Half groups.  A row whose length L is an odd multiple of 32 ends in a group of 32 columns:
+// 16 sites of each colour, sites 0 .. 15, i.e. bits 0 .. 3 of every byte in site order.
+constexpr uint32_t kHalfSites = 0x0F0F0F0Fu;
+
+// shift_next for a half group: S[p(i)] = y[p(i + 1)] for i < 15, S[p(15)] = bit0 (site 0 of the next
+// group); the bits of sites 16 .. 31 are zero.
+__device__ __forceinline__ uint32_t shift_next_half(uint32_t y, uint32_t bit0) {
+    const uint32_t top = ((y >> 1) & 0x07u) | (bit0 << 3);
+    return perm(top, y, 0x04010302u) & kHalfSites;
+}
+
+// The bit of a group word's last site: site 31 (bit 31), or site 15 (bit 27) of a half group.
+__device__ __forceinline__ uint32_t last_site_bit(uint32_t y, bool half) { return half ? (y >> 27) & 1u : y >> 31; }
+
+// A half group's 32 bytes; the other half of the row buffer holds +1 spins (0x01), which no decision
+// reads (every result is masked with kHalfSites).
+__device__ __forceinline__ void load_row_half(Row& row, const int8_t* p) {
+    const uint4* v = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const uint4 x = v[i];
+        row.d[4 * i + 0] = x.x;
+        row.d[4 * i + 1] = x.y;
+        row.d[4 * i + 2] = x.z;
+        row.d[4 * i + 3] = x.w;
+    }
+#pragma unroll
+    for (int k = 8; k < 16; ++k) row.d[k] = 0x01010101u;
+}
+
+__device__ __forceinline__ void store_row_half(int8_t* p, const Row& row) {
+    uint4* v = reinterpret_cast<uint4*>(p);
+    v[0] = make_uint4(row.d[0], row.d[1], row.d[2], row.d[3]);
+    v[1] = make_uint4(row.d[4], row.d[5], row.d[6], row.d[7]);
 }
 
 // Flip the colour-OFF bytes of `row` whose site bit is set in F.  The two sites of dword

@@ -50,6 +50,7 @@ _SIGNATURES = {
                                  ctypes.c_int),
     "ising_init_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p], ctypes.c_int),
     "ising_fill_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "ising_packed_words": ([ctypes.c_int64], ctypes.c_int64),
     "ising_half_sweep_packed": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
                                  ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "ising_thresholds": ([ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -152,6 +153,20 @@ def _opt_ptr(t, dtype_name: str, numel: int):
     return None if t is None else _dev_ptr(t, dtype_name, numel)
 
 
+def _packed_n(L: int):
+    """Words of the packed layout for L (None for an invalid L: the library call then rejects it)."""
+    n = library().ising_packed_words(L)
+    return n if n >= 0 else None
+
+
+def ising_packed_words(L: int) -> int:
+    """uint32 words of both colour planes of an L x L lattice: 2 L ceil(L / 64)."""
+    n = library().ising_packed_words(L)
+    if n < 0:
+        _check("ising_packed_words", int(n))
+    return int(n)
+
+
 # ---- same names as the C ABI -----------------------------------------------------------------
 
 def ising_init(spins, L: int, seed: int, stream=None) -> None:
@@ -181,39 +196,39 @@ def ising_observables(spins, L: int, out_ME, stream=None) -> None:
 
 def ising_pack(spins, L: int, planes, stream=None) -> None:
     _check("ising_pack", library().ising_pack(
-        _dev_ptr(spins, "torch.int8", L * L), L, _dev_ptr(planes, "torch.int32", L * L // 32), _stream(stream)))
+        _dev_ptr(spins, "torch.int8", L * L), L, _dev_ptr(planes, "torch.int32", _packed_n(L)), _stream(stream)))
 
 
 def ising_unpack(planes, L: int, spins, stream=None) -> None:
     _check("ising_unpack", library().ising_unpack(
-        _dev_ptr(planes, "torch.int32", L * L // 32), L, _dev_ptr(spins, "torch.int8", L * L), _stream(stream)))
+        _dev_ptr(planes, "torch.int32", _packed_n(L)), L, _dev_ptr(spins, "torch.int8", L * L), _stream(stream)))
 
 
 def ising_sweep_packed(planes, L: int, beta: float, n_sweeps: int, seed: int, sweep_offset: int = 0,
                        trace_ME=None, stream=None) -> None:
     _check("ising_sweep_packed", library().ising_sweep_packed(
-        _dev_ptr(planes, "torch.int32", L * L // 32), L, float(beta), n_sweeps, seed, sweep_offset,
+        _dev_ptr(planes, "torch.int32", _packed_n(L)), L, float(beta), n_sweeps, seed, sweep_offset,
         _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
 
 
 def ising_init_packed(planes, L: int, seed: int, stream=None) -> None:
     _check("ising_init_packed", library().ising_init_packed(
-        _dev_ptr(planes, "torch.int32", L * L // 32), L, seed, _stream(stream)))
+        _dev_ptr(planes, "torch.int32", _packed_n(L)), L, seed, _stream(stream)))
 
 
 def ising_fill_packed(planes, L: int, value: int, stream=None) -> None:
     _check("ising_fill_packed", library().ising_fill_packed(
-        _dev_ptr(planes, "torch.int32", L * L // 32), L, value, _stream(stream)))
+        _dev_ptr(planes, "torch.int32", _packed_n(L)), L, value, _stream(stream)))
 
 
 def ising_half_sweep_packed(planes, L: int, beta: float, seed: int, t: int, q: int, stream=None) -> None:
     _check("ising_half_sweep_packed", library().ising_half_sweep_packed(
-        _dev_ptr(planes, "torch.int32", L * L // 32), L, float(beta), seed, t, q, _stream(stream)))
+        _dev_ptr(planes, "torch.int32", _packed_n(L)), L, float(beta), seed, t, q, _stream(stream)))
 
 
 def ising_observables_packed(planes, L: int, out_ME, stream=None) -> None:
     _check("ising_observables_packed", library().ising_observables_packed(
-        _dev_ptr(planes, "torch.int32", L * L // 32), L, _dev_ptr(out_ME, "torch.int64", 2), _stream(stream)))
+        _dev_ptr(planes, "torch.int32", _packed_n(L)), L, _dev_ptr(out_ME, "torch.int64", 2), _stream(stream)))
 
 
 def ising_thresholds(beta: float) -> tuple[int, int]:
@@ -342,7 +357,7 @@ def ising3_observables_packed(planes, L: int, out_ME, stream=None) -> None:
 def ising_sweep_packed_fmt(planes, L: int, beta: float, fmt, n_sweeps: int, seed: int, sweep_offset: int = 0,
                            trace_ME=None, stream=None) -> None:
     _check("ising_sweep_packed_fmt", library().ising_sweep_packed_fmt(
-        _dev_ptr(planes, "torch.int32", L * L // 32), L, float(beta), _fmt(fmt), n_sweeps, seed, sweep_offset,
+        _dev_ptr(planes, "torch.int32", _packed_n(L)), L, float(beta), _fmt(fmt), n_sweeps, seed, sweep_offset,
         _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
 
 
@@ -421,7 +436,7 @@ def new_packed(L: int, seed: int | None, device: str = "cuda"):
     """Allocate the packed form of an L x L lattice (int32 words): hot start of `seed`, or all +1
     when seed is None."""
     import torch
-    planes = torch.empty(L * L // 32, dtype=torch.int32, device=device)
+    planes = torch.empty(_packed_n(L), dtype=torch.int32, device=device)
     if seed is None:
         ising_fill_packed(planes, L, 1)
     else:

@@ -63,7 +63,10 @@ def test_argument_checks_before_any_launch(lib):
     null = ctypes.c_void_p(0)
     EINVAL = -1
     assert lib.ising_init(null, 64, 1, null) == EINVAL
-    assert lib.ising_init(fake, 60, 1, null) == EINVAL               # L % 64 != 0
+    assert lib.ising_init(fake, 60, 1, null) == EINVAL               # L % 32 != 0
+    assert lib.ising_init(fake, 80, 1, null) == EINVAL
+    assert lib.ising_init(fake, 16, 1, null) == EINVAL               # L < 32
+    assert lib.ising_init(fake, 2**20 + 32, 1, null) == EINVAL       # L > 2^20
     assert lib.ising_init(fake, 0, 1, null) == EINVAL
     assert lib.ising_init(ctypes.c_void_p(4097), 64, 1, null) == EINVAL  # misaligned
     assert lib.ising_fill(fake, 64, 0, null) == EINVAL               # value must be +-1
@@ -71,14 +74,14 @@ def test_argument_checks_before_any_launch(lib):
     assert lib.ising_sweep(fake, 64, -1.0, 1, 1, 0, null, null) == EINVAL
     assert lib.ising_sweep(fake, 64, 0.4, -1, 1, 0, null, null) == EINVAL
     assert lib.ising_sweep(fake, 64, 0.4, 2, 1, 2**32 - 1, null, null) == EINVAL  # t overflows
-    assert lib.ising_sweep(fake, 96, 0.4, 1, 1, 0, null, null) == EINVAL
+    assert lib.ising_sweep(fake, 112, 0.4, 1, 1, 0, null, null) == EINVAL
     assert lib.ising_half_sweep(fake, 64, 0.4, 1, 0, 2, null) == EINVAL
     assert lib.ising_half_sweep(fake, 64, 0.4, 1, 2**32, 0, null) == EINVAL
     assert lib.ising_observables(fake, 64, null, null) == EINVAL
     assert lib.ising_pack(fake, 64, null, null) == EINVAL
     assert lib.ising_unpack(null, 64, fake, null) == EINVAL
     assert lib.ising_sweep_packed(null, 64, 0.4, 1, 1, 0, null, null) == EINVAL
-    assert lib.ising_observables_packed(fake, 32, fake, null) == EINVAL
+    assert lib.ising_observables_packed(fake, 48, fake, null) == EINVAL
     # 3-D: L a power of two in [64, 2048]
     for bad_L in (32, 96, 192, 4096):
         assert lib.ising3_init(fake, bad_L, 1, null) == EINVAL, bad_L
@@ -109,10 +112,10 @@ def test_argument_checks_before_any_launch(lib):
     assert lib.ising_sweep_fused(fake, other, 64, 0.4, 0, 2, 1, 2**32 - 1, null, null) == EINVAL
     assert lib.ising_sweep_fused_step(fake, fake, 64, 0.4, 0, 1, 0, null, null) == EINVAL
     assert lib.ising_sweep_fused_step(fake, other, 64, 0.4, 0, 1, 2**32, null, null) == EINVAL
-    assert lib.ising_sweep_fused_step(fake, other, 96, 0.4, 0, 1, 0, null, null) == EINVAL
+    assert lib.ising_sweep_fused_step(fake, other, 112, 0.4, 0, 1, 0, null, null) == EINVAL
     assert lib.ising_sweep_fused_pair(fake, fake, 64, 0.4, 0, 1, 0, null, null) == EINVAL
     assert lib.ising_sweep_fused_pair(fake, other, 64, 0.4, 0, 1, 2**32 - 1, null, null) == EINVAL
-    assert lib.ising_sweep_fused_pair(fake, other, 96, 0.4, 0, 1, 0, null, null) == EINVAL
+    assert lib.ising_sweep_fused_pair(fake, other, 112, 0.4, 0, 1, 0, null, null) == EINVAL
     assert lib.ising_sweep_fused_pair(fake, other, 64, -1.0, 0, 1, 0, null, null) == EINVAL
 
 
@@ -136,6 +139,7 @@ def test_options_round_trip(lib):
                             ("staged", [0, 1], [-1]), ("nt_store", [0, 1], [5]),
                             ("fused_rows", [0, 2, 16, 256], [1, 6, 512, -4]), ("fused_alternate", [0, 1], [2]), ("fused_sweeps", [1, 2], [0, 3]),
                             ("fused_ties", [0, 1], [2, -1]), ("packed_ties", [0, 1], [2]), ("ties3", [0, 1], [2]),
+                            ("fused_bands", [0, 1], [2, -1]), ("band_rows", [0, 2, 128, 1024], [1, 6, 2048, -8]),
                             ("planes3", [0, 2, 32, 256], [1, 3, 512]),
                             ("batch_threads", [0, 256, 512, 1024], [128, 2048, -1]),
                             ("batch_slab_sites", [0, -1, 1024, 65536, 262144], [512, 3000, 524288, -2]),
@@ -182,3 +186,12 @@ def test_batch_table_validation(lib):
     for bad in ([(96, 0.4, 1)], [(16, 0.4, 1)], [(576, 0.4, 1)], [(100, 0.4, 1)]):
         with pytest.raises(ising.IsingError):
             ising.ising_batch_workspace_bytes(bad)
+
+
+def test_packed_words(lib):
+    # 2 L ceil(L / 64) words: two colour planes of L rows; a row of an odd multiple of 32 ends in a half
+    # word
+    for L, words in ((32, 64), (64, 128), (96, 384), (160, 960), (4096, 4096 * 4096 // 32), (2**20, 2**35)):
+        assert lib.ising_packed_words(L) == words, L
+    for L in (0, 16, 48, 100, 2**20 + 32):
+        assert lib.ising_packed_words(L) == -1, L

@@ -4,7 +4,7 @@ The fused pass reads one buffer and writes the other; every decision uses the si
 so the lattice and the (M, E) trace must equal the oracle's two half-sweeps bit for bit.  Cases:
 one workgroup thread per 64-column group with threads past the last group idle (L = 64, 192,
 320), whole waves staged through LDS (L = 4096, 8192), the full 16384^2 benchmark lattice, the
-largest fused lattice (65536^2, 1024 threads per workgroup) and the in-place path above it.
+largest full-row lattice (65536^2, 1024 threads per workgroup) and the column-band pass above it.
 """
 import math
 import sys
@@ -197,9 +197,10 @@ def test_fused_full_size_16384_crops_and_trace(dev, oracle_lib):
     assert torch.equal(trace, tr2)
 
 
-def test_fused_largest_lattice_and_in_place_above_it(dev):
-    # L = 65536: 1024 threads per workgroup, 72 KiB of LDS.  L = 65600: above the fused limit,
-    # every sweep runs in place and the scratch buffer is not touched.
+def test_fused_largest_full_row_lattice_and_bands_above_it(dev):
+    # L = 65536: 1024 threads per workgroup, 72 KiB of LDS.  L = 65600 (1025 groups): above the
+    # full-row limit, the two-sweep pass runs in column bands (17 bands of 60 or 61 groups, strips of
+    # 64 rows); both equal the in-place two-launch path
     for L, n in ((65536, 2), (65600, 2)):
         _say("fused large", L, n)
         s = torch.empty((L, L), dtype=torch.int8, device="cuda")
@@ -212,8 +213,6 @@ def test_fused_largest_lattice_and_in_place_above_it(dev):
         dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", n, 5, 9, tr)
         assert torch.equal(s, ref), L
         assert torch.equal(tr, tr_ref), L
-        if L > 65536:
-            assert int(scratch.abs().sum()) == 0
         del s, ref, scratch
         torch.cuda.empty_cache()
 

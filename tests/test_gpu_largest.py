@@ -1,7 +1,8 @@
 """GPU parity at the largest single-GPU lattice: L = 131072 (1.7e10 spins), both layouts.
 
-The int8 lattice (16 GiB) is swept one colour per launch, as the benchmark times it at this size;
-the 1-bit lattice (2 GiB) by the packed kernel.  For each of T = 2.0, T_c and 2.6, 100 sweeps from
+The int8 lattice (16 GiB) is swept two sweeps per pass in column bands (the benchmark's path at this
+size, with a second 16 GiB buffer), the 1-bit lattice (2 GiB) by the packed kernel, and at T_c also one
+colour per launch in place.  For each of T = 2.0, T_c and 2.6, 100 sweeps from
 the seed-1 hot start; then a 2048 x 2048 window across the torus seam is checked against the
 oracle's light-cone run (a (2048 + 4 * 100)^2 window, Sec. 3.1: after n sweeps a site depends only
 on sites within distance 2n), the traced (M, E) against a fresh reduction, and the two layouts
@@ -40,11 +41,12 @@ def dev():
 @pytest.mark.parametrize("T", [2.0, T_C, 2.6])
 def test_largest_lattice_both_layouts(dev, oracle_lib, T):
     beta = 1.0 / T
-    _say("L=131072 int8", T)
-    s = torch.empty((L, L), dtype=torch.int8, device="cuda")
+    _say("L=131072 int8, two sweeps per pass in column bands", T)
+    buf = torch.empty(2 * L * L, dtype=torch.int8, device="cuda")
+    s, scratch = buf[:L * L].view(L, L), buf[L * L:].view(L, L)
     dev.ising_init(s, L, SEED)
     tr8 = torch.empty((N_SWEEPS, 2), dtype=torch.int64, device="cuda")
-    dev.ising_sweep(s, L, beta, N_SWEEPS, SEED, 0, tr8)
+    dev.ising_sweep_fused(s, scratch, L, beta, "exact", N_SWEEPS, SEED, 0, tr8)
     torch.cuda.synchronize()
 
     _say("L=131072 oracle window", T)
@@ -65,8 +67,17 @@ def test_largest_lattice_both_layouts(dev, oracle_lib, T):
     trp = torch.empty((N_SWEEPS, 2), dtype=torch.int64, device="cuda")
     dev.ising_sweep_packed(p, L, beta, N_SWEEPS, SEED, 0, trp)
     assert torch.equal(trp, tr8)
-    u = torch.empty_like(s)
-    dev.ising_unpack(p, L, u)
-    assert torch.equal(u, s)
-    del s, u, p
+    dev.ising_unpack(p, L, scratch)
+    assert torch.equal(scratch, s)
+    del p
+
+    if abs(T - T_C) < 1e-9:
+        # and the in-place two-launch path (one colour per launch) gives the same lattice and trace
+        _say("L=131072 int8 in place", T)
+        dev.ising_init(scratch, L, SEED)
+        tr2 = torch.empty((N_SWEEPS, 2), dtype=torch.int64, device="cuda")
+        dev.ising_sweep(scratch, L, beta, N_SWEEPS, SEED, 0, tr2)
+        assert torch.equal(tr2, tr8)
+        assert torch.equal(scratch, s)
+    del s, scratch, buf
     torch.cuda.empty_cache()

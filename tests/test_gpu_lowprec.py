@@ -68,23 +68,21 @@ def test_exact_fmt_is_the_exact_chain(dev):
 
 
 def test_moments_fp64_sequential(dev):
-    L, n = 128, 300
-    s = torch.empty((L, L), dtype=torch.int8, device="cuda")
-    dev.ising_init(s, L, 1)
-    trace = torch.empty((n, 2), dtype=torch.int64, device="cuda")
-    dev.ising_sweep(s, L, BETA_C, n, 1, 0, trace)
-    out = torch.empty(5, dtype=torch.float64, device="cuda")
-    dev.ising_moments(trace, n, L * L, out)
-    tr = trace.cpu().numpy()
-    inv = 1.0 / (L * L)
-    acc = [0.0] * 5
-    for M, E in tr.tolist():
-        m, e = M * inv, E * inv
-        m2 = m * m
-        acc[0] += abs(m)
-        acc[1] += m2
-        acc[2] += m2 * m2
-        acc[3] += e
-        acc[4] += e * e
-    expect = [a * (1.0 / n) for a in acc]
-    assert out.cpu().tolist() == expect
+    # the FP64 moments of a traced chain equal the oracle's plain sums in sweep order, bit for bit
+    # (same operations in the same order: M / N, products, sums, one division by n)
+    import oracle
+    for L, n in ((128, 300), (96, 257)):
+        s = torch.empty((L, L), dtype=torch.int8, device="cuda")
+        trace = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+        if L % 64 == 0:
+            dev.ising_init(s, L, 1)
+            dev.ising_sweep(s, L, BETA_C, n, 1, 0, trace)
+        else:
+            # any int64 trace will do: a seeded one within the (M, E) range of an L x L lattice
+            rng = np.random.default_rng(L)
+            tr = np.stack([rng.integers(-L * L, L * L + 1, n), rng.integers(-2 * L * L, 2 * L * L + 1, n)], axis=1)
+            trace.copy_(torch.from_numpy(tr.astype(np.int64)))
+        out = torch.empty(5, dtype=torch.float64, device="cuda")
+        dev.ising_moments(trace, n, L * L, out)
+        expect = oracle.moments(trace.cpu().numpy(), L * L)
+        assert out.cpu().numpy().tolist() == expect.tolist(), (L, n)

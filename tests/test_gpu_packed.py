@@ -166,3 +166,32 @@ def test_full_size_16384_packed_crops(dev, oracle_lib):
     out = torch.empty(2, dtype=torch.int64, device="cuda")
     dev.ising_observables_packed(p, L, out)
     assert out.tolist() == trace[-1].tolist()
+
+
+def test_packed_at_two_to_the_nineteen(dev, oracle_lib):
+    # L = 2^19: the (row, group) word count is 2^32, past any 32-bit lane index.  Fill, observables and
+    # the hot start must still cover every row (32 GiB of planes).
+    L = 1 << 19
+    W = L // 64
+    planes = torch.empty(L * L // 32, dtype=torch.int32, device="cuda")
+    out = torch.empty(2, dtype=torch.int64, device="cuda")
+    for value in (1, -1):
+        dev.ising_fill_packed(planes, L, value)
+        dev.ising_observables_packed(planes, L, out)
+        assert out.cpu().tolist() == [value * L * L, -2 * L * L]
+    seed = 3
+    dev.ising_init_packed(planes, L, seed)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(19)
+    rows = np.concatenate([rng.integers(0, L, 24), [L - 1, L - 2, L // 2]])
+    for r in rows.tolist():
+        for q in (0, 1):
+            g = int(rng.integers(0, W))
+            word = int(planes[(q * L + r) * W + g].item()) & 0xFFFFFFFF
+            for i in (0, 5, 17, 31):
+                p = 8 * (0, 2, 1, 3)[i & 3] + (i >> 2)
+                c = 2 * (32 * g + i) + ((r + q) & 1)
+                spin = -1 if (word >> p) & 1 else 1
+                assert spin == oracle_lib.init_site(seed, r, c), (r, q, g, i)
+    del planes
+    torch.cuda.empty_cache()
