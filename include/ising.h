@@ -96,6 +96,15 @@ int ising_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sw
 int ising_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, int fmt, int64_t n_sweeps,
                       uint64_t seed, uint64_t sweep_offset, int64_t* trace_ME, void* stream);
 
+/* ising_sweep_fused for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the second lattice buffer is the library's own
+ * static device array of 64 MiB, so L * L <= 2^26 (L <= 8192); larger L returns ISING_EINVAL.  The
+ * call allocates and frees nothing.  Every call on one GPU shares that GPU's array (each GPU holds
+ * its own until the process ends); calls that overlap on one GPU, on different streams or threads,
+ * race and give unspecified results.  Arguments, results and errors otherwise as ising_sweep_fused. */
+int ising_sweep_fused_static(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sweeps, uint64_t seed,
+                             uint64_t sweep_offset, int64_t* trace_ME, void* stream);
+
 /* One sweep with sweep index t (< 2^32) out of place: dst = the sweep of src (both device
  * int8[L * L], 16-byte aligned, disjoint; src is not modified).  out_ME: NULL or device int64[2]
  * receiving (M, E) of dst.  For a caller that manages its own pair of buffers (a captured graph

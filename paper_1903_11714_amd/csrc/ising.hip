@@ -1771,6 +1771,12 @@ __global__ void k_moments(const int64_t* trace, int64_t n, int64_t n_sites, doub
     out[4] = s_e2 / k;
 }
 
+// The second lattice buffer of ising_sweep_fused_static, for callers that cannot allocate device
+// memory: 64 MiB, the scratch lattice of L <= 8192.  Each GPU the library runs on holds its own copy
+// from the module's load to the end of the process.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+__device__ __align__(256) int8_t scratch[kStaticScratchBytes];
+
 }  // namespace ising
 
 // ==========================================================================================
@@ -2076,6 +2082,28 @@ int zero_trace(int64_t* p, int64_t n, hipStream_t stream) {
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
     hipLaunchKernelGGL(ising::k_zero_n, dim3((unsigned)blocks), dim3(256), 0, stream, p, n);
     return check_launch("k_zero_n");
+}
+
+// The device address of ising::scratch on the current device, looked up once per device (with that
+// device current) and kept: in host code the array's name is only a host-side stand-in.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int8_t* g_scratch_addr[kMaxDevices] = {};
+
+int static_scratch(int8_t** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_failed(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return ISING_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(ising::scratch));
+        if (e != hipSuccess) return hip_failed(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_addr[dev] = reinterpret_cast<int8_t*>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return ISING_OK;
 }
 
 }  // namespace
@@ -2594,6 +2622,15 @@ int ising_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, in
         if (rc) return rc;
     }
     return ISING_OK;
+}
+
+int ising_sweep_fused_static(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sweeps, uint64_t seed,
+                             uint64_t sweep_offset, int64_t* trace_ME, void* stream) {
+    if (!spins || !valid_L(L) || (uint64_t)L * (uint64_t)L > ising::kStaticScratchBytes) return ISING_EINVAL;
+    int8_t* scratch = nullptr;
+    const int rc = static_scratch(&scratch);
+    if (rc) return rc;
+    return ising_sweep_fused(spins, scratch, L, beta, fmt, n_sweeps, seed, sweep_offset, trace_ME, stream);
 }
 
 int ising_sweep_fused_step(const int8_t* src, int8_t* dst, int64_t L, double beta, int fmt, uint64_t seed,

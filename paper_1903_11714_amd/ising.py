@@ -62,6 +62,8 @@ _SIGNATURES = {
     "ising_sweep_fused": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
                            ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p],
                           ctypes.c_int),
+    "ising_sweep_fused_static": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_int64,
+                                  ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "ising_sweep_fused_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "ising_sweep_fused_pair": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
@@ -262,6 +264,13 @@ def ising_sweep_fused(spins, scratch, L: int, beta: float, fmt, n_sweeps: int, s
     _check("ising_sweep_fused", library().ising_sweep_fused(
         _dev_ptr(spins, "torch.int8", L * L), _dev_ptr(scratch, "torch.int8", L * L), L, float(beta), _fmt(fmt),
         n_sweeps, seed, sweep_offset, _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
+
+
+def ising_sweep_fused_static(spins, L: int, beta: float, fmt, n_sweeps: int, seed: int, sweep_offset: int = 0,
+                             trace_ME=None, stream=None) -> None:
+    _check("ising_sweep_fused_static", library().ising_sweep_fused_static(
+        _dev_ptr(spins, "torch.int8", L * L), L, float(beta), _fmt(fmt), n_sweeps, seed, sweep_offset,
+        _opt_ptr(trace_ME, "torch.int64", 2 * n_sweeps), _stream(stream)))
 
 
 def ising_sweep_fused_step(src, dst, L: int, beta: float, fmt, seed: int, t: int, out_ME=None,
