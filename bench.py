@@ -477,6 +477,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20,
                     help="untimed sweeps first (more follow until %.1f s of GPU time has gone into sweeps)" % WARM_FLOOR_S)
     ap.add_argument("--repeats", type=int, default=5, help="timed runs of --steps sweeps; the median is reported")
+    ap.add_argument("--warm-floor", type=float, default=WARM_FLOOR_S,
+                    help="GPU seconds of sweeps before anything is timed (0 under a counter-collecting profiler)")
     ap.add_argument("--L", type=int, default=16384)
     ap.add_argument("--beta", type=float, default=BETA_C)
     ap.add_argument("--seed", type=int, default=1)
@@ -501,6 +503,8 @@ def main() -> int:
     ap.add_argument("--record", default=None,
                     help="precision/batch forms: write the full JSON record to this path and a markdown "
                          "table beside it (.md)")
+    ap.add_argument("--option", action="append", default=[], metavar="NAME=VALUE",
+                    help="library launch option (ising_set_option) for this run; every setting gives the same chain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run this many plain device copies of an L^2-byte buffer (counter calibration)")
@@ -521,6 +525,9 @@ def main() -> int:
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
     L, beta, seed, K, W = args.L, args.beta, args.seed, args.steps, args.warmup
+    for opt in args.option:
+        name, value = opt.split("=", 1)
+        ising.ising_set_option(name, int(value))
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
 
@@ -553,7 +560,7 @@ def main() -> int:
         return 0
 
     main = run_layout(ising, torch, args.layout, L, beta, seed, K, W, args.kernel_sweeps, stream,
-                      repeats=args.repeats)
+                      repeats=args.repeats, warm_floor=args.warm_floor)
     lat_bytes = L * L // 8 if args.layout == "packed" else L * L
     layout_text = {
         "fused": f"int8 layout, two sweeps per launch, lattice + scratch buffer ({2 * lat_bytes / 2**20:.0f} MiB)",
@@ -594,7 +601,7 @@ def main() -> int:
         # u < p with both rounded to the format), on the same fused kernel
         for fmt in ("bf16", "fp16"):
             low = run_layout(ising, torch, "fused", L, beta, seed, K, W, args.kernel_sweeps, stream, fmt=fmt,
-                             repeats=3)
+                             repeats=3, warm_floor=args.warm_floor)
             r = roofline("fused", L, low["avg_launch_ms"], low["untraced_launch_ms"], cb)
             result[f"{fmt}_accept"] = {
                 "value": low["value"], "unit": "attempts/ns", "steps": K, "kernel": KERNEL_NAME["fused"],
@@ -604,7 +611,8 @@ def main() -> int:
         # the same workload on the other layouts (same chain, bit-identical spins), for reference
         ks = max(K // 4, 1)
         for lay in ("int8", "packed"):
-            other = run_layout(ising, torch, lay, L, beta, seed, ks, W, args.kernel_sweeps, stream, repeats=3)
+            other = run_layout(ising, torch, lay, L, beta, seed, ks, W, args.kernel_sweeps, stream, repeats=3,
+                               warm_floor=args.warm_floor)
             r = roofline(lay, L, other["avg_launch_ms"], other["untraced_launch_ms"], 0.0)
             result[f"{lay}_layout"] = {
                 "value": other["value"], "unit": "attempts/ns", "steps": ks, "kernel": KERNEL_NAME[lay],
@@ -612,7 +620,7 @@ def main() -> int:
                 "bytes_per_attempt": BYTES_PER_ATTEMPT[lay],
             }
     if args.largest and args.layout == "fused" and L != LARGEST_L:
-        result["largest"] = bench_largest(ising, torch, stream, seed)
+        result["largest"] = bench_largest(ising, torch, stream, seed, warm_floor=args.warm_floor)
     if args.copy_calibration:
         calibration_copies(torch, L * L, args.copy_calibration)
     if not args.no_cpu_baseline:
@@ -625,7 +633,8 @@ def main() -> int:
 LARGEST_L = 131072
 
 
-def bench_largest(ising, torch, stream, seed: int, temps=(2.0, 1.0 / BETA_C, 2.6), K: int = 8) -> dict:
+def bench_largest(ising, torch, stream, seed: int, temps=(2.0, 1.0 / BETA_C, 2.6), K: int = 8,
+                  warm_floor: float = WARM_FLOOR_S) -> dict:
     """The largest single-GPU lattice (L = 131072: 16 GiB int8, 2 GiB 1-bit), hot start, at three
     temperatures on both layouts: throughput over 3 x K timed sweeps (after the warm-up floor) and the
     roofline of each layout's dominant kernel."""
@@ -633,7 +642,8 @@ def bench_largest(ising, torch, stream, seed: int, temps=(2.0, 1.0 / BETA_C, 2.6
     layouts = ("fused", "packed")
     for T in temps:
         for lay in layouts:
-            r = run_layout(ising, torch, lay, LARGEST_L, 1.0 / T, seed, K, 0, 4, stream, repeats=3)
+            r = run_layout(ising, torch, lay, LARGEST_L, 1.0 / T, seed, K, 0, 4, stream, repeats=3,
+                           warm_floor=warm_floor)
             roof = roofline(lay, LARGEST_L, r["avg_launch_ms"], r["untraced_launch_ms"], 0.0)
             out["runs"].append({"T": T, "layout": lay, "value": r["value"], "unit": "attempts/ns",
                                 "per_repeat": r["repeats"], "kernel": kernel_name(lay, LARGEST_L),

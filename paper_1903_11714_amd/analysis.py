@@ -169,6 +169,14 @@ def _crossing_in(temps, d, k):
     return float(temps[k] - d[k] / slope) if slope != 0 else float("nan")
 
 
+def crossing_blocks(m_series_pair, n: int, max_blocks: int = 50, min_blocks: int = 8) -> int:
+    """Jackknife blocks for a crossing: each block spans at least four tau_int of the slowest replica
+    of the two sizes (tau_int of m^2 and |m|), between min_blocks and max_blocks blocks."""
+    tau = max(max(tau_int(np.asarray(m, dtype=np.float64) ** 2), tau_int(np.abs(np.asarray(m, dtype=np.float64))))
+              for m in m_series_pair)
+    return int(max(min_blocks, min(max_blocks, n // max(1, int(math.ceil(4 * tau))))))
+
+
 def u4_crossings(Ls, temps, m_series, n_blocks: int = 50) -> list:
     """Crossing temperatures of the U4(T) curves of neighbouring sizes a < b.
 
@@ -182,31 +190,45 @@ def u4_crossings(Ls, temps, m_series, n_blocks: int = 50) -> list:
     Error: a jackknife over n_blocks synchronised time blocks.  Leaving block k out of EVERY
     replica's series (the replicas are independent chains, so any pairing of their blocks is a
     valid resampling) gives U4 curves, hence a crossing T_k in the same bracket; the error is
-    sqrt((n - 1) / n sum_k (T_k - mean T_k)^2).
+    sqrt((n - 1) / n sum_k (T_k - mean T_k)^2).  n_blocks may be a number, or a function of
+    (list of the two sizes' series at the bracket's two temperatures, series length) that picks it
+    per pair (crossing_blocks: blocks of at least four tau_int).
     """
     temps = np.asarray(temps, dtype=np.float64)
-    u4 = {}
-    for L in Ls:
+
+    def curves(L, nb):
         full, loo = [], []
         for m in m_series[L]:
             m = np.asarray(m, dtype=np.float64)
-            f, lo = jackknife_samples(binder, [m * m, m ** 4], n_blocks)
+            f, lo = jackknife_samples(binder, [m * m, m ** 4], nb)
             full.append(f)
             loo.append(lo)
-        u4[L] = (np.array(full), np.array(loo))  # (n_T,), (n_T, n_blocks)
-    out = []
-    for a, b in zip(Ls[:-1], Ls[1:]):
-        fa, la = u4[a]
-        fb, lb = u4[b]
-        d = fa - fb
-        dl = la - lb                                              # (n_T, n_blocks)
-        de = np.array([jackknife_error(dl[i]) for i in range(len(temps))])
+        return np.array(full), np.array(loo)  # (n_T,), (n_T, nb)
+
+    def bracket(d, de):
         best = None
         for k in range(len(temps) - 1):
             if d[k] <= 0 < d[k + 1]:
                 sig = (abs(d[k]) + abs(d[k + 1])) / max(de[k] + de[k + 1], 1e-300)
                 if best is None or sig > best[0]:
                     best = (sig, k)
+        return best
+
+    out = []
+    for a, b in zip(Ls[:-1], Ls[1:]):
+        nb = n_blocks if not callable(n_blocks) else 50
+        fa, la = curves(a, nb)
+        fb, lb = curves(b, nb)
+        d, dl = fa - fb, la - lb
+        best = bracket(d, np.array([jackknife_error(dl[i]) for i in range(len(temps))]))
+        if best is not None and callable(n_blocks):
+            # blocks sized by the slowest of the four replicas at the bracket
+            k = best[1]
+            n = len(m_series[a][k])
+            nb = n_blocks([m_series[a][k], m_series[a][k + 1], m_series[b][k], m_series[b][k + 1]], n)
+            fa, la = curves(a, nb)
+            fb, lb = curves(b, nb)
+            d, dl = fa - fb, la - lb
         if best is None:
             out.append({"pair": [int(a), int(b)], "T_cross": None})
             continue
@@ -214,7 +236,7 @@ def u4_crossings(Ls, temps, m_series, n_blocks: int = 50) -> list:
         t_star = _crossing_in(temps, d, k)
         t_loo = np.array([_crossing_in(temps, dl[:, j], k) for j in range(dl.shape[1])])
         err = jackknife_error(t_loo)
-        out.append({"pair": [int(a), int(b)], "T_cross": t_star, "err": err, "bracket": [float(temps[k]),
-                    float(temps[k + 1])], "significance": float(sig),
+        out.append({"pair": [int(a), int(b)], "T_cross": t_star, "err": err, "n_blocks": int(dl.shape[1]),
+                    "bracket": [float(temps[k]), float(temps[k + 1])], "significance": float(sig),
                     "z_vs_Tc": float((t_star - T_C) / err) if err > 0 else None})
     return out

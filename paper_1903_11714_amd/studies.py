@@ -211,7 +211,8 @@ def batch_study(Ls=(32, 64, 128, 256, 512), n_temps: int = 51, n_therm: int = 20
                                  "abs_m": [float(x) for x in mo[idx - len(temps):idx, 0]]}
     res["tau_limit"] = tau_limit
     res["tau_flagged"] = flagged
-    res["crossings"] = A.u4_crossings(Ls, temps, m_series, n_blocks=50)
+    # jackknife blocks of at least four tau_int of the slowest replica at each crossing
+    res["crossings"] = A.u4_crossings(Ls, temps, m_series, n_blocks=A.crossing_blocks)
     # the batched replicas are the plain chain: re-run one replica of every size >= 64 (the
     # middle of its temperature range) with the single-lattice path and compare the traces
     checks = []
@@ -234,14 +235,15 @@ def batch_table(rec: dict) -> str:
     lines = [f"{rec['replicas']} replicas, L in {rec['Ls']}, {len(rec['temps'])} temperatures on "
              f"[{rec['temps'][0]:.3f}, {rec['temps'][-1]:.3f}], {rec['n_therm']} + {rec['n_meas']} sweeps: "
              f"{rec['seconds']:.3f} s, {rec['attempts_per_ns']:.0f} attempts/ns; schedule {rec['schedule']}.", "",
-             "| pair | T_cross ± jackknife | z vs T_c | bracket |", "|---|---|---|---|"]
+             "| pair | T_cross ± jackknife | z vs T_c | bracket | jackknife blocks |", "|---|---|---|---|---|"]
     for c in rec["crossings"]:
         if c.get("T_cross") is None:
-            lines.append(f"| {c['pair']} | none | — | — |")
+            lines.append(f"| {c['pair']} | none | — | — | — |")
         else:
             z = c.get("z_vs_Tc")
             lines.append(f"| {c['pair'][0]}, {c['pair'][1]} | {c['T_cross']:.4f} ± {c['err']:.4f} | "
-                         f"{'—' if z is None else f'{z:.1f}'} | {c['bracket'][0]:.3f}–{c['bracket'][1]:.3f} |")
+                         f"{'—' if z is None else f'{z:.1f}'} | {c['bracket'][0]:.3f}–{c['bracket'][1]:.3f} | "
+                         f"{c['n_blocks']} |")
     lines += ["", f"Replicas with tau_int(|m| or m^2) above n_meas / 50 = {rec['tau_limit']:.0f} sweeps: "
               f"{len(rec['tau_flagged'])} of {rec['replicas']}"]
     by_L = {}

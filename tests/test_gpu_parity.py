@@ -169,9 +169,9 @@ def test_full_size_16384_crops_and_invariants(dev, oracle_lib):
 
 
 def test_invalid_arguments_raise(dev):
-    s = torch.empty((96, 96), dtype=torch.int8, device="cuda")
+    s = torch.empty((80, 80), dtype=torch.int8, device="cuda")   # L % 32 != 0
     with pytest.raises(dev.IsingError):
-        dev.ising_init(s, 96, 1)
+        dev.ising_init(s, 80, 1)
     s = torch.empty((64, 64), dtype=torch.int8, device="cuda")
     with pytest.raises(dev.IsingError):
         dev.ising_sweep(s, 64, -1.0, 1, 1)
