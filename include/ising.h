@@ -19,7 +19,14 @@
  *   - Library state is process-wide: the options below (each an atomic value; every valid setting
  *     gives the same results, so a setting that races a launch is harmless) and the batched form's
  *     tuned schedules and captured graphs (guarded by a mutex held for the whole of each batch
- *     call).  ising_last_error is per thread.
+ *     call), and one stream-ordered memory pool per device (created once under a mutex).
+ *     ising_last_error is per thread.
+ *   - Traced sweeps (a non-NULL trace_ME on ising_sweep, ising_sweep_fmt, ising_sweep_fused and
+ *     ising_sweep_packed) take 512 KiB of device memory from that pool for the call, in stream
+ *     order (hipMallocFromPoolAsync, then hipFreeAsync after the call's last launch), so calls on
+ *     different streams never share it.  Their workgroups add (M, E) into 64 spread cache lines per
+ *     launch instead of two words; one small kernel per 64 traced launches writes the sums into
+ *     trace_ME.  The trace is complete once the stream reaches the end of the call.
  *
  * Lattice conventions (Sec. 3, Sec. 3.1, Sec. 3.2 of the paper):
  *   int8 layout: row-major L x L bytes, sigma[r][c] at offset r * L + c, periodic in r and c.
@@ -97,9 +104,9 @@ int ising_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, in
                       uint64_t seed, uint64_t sweep_offset, int64_t* trace_ME, void* stream);
 
 /* ising_sweep_fused for callers that cannot allocate device memory (code under HIP graph capture,
- * serving loops, harnesses that forbid hipMalloc): the second lattice buffer is the library's own
- * static device array of 64 MiB, so L * L <= 2^26 (L <= 8192); larger L returns ISING_EINVAL.  The
- * call allocates and frees nothing.  Every call on one GPU shares that GPU's array (each GPU holds
+ * serving loops, harnesses that forbid hipMalloc): the second lattice buffer and the spread sets of
+ * a traced call are the library's own static device array of 64 MiB + 512 KiB, so L * L <= 2^26
+ * (L <= 8192); larger L returns ISING_EINVAL.  The call allocates and frees nothing.  Every call on one GPU shares that GPU's array (each GPU holds
  * its own until the process ends); calls that overlap on one GPU, on different streams or threads,
  * race and give unspecified results.  Arguments, results and errors otherwise as ising_sweep_fused. */
 int ising_sweep_fused_static(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sweeps, uint64_t seed,

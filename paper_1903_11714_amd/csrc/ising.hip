@@ -97,8 +97,7 @@ struct SweepArgs {
     uint32_t L, groups, rows, n_lanes;  // rows = rows per lane (even, divides L)
     uint32_t t, key0, key1;
     Thresholds th;
-    int64_t* obs;        // OBS: (M, E) accumulator, zeroed beforehand
-    int64_t* zero_slot;  // if non-null, block 0 zeroes these two int64 (a later launch's obs)
+    int64_t* obs;        // OBS: a spread set (zeroed beforehand) that takes (M, E)
     uint32_t xcd_remap;  // renumber blocks per XCD (see logical_block)
     uint32_t nt_store;   // non-temporal stores of the updated rows
 };
@@ -110,7 +109,6 @@ template <int Q, bool OBS, bool STAGED, bool HALF = false>
 __global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
     __shared__ uint4 lds_all[4][256];
     const uint32_t lane_id = logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * blockDim.x + threadIdx.x;
-    if (a.zero_slot && lane_id == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
     const bool active = lane_id < a.n_lanes;
     Counts cnt{0u, 0u};
     if (active) {
@@ -208,7 +206,7 @@ __global__ __launch_bounds__(256) void k_sweep_int8(SweepArgs a) {
     }
     // sites in units of 32: a lane covers two per row, one in a half group
     const uint32_t units = !active ? 0u : (HALF && lane_id % a.groups + 1 == a.groups) ? 1u : 2u;
-    if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, units, 32u * a.rows);
+    if (OBS) block_accumulate(spread_line(a.obs, blockIdx.x), cnt.anti, cnt.neg, units, 32u * a.rows);
 }
 
 // ---- Fused sweep: both colours of one sweep in one pass over the lattice, out of place.
@@ -238,6 +236,7 @@ struct FusedArgs {
     uint32_t xcd_remap;  // renumber blocks per XCD (see logical_block)
     uint32_t nt_store;   // non-temporal stores of the output rows
     uint32_t alternate;  // walk odd strips upwards
+    uint32_t spread;     // k_sweep_fused2q: obs is a spread set (each workgroup adds into its line)
 };
 
 // Edge bits a thread publishes after step x: bit 0 / 1 = site 0 of the even columns / site 31 of
@@ -724,9 +723,10 @@ __global__ __launch_bounds__(1024) void k_sweep_fused2q(FusedArgs a) {
     else fused2q_strip<OBS, STAGED, false>(a, strip, fused_lds, ct, ct1);
     const bool active = threadIdx.x < a.groups;
     if (OBS) {
-        block_accumulate(a.obs, active ? ct.anti : 0u, active ? ct.neg : 0u, active ? 1u : 0u, 64u * a.rows);
+        int64_t* const out = a.spread ? spread_line(a.obs, blockIdx.x) : a.obs;
+        block_accumulate(out, active ? ct.anti : 0u, active ? ct.neg : 0u, active ? 1u : 0u, 64u * a.rows);
         __syncthreads();  // block_accumulate's LDS is reused
-        block_accumulate(a.obs + 2, active ? ct1.anti : 0u, active ? ct1.neg : 0u, active ? 1u : 0u, 64u * a.rows);
+        block_accumulate(out + 2, active ? ct1.anti : 0u, active ? ct1.neg : 0u, active ? 1u : 0u, 64u * a.rows);
     }
 }
 
@@ -1023,6 +1023,25 @@ __global__ void k_zero2(int64_t* p) {
     if (threadIdx.x == 0) { p[0] = 0; p[1] = 0; }
 }
 
+// One wave per spread set s: dst[s n + k] = the sum of word k (k < n <= 4) over the set's lines; the
+// lines are then cleared for the next launches that take the set.
+__global__ __launch_bounds__(64) void k_fold_spread(int64_t* sets, int64_t* dst, uint32_t n) {
+    const uint32_t lane = threadIdx.x;
+    int64_t* const line = sets + (size_t)blockIdx.x * kSpreadSetWords + (size_t)lane * kSpreadLineWords;
+    long long v[4];
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) v[k] = k < n ? line[k] : 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k)
+        if (k < n) line[k] = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    if (lane == 0)
+        for (uint32_t k = 0; k < n; ++k) dst[(size_t)blockIdx.x * n + k] = v[k];
+}
+
 // ---- hot start: bit (c & 31) of word (c >> 5) & 3 of Philox(c >> 7, r, 0, 0x80000000).
 __device__ __forceinline__ uint32_t nibble_to_bytes(uint32_t nib) {
     const uint32_t t = (nib * 0x00204081u) & 0x01010101u;  // bit j -> byte j (no carries)
@@ -1067,8 +1086,7 @@ struct PackedArgs {
     uint32_t L, groups, rows, n_lanes;
     uint32_t t, key0, key1;
     Thresholds th;
-    int64_t* obs;
-    int64_t* zero_slot;
+    int64_t* obs;  // OBS: a spread set (zeroed beforehand) that takes (M, E)
     uint32_t xcd_remap;
 };
 
@@ -1079,7 +1097,6 @@ struct PackedArgs {
 template <int Q, bool OBS, bool HALF = false>
 __global__ __launch_bounds__(256) void k_sweep_packed(PackedArgs a) {
     const uint32_t lane_id = logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * blockDim.x + threadIdx.x;
-    if (a.zero_slot && lane_id == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
     const bool active = lane_id < a.n_lanes;
     Counts cnt{0u, 0u};
     if (active) {
@@ -1125,7 +1142,7 @@ __global__ __launch_bounds__(256) void k_sweep_packed(PackedArgs a) {
     }
     // sites in units of 32: a lane covers two per row, one in a half group
     const uint32_t units = !active ? 0u : (HALF && lane_id % a.groups + 1 == a.groups) ? 1u : 2u;
-    if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, units, 32u * a.rows);
+    if (OBS) block_accumulate(spread_line(a.obs, blockIdx.x), cnt.anti, cnt.neg, units, 32u * a.rows);
 }
 
 // Half-sweep on the packed layout with the ties of four rows settled together.  All colour-Q sites
@@ -1140,7 +1157,6 @@ __global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
     uint4* const mine = packed_lds + (tid >> 6) * (kTieQueueBytes / 16u);
     const TieQueue q{reinterpret_cast<uint32_t*>(mine), mine + 256};
     const uint32_t raw_id = logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * blockDim.x + tid;
-    if (a.zero_slot && raw_id == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
     const bool active = raw_id < a.n_lanes;
     const uint32_t lane_id = active ? raw_id : a.n_lanes - 1u;
     Counts cnt{0u, 0u};
@@ -1223,7 +1239,8 @@ __global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
     }
     // sites in units of 32: a lane covers two per row, one in a half group
     const uint32_t units = !active ? 0u : half ? 1u : 2u;
-    if (OBS) block_accumulate(a.obs, active ? cnt.anti : 0u, active ? cnt.neg : 0u, units, 32u * a.rows);
+    if (OBS) block_accumulate(spread_line(a.obs, blockIdx.x), active ? cnt.anti : 0u, active ? cnt.neg : 0u, units,
+                              32u * a.rows);
 }
 
 // (M, E) of a packed lattice: every bond has exactly one black (q = 0) end, so the black sites'
@@ -1771,10 +1788,14 @@ __global__ void k_moments(const int64_t* trace, int64_t n, int64_t n_sites, doub
     out[4] = s_e2 / k;
 }
 
-// The second lattice buffer of ising_sweep_fused_static, for callers that cannot allocate device
-// memory: 64 MiB, the scratch lattice of L <= 8192.  Each GPU the library runs on holds its own copy
-// from the module's load to the end of the process.
-constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+// The device memory of ising_sweep_fused_static, for callers that cannot allocate: 64 MiB for the
+// second lattice buffer (L <= 8192), then 512 KiB for the spread sets of its traced launches (64
+// sets of 8 KiB).  Each GPU the library runs on holds its own copy from the module's load to the end
+// of the process.
+constexpr size_t kStaticLatticeBytes = size_t(64) << 20;
+constexpr uint32_t kSpreadFold = 64;  // traced launches per fold (k_fold_spread)
+constexpr size_t kSpreadBytes = size_t(kSpreadFold) * kSpreadSetWords * sizeof(int64_t);
+constexpr size_t kStaticScratchBytes = kStaticLatticeBytes + kSpreadBytes;
 __device__ __align__(256) int8_t scratch[kStaticScratchBytes];
 
 }  // namespace ising
@@ -1920,7 +1941,7 @@ uint32_t rows_per_lane(int64_t L) {
 }
 
 int launch_half_sweep(int8_t* spins, int64_t L, const ising::Thresholds& th, uint64_t seed, uint32_t t,
-                      int q, int64_t* obs, int64_t* zero_slot, hipStream_t stream) {
+                      int q, int64_t* obs, hipStream_t stream) {
     ising::SweepArgs a;
     a.spins = spins;
     a.L = (uint32_t)L;
@@ -1932,7 +1953,6 @@ int launch_half_sweep(int8_t* spins, int64_t L, const ising::Thresholds& th, uin
     a.key1 = (uint32_t)(seed >> 32);
     a.th = th;
     a.obs = obs;
-    a.zero_slot = zero_slot;
     a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
     a.nt_store = g_opt.nt_store ? 1u : 0u;
     const dim3 grid((a.n_lanes + 255u) / 256u), block(256);
@@ -1974,9 +1994,9 @@ uint32_t fused_rows(int64_t L, int sweeps = 1) {
 
 // one fused sweep src -> dst (L <= kFusedMaxL, src and dst disjoint); obs: (M, E), zeroed beforehand
 // One pass of the fused kernel: `sweeps` (1 or 2) sweeps t, t + 1 from src to dst; obs: NULL or
-// 2 * sweeps int64, zeroed beforehand.
+// 2 * sweeps int64, zeroed beforehand, or with `spread` a spread set (zeroed beforehand).
 int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::Thresholds& th, uint64_t seed,
-                       uint32_t t, int64_t* obs, hipStream_t stream, int sweeps = 1) {
+                       uint32_t t, int64_t* obs, hipStream_t stream, int sweeps = 1, bool spread = false) {
     ising::FusedArgs a;
     a.src = src;
     a.dst = dst;
@@ -1991,6 +2011,8 @@ int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::T
     a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
     a.nt_store = g_opt.nt_store ? 1u : 0u;
     a.alternate = g_opt.fused_alternate ? 1u : 0u;
+    // a kernel other than k_sweep_fused2q adds into the set's first line, which the fold counts as well
+    a.spread = spread ? 1u : 0u;
     const uint32_t threads = (a.groups + 63u) / 64u * 64u;
     const bool staged = g_opt.staged && a.groups % 64u == 0;
     const bool ties = g_opt.fused_ties != 0;
@@ -2077,6 +2099,11 @@ bool disjoint(const void* a, const void* b, uint64_t bytes) {
     return x + bytes <= y || y + bytes <= x;
 }
 
+bool disjoint_ranges(const void* a, uint64_t a_bytes, const void* b, uint64_t b_bytes) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x + a_bytes <= y || y + b_bytes <= x;
+}
+
 int zero_trace(int64_t* p, int64_t n, hipStream_t stream) {
     if (n <= 0) return ISING_OK;
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
@@ -2105,6 +2132,100 @@ int static_scratch(int8_t** out) {
     *out = g_scratch_addr[dev];
     return ISING_OK;
 }
+
+// ---- Spread sets of the traced sweep loops.  Up to kSpreadFold traced launches take a set each
+// (their workgroups add (M, E) into the set's lines, see spread_line), then one k_fold_spread launch
+// writes each set's sums into its trace entries and clears the set.  The sets come from a
+// stream-ordered pool that the library keeps per device, so that calls on different streams never
+// share one and no call waits for another; ising_sweep_fused_static passes its own.
+std::mutex g_pool_mu;
+hipMemPool_t g_pool[kMaxDevices] = {};
+
+int spread_pool(hipMemPool_t* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_failed(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return ISING_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (!g_pool[dev]) {
+        hipMemPoolProps props = {};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t pool = nullptr;
+        e = hipMemPoolCreate(&pool, &props);
+        if (e != hipSuccess) return hip_failed(e, "hipMemPoolCreate");
+        // keep freed blocks for the next calls rather than returning them at each synchronisation
+        uint64_t keep = UINT64_MAX;
+        e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        if (e != hipSuccess) {
+            (void)hipMemPoolDestroy(pool);
+            return hip_failed(e, "hipMemPoolSetAttribute");
+        }
+        g_pool[dev] = pool;
+    }
+    *out = g_pool[dev];
+    return ISING_OK;
+}
+
+class SpreadTrace {
+  public:
+    SpreadTrace() = default;
+    SpreadTrace(const SpreadTrace&) = delete;
+    SpreadTrace& operator=(const SpreadTrace&) = delete;
+    ~SpreadTrace() {
+        if (owned_) (void)hipFreeAsync(sets_, s_);
+    }
+    // n_launches: traced launches to come (the sets to clear); given: kSpreadBytes of device memory
+    // for the sets, or null to take them from the pool (returned at destruction, in stream order)
+    int begin(int64_t* given, int64_t n_launches, hipStream_t s) {
+        s_ = s;
+        if (given) {
+            sets_ = given;
+        } else {
+            hipMemPool_t pool = nullptr;
+            const int rc = spread_pool(&pool);
+            if (rc) return rc;
+            void* p = nullptr;
+            const hipError_t e = hipMallocFromPoolAsync(&p, ising::kSpreadBytes, pool, s);
+            if (e != hipSuccess) return hip_failed(e, "hipMallocFromPoolAsync");
+            sets_ = static_cast<int64_t*>(p);
+            owned_ = true;
+        }
+        const int64_t n = std::min<int64_t>(n_launches, ising::kSpreadFold);
+        return zero_trace(sets_, n * (int64_t)ising::kSpreadSetWords, s);
+    }
+    // The set of the next traced launch, whose n (<= 4) values belong at dst.  The launches between two
+    // folds write consecutive trace entries; a launch that does not continue them folds first.
+    int next(int64_t* dst, uint32_t n, int64_t** set) {
+        if (used_ == ising::kSpreadFold || (used_ > 0 && (n != n_ || dst != dst0_ + (size_t)used_ * n_))) {
+            const int rc = fold();
+            if (rc) return rc;
+        }
+        if (used_ == 0) {
+            dst0_ = dst;
+            n_ = n;
+        }
+        *set = sets_ + (size_t)used_ * ising::kSpreadSetWords;
+        ++used_;
+        return ISING_OK;
+    }
+    // the sums of the sets taken since the last fold into their trace entries
+    int fold() {
+        if (used_ == 0) return ISING_OK;
+        hipLaunchKernelGGL(ising::k_fold_spread, dim3(used_), dim3(64), 0, s_, sets_, dst0_, n_);
+        used_ = 0;
+        return check_launch("k_fold_spread");
+    }
+
+  private:
+    int64_t* sets_ = nullptr;
+    bool owned_ = false;
+    hipStream_t s_ = nullptr;
+    int64_t* dst0_ = nullptr;
+    uint32_t n_ = 0, used_ = 0;
+};
 
 }  // namespace
 
@@ -2412,7 +2533,7 @@ int autotune_batch(const ising_replica_t* reps, int64_t n, const BatchBuffers& b
 
 namespace {
 int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Thresholds& th, uint64_t seed, uint32_t t,
-                             int q, int64_t* obs, int64_t* zero_slot, hipStream_t stream) {
+                             int q, int64_t* obs, hipStream_t stream) {
     ising::PackedArgs a;
     a.planes = planes;
     a.L = (uint32_t)L;
@@ -2424,7 +2545,6 @@ int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Threshold
     a.key1 = (uint32_t)(seed >> 32);
     a.th = th;
     a.obs = obs;
-    a.zero_slot = zero_slot;
     a.xcd_remap = g_opt.xcd_remap ? 1u : 0u;
     const bool half = L % 64 != 0;  // each row ends in a half group
     const dim3 grid((a.n_lanes + 255u) / 256u), block(256);
@@ -2458,6 +2578,99 @@ int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Threshold
 #undef ISING_LAUNCH_PACKED
     return check_launch("k_sweep_packed");
 }
+}  // namespace
+
+namespace {
+
+// n_sweeps sweeps in place, one launch per colour; trace_ME: NULL or 2 n_sweeps int64 (M, E after
+// each sweep).  sets: kSpreadBytes for the spread sets of the traced launches, or NULL (the pool).
+int sweep_int8(int8_t* spins, int64_t L, const ising::Thresholds& th, int64_t n_sweeps, uint64_t seed,
+               uint64_t sweep_offset, int64_t* trace_ME, hipStream_t s, int64_t* sets) {
+    SpreadTrace sp;
+    if (trace_ME && n_sweeps > 0) {
+        const int rc = sp.begin(sets, n_sweeps, s);
+        if (rc) return rc;
+    }
+    for (int64_t i = 0; i < n_sweeps; ++i) {
+        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
+        int64_t* set = nullptr;
+        if (trace_ME) {
+            const int rc = sp.next(trace_ME + 2 * i, 2, &set);
+            if (rc) return rc;
+        }
+        int rc = launch_half_sweep(spins, L, th, seed, t, 1, nullptr, s);  // white
+        if (rc) return rc;
+        rc = launch_half_sweep(spins, L, th, seed, t, 0, set, s);          // black (+ M, E)
+        if (rc) return rc;
+    }
+    return sp.fold();
+}
+
+// ising_sweep_fused after validation (scratch: the second lattice buffer; sets as in sweep_int8).
+int sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, const ising::Thresholds& th, int64_t n_sweeps,
+                uint64_t seed, uint64_t sweep_offset, int64_t* trace_ME, hipStream_t s, int64_t* sets) {
+    // the passes take whole 64-column groups: a row that ends in a half group sweeps in place
+    if (L % 64 != 0) return sweep_int8(spins, L, th, n_sweeps, seed, sweep_offset, trace_ME, s, sets);
+    const bool bands = use_bands(L);
+    const bool single_passes = L <= kFusedMaxL;  // the one-sweep pass needs a whole row per workgroup
+    const bool two = g_opt.fused_sweeps == 2;
+    if (!single_passes && !two) return sweep_int8(spins, L, th, n_sweeps, seed, sweep_offset, trace_ME, s, sets);
+    int64_t i = 0;
+    if (n_sweeps & 1) {  // an odd count: the first sweep in place, so that the pairs end in `spins`
+        const int rc = sweep_int8(spins, L, th, 1, seed, sweep_offset, trace_ME, s, sets);
+        if (rc) return rc;
+        i = 1;
+    }
+    if (trace_ME) {  // for the launches that add into the trace itself
+        const int rc = zero_trace(trace_ME + 2 * i, 2 * (n_sweeps - i), s);
+        if (rc) return rc;
+    }
+    // The rest (an even count) in passes that alternate between the two buffers and end in
+    // `spins`: two sweeps per pass when the option allows, in an even number of passes.  An odd
+    // number of two-sweep passes gives one of them up for two one-sweep passes, or, where there is no
+    // one-sweep pass (above L = 65536), for two sweeps in place at the end.  Traced full-row
+    // two-sweep passes add (M, E) into spread sets.
+    const int64_t rest = n_sweeps - i;
+    int64_t pairs = two ? rest / 2 : 0;
+    if (pairs & 1) --pairs;
+    SpreadTrace sp;
+    if (trace_ME && pairs > 0 && !bands) {
+        const int rc = sp.begin(sets, pairs, s);
+        if (rc) return rc;
+    }
+    int8_t* bufs[2] = {spins, scratch};
+    int64_t pass = 0;
+    while (i < n_sweeps) {
+        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
+        int64_t* obs = trace_ME ? trace_ME + 2 * i : nullptr;
+        int rc = ISING_OK;
+        if (pairs > 0) {
+            if (bands) {
+                rc = launch_band_pass(bufs[pass & 1], bufs[(pass + 1) & 1], L, th, seed, t, obs, s);
+            } else {
+                int64_t* set = nullptr;
+                if (obs) rc = sp.next(obs, 4, &set);
+                if (!rc)
+                    rc = launch_fused_sweep(bufs[pass & 1], bufs[(pass + 1) & 1], L, th, seed, t, set ? set : obs, s, 2,
+                                            set != nullptr);
+            }
+            --pairs;
+            i += 2;
+            ++pass;
+        } else if (single_passes) {
+            rc = launch_fused_sweep(bufs[pass & 1], bufs[(pass + 1) & 1], L, th, seed, t, obs, s, 1);
+            i += 1;
+            ++pass;
+        } else {
+            rc = sp.fold();  // the in-place sweeps may take the same sets
+            if (!rc) rc = sweep_int8(spins, L, th, n_sweeps - i, seed, t, obs, s, sets);
+            i = n_sweeps;
+        }
+        if (rc) return rc;
+    }
+    return sp.fold();
+}
+
 }  // namespace
 
 // Definitions of the helpers declared in host.hpp (used by the 3-D translation unit).
@@ -2541,8 +2754,7 @@ int ising_half_sweep(int8_t* spins, int64_t L, double beta, uint64_t seed, uint6
     if (!spins || !valid_L(L) || !aligned16(spins) || !valid_beta(beta) || (q != 0 && q != 1) ||
         t >= (uint64_t(1) << 32))
         return ISING_EINVAL;
-    return launch_half_sweep(spins, L, make_thresholds(beta), seed, (uint32_t)t, q, nullptr, nullptr,
-                             (hipStream_t)stream);
+    return launch_half_sweep(spins, L, make_thresholds(beta), seed, (uint32_t)t, q, nullptr, (hipStream_t)stream);
 }
 
 int ising_sweep(int8_t* spins, int64_t L, double beta, int64_t n_sweeps, uint64_t seed, uint64_t sweep_offset,
@@ -2555,17 +2767,8 @@ int ising_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sw
     if (!spins || !valid_L(L) || !aligned16(spins) || !valid_beta(beta) || n_sweeps < 0 || fmt < 0 || fmt > 2 ||
         sweep_offset > (uint64_t(1) << 32) || (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset)
         return ISING_EINVAL;
-    const ising::Thresholds th = make_thresholds(beta, fmt);
-    hipStream_t s = (hipStream_t)stream;
-    for (int64_t i = 0; i < n_sweeps; ++i) {
-        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
-        int64_t* slot = trace_ME ? trace_ME + 2 * i : nullptr;
-        int rc = launch_half_sweep(spins, L, th, seed, t, 1, nullptr, slot, s);  // white
-        if (rc) return rc;
-        rc = launch_half_sweep(spins, L, th, seed, t, 0, slot, nullptr, s);      // black (+ M, E)
-        if (rc) return rc;
-    }
-    return ISING_OK;
+    return sweep_int8(spins, L, make_thresholds(beta, fmt), n_sweeps, seed, sweep_offset, trace_ME,
+                      (hipStream_t)stream, nullptr);
 }
 
 int ising_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, int fmt, int64_t n_sweeps,
@@ -2574,63 +2777,25 @@ int ising_sweep_fused(int8_t* spins, int8_t* scratch, int64_t L, double beta, in
         n_sweeps < 0 || fmt < 0 || fmt > 2 || sweep_offset > (uint64_t(1) << 32) ||
         (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset || !disjoint(spins, scratch, (uint64_t)L * (uint64_t)L))
         return ISING_EINVAL;
-    // the passes take whole 64-column groups: a row that ends in a half group sweeps in place
-    if (L % 64 != 0) return ising_sweep_fmt(spins, L, beta, fmt, n_sweeps, seed, sweep_offset, trace_ME, stream);
-    const bool bands = use_bands(L);
-    const bool single_passes = L <= kFusedMaxL;  // the one-sweep pass needs a whole row per workgroup
-    if (!single_passes && g_opt.fused_sweeps != 2)
-        return ising_sweep_fmt(spins, L, beta, fmt, n_sweeps, seed, sweep_offset, trace_ME, stream);
-    const ising::Thresholds th = make_thresholds(beta, fmt);
-    hipStream_t s = (hipStream_t)stream;
-    int64_t i = 0;
-    if (n_sweeps & 1) {  // an odd count: the first sweep in place, so that the pairs end in `spins`
-        const int rc = ising_sweep_fmt(spins, L, beta, fmt, 1, seed, sweep_offset, trace_ME, stream);
-        if (rc) return rc;
-        i = 1;
-    }
-    if (trace_ME) {
-        const int rc = zero_trace(trace_ME + 2 * i, 2 * (n_sweeps - i), s);
-        if (rc) return rc;
-    }
-    // The rest (an even count) in passes that alternate between the two buffers and end in
-    // `spins`: two sweeps per pass when the option allows, in an even number of passes.  An odd
-    // number of two-sweep passes gives one of them up for two one-sweep passes, or, where there is no
-    // one-sweep pass (above L = 65536), for two sweeps in place at the end.
-    const int64_t rest = n_sweeps - i;
-    int64_t pairs = g_opt.fused_sweeps == 2 ? rest / 2 : 0;
-    if (pairs & 1) --pairs;
-    int8_t* bufs[2] = {spins, scratch};
-    int64_t pass = 0;
-    while (i < n_sweeps) {
-        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
-        int64_t* obs = trace_ME ? trace_ME + 2 * i : nullptr;
-        int rc;
-        if (pairs > 0) {
-            rc = bands ? launch_band_pass(bufs[pass & 1], bufs[(pass + 1) & 1], L, th, seed, t, obs, s)
-                       : launch_fused_sweep(bufs[pass & 1], bufs[(pass + 1) & 1], L, th, seed, t, obs, s, 2);
-            --pairs;
-            i += 2;
-            ++pass;
-        } else if (single_passes) {
-            rc = launch_fused_sweep(bufs[pass & 1], bufs[(pass + 1) & 1], L, th, seed, t, obs, s, 1);
-            i += 1;
-            ++pass;
-        } else {
-            rc = ising_sweep_fmt(spins, L, beta, fmt, n_sweeps - i, seed, t, obs, stream);
-            i = n_sweeps;
-        }
-        if (rc) return rc;
-    }
-    return ISING_OK;
+    return sweep_fused(spins, scratch, L, make_thresholds(beta, fmt), n_sweeps, seed, sweep_offset, trace_ME,
+                       (hipStream_t)stream, nullptr);
 }
 
 int ising_sweep_fused_static(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sweeps, uint64_t seed,
                              uint64_t sweep_offset, int64_t* trace_ME, void* stream) {
-    if (!spins || !valid_L(L) || (uint64_t)L * (uint64_t)L > ising::kStaticScratchBytes) return ISING_EINVAL;
-    int8_t* scratch = nullptr;
-    const int rc = static_scratch(&scratch);
+    if (!spins || !valid_L(L) || (uint64_t)L * (uint64_t)L > ising::kStaticLatticeBytes || !aligned16(spins) ||
+        !valid_beta(beta) || n_sweeps < 0 || fmt < 0 || fmt > 2 || sweep_offset > (uint64_t(1) << 32) ||
+        (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset)
+        return ISING_EINVAL;
+    int8_t* base = nullptr;
+    const int rc = static_scratch(&base);
     if (rc) return rc;
-    return ising_sweep_fused(spins, scratch, L, beta, fmt, n_sweeps, seed, sweep_offset, trace_ME, stream);
+    // the lattice buffer, then the spread sets
+    int8_t* const lattice = base;
+    int64_t* const sets = reinterpret_cast<int64_t*>(base + ising::kStaticLatticeBytes);
+    if (!disjoint_ranges(spins, (uint64_t)L * (uint64_t)L, base, ising::kStaticScratchBytes)) return ISING_EINVAL;
+    return sweep_fused(spins, lattice, L, make_thresholds(beta, fmt), n_sweeps, seed, sweep_offset, trace_ME,
+                       (hipStream_t)stream, sets);
 }
 
 int ising_sweep_fused_step(const int8_t* src, int8_t* dst, int64_t L, double beta, int fmt, uint64_t seed,
@@ -2735,7 +2900,7 @@ int ising_half_sweep_packed(uint32_t* planes, int64_t L, double beta, uint64_t s
     if (!planes || !valid_L(L) || !aligned16(planes) || !valid_beta(beta) || (q != 0 && q != 1) ||
         t >= (uint64_t(1) << 32))
         return ISING_EINVAL;
-    return launch_half_sweep_packed(planes, L, make_thresholds(beta), seed, (uint32_t)t, q, nullptr, nullptr,
+    return launch_half_sweep_packed(planes, L, make_thresholds(beta), seed, (uint32_t)t, q, nullptr,
                                     (hipStream_t)stream);
 }
 
@@ -2752,15 +2917,24 @@ int ising_sweep_packed_fmt(uint32_t* planes, int64_t L, double beta, int fmt, in
         return ISING_EINVAL;
     const ising::Thresholds th = make_thresholds(beta, fmt);
     hipStream_t s = (hipStream_t)stream;
-    for (int64_t i = 0; i < n_sweeps; ++i) {
-        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
-        int64_t* slot = trace_ME ? trace_ME + 2 * i : nullptr;
-        int rc = launch_half_sweep_packed(planes, L, th, seed, t, 1, nullptr, slot, s);
-        if (rc) return rc;
-        rc = launch_half_sweep_packed(planes, L, th, seed, t, 0, slot, nullptr, s);
+    SpreadTrace sp;
+    if (trace_ME && n_sweeps > 0) {
+        const int rc = sp.begin(nullptr, n_sweeps, s);
         if (rc) return rc;
     }
-    return ISING_OK;
+    for (int64_t i = 0; i < n_sweeps; ++i) {
+        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
+        int64_t* set = nullptr;
+        if (trace_ME) {
+            const int rc = sp.next(trace_ME + 2 * i, 2, &set);
+            if (rc) return rc;
+        }
+        int rc = launch_half_sweep_packed(planes, L, th, seed, t, 1, nullptr, s);
+        if (rc) return rc;
+        rc = launch_half_sweep_packed(planes, L, th, seed, t, 0, set, s);  // (+ M, E)
+        if (rc) return rc;
+    }
+    return sp.fold();
 }
 
 int ising_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME, void* stream) {

@@ -338,6 +338,18 @@ __device__ __forceinline__ void block_accumulate(int64_t* out, uint32_t anti, ui
     }
 }
 
+// ---- Spread accumulation of (M, E).  Atomics of every workgroup of a launch on the same two words
+// queue at one memory channel as the workgroups end.  A traced launch of the sweep loops adds into
+// one of kSpreadLines 128-byte lines of a set (the line chosen by workgroup) instead, and a later
+// one-wave-per-set kernel sums each set's lines into the trace and clears them.
+constexpr uint32_t kSpreadLines = 64;
+constexpr uint32_t kSpreadLineWords = 16;                              // int64 per 128-byte line
+constexpr uint32_t kSpreadSetWords = kSpreadLines * kSpreadLineWords;  // one launch's set: 8 KiB
+
+__device__ __forceinline__ int64_t* spread_line(int64_t* set, uint32_t block) {
+    return set + (size_t)(block % kSpreadLines) * kSpreadLineWords;
+}
+
 struct RowBits {
     uint32_t e, o;  // sign bits of the even / odd columns of one group of one row, site order
 };

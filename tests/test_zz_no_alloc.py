@@ -40,7 +40,25 @@ def test_static_scratch_matches_caller_scratch_on_two_calls(dev):
 
 
 def test_static_scratch_rejects_lattices_past_its_size(dev):
-    L = 8256                                    # L^2 > 64 MiB
+    L = 8256                                    # L^2 > 64 MiB (the lattice part of the array)
     s = torch.empty((L, L), dtype=torch.int8, device="cuda")
     with pytest.raises(dev.IsingError):
         dev.ising_sweep_fused_static(s, L, BETA_C, "exact", 2, 1, 0)
+
+
+def test_static_spread_sets_over_several_folds(dev):
+    # the traced launches' spread sets sit in the static array too: more traced launches than one
+    # fold takes (64), on the two-sweep path (L = 192) and in place (L = 160, a half group per row)
+    for L, n, seed in ((192, 261, 6), (160, 70, 7)):
+        print("no-alloc long trace", L, n, seed, flush=True)
+        a = torch.empty((L, L), dtype=torch.int8, device="cuda")
+        dev.ising_init(a, L, seed)
+        b = a.clone()
+        scratch = torch.empty_like(a)
+        ta = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+        tb = torch.full_like(ta, -3)
+        dev.ising_sweep_fused(a, scratch, L, BETA_C, "exact", n, seed, 2, ta)
+        dev.ising_sweep_fused_static(b, L, BETA_C, "exact", n, seed, 2, tb)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), L
+        assert torch.equal(ta, tb), L
