@@ -302,8 +302,10 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
 /* Launch-shape options of the int8 kernels, process-wide; results are bit-identical for every
  * valid setting (the random numbers depend only on site, sweep and colour).  Not thread-safe
  * against concurrent launches.
- *   "rows_per_lane"  rows each lane streams through: 0 = automatic, else a power of two in
- *                    [2, 64] (ignored for lattices it does not divide).
+ *   "rows_per_lane"  rows each lane of a one-colour launch (int8 or packed) streams through:
+ *                    0 = automatic (int8: the tallest up to 32 that leaves 2^18 lanes; packed: up
+ *                    to 32 leaving 2^19 lanes, 4 at least), else a power of two in [2, 64]
+ *                    (ignored for lattices it does not divide).
  *   "xcd_remap"      1 = hand each XCD one contiguous range of row strips (default), 0 = not.
  *   "nt_store"       1 = non-temporal stores of updated rows, 0 = ordinary stores (default).
  *   "staged"         1 = coalesced row loads and stores regrouped through LDS when L is a

@@ -1150,7 +1150,7 @@ __global__ __launch_bounds__(256) void k_sweep_packed(PackedArgs a) {
 // the first two Philox blocks of each row's word, queues the words still holding tied sites and
 // settles them with the other lanes' (as in the two-sweep pass).  Same uniforms and results as
 // k_sweep_packed.  rows % 4 == 0; lanes past n_lanes shadow the last lane without storing.
-template <int Q, bool OBS, bool HALF = false>
+template <int Q, bool OBS, bool HALF = false, bool O32 = false>
 __global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
     extern __shared__ uint4 packed_lds[];
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
@@ -1170,24 +1170,48 @@ __global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
     const uint32_t valid = half ? kHalfSites : 0xFFFFFFFFu;
     uint32_t* const pq = a.planes + (size_t)Q * L * W;              // sites being updated
     const uint32_t* const po = a.planes + (size_t)(1 - Q) * L * W;  // other colour
+    // O32 (a plane of at most 4 GiB): word (r, gg) of a plane at a 32-bit byte offset from its base,
+    // so that a load takes the base from scalar registers and one 32-bit offset per lane
+    auto word_at = [&](const uint32_t* plane, uint32_t r, uint32_t gg) -> const uint32_t* {
+        if (O32) return reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(plane) + (r * W + gg) * 4u);
+        return plane + (size_t)r * W + gg;
+    };
+    // the same from a row's word offset r W (O32)
+    auto word_off = [&](const uint32_t* plane, uint32_t rw, uint32_t gg) -> const uint32_t* {
+        return reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(plane) + (rw + gg) * 4u);
+    };
     // row r + i (r even): colour-Q sites at column parity Q for even i, 1 - Q for odd i; parity 1
     // takes the right group's site 0 as the far horizontal neighbour, parity 0 the left group's
     // site 31
-    uint32_t bprev = po[(size_t)(r0 == 0 ? L - 1 : r0 - 1) * W + g];
-    uint32_t bcur = po[(size_t)r0 * W + g];
+    uint32_t bprev = *word_at(po, r0 == 0 ? L - 1 : r0 - 1, g);
+    uint32_t bcur = *word_at(po, r0, g);
 #pragma unroll 1
     for (uint32_t s = 0; s < R; s += 4) {
         const uint32_t r = r0 + s;
         uint32_t b[6], w[4], e[4];
         b[0] = bprev;
         b[1] = bcur;
+        if (O32) {
+            // row offsets by additions from r W; only row r + 4 == L wraps (to row 0)
+            const uint32_t rw = r * W;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t ri = r + (uint32_t)i, rn = ri + 1u >= L ? ri + 1u - L : ri + 1u;
-            b[i + 2] = po[(size_t)rn * W + g];
-            w[i] = pq[(size_t)ri * W + g];
-            const bool right = (Q == 1) == ((i & 1) == 0);
-            e[i] = po[(size_t)ri * W + (right ? gr : gl)];
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t ri_w = rw + (uint32_t)i * W;
+                const uint32_t rn_w = r + (uint32_t)i + 1u == L ? 0u : ri_w + W;
+                b[i + 2] = *word_off(po, rn_w, g);
+                w[i] = *word_off(pq, ri_w, g);
+                const bool right = (Q == 1) == ((i & 1) == 0);
+                e[i] = *word_off(po, ri_w, right ? gr : gl);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t ri = r + (uint32_t)i, rn = ri + 1u >= L ? ri + 1u - L : ri + 1u;
+                b[i + 2] = *word_at(po, rn, g);
+                w[i] = *word_at(pq, ri, g);
+                const bool right = (Q == 1) == ((i & 1) == 0);
+                e[i] = *word_at(po, ri, right ? gr : gl);
+            }
         }
         q.res[lane] = make_uint4(0u, 0u, 0u, 0u);
         uint32_t n = 0u;
@@ -1223,7 +1247,7 @@ __global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
         w[3] ^= res.w;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            if (active) pq[(size_t)(r + (uint32_t)i) * W + g] = w[i];
+            if (active) *const_cast<uint32_t*>(word_at(pq, r + (uint32_t)i, g)) = w[i];
             if (OBS) {
                 const bool right = (Q == 1) == ((i & 1) == 0);
                 const uint32_t side = b[i + 1];
@@ -2532,13 +2556,24 @@ int autotune_batch(const ising_replica_t* reps, int64_t n, const BatchBuffers& b
 }  // namespace
 
 namespace {
+// Rows per lane of the packed half-sweep: a lane's word is 32 sites (a quarter of the int8 lane's
+// 128), so it takes more lanes to fill the chip.  The tallest strip up to 32 rows that leaves 2^19
+// lanes (8 waves per SIMD), 4 rows at least (the tie queue takes four rows at a time).
+uint32_t packed_rows(int64_t L) {
+    if (g_opt.rows_per_lane > 0 && L % g_opt.rows_per_lane == 0) return (uint32_t)g_opt.rows_per_lane;
+    const uint64_t groups = groups_of(L);
+    uint32_t R = 32;
+    while (R > 4 && (groups * (uint64_t)(L / R) < (1ull << 19) || L % R != 0)) R >>= 1;
+    return R;
+}
+
 int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Thresholds& th, uint64_t seed, uint32_t t,
                              int q, int64_t* obs, hipStream_t stream) {
     ising::PackedArgs a;
     a.planes = planes;
     a.L = (uint32_t)L;
     a.groups = groups_of(L);
-    a.rows = rows_per_lane(L);
+    a.rows = packed_rows(L);
     a.n_lanes = a.groups * (uint32_t)(L / a.rows);
     a.t = t;
     a.key0 = (uint32_t)seed;
@@ -2554,18 +2589,31 @@ int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Threshold
         else hipLaunchKernelGGL((ising::K<QQ, OO, false>), G, B, LDS, stream, a);                  \
     } while (0)
     if (g_opt.packed_ties && a.rows % 4u == 0) {
-        // a counting launch ends every workgroup with atomics on the same two words: 512 threads
-        // per workgroup halve them (the others keep 256, which leaves more waves per CU)
+        // a counting launch takes 512 threads per workgroup (half the end-of-launch reductions of
+        // 256; measured no slower), the others 256, which leaves more waves per CU
         const uint32_t threads = obs ? 512u : 256u;
         const dim3 qgrid((a.n_lanes + threads - 1u) / threads), qblock(threads);
         const size_t lds = (threads / 64u) * ising::kTieQueueBytes;
+        // 32-bit offsets within a plane while it spans at most 4 GiB (L <= 2^18)
+        const bool o32 = (uint64_t)L * a.groups * 4u <= (uint64_t(1) << 32);
+#define ISING_LAUNCH_PACKED_Q(QQ, OO)                                                                      \
+    do {                                                                                                   \
+        if (half) {                                                                                        \
+            if (o32) hipLaunchKernelGGL((ising::k_sweep_packed_q<QQ, OO, true, true>), qgrid, qblock, lds, stream, a);   \
+            else hipLaunchKernelGGL((ising::k_sweep_packed_q<QQ, OO, true, false>), qgrid, qblock, lds, stream, a);      \
+        } else {                                                                                           \
+            if (o32) hipLaunchKernelGGL((ising::k_sweep_packed_q<QQ, OO, false, true>), qgrid, qblock, lds, stream, a);  \
+            else hipLaunchKernelGGL((ising::k_sweep_packed_q<QQ, OO, false, false>), qgrid, qblock, lds, stream, a);     \
+        }                                                                                                  \
+    } while (0)
         if (q == 1) {
-            if (obs) ISING_LAUNCH_PACKED(k_sweep_packed_q, 1, true, qgrid, qblock, lds);
-            else ISING_LAUNCH_PACKED(k_sweep_packed_q, 1, false, qgrid, qblock, lds);
+            if (obs) ISING_LAUNCH_PACKED_Q(1, true);
+            else ISING_LAUNCH_PACKED_Q(1, false);
         } else {
-            if (obs) ISING_LAUNCH_PACKED(k_sweep_packed_q, 0, true, qgrid, qblock, lds);
-            else ISING_LAUNCH_PACKED(k_sweep_packed_q, 0, false, qgrid, qblock, lds);
+            if (obs) ISING_LAUNCH_PACKED_Q(0, true);
+            else ISING_LAUNCH_PACKED_Q(0, false);
         }
+#undef ISING_LAUNCH_PACKED_Q
         return check_launch("k_sweep_packed_q");
     }
     if (q == 1) {
