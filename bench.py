@@ -169,6 +169,14 @@ def copy_bandwidth(torch, L: int, stream, reps: int = 20, in_place: bool = False
     return 2.0 * n / (ms * 1e-3) / 1e9
 
 
+CALIBRATION_MAX_BYTES = 1 << 30  # torch splits larger copies into several dispatches
+
+
+def calibration_bytes(L: int) -> int:
+    """Bytes of the plain copy whose counters calibrate FETCH_SIZE / WRITE_SIZE (one dispatch)."""
+    return min(L * L, CALIBRATION_MAX_BYTES)
+
+
 def calibration_copies(torch, nbytes: int, reps: int) -> None:
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the per-launch
     HBM traffic read from the same counters for a sweep kernel.  (int8 -> uint8 goes through an
@@ -470,6 +478,85 @@ def roofline(layout: str, L: int, avg_launch_ms: float, untraced_launch_ms: floa
     return roof
 
 
+COUNTER_KEYS = {
+    "FETCH_SIZE": "fetch_kib_raw", "WRITE_SIZE": "write_kib_raw", "VALUBusy": "valu_busy_pct",
+    "SQ_INSTS_VALU": "valu_insts_per_launch", "SQ_INSTS_SALU": "salu_insts_per_launch",
+    "SQ_INSTS_LDS": "lds_insts_per_launch", "SQ_WAVES": "waves_per_launch", "SQ_WAVE_CYCLES": "wave_cycles",
+    "SQ_WAIT_ANY": "wait_any_cycles", "SQ_WAIT_INST_ANY": "wait_inst_any_cycles",
+    "SQ_ACTIVE_INST_ANY": "active_inst_any_cycles", "SQ_ACTIVE_INST_VALU": "active_inst_valu_cycles",
+    "SQ_ACTIVE_INST_LDS": "active_inst_lds_cycles",
+}
+COPY_KERNEL = "direct_copy_kernel"  # the elementwise int8 -> uint8 copy of calibration_copies
+
+
+def read_counters(dirs) -> dict:
+    """Per-dispatch counter values from rocprofv3 --pmc CSV output: {kernel name: {counter: [value per
+    dispatch]}} (a counter's rows of one dispatch are summed)."""
+    import csv
+    import glob
+    per = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            acc = {}
+            with open(f, newline="") as fh:
+                for row in csv.DictReader(fh):
+                    key = (row["Dispatch_Id"], row["Kernel_Name"], row["Counter_Name"])
+                    acc[key] = acc.get(key, 0.0) + float(row["Counter_Value"])
+            for (_, kname, cname), v in acc.items():
+                per.setdefault(kname, {}).setdefault(cname, []).append(v)
+    return per
+
+
+def ingest_counters(key: str, layout: str, L: int, dirs, traced: str, untraced: str | None, copy_bytes: int,
+                    command: str) -> dict:
+    """Write profiles/traffic.json[key] from rocprofv3 --pmc runs of this repository's bench (`dirs`):
+    per-dispatch means of the kernel whose name contains `traced` (and of `untraced`, if given), the
+    HBM bytes per launch with FETCH_SIZE and WRITE_SIZE each scaled by what the same counter reads for
+    the plain copy of `copy_bytes` bytes each way (--copy-calibration), and the kernel source hash."""
+    per = read_counters(dirs)
+
+    def means(sub):
+        names = [k for k in per if sub in k]
+        if not names:
+            raise SystemExit(f"bench.py: no dispatch of a kernel matching {sub!r} in {dirs}")
+        out = {}
+        for cname, field in COUNTER_KEYS.items():
+            vals = [v for k in names for v in per[k].get(cname, [])]
+            if vals:
+                out[field] = sum(vals) / len(vals)
+        return out, names
+
+    entry, names = means(traced)
+    entry = {"kernel": names, **entry}
+    if untraced:
+        u, unames = means(untraced)
+        entry.update({"untraced_kernel": unames, **{f"untraced_{k}": v for k, v in u.items()}})
+    copy = [k for k in per if COPY_KERNEL in k]
+    if "fetch_kib_raw" in entry and "write_kib_raw" in entry and copy:
+        cf = [v for k in copy for v in per[k].get("FETCH_SIZE", [])]
+        cw = [v for k in copy for v in per[k].get("WRITE_SIZE", [])]
+        kib = copy_bytes / 1024.0
+        entry["fetch_scale"] = kib / (sum(cf) / len(cf))
+        entry["write_scale"] = kib / (sum(cw) / len(cw))
+        entry["copy_fetch_kib_raw"] = sum(cf) / len(cf)
+        entry["copy_write_kib_raw"] = sum(cw) / len(cw)
+        entry["hbm_bytes_per_launch"] = round(1024.0 * (entry["fetch_kib_raw"] * entry["fetch_scale"] +
+                                                        entry["write_kib_raw"] * entry["write_scale"]))
+    entry["alg_bytes_per_launch"] = algorithmic_bytes(layout, L)
+    entry["source_hash"] = kernel_source_hash()
+    entry["command"] = command
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        rec = {}
+    rec[key] = entry
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    return entry
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -507,8 +594,21 @@ def main() -> int:
                     help="library launch option (ising_set_option) for this run; every setting gives the same chain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
-                    help="also run this many plain device copies of an L^2-byte buffer (counter calibration)")
+                    help="also run this many plain device copies of min(L^2, 2^30) bytes (counter calibration)")
+    ap.add_argument("--ingest-counters", nargs="+", metavar="DIR", default=None,
+                    help="no GPU run: summarise the rocprofv3 --pmc output directories DIR... of this bench "
+                         "(--layout, --L, with --copy-calibration) into profiles/traffic.json")
+    ap.add_argument("--traced-kernel", default=None, help="--ingest-counters: name substring of the traced kernel")
+    ap.add_argument("--untraced-kernel", default=None, help="--ingest-counters: name substring of its untraced form")
+    ap.add_argument("--counters-command", default="", help="--ingest-counters: the profiling commands, for the record")
     args = ap.parse_args()
+
+    if args.ingest_counters:
+        key = f"{args.layout}_L{args.L}"
+        entry = ingest_counters(key, args.layout, args.L, args.ingest_counters, args.traced_kernel,
+                                args.untraced_kernel, calibration_bytes(args.L), args.counters_command)
+        print(json.dumps({key: entry}))
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -622,7 +722,7 @@ def main() -> int:
     if args.largest and args.layout == "fused" and L != LARGEST_L:
         result["largest"] = bench_largest(ising, torch, stream, seed, warm_floor=args.warm_floor)
     if args.copy_calibration:
-        calibration_copies(torch, L * L, args.copy_calibration)
+        calibration_copies(torch, calibration_bytes(L), args.copy_calibration)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(L, beta, seed, args.cpu_sweeps)

@@ -309,10 +309,21 @@ struct Counts {
     uint32_t neg;   // spins equal to -1 in the rows processed
 };
 
+// Sum over the 64 lanes of a wave (every lane active), returned to every lane.  Lane shifts (DPP)
+// instead of LDS permutes: prefix sums within each row of 16 lanes (row_shr by 1, 2, 3 of the value,
+// then by 4 and 8 on the upper banks), rows 1 and 3 add the last lane of the row before (row_bcast:15),
+// rows 2 and 3 that of row 1 (row_bcast:31); lane 63 then holds the total.  Masked-off lanes and lanes
+// shifted in from outside a row take 0.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    uint32_t x = v;
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x113, 0xf, 0xf, true);  // row_shr:3
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xe, true);  // row_shr:4, lanes 4..15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xc, true);  // row_shr:8, lanes 8..15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, true);  // row_bcast:15, rows 1, 3
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, true);  // row_bcast:31, rows 2, 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
 // Block-level sum of (anti, neg) -> one pair of 64-bit atomics per block.
