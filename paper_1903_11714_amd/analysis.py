@@ -169,6 +169,22 @@ def _crossing_in(temps, d, k):
     return float(temps[k] - d[k] / slope) if slope != 0 else float("nan")
 
 
+def _crossing_quad(temps, d, k):
+    """Zero of the least-squares quadratic through d at the four grid points around the bracket
+    [temps[k], temps[k + 1]] (three at the ends of the grid), the one nearest the bracket."""
+    lo, hi = max(0, k - 1), min(len(temps), k + 3)
+    if hi - lo < 3:
+        return _crossing_in(temps, d, k)
+    x = np.asarray(temps[lo:hi], dtype=np.float64) - temps[k]
+    c2, c1, c0 = np.polyfit(x, np.asarray(d[lo:hi], dtype=np.float64), 2)
+    roots = np.roots([c2, c1, c0]) if c2 != 0 else np.array([-c0 / c1])
+    roots = roots[np.isreal(roots)].real
+    if roots.size == 0:
+        return _crossing_in(temps, d, k)
+    mid = 0.5 * (temps[k + 1] - temps[k])
+    return float(temps[k] + roots[np.argmin(np.abs(roots - mid))])
+
+
 def crossing_blocks(m_series_pair, n: int, max_blocks: int = 50, min_blocks: int = 8) -> int:
     """Jackknife blocks for a crossing: each block spans at least four tau_int of the slowest replica
     of the two sizes (tau_int of m^2 and |m|), between min_blocks and max_blocks blocks."""
@@ -186,6 +202,10 @@ def u4_crossings(Ls, temps, m_series, n_blocks: int = 50) -> list:
     below T_c, near 0 above) D is noise and can change sign by chance, so the bracket taken is the
     rising sign change whose two end points are largest in units of their errors.  The crossing is
     the linear interpolation of D's zero in that bracket.
+
+    Interpolation: the zero of a quadratic through the four grid points around the bracket gives a
+    second estimate; their difference is reported as the interpolation error (syst), which the
+    jackknife does not see, and z_total divides by both errors in quadrature.
 
     Error: a jackknife over n_blocks synchronised time blocks.  Leaving block k out of EVERY
     replica's series (the replicas are independent chains, so any pairing of their blocks is a
@@ -236,7 +256,12 @@ def u4_crossings(Ls, temps, m_series, n_blocks: int = 50) -> list:
         t_star = _crossing_in(temps, d, k)
         t_loo = np.array([_crossing_in(temps, dl[:, j], k) for j in range(dl.shape[1])])
         err = jackknife_error(t_loo)
+        t_quad = _crossing_quad(temps, d, k)
+        syst = abs(t_quad - t_star)
+        tot = math.hypot(err, syst)
         out.append({"pair": [int(a), int(b)], "T_cross": t_star, "err": err, "n_blocks": int(dl.shape[1]),
                     "bracket": [float(temps[k]), float(temps[k + 1])], "significance": float(sig),
-                    "z_vs_Tc": float((t_star - T_C) / err) if err > 0 else None})
+                    "z_vs_Tc": float((t_star - T_C) / err) if err > 0 else None,
+                    "T_cross_quad": t_quad, "syst": syst,
+                    "z_total": float((t_star - T_C) / tot) if tot > 0 else None})
     return out

@@ -235,15 +235,18 @@ def batch_table(rec: dict) -> str:
     lines = [f"{rec['replicas']} replicas, L in {rec['Ls']}, {len(rec['temps'])} temperatures on "
              f"[{rec['temps'][0]:.3f}, {rec['temps'][-1]:.3f}], {rec['n_therm']} + {rec['n_meas']} sweeps: "
              f"{rec['seconds']:.3f} s, {rec['attempts_per_ns']:.0f} attempts/ns; schedule {rec['schedule']}.", "",
-             "| pair | T_cross ± jackknife | z vs T_c | bracket | jackknife blocks |", "|---|---|---|---|---|"]
+             "| pair | T_cross ± jackknife | z vs T_c | quadratic interpolation | ± interpolation | z (both errors) "
+             "| bracket | jackknife blocks |", "|---|---|---|---|---|---|---|---|"]
     for c in rec["crossings"]:
         if c.get("T_cross") is None:
-            lines.append(f"| {c['pair']} | none | — | — | — |")
+            lines.append(f"| {c['pair']} | none | — | — | — | — | — | — |")
         else:
-            z = c.get("z_vs_Tc")
+            z, zt = c.get("z_vs_Tc"), c.get("z_total")
+            quad = c.get("T_cross_quad")
             lines.append(f"| {c['pair'][0]}, {c['pair'][1]} | {c['T_cross']:.4f} ± {c['err']:.4f} | "
-                         f"{'—' if z is None else f'{z:.1f}'} | {c['bracket'][0]:.3f}–{c['bracket'][1]:.3f} | "
-                         f"{c['n_blocks']} |")
+                         f"{'—' if z is None else f'{z:.1f}'} | {'—' if quad is None else f'{quad:.4f}'} | "
+                         f"{'—' if quad is None else format(c['syst'], '.4f')} | {'—' if zt is None else f'{zt:.1f}'} | "
+                         f"{c['bracket'][0]:.3f}–{c['bracket'][1]:.3f} | {c['n_blocks']} |")
     lines += ["", f"Replicas with tau_int(|m| or m^2) above n_meas / 50 = {rec['tau_limit']:.0f} sweeps: "
               f"{len(rec['tau_flagged'])} of {rec['replicas']}"]
     by_L = {}

@@ -184,3 +184,28 @@ def test_u4_crossing_estimate_and_its_jackknife_error():
     assert abs(found.mean() - Tc) < 4 * found.std(ddof=1) / math.sqrt(found.size) + 2e-3
     ratio = np.sqrt(np.mean(np.square(errs))) / found.std(ddof=1)
     assert 0.7 < ratio < 1.5, ratio
+
+
+def test_quadratic_crossing_is_exact_for_a_quadratic_difference():
+    # d(T) = (T - 2.27)(T + 1) on a 0.012 grid: the quadratic through four points is d itself, while the
+    # chord between the bracket's end points misses the root by the curvature term
+    temps = np.round(np.arange(2.2, 2.35, 0.012), 6)
+    d = (temps - 2.27) * (temps + 1.0)
+    k = int(np.searchsorted(temps, 2.27)) - 1
+    assert A._crossing_quad(temps, d, k) == pytest.approx(2.27, abs=1e-12)
+    lin = A._crossing_in(temps, d, k)
+    assert abs(lin - 2.27) > 1e-7
+    d2 = (temps - 2.27) * (temps - 1.8) * 40.0          # stronger curvature, the same root
+    assert A._crossing_quad(temps, d2, k) == pytest.approx(2.27, abs=1e-12)
+    assert abs(A._crossing_in(temps, d2, k) - 2.27) > abs(lin - 2.27)
+
+
+def test_crossing_reports_interpolation_error_and_combined_z():
+    Tc, c, n = 2.275, 1.0, 20000
+    temps = np.linspace(2.17, 2.37, 11)
+    rng = np.random.default_rng(5)
+    series = {L: [_synthetic_m(rng, L, T, n, Tc, c) for T in temps] for L in (8, 16)}
+    (res,) = A.u4_crossings((8, 16), temps, series, n_blocks=20)
+    assert res["syst"] == pytest.approx(abs(res["T_cross_quad"] - res["T_cross"]))
+    assert abs(res["z_total"]) <= abs(res["z_vs_Tc"]) + 1e-12
+    assert res["z_total"] == pytest.approx((res["T_cross"] - A.T_C) / math.hypot(res["err"], res["syst"]))
