@@ -42,9 +42,10 @@ def _run(dev, layout, L, beta, n, seed, offset, stream=None):
 
 
 # (layout, L, sweeps): 259 sweeps on the two-sweep path = 1 in place + 129 passes -> 128 two-sweep
-# passes (two folds) and two one-sweep passes; 131 sweeps of one colour per launch = three folds
-@pytest.mark.parametrize("layout,L,n", [("fused", 128, 259), ("fused", 160, 70), ("int8", 96, 131),
-                                        ("packed", 128, 131), ("packed", 96, 65)])
+# passes (two folds) and two one-sweep passes; 260 sweeps = 130 passes, folds of 64, 64 and 2; 131 sweeps of one
+# colour per launch = three folds
+@pytest.mark.parametrize("layout,L,n", [("fused", 128, 259), ("fused", 64, 260), ("fused", 160, 70),
+                                        ("int8", 96, 131), ("packed", 128, 131), ("packed", 96, 65)])
 def test_long_traces_match_oracle(dev, oracle_lib, layout, L, n):
     seed, offset = 21, 5
     print("spread", layout, L, n, flush=True)
