@@ -43,11 +43,21 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_11714_amd", "csrc", f) for f in
 KERNEL_SOURCES_3D = KERNEL_SOURCES + [os.path.join(ROOT, "paper_1903_11714_amd", "csrc", "ising3d.hip")]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and with whitespace runs collapsed (string literals kept)."""
+    import re
+    pattern = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\])*"', re.S)
+    text = pattern.sub(lambda m: m.group(0) if m.group(0).startswith('"') else " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash(sources=None) -> str:
+    """Hash of the kernel sources' code (comments and layout ignored): the committed counters belong
+    to the kernels while it matches."""
     h = hashlib.sha256()
     for p in sources or KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+        with open(p, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

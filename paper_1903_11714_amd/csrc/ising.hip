@@ -232,7 +232,7 @@ struct FusedArgs {
     uint32_t L, groups, rows;  // rows = R, even, divides L; one workgroup per strip of R rows
     uint32_t t, key0, key1;
     Thresholds th;
-    int64_t* obs;        // OBS: (M, E) accumulator, zeroed beforehand
+    int64_t* obs;        // OBS: (M, E) accumulator zeroed beforehand, or a spread set (see spread)
     uint32_t xcd_remap;  // renumber blocks per XCD (see logical_block)
     uint32_t nt_store;   // non-temporal stores of the output rows
     uint32_t alternate;  // walk odd strips upwards
@@ -2002,11 +2002,9 @@ int launch_half_sweep(int8_t* spins, int64_t L, const ising::Thresholds& th, uin
 // The fused sweep puts a whole row in one workgroup (one thread per 64-column group).
 constexpr int64_t kFusedMaxL = 64 * 1024;
 
-// rows per strip of the fused sweep: even, divides L.  Every strip re-reads 4 rows and recomputes
-// the white sites of 2, so taller is cheaper; keep at least ~4096 waves in the grid, and 8..64 rows.
-// Rows per strip of a fused pass: the tallest (fewest re-read and recomputed rows around each
-// strip) that still leaves 4096 waves; a two-sweep pass recomputes four rows on either side, so
-// it starts from taller strips.
+// Rows per strip of a fused pass (even, divides L): the tallest (fewest re-read and recomputed rows
+// around each strip) that still leaves 4096 waves, 8 at least; a two-sweep pass recomputes four rows
+// on either side, so it starts from taller strips (128 against 64).
 uint32_t fused_rows(int64_t L, int sweeps = 1) {
     if (g_opt.fused_rows > 0 && L % g_opt.fused_rows == 0 && g_opt.fused_rows <= L) return (uint32_t)g_opt.fused_rows;
     const uint64_t waves = (uint64_t)(L / 64 + 63) / 64;
@@ -2016,7 +2014,6 @@ uint32_t fused_rows(int64_t L, int sweeps = 1) {
     return R;
 }
 
-// one fused sweep src -> dst (L <= kFusedMaxL, src and dst disjoint); obs: (M, E), zeroed beforehand
 // One pass of the fused kernel: `sweeps` (1 or 2) sweeps t, t + 1 from src to dst; obs: NULL or
 // 2 * sweeps int64, zeroed beforehand, or with `spread` a spread set (zeroed beforehand).
 int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::Thresholds& th, uint64_t seed,

@@ -1,0 +1,51 @@
+"""Host-side helpers of bench.py: the kernel-source hash that keys the committed counter summaries
+ignores comments and layout but not code, and the counter ingest reads rocprofv3's CSV layout."""
+import csv
+import json
+import os
+
+import bench
+
+
+def test_code_hash_ignores_comments_and_layout(tmp_path):
+    a = tmp_path / "a.hip"
+    a.write_text('int f(int x) {  // add one\n    return x + 1; /* block\ncomment */ }\nconst char* s = "// kept";\n')
+    b = tmp_path / "b.hip"
+    b.write_text('int f(int x) { return x + 1; }\n\n// another comment\nconst char* s = "// kept";\n')
+    c = tmp_path / "c.hip"
+    c.write_text('int f(int x) { return x + 2; }\nconst char* s = "// kept";\n')
+    d = tmp_path / "d.hip"
+    d.write_text('int f(int x) { return x + 1; }\nconst char* s = "// changed";\n')
+    h = lambda p: bench.kernel_source_hash([str(p)])
+    assert h(a) == h(b)
+    assert h(a) != h(c)
+    assert h(a) != h(d)
+
+
+def test_ingest_counters_scales_by_the_copy_calibration(tmp_path, monkeypatch):
+    # one pass directory per counter, rows as rocprofv3 --pmc -f csv writes them
+    fields = ["Correlation_Id", "Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    rows = {"FETCH_SIZE": [("k_sweep_fused2q<true, true>", 1000.0), ("k_sweep_fused2q<true, true>", 1200.0),
+                           ("direct_copy_kernel_cuda", 131072.0)],
+            "WRITE_SIZE": [("k_sweep_fused2q<true, true>", 2000.0), ("k_sweep_fused2q<true, true>", 2000.0),
+                           ("direct_copy_kernel_cuda", 262144.0)]}
+    dirs = []
+    for counter, entries in rows.items():
+        d = tmp_path / counter
+        d.mkdir()
+        with open(d / "pmc_counter_collection.csv", "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=fields)
+            w.writeheader()
+            for i, (k, v) in enumerate(entries):
+                w.writerow({"Correlation_Id": i, "Dispatch_Id": i, "Kernel_Name": k, "Counter_Name": counter,
+                            "Counter_Value": v})
+        dirs.append(str(d))
+    out = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
+    e = bench.ingest_counters("fused_L16384", "fused", 16384, dirs, "k_sweep_fused2q<true", None, 1 << 28, "cmd")
+    # a 2^28-byte copy reads 131072 KiB in FETCH_SIZE: the read counter is scaled x2, writes x1
+    assert e["fetch_scale"] == 2.0 and e["write_scale"] == 1.0
+    assert e["fetch_kib_raw"] == 1100.0 and e["write_kib_raw"] == 2000.0
+    assert e["hbm_bytes_per_launch"] == 1024 * (1100 * 2 + 2000)
+    assert e["source_hash"] == bench.kernel_source_hash()
+    assert json.load(open(out))["fused_L16384"]["command"] == "cmd"
