@@ -518,7 +518,7 @@ def read_counters(dirs) -> dict:
 
 
 def ingest_counters(key: str, layout: str, L: int, dirs, traced: str, untraced: str | None, copy_bytes: int,
-                    command: str) -> dict:
+                    command: str, alg_bytes: float | None = None) -> dict:
     """Write profiles/traffic.json[key] from rocprofv3 --pmc runs of this repository's bench (`dirs`):
     per-dispatch means of the kernel whose name contains `traced` (and of `untraced`, if given), the
     HBM bytes per launch with FETCH_SIZE and WRITE_SIZE each scaled by what the same counter reads for
@@ -552,7 +552,7 @@ def ingest_counters(key: str, layout: str, L: int, dirs, traced: str, untraced: 
         entry["copy_write_kib_raw"] = sum(cw) / len(cw)
         entry["hbm_bytes_per_launch"] = round(1024.0 * (entry["fetch_kib_raw"] * entry["fetch_scale"] +
                                                         entry["write_kib_raw"] * entry["write_scale"]))
-    entry["alg_bytes_per_launch"] = algorithmic_bytes(layout, L)
+    entry["alg_bytes_per_launch"] = algorithmic_bytes(layout, L) if alg_bytes is None else alg_bytes
     entry["source_hash"] = kernel_source_hash()
     entry["command"] = command
     try:
@@ -614,9 +614,13 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.ingest_counters:
-        key = f"{args.layout}_L{args.L}"
+        if args.form == "3d":  # one colour of the cubic lattice per launch: its L^3 bytes read and written once
+            key, alg = f"int8_3d_L{args.L3}", 2.0 * args.L3 ** 3
+        else:
+            key, alg = f"{args.layout}_L{args.L}", None
         entry = ingest_counters(key, args.layout, args.L, args.ingest_counters, args.traced_kernel,
-                                args.untraced_kernel, calibration_bytes(args.L), args.counters_command)
+                                args.untraced_kernel, calibration_bytes(16384 if args.form == "3d" else args.L),
+                                args.counters_command, alg)
         print(json.dumps({key: entry}))
         return 0
 
