@@ -440,7 +440,8 @@ def run_layout(ising, torch, layout, L, beta, seed, K, W, kernel_sweeps, stream,
     del lat
     if layout == "fused":
         pairs, singles, in_place = fused_passes(K)
-        # the timed region holds only two-sweep passes (and the trace's zeroing) when K % 4 == 0
+        # the timed region holds only two-sweep passes when K % 4 == 0 (and the trace's zeroing and one
+        # fold of the spread sets per 64 passes, 4-5 us each)
         launches = pairs if (singles == 0 and in_place == 0) else 0
     else:
         launches = 2 * K
