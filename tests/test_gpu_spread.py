@@ -72,3 +72,36 @@ def test_two_streams_trace_independently(dev):
     for (rs, rt), (gs, gt) in zip(ref, (a, b)):
         assert torch.equal(rs, gs)
         assert torch.equal(rt, gt)
+
+
+def test_two_host_threads_trace_independently(dev):
+    # ctypes releases the GIL: two threads call into the library at once, each on its own stream, and
+    # take spread sets from the shared per-device pool
+    import threading
+    L, n = 512, 150
+    print("spread two threads", L, n, flush=True)
+    jobs = [("fused", 41), ("packed", 42), ("int8", 43), ("fused", 44)]
+    ref = [_run(dev, lay, L, BETA_C, n, seed, 3) for lay, seed in jobs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in jobs]
+    out = [None] * len(jobs)
+    errors = []
+
+    def work(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                out[i] = _run(dev, jobs[i][0], L, BETA_C, n, jobs[i][1], 3, streams[i])
+            streams[i].synchronize()
+        except Exception as e:  # reported below, on the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(len(jobs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    torch.cuda.synchronize()
+    for (rs, rt), (gs, gt) in zip(ref, out):
+        assert torch.equal(rs, gs)
+        assert torch.equal(rt, gt)
