@@ -286,7 +286,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, uint32_t strip, 
     const uint32_t g = active ? tid : G - 1;
     const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
     const uint32_t lane = tid & 63u;
-    const uint32_t r0 = strip * R;
+    const uint32_t r0 = __builtin_amdgcn_readfirstlane(strip * R);  // uniform: keeps the row arithmetic scalar
     const size_t col = (size_t)(STAGED ? g - lane : g) * 64u;
     // k-th row of the walk, k = 0 .. R + 3: r0 - 2 .. r0 + R + 1 (down) or r0 + R + 1 .. r0 - 2
     // (up), wrapped onto the torus.  Prefetches past the walk's last row are clamped to it (already
@@ -443,15 +443,15 @@ __device__ __forceinline__ void fused2_strip(const FusedArgs& a, uint32_t strip,
     const uint32_t g = active ? tid : G - 1;
     const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
     const uint32_t lane = tid & 63u;
-    const uint32_t r0 = strip * R;
+    const uint32_t r0 = __builtin_amdgcn_readfirstlane(strip * R);  // uniform: keeps the row arithmetic scalar
     const size_t col = (size_t)(STAGED ? g - lane : g) * 64u;
     // walk row k = 0 .. R + 7: r0 - 4 .. r0 + R + 3 (down) or r0 + R + 3 .. r0 - 4 (up), wrapped
     // onto the torus; prefetches past the last walk row are clamped to it
     auto vrow = [&](uint32_t k) {
         const uint32_t kk = k < R + 7 ? k : R + 7;
-        uint32_t v = UP ? r0 + R + 3 + L - kk : r0 + L - 4 + kk;  // in [L - 4, 2L + 4) since R <= L
-        v = v >= L ? v - L : v;
-        return v >= L ? v - L : v;
+        // in [-4, L + 4) since r0 + R <= L; signed compares keep the wrap on the scalar unit
+        const int32_t v = (int32_t)(UP ? r0 + R + 3 - kk : r0 + kk) - (UP ? 0 : 4);
+        return (uint32_t)(v < 0 ? v + (int32_t)L : v >= (int32_t)L ? v - (int32_t)L : v);
     };
     auto fetch = [&](Row& raw, uint32_t r) {
         if (STAGED) load_row_coalesced(raw, a.src + (size_t)r * L + col, lane);
@@ -577,15 +577,17 @@ __device__ __forceinline__ void tq_update(RowBits& own, const RowBits& v0, const
     const uint32_t o12 = x1 | x2, o34 = x3 | x4;
     const uint32_t ge2 = (x1 & x2) | (x3 & x4) | (o12 & o34);  // s <= 0: always flips
     const uint32_t any = o12 | o34;
-    uint32_t sel2 = any & ~ge2, sel4 = ~any;
-    uint32_t acc = ge2;
-    if (th.full2) { acc |= sel2; sel2 = 0u; }
-    if (th.full4) { acc |= sel4; sel4 = 0u; }
-    uint32_t tied = sel2 | sel4;
+    // sites that flip without a uniform: s <= 0, and s = 2 / s = 4 where T_s = 2^32 (uniform masks)
+    const uint32_t flip = (ge2 | (any & th.f2)) | (~any & th.f4);
+    const uint32_t sel2 = any & ~flip;
+    uint32_t acc = flip, tied = ~flip;
+    // the row is the same for the whole wave: keeping it in a scalar register lets the Philox rounds
+    // that depend only on (row, sweep, colour) run on the scalar unit
+    const uint32_t urow = __builtin_amdgcn_readfirstlane(row);
 #pragma unroll
     for (uint32_t m = 0; m < 2; ++m) {
         if (!wave_any(tied != 0u)) break;
-        compare_planes(acc, tied, sel2, philox4x32_10(g, row, t, 2u * m + (uint32_t)Q, key0, key1), th, m);
+        compare_planes(acc, tied, sel2, philox4x32_10<2, 3>(g, urow, t, 2u * m + (uint32_t)Q, key0, key1), th, m);
     }
     if (O) own.o ^= acc; else own.e ^= acc;
     tq_push(q, n, tied, sel2, row, (uint32_t)P | (lane << 2) | (g << 8));
@@ -645,15 +647,15 @@ __device__ __forceinline__ void fused2q_strip(const FusedArgs& a, uint32_t strip
     const uint32_t g = active ? tid : G - 1;
     const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
     const uint32_t lane = tid & 63u;
-    const uint32_t r0 = strip * R;
+    const uint32_t r0 = __builtin_amdgcn_readfirstlane(strip * R);  // uniform: keeps the row arithmetic scalar
     const size_t col = (size_t)(STAGED ? g - lane : g) * 64u;
     // walk row k = 0 .. R + 7: r0 - 4 .. r0 + R + 3 (down) or r0 + R + 3 .. r0 - 4 (up), wrapped
     // onto the torus; prefetches past the last walk row are clamped to it
     auto vrow = [&](uint32_t k) {
         const uint32_t kk = k < R + 7 ? k : R + 7;
-        uint32_t v = UP ? r0 + R + 3 + L - kk : r0 + L - 4 + kk;  // in [L - 4, 2L + 4) since R <= L
-        v = v >= L ? v - L : v;
-        return v >= L ? v - L : v;
+        // in [-4, L + 4) since r0 + R <= L; signed compares keep the wrap on the scalar unit
+        const int32_t v = (int32_t)(UP ? r0 + R + 3 - kk : r0 + kk) - (UP ? 0 : 4);
+        return (uint32_t)(v < 0 ? v + (int32_t)L : v >= (int32_t)L ? v - (int32_t)L : v);
     };
     auto fetch = [&](Row& raw, uint32_t r) {
         if (STAGED) load_row_coalesced(raw, a.src + (size_t)r * L + col, lane);
@@ -789,12 +791,12 @@ __device__ __forceinline__ void fused2b_strip(const BandArgs& a, uint32_t band, 
     uint32_t gbase = b0 + G - 1u + (lane >> 2);
     gbase = gbase >= G ? gbase - G : gbase;
     gbase = gbase >= G ? gbase - G : gbase;
-    const uint32_t r0 = strip * R;
+    const uint32_t r0 = __builtin_amdgcn_readfirstlane(strip * R);  // uniform: keeps the row arithmetic scalar
     auto vrow = [&](uint32_t k) {
         const uint32_t kk = k < R + 7 ? k : R + 7;
-        uint32_t v = UP ? r0 + R + 3 + L - kk : r0 + L - 4 + kk;  // in [L - 4, 2L + 4) since R <= L
-        v = v >= L ? v - L : v;
-        return v >= L ? v - L : v;
+        // in [-4, L + 4) since r0 + R <= L; signed compares keep the wrap on the scalar unit
+        const int32_t v = (int32_t)(UP ? r0 + R + 3 - kk : r0 + kk) - (UP ? 0 : 4);
+        return (uint32_t)(v < 0 ? v + (int32_t)L : v >= (int32_t)L ? v - (int32_t)L : v);
     };
     auto fetch = [&](Row& raw, uint32_t r) { load_row_chunks(raw, a.src + (size_t)r * L, gbase, G, lane); };
     auto own = [&](const Row& raw) {
@@ -881,7 +883,7 @@ __device__ __forceinline__ void fusedq_strip(const FusedArgs& a, uint32_t strip,
     const uint32_t g = active ? tid : G - 1;
     const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
     const uint32_t lane = tid & 63u;
-    const uint32_t r0 = strip * R;
+    const uint32_t r0 = __builtin_amdgcn_readfirstlane(strip * R);  // uniform: keeps the row arithmetic scalar
     const size_t col = (size_t)(STAGED ? g - lane : g) * 64u;
     // walk row k = 0 .. R + 3: r0 - 2 .. r0 + R + 1 (down) or r0 + R + 1 .. r0 - 2 (up), wrapped;
     // prefetches past the last walk row are clamped to it
@@ -1150,7 +1152,9 @@ __global__ __launch_bounds__(256) void k_sweep_packed(PackedArgs a) {
 // the first two Philox blocks of each row's word, queues the words still holding tied sites and
 // settles them with the other lanes' (as in the two-sweep pass).  Same uniforms and results as
 // k_sweep_packed.  rows % 4 == 0; lanes past n_lanes shadow the last lane without storing.
-template <int Q, bool OBS, bool HALF = false, bool O32 = false>
+// UROW (groups % 64 == 0): every wave lies in one strip, so its rows are uniform and the Philox rounds
+// that depend only on (row, sweep, colour) run on the scalar unit.
+template <int Q, bool OBS, bool HALF = false, bool O32 = false, bool UROW = false>
 __global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
     extern __shared__ uint4 packed_lds[];
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
@@ -1162,7 +1166,7 @@ __global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
     Counts cnt{0u, 0u};
     const uint32_t W = a.groups, L = a.L, R = a.rows;
     const uint32_t g = lane_id % W;
-    const uint32_t r0 = (lane_id / W) * R;
+    const uint32_t r0 = UROW ? __builtin_amdgcn_readfirstlane((lane_id / W) * R) : (lane_id / W) * R;
     const uint32_t gl = g == 0 ? W - 1 : g - 1;
     const uint32_t gr = g + 1 == W ? 0 : g + 1;
     // HALF: the last word of each row holds a half group (sites 0 .. 15)
@@ -1225,15 +1229,14 @@ __global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
             const uint32_t o12 = x1 | x2, o34 = x3 | x4;
             const uint32_t ge2 = ((x1 & x2) | (x3 & x4) | (o12 & o34)) & valid;
             const uint32_t any = o12 | o34;
-            uint32_t sel2 = any & ~ge2 & valid, sel4 = ~any & valid;
-            uint32_t acc = ge2;
-            if (a.th.full2) { acc |= sel2; sel2 = 0u; }
-            if (a.th.full4) { acc |= sel4; sel4 = 0u; }
-            uint32_t tied = sel2 | sel4;
+            const uint32_t flip = ge2 | (any & a.th.f2 & valid) | (~any & a.th.f4 & valid);
+            const uint32_t sel2 = any & ~flip & valid;
+            uint32_t acc = flip, tied = ~flip & valid;
 #pragma unroll
             for (uint32_t m = 0; m < 2; ++m) {
                 if (!wave_any(tied != 0u)) break;
-                compare_planes(acc, tied, sel2, philox4x32_10(g, r + (uint32_t)i, a.t, 2u * m + (uint32_t)Q, a.key0, a.key1),
+                compare_planes(acc, tied, sel2,
+                               philox4x32_10<2, UROW ? 3 : 1>(g, r + (uint32_t)i, a.t, 2u * m + (uint32_t)Q, a.key0, a.key1),
                                a.th, m);
             }
             w[i] ^= acc;
@@ -1525,7 +1528,7 @@ __device__ __forceinline__ void batch_update(uint32_t* lds, const BatchUnit* us,
             const uint32_t pw = (rows + 2u * K) * W, base = uni(x.lds);
             uint32_t* pq = lds + base + Q * pw;
             const uint32_t* po = lds + base + (1 - Q) * pw;
-            const Thresholds th{uni(rp.th.t2), uni(rp.th.t4), uni(rp.th.full2), uni(rp.th.full4), uni(rp.th.blocks)};
+            const Thresholds th{uni(rp.th.t2), uni(rp.th.t4), uni(rp.th.f2), uni(rp.th.f4), uni(rp.th.blocks)};
             const uint32_t t = uni(rp.t0) + i, key0 = uni(rp.key0), key1 = uni(rp.key1);
             uint32_t lr, lup, ldn, r;
             bool own;
@@ -1942,10 +1945,11 @@ ising::Thresholds make_thresholds(double beta, int fmt = 0) {
     uint64_t T[2];
     host_thresholds_fmt(beta, fmt, T);
     ising::Thresholds th;
-    th.full2 = T[0] >= (uint64_t(1) << 32);
-    th.full4 = T[1] >= (uint64_t(1) << 32);
-    th.t2 = th.full2 ? 0u : (uint32_t)T[0];
-    th.t4 = th.full4 ? 0u : (uint32_t)T[1];
+    const bool full2 = T[0] >= (uint64_t(1) << 32), full4 = T[1] >= (uint64_t(1) << 32);
+    th.f2 = full2 ? 0xFFFFFFFFu : 0u;
+    th.f4 = full4 ? 0xFFFFFFFFu : 0u;
+    th.t2 = full2 ? 0u : (uint32_t)T[0];
+    th.t4 = full4 ? 0u : (uint32_t)T[1];
     th.blocks = ((th.t2 | th.t4) & 0xFFFFu) == 0 ? 4u : 8u;
     return th;
 }
@@ -2593,11 +2597,16 @@ int launch_half_sweep_packed(uint32_t* planes, int64_t L, const ising::Threshold
         const size_t lds = (threads / 64u) * ising::kTieQueueBytes;
         // 32-bit offsets within a plane while it spans at most 4 GiB (L <= 2^18)
         const bool o32 = (uint64_t)L * a.groups * 4u <= (uint64_t(1) << 32);
+        // whole waves in one strip (64 whole groups per wave of a row)
+        const bool urow = !half && a.groups % 64u == 0;
 #define ISING_LAUNCH_PACKED_Q(QQ, OO)                                                                      \
     do {                                                                                                   \
         if (half) {                                                                                        \
             if (o32) hipLaunchKernelGGL((ising::k_sweep_packed_q<QQ, OO, true, true>), qgrid, qblock, lds, stream, a);   \
             else hipLaunchKernelGGL((ising::k_sweep_packed_q<QQ, OO, true, false>), qgrid, qblock, lds, stream, a);      \
+        } else if (urow) {                                                                                 \
+            if (o32) hipLaunchKernelGGL((ising::k_sweep_packed_q<QQ, OO, false, true, true>), qgrid, qblock, lds, stream, a); \
+            else hipLaunchKernelGGL((ising::k_sweep_packed_q<QQ, OO, false, false, true>), qgrid, qblock, lds, stream, a);    \
         } else {                                                                                           \
             if (o32) hipLaunchKernelGGL((ising::k_sweep_packed_q<QQ, OO, false, true>), qgrid, qblock, lds, stream, a);  \
             else hipLaunchKernelGGL((ising::k_sweep_packed_q<QQ, OO, false, false>), qgrid, qblock, lds, stream, a);     \

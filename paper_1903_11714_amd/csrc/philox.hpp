@@ -21,6 +21,13 @@ struct Words4 {
     uint32_t w0, w1, w2, w3;
 };
 
+// P0 / P2: the number of leading rounds whose new word 0 / word 2 is formed with plain xors instead of
+// v_bitop3_b32.  A plain xor lets the compiler keep a round whose inputs are uniform on the scalar
+// unit, and it folds two uniform operands into one before a single vector xor; v_bitop3_b32 is the
+// better form once two of the three inputs vary by lane.  The defaults suit a counter of a
+// lane-varying group and row with a uniform sweep and colour word; a caller whose row is uniform
+// passes <2, 3>.  Every choice computes the same function.
+template <int P0 = 2, int P2 = 1>
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -28,8 +35,10 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
         const uint64_t a = (uint64_t)kPhiloxM0 * c0;
         const uint64_t b = (uint64_t)kPhiloxM1 * c2;
         // three-input xor in one gfx950 v_bitop3_b32 (truth table 0x96)
-        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), c1, k0, 0x96);
-        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), c3, k1, 0x96);
+        const uint32_t n0 = round < P0 ? (uint32_t)(b >> 32) ^ (c1 ^ k0)
+                                       : __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), c1, k0, 0x96);
+        const uint32_t n2 = round < P2 ? (uint32_t)(a >> 32) ^ (c3 ^ k1)
+                                       : __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), c3, k1, 0x96);
         c1 = (uint32_t)b;
         c3 = (uint32_t)a;
         c0 = n0;

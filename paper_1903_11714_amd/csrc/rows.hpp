@@ -258,7 +258,7 @@ __device__ __forceinline__ bool wave_any(bool v) { return __builtin_amdgcn_ballo
 // s = 4 - 2a; a >= 2 always flips, a = 1 compares with T_2, a = 0 with T_4.
 struct Thresholds {
     uint32_t t2, t4;      // low 32 bits of T_2, T_4
-    uint32_t full2, full4;  // 1 when T_s = 2^32 (always accept)
+    uint32_t f2, f4;      // all ones when T_s = 2^32 (always accept), else zero
     uint32_t blocks;        // Philox blocks (4 bit planes each) that can decide: 8, or 4 when
                             // both thresholds are multiples of 2^16 (16-bit uniforms)
 };
@@ -289,9 +289,9 @@ __device__ __forceinline__ void compare_planes(uint32_t& acc, uint32_t& tied, ui
 __device__ __forceinline__ uint32_t accept_mask(uint32_t sel2, uint32_t sel4, const Thresholds& th,
                                                 uint32_t g, uint32_t r, uint32_t t, uint32_t q,
                                                 uint32_t key0, uint32_t key1) {
-    uint32_t acc = 0;
-    if (th.full2) { acc |= sel2; sel2 = 0; }
-    if (th.full4) { acc |= sel4; sel4 = 0; }
+    uint32_t acc = (sel2 & th.f2) | (sel4 & th.f4);
+    sel2 &= ~th.f2;
+    sel4 &= ~th.f4;
     uint32_t tied = sel2 | sel4;
     // sites outside sel2 are compared with T_4 below; make sure only tied ones matter
 #pragma unroll 1
