@@ -102,15 +102,21 @@ def alu_roofline(layout: str, L: int, avg_launch_ms: float):
 FUSED_MAX_L = 65536  # above this the two-sweep pass runs as column bands of one wave each
 
 KERNEL_NAME = {
-    "fused": "k_sweep_fused2q (two sweeps per launch, tie queue)",
+    "fused": "k_sweep_fused2p (two sweeps per launch, ties of two steps settled together)",
+    "fused_wide": "k_sweep_fused2q (two sweeps per launch, tie queue)",
     "bands": "k_sweep_fused2b (two sweeps per launch in column bands of one wave, tie queue)",
     "int8": "k_sweep_int8 (one colour per launch)",
     "packed": "k_sweep_packed_q (one colour per launch, tie queue)",
 }
 
 
+FUSED_PAIRS_MAX_L = 32768  # up to here the two-sweep pass settles the ties of two steps together
+
+
 def kernel_name(layout: str, L: int) -> str:
-    return KERNEL_NAME["bands" if layout == "fused" and L > FUSED_MAX_L else layout]
+    if layout == "fused" and L > FUSED_PAIRS_MAX_L:
+        return KERNEL_NAME["bands" if L > FUSED_MAX_L else "fused_wide"]
+    return KERNEL_NAME[layout]
 
 
 FUSED_SWEEPS_PER_LAUNCH = 2

@@ -95,7 +95,9 @@ int ising_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sw
  * with the same arguments, and so is trace_ME.  Passes alternate spins -> scratch -> spins, an
  * even number of them; an odd count runs its first sweep in place.  Option "fused_sweeps" sets
  * the sweeps per pass (2 by default, 1).  Up to L = 65536 a pass gives each row to one workgroup
- * (one thread per 64-column group); above, the two-sweep pass runs in column bands of one wave each
+ * (one thread per 64-column group); up to L = 32768 the two-sweep pass spaces its four updates three
+ * rows apart, so that two consecutive steps are independent and their still-tied words are settled
+ * together (option "fused_pairs"); above L = 65536 the two-sweep pass runs in column bands of one wave each
  * (62 own groups and one recomputed group on either side), and the one-sweep pass is not available
  * (fused_sweeps = 1 then sweeps in place as ising_sweep_fmt).  When L % 64 != 0 every sweep runs in
  * place as in ising_sweep_fmt (scratch unused).  Returns ISING_EINVAL for the checks of
@@ -318,13 +320,19 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
  *                    (1, 2 or 4), 0 = autotune (default).
  *   "batch_lists_per_cu"  ising_batch_run: work lists per compute unit of a split schedule (1 or
  *                    2), 0 = autotune (default).
- *   "fused_rows"     rows per workgroup strip of ising_sweep_fused: 0 = automatic, else a power
- *                    of two in [2, 256] (ignored for lattices it does not divide).
+ *   "fused_rows"     rows per workgroup strip of ising_sweep_fused: 0 = automatic, else an even
+ *                    number in [2, 256].  The two-sweep pass with paired steps takes any such value
+ *                    (its last strip takes the rows left over); the other passes ignore a value that
+ *                    does not divide L.
  *   "fused_alternate" 1 = odd strips of ising_sweep_fused walk upwards (default), 0 = all down.
  *   "fused_sweeps"   sweeps per pass of ising_sweep_fused: 2 (default) or 1.
  *   "fused_ties"     fused passes (two sweeps or one): 1 = the updates of a step are independent
  *                    and the words still tied after two Philox blocks are settled together
  *                    (default), 0 = each update settles its own words before the next one.
+ *   "fused_pairs"    two-sweep passes of rows of at most 512 groups (L <= 32768): 1 = the four
+ *                    updates of a step are three rows apart, and two steps share one edge exchange
+ *                    and one settle of their still-tied words (default), 0 = two rows apart, one
+ *                    step at a time (used only with "fused_ties" = 1).
  *   "packed_ties"    ising_sweep_packed / ising_half_sweep_packed (and the 3-D packed sweep, four
  *                    planes): 1 = each lane takes four rows at a time and their still-tied words are
  *                    settled together (default; used when the rows per lane are a multiple of 4),

@@ -237,6 +237,7 @@ struct FusedArgs {
     uint32_t nt_store;   // non-temporal stores of the output rows
     uint32_t alternate;  // walk odd strips upwards
     uint32_t spread;     // k_sweep_fused2q: obs is a spread set (each workgroup adds into its line)
+    uint32_t rows_last;  // k_sweep_fused2p: rows of the last strip (even, <= rows; the others have rows)
 };
 
 // Edge bits a thread publishes after step x: bit 0 / 1 = site 0 of the even columns / site 31 of
@@ -729,6 +730,228 @@ __global__ __launch_bounds__(1024) void k_sweep_fused2q(FusedArgs a) {
         block_accumulate(out, active ? ct.anti : 0u, active ? ct.neg : 0u, active ? 1u : 0u, 64u * a.rows);
         __syncthreads();  // block_accumulate's LDS is reused
         block_accumulate(out + 2, active ? ct1.anti : 0u, active ? ct1.neg : 0u, active ? 1u : 0u, 64u * a.rows);
+    }
+}
+
+// ---- Two sweeps per pass, the ties of two steps settled together.
+//
+// The walk of the pass above with three rows between its updates instead of two: step s updates the
+// white sites of walk row s + 1 (sweep t), the black sites of s - 2 (t), the white sites of s - 5
+// (t + 1) and the black sites of s - 8 (t + 1).  Each update reads only rows that the updates of
+// steps s - 2 and earlier have finished (the neighbours of a black update of sweep t are white sites
+// of sweep t two, three and four steps back, and so on down the chain of Sec. 3.1's colour updates),
+// and no update of step s + 1 reads a row that step s writes.  So the eight updates of an even step
+// and the step after it are independent: they share one edge exchange, one workgroup barrier and
+// one settle of the wave's tie queue (about twice as many queued words per settle, so fewer Philox
+// blocks past the eighth plane).  The strip reads, recomputes and writes the same rows as the pass
+// above, and every decision takes the same uniform, so the result is the same two sweeps, bit for
+// bit.  Two waves per SIMD (up to 256 registers): each update draws its first two Philox blocks as
+// two independent chains, and the next two walk rows are fetched a pair ahead.
+
+constexpr uint32_t kPairQueueCap = 512;                        // 8 updates x 64 lanes
+constexpr uint32_t kPairQueueSlots = kPairQueueCap + 64u;       // and one write-off slot per lane
+constexpr uint32_t kPairWaveBytes = 4u * kPairQueueSlots * 4u + 64u * 8u * 4u;  // 9 KiB entries, 2 KiB results
+
+// Per-wave LDS of the pair's tie queue: task[4][576] = (tied, tied & sel2, Philox row, meta = u | lane
+// << 3 | group << 9) and res[64][8] = the sites of update u of lane l that the queue accepted.  A lane
+// with no tied site writes its entry to its own slot past the queue (512 + lane), so that a push is
+// straight-line code.  The first 4 KiB double as the row staging buffer outside the pushes and the
+// settle.
+struct PairQueue {
+    uint32_t* task;
+    uint32_t* res;
+};
+
+// Edge bits of the pair's eight update rows (2U, 2U + 1: site 0 of the even columns and site 31 of the
+// odd columns of update U's row), taken when the pair starts.
+__device__ __forceinline__ uint32_t pair_edges(const RowBits& r0, const RowBits& r1, const RowBits& r2,
+                                               const RowBits& r3, const RowBits& r4, const RowBits& r5,
+                                               const RowBits& r6, const RowBits& r7) {
+    return edge_word4(r0, r1, r2, r3) | (edge_word4(r4, r5, r6, r7) << 8);
+}
+
+// Update U (0 .. 7) of a pair: colour Q at column parity O of `own` between v0 and v1; sweep t is the
+// update's own.  The first two Philox blocks decide at once; words still tied go to the queue.
+template <int O, int Q, int U>
+__device__ __forceinline__ void pair_update(RowBits& own, const RowBits& v0, const RowBits& v1, uint32_t nbL,
+                                            uint32_t nbR, const Thresholds& th, uint32_t g, uint32_t row, uint32_t t,
+                                            uint32_t key0, uint32_t key1, const PairQueue& q, uint32_t& n,
+                                            uint32_t lane) {
+    const uint32_t side = O ? own.e : own.o;
+    const uint32_t hs = O ? shift_next(side, (nbR >> (2 * U)) & 1u) : shift_prev(side, (nbL >> (2 * U + 1)) & 1u);
+    const uint32_t a = O ? own.o : own.e;
+    const uint32_t x1 = a ^ (O ? v0.o : v0.e), x2 = a ^ (O ? v1.o : v1.e), x3 = a ^ side, x4 = a ^ hs;
+    const uint32_t o12 = x1 | x2, o34 = x3 | x4;
+    const uint32_t ge2 = (x1 & x2) | (x3 & x4) | (o12 & o34);  // s <= 0: always flips
+    const uint32_t any = o12 | o34;
+    const uint32_t flip = (ge2 | (any & th.f2)) | (~any & th.f4);
+    const uint32_t sel2 = any & ~flip;
+    uint32_t acc = flip, tied = ~flip;
+    const uint32_t urow = __builtin_amdgcn_readfirstlane(row);
+    const Words4 b0 = philox4x32_10<2, 3>(g, urow, t, (uint32_t)Q, key0, key1);
+    const Words4 b1 = philox4x32_10<2, 3>(g, urow, t, 2u + (uint32_t)Q, key0, key1);
+    compare_planes(acc, tied, sel2, b0, th, 0u);
+    compare_planes(acc, tied, sel2, b1, th, 1u);
+    if (O) own.o ^= acc; else own.e ^= acc;
+    const uint64_t B = __builtin_amdgcn_ballot_w64(tied != 0u);
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, 0u));
+    const uint32_t pos = tied != 0u ? n + rank : kPairQueueCap + lane;
+    q.task[pos] = tied;
+    q.task[kPairQueueSlots + pos] = sel2 & tied;
+    q.task[2u * kPairQueueSlots + pos] = urow;
+    q.task[3u * kPairQueueSlots + pos] = (uint32_t)U | (lane << 3) | (g << 9);
+    n += (uint32_t)__builtin_popcountll(B);
+}
+
+// Settles the n queued words, one per lane, with the planes of blocks 2 onwards.  Update u of the pair
+// (u & 3 = white t, black t, white t + 1, black t + 1) has sweep t + ((u >> 1) & 1) and colour 1 - (u & 1).
+__device__ __forceinline__ void pair_settle(const PairQueue& q, uint32_t n, const Thresholds& th, uint32_t t,
+                                            uint32_t key0, uint32_t key1, uint32_t lane) {
+    wave_lds_sync();
+#pragma unroll 1
+    for (uint32_t b = 0; b < n; b += 64u) {
+        const uint32_t j = b + lane;
+        const bool have = j < n;
+        uint32_t tied = 0u, s2 = 0u, row = 0u, meta = 0u;
+        if (have) {
+            tied = q.task[j];
+            s2 = q.task[kPairQueueSlots + j];
+            row = q.task[2u * kPairQueueSlots + j];
+            meta = q.task[3u * kPairQueueSlots + j];
+        }
+        const uint32_t u = meta & 7u, src = (meta >> 3) & 63u, g = meta >> 9;
+        const uint32_t tu = t + ((u >> 1) & 1u), qu = (u & 1u) ^ 1u;
+        uint32_t acc = 0u;
+#pragma unroll 1
+        for (uint32_t m = 2; m < th.blocks; ++m) {
+            if (!wave_any(tied != 0u)) break;
+            compare_planes(acc, tied, s2, philox4x32_10(g, row, tu, 2u * m + qu, key0, key1), th, m);
+        }
+        if (have) q.res[8u * src + u] = acc;
+    }
+    wave_lds_sync();
+}
+
+// Strip `strip` holds rows strip * a.rows .. + R - 1 (R = a.rows, or a.rows_last for the last strip).
+template <bool OBS, bool STAGED, bool UP>
+__device__ __forceinline__ void fused2p_strip(const FusedArgs& a, uint32_t strip, uint32_t R, uint4* fused_lds,
+                                              Counts& ct, Counts& ct1) {
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t G = a.groups, L = a.L;
+    uint32_t* const wl = reinterpret_cast<uint32_t*>(fused_lds) + (tid >> 6) * (kPairWaveBytes / 4u);
+    uint4* const stage = reinterpret_cast<uint4*>(wl);
+    uint32_t* const xch = reinterpret_cast<uint32_t*>(fused_lds) + (nt >> 6) * (kPairWaveBytes / 4u);
+    const PairQueue q{wl, wl + 4u * kPairQueueSlots};
+    const bool active = tid < G;
+    const uint32_t g = active ? tid : G - 1;
+    const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
+    const uint32_t lane = tid & 63u;
+    const uint32_t r0 = __builtin_amdgcn_readfirstlane(strip * a.rows);  // uniform: keeps the row arithmetic scalar
+    const size_t col = (size_t)(STAGED ? g - lane : g) * 64u;
+    // walk row k = 0 .. R + 7: r0 - 4 .. r0 + R + 3 (down) or r0 + R + 3 .. r0 - 4 (up), wrapped onto the
+    // torus; callers pass k <= R + 7 for every row they load or store
+    auto vrow = [&](uint32_t k) {
+        const int32_t v = (int32_t)(UP ? r0 + R + 3 - k : r0 + k) - (UP ? 0 : 4);  // in [-4, L + 4)
+        return (uint32_t)(v < 0 ? v + (int32_t)L : v >= (int32_t)L ? v - (int32_t)L : v);
+    };
+    auto fetch = [&](Row& raw, uint32_t r) {
+        if (STAGED) load_row_coalesced(raw, a.src + (size_t)r * L + col, lane);
+        else load_row(raw, a.src + (size_t)r * L + col);
+    };
+    auto own = [&](const Row& raw) {
+        if (!STAGED) return row_bits(raw);
+        Row row;
+        regroup_to_owner(row, raw, stage, lane);
+        return row_bits(row);
+    };
+    auto put = [&](uint32_t r, const RowBits& b) {
+        Row row;
+        bits_to_row(row, b);
+        if (STAGED) store_row_coalesced(a.dst + (size_t)r * L + col, row, stage, lane, a.nt_store);
+        else if (active) store_row(a.dst + (size_t)r * L + col, row, a.nt_store);
+    };
+    // Window at the start of the pair of steps s, s + 1 (s even): w_j = walk row s + 3 - j, j = 0 .. 12.
+    // The updates of step s lie on columns of parity OA, those of step s + 1 on OB.
+    constexpr int OA = UP ? 1 : 0, OB = 1 - OA;
+    const uint32_t t = a.t, k0 = a.key0, k1 = a.key1;
+    const RowBits z{0u, 0u};
+    RowBits w12 = z, w11 = z, w10 = z, w9 = z, w8 = z, w7 = z, w6 = z, w5 = z, w4 = z;
+    Row rawA, rawB;
+    fetch(rawA, vrow(0));
+    RowBits w3 = own(rawA);
+    fetch(rawA, vrow(1));
+    RowBits w2 = own(rawA);
+    fetch(rawA, vrow(2));
+    RowBits w1 = own(rawA);
+    fetch(rawA, vrow(3));
+    RowBits w0 = own(rawA);
+    fetch(rawA, vrow(4));
+    fetch(rawB, vrow(5));
+    xch[tid] = pair_edges(w2, w5, w8, w11, w1, w4, w7, w10);
+    workgroup_lds_sync();
+#pragma unroll 1
+    for (uint32_t s = 0; s < R + 12; s += 2) {
+        const uint32_t sl = ((s >> 1) & 1u) * nt;
+        const uint32_t nbL = xch[sl + gl], nbR = xch[sl + gr];
+        // step s makes U1 for s <= R + 5, U2 for 4 <= s <= R + 7, U3 for 8 <= s <= R + 9, U4 for 12 <= s
+        const uint32_t s1 = s + 1u;
+        const bool u1a = s <= R + 5, u1b = s1 <= R + 5;
+        const bool u2a = s >= 4u && s <= R + 7, u2b = s1 >= 4u && s1 <= R + 7;
+        const bool u3a = s >= 8u && s <= R + 9, u3b = s1 >= 8u && s1 <= R + 9;
+        const bool u4a = s >= 12u, u4b = s1 >= 12u;
+        reinterpret_cast<uint4*>(q.res)[2u * lane] = make_uint4(0u, 0u, 0u, 0u);
+        reinterpret_cast<uint4*>(q.res)[2u * lane + 1u] = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t n = 0u;
+        if (u1a) pair_update<OA, 1, 0>(w2, w3, w1, nbL, nbR, a.th, g, vrow(s + 1u), t, k0, k1, q, n, lane);
+        if (u2a) pair_update<OA, 0, 1>(w5, w6, w4, nbL, nbR, a.th, g, vrow(s - 2u), t, k0, k1, q, n, lane);
+        if (u3a) pair_update<OA, 1, 2>(w8, w9, w7, nbL, nbR, a.th, g, vrow(s - 5u), t + 1u, k0, k1, q, n, lane);
+        if (u4a) pair_update<OA, 0, 3>(w11, w12, w10, nbL, nbR, a.th, g, vrow(s - 8u), t + 1u, k0, k1, q, n, lane);
+        if (u1b) pair_update<OB, 1, 4>(w1, w2, w0, nbL, nbR, a.th, g, vrow(s + 2u), t, k0, k1, q, n, lane);
+        if (u2b) pair_update<OB, 0, 5>(w4, w5, w3, nbL, nbR, a.th, g, vrow(s - 1u), t, k0, k1, q, n, lane);
+        if (u3b) pair_update<OB, 1, 6>(w7, w8, w6, nbL, nbR, a.th, g, vrow(s - 4u), t + 1u, k0, k1, q, n, lane);
+        if (u4b) pair_update<OB, 0, 7>(w10, w11, w9, nbL, nbR, a.th, g, vrow(s - 7u), t + 1u, k0, k1, q, n, lane);
+        pair_settle(q, n, a.th, t, k0, k1, lane);
+        const uint4 ra = reinterpret_cast<const uint4*>(q.res)[2u * lane];  // zero for updates not made
+        const uint4 rb = reinterpret_cast<const uint4*>(q.res)[2u * lane + 1u];
+        if (OA) { w2.o ^= ra.x; w5.o ^= ra.y; w8.o ^= ra.z; w11.o ^= ra.w; w1.e ^= rb.x; w4.e ^= rb.y; w7.e ^= rb.z; w10.e ^= rb.w; }
+        else { w2.e ^= ra.x; w5.e ^= ra.y; w8.e ^= ra.z; w11.e ^= ra.w; w1.o ^= rb.x; w4.o ^= rb.y; w7.o ^= rb.z; w10.o ^= rb.w; }
+        if (OBS) {
+            // sweep t: the black update of an own row (walk rows 4 .. R + 3); sweep t + 1: every U4 row
+            if (s >= 6u && s <= R + 5) tq_count<OA, 1>(w5, w6, w4, nbL, nbR, ct);
+            if (s1 >= 6u && s1 <= R + 5) tq_count<OB, 5>(w4, w5, w3, nbL, nbR, ct);
+            if (u4a) tq_count<OA, 3>(w11, w12, w10, nbL, nbR, ct1);
+            if (u4b) tq_count<OB, 7>(w10, w11, w9, nbL, nbR, ct1);
+        }
+        if (u4a) put(vrow(s - 8u), w11);
+        if (u4b) put(vrow(s - 7u), w10);
+        // walk rows s + 4, s + 5 (fetched a pair ago) and the requests for s + 6, s + 7
+        RowBits n4 = z, n5 = z;
+        if (s + 4u <= R + 7) n4 = own(rawA);
+        if (s + 5u <= R + 7) n5 = own(rawB);
+        if (s + 6u <= R + 7) fetch(rawA, vrow(s + 6u));
+        if (s + 7u <= R + 7) fetch(rawB, vrow(s + 7u));
+        w12 = w10; w11 = w9; w10 = w8; w9 = w7; w8 = w6; w7 = w5; w6 = w4; w5 = w3; w4 = w2; w3 = w1; w2 = w0;
+        w1 = n4;
+        w0 = n5;
+        xch[(((s >> 1) + 1u) & 1u) * nt + tid] = pair_edges(w2, w5, w8, w11, w1, w4, w7, w10);
+        workgroup_lds_sync();
+    }
+}
+
+template <bool OBS, bool STAGED>
+__global__ __launch_bounds__(512) void k_sweep_fused2p(FusedArgs a) {
+    extern __shared__ uint4 fused_lds[];
+    const uint32_t strip = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
+    const uint32_t R = strip + 1u == gridDim.x ? a.rows_last : a.rows;
+    Counts ct{0u, 0u}, ct1{0u, 0u};
+    if (a.alternate && (strip & 1u)) fused2p_strip<OBS, STAGED, true>(a, strip, R, fused_lds, ct, ct1);
+    else fused2p_strip<OBS, STAGED, false>(a, strip, R, fused_lds, ct, ct1);
+    const bool active = threadIdx.x < a.groups;
+    if (OBS) {
+        int64_t* const out = a.spread ? spread_line(a.obs, blockIdx.x) : a.obs;
+        block_accumulate(out, active ? ct.anti : 0u, active ? ct.neg : 0u, active ? 1u : 0u, 64u * R);
+        __syncthreads();  // block_accumulate's LDS is reused
+        block_accumulate(out + 2, active ? ct1.anti : 0u, active ? ct1.neg : 0u, active ? 1u : 0u, 64u * R);
     }
 }
 
@@ -1850,6 +2073,7 @@ struct Options {
     std::atomic<int64_t> fused_alternate = 1;  // fused sweep: odd strips walk upwards
     std::atomic<int64_t> fused_sweeps = 2;     // fused sweep: sweeps per pass over the lattice (1 or 2)
     std::atomic<int64_t> fused_ties = 1;       // two-sweep pass: settle the ties of a step's four updates together
+    std::atomic<int64_t> fused_pairs = 1;      // two-sweep pass, rows of at most 512 groups: ties of two steps together
     std::atomic<int64_t> fused_bands = 0;      // two-sweep pass in column bands of one wave: 0 = above L = 65536, 1 = always
     std::atomic<int64_t> band_rows = 0;        // rows per strip of the band pass; 0 = choose from L
     std::atomic<int64_t> packed_ties = 1;      // packed half-sweep: settle the ties of four rows together
@@ -2018,6 +2242,34 @@ uint32_t fused_rows(int64_t L, int sweeps = 1) {
     return R;
 }
 
+// Compute units of the current device (cached per device).
+uint32_t device_cus() {
+    static std::atomic<uint32_t> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    uint32_t v = cache[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        v = (uint32_t)n;
+        cache[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
+// Rows per strip of the two-sweep pass with paired steps (even, need not divide L: the last strip takes
+// the rest).  Its waves hold up to 168 registers, three per SIMD: the strips are made just tall enough
+// that all of them fit on the device at once (tall strips recompute fewer rows), 8 rows at least.
+uint32_t fused_rows_pairs(int64_t L) {
+    if (g_opt.fused_rows > 0 && g_opt.fused_rows <= L) return (uint32_t)g_opt.fused_rows;
+    const uint64_t waves_per_strip = (uint64_t)(L / 64 + 63) / 64;
+    const uint64_t slots = (uint64_t)device_cus() * 4u * 3u;
+    const uint64_t strips = std::max<uint64_t>(1, slots / waves_per_strip);
+    uint64_t R = ((uint64_t)L + strips - 1) / strips;
+    R += R & 1u;
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(R, 8), 128);
+}
+
 // One pass of the fused kernel: `sweeps` (1 or 2) sweeps t, t + 1 from src to dst; obs: NULL or
 // 2 * sweeps int64, zeroed beforehand, or with `spread` a spread set (zeroed beforehand).
 int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::Thresholds& th, uint64_t seed,
@@ -2027,7 +2279,11 @@ int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::T
     a.dst = dst;
     a.L = (uint32_t)L;
     a.groups = (uint32_t)(L / 64);
-    a.rows = fused_rows(L, sweeps);
+    // paired steps: two sweeps with the ties of two steps settled together, rows of at most 512 groups
+    const bool pairs = sweeps == 2 && g_opt.fused_ties != 0 && g_opt.fused_pairs != 0 && a.groups <= 512u;
+    a.rows = pairs ? fused_rows_pairs(L) : fused_rows(L, sweeps);
+    const uint32_t n_strips = (a.L + a.rows - 1u) / a.rows;
+    a.rows_last = a.L - (n_strips - 1u) * a.rows;
     a.t = t;
     a.key0 = (uint32_t)seed;
     a.key1 = (uint32_t)(seed >> 32);
@@ -2041,9 +2297,9 @@ int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::T
     const uint32_t threads = (a.groups + 63u) / 64u * 64u;
     const bool staged = g_opt.staged && a.groups % 64u == 0;
     const bool ties = g_opt.fused_ties != 0;
-    const size_t per_wave = ties ? ising::kTieQueueBytes : staged ? 4096u : 0u;
+    const size_t per_wave = pairs ? ising::kPairWaveBytes : ties ? ising::kTieQueueBytes : staged ? 4096u : 0u;
     const size_t lds = (size_t)(threads / 64u) * per_wave + 2u * threads * sizeof(uint32_t);
-    const dim3 grid(a.L / a.rows), block(threads);
+    const dim3 grid(n_strips), block(threads);
 #define ISING_LAUNCH_FUSED(K, OO, SS)                                                                    \
     do {                                                                                                 \
         if (lds > 65536) {                                                                               \
@@ -2053,6 +2309,11 @@ int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::T
         }                                                                                                \
         hipLaunchKernelGGL((ising::K<OO, SS>), grid, block, lds, stream, a);                            \
     } while (0)
+    if (pairs) {
+        if (staged) { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused2p, true, true); else ISING_LAUNCH_FUSED(k_sweep_fused2p, false, true); }
+        else { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused2p, true, false); else ISING_LAUNCH_FUSED(k_sweep_fused2p, false, false); }
+        return check_launch("k_sweep_fused2p");
+    }
     if (ties && sweeps == 2) {
         if (staged) { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused2q, true, true); else ISING_LAUNCH_FUSED(k_sweep_fused2q, false, true); }
         else { if (obs) ISING_LAUNCH_FUSED(k_sweep_fused2q, true, false); else ISING_LAUNCH_FUSED(k_sweep_fused2q, false, false); }
@@ -3042,6 +3303,9 @@ int ising_set_option(const char* name, int64_t value) {
     } else if (n == "fused_sweeps") {
         if (value != 1 && value != 2) return ISING_EINVAL;
         g_opt.fused_sweeps = value;
+    } else if (n == "fused_pairs") {
+        if (value != 0 && value != 1) return ISING_EINVAL;
+        g_opt.fused_pairs = value;
     } else if (n == "fused_ties") {
         if (value != 0 && value != 1) return ISING_EINVAL;
         g_opt.fused_ties = value;
@@ -3058,7 +3322,7 @@ int ising_set_option(const char* name, int64_t value) {
         if (value != 0 && (value < 2 || value > 1024 || (value & (value - 1)) != 0)) return ISING_EINVAL;
         g_opt.band_rows = value;
     } else if (n == "fused_rows") {
-        if (value != 0 && (value < 2 || value > 256 || (value & (value - 1)) != 0)) return ISING_EINVAL;
+        if (value != 0 && (value < 2 || value > 256 || (value & 1) != 0)) return ISING_EINVAL;
         g_opt.fused_rows = value;
     } else {
         return ISING_EINVAL;
@@ -3083,6 +3347,7 @@ int ising_get_option(const char* name, int64_t* value) {
     else if (n == "fused_alternate") *value = g_opt.fused_alternate;
     else if (n == "fused_sweeps") *value = g_opt.fused_sweeps;
     else if (n == "fused_ties") *value = g_opt.fused_ties;
+    else if (n == "fused_pairs") *value = g_opt.fused_pairs;
     else if (n == "packed_ties") *value = g_opt.packed_ties;
     else if (n == "ties3") *value = g_opt.ties3;
     else if (n == "planes3") *value = g_opt.planes3;

@@ -4,7 +4,9 @@ The fused pass reads one buffer and writes the other; every decision uses the si
 so the lattice and the (M, E) trace must equal the oracle's two half-sweeps bit for bit.  Cases:
 one workgroup thread per 64-column group with threads past the last group idle (L = 64, 192,
 320), whole waves staged through LDS (L = 4096, 8192), the full 16384^2 benchmark lattice, the
-largest full-row lattice (65536^2, 1024 threads per workgroup) and the column-band pass above it.
+largest full-row lattice (65536^2, 1024 threads per workgroup) and the column-band pass above it;
+the two-sweep pass with two steps' ties settled together (rows of up to 512 groups, the default
+there) and with one step's.
 """
 import math
 import sys
@@ -39,23 +41,25 @@ def _to_dev(a: np.ndarray):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-@pytest.mark.parametrize("ties", [1, 0])
+@pytest.mark.parametrize("ties,pairs", [(1, 1), (1, 0), (0, 0)])
 @pytest.mark.parametrize("fmt", ["exact", "bf16", "fp16"])
 @pytest.mark.parametrize("L,beta,n,seed,offset", [
     (64, BETA_C, 1, 1, 0), (64, BETA_C, 6, 2, 5), (128, 0.3, 4, 3, 0), (192, 0.7, 5, 2**40 + 3, 11),
     (320, 1 / 2.6, 2, 8, 1000), (256, 0.0, 3, 9, 0), (128, math.inf, 4, 10, 2**32 - 4)])
-def test_fused_sweeps_match_oracle(dev, oracle_lib, L, beta, n, seed, offset, fmt, ties):
+def test_fused_sweeps_match_oracle(dev, oracle_lib, L, beta, n, seed, offset, fmt, ties, pairs):
     # ties: the fused passes settle the still-tied words of a step's updates together (1) or each
-    # update finishes its own words (0)
-    _say("fused", L, beta, n, seed, offset, fmt, ties)
+    # update finishes its own words (0); pairs: the two-sweep pass settles two steps' words together
+    _say("fused", L, beta, n, seed, offset, fmt, ties, pairs)
     host = inputs.random_lattice(L, seed=L + n)
     s, scratch = _to_dev(host), torch.empty((L, L), dtype=torch.int8, device="cuda")
     trace = torch.empty((n, 2), dtype=torch.int64, device="cuda")
     dev.ising_set_option("fused_ties", ties)
+    dev.ising_set_option("fused_pairs", pairs)
     try:
         dev.ising_sweep_fused(s, scratch, L, beta, fmt, n, seed, offset, trace)
     finally:
         dev.ising_set_option("fused_ties", 1)
+        dev.ising_set_option("fused_pairs", 1)
     if fmt == "exact":
         ref = oracle_lib.sweep(host, beta, n, seed, offset, trace=True)
     else:
@@ -105,9 +109,10 @@ def test_fused_equals_two_half_sweeps_for_every_strip_height(dev, L):
     dev.ising_sweep_fmt(ref, L, BETA_C, "exact", 4, 17, 40, ref_tr)
     scratch = torch.empty_like(base)
     try:
-        for sweeps, ties in ((1, 0), (1, 1), (2, 0), (2, 1)):
+        for sweeps, ties, pairs in ((1, 0, 1), (1, 1, 1), (2, 0, 1), (2, 1, 0), (2, 1, 1)):
             dev.ising_set_option("fused_sweeps", sweeps)
             dev.ising_set_option("fused_ties", ties)
+            dev.ising_set_option("fused_pairs", pairs)
             for rows in (0, 2, 4, 8, 16, 32, 64, 128, 256):
                 if rows and (L % rows or rows > L):
                     continue
@@ -119,11 +124,11 @@ def test_fused_equals_two_half_sweeps_for_every_strip_height(dev, L):
                     s = base.clone()
                     tr = torch.empty((4, 2), dtype=torch.int64, device="cuda")
                     dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", 4, 17, 40, tr)
-                    assert torch.equal(s, ref), (sweeps, ties, rows, remap, staged, alt)
-                    assert torch.equal(tr, ref_tr), (sweeps, ties, rows, remap, staged, alt)
+                    assert torch.equal(s, ref), (sweeps, ties, pairs, rows, remap, staged, alt)
+                    assert torch.equal(tr, ref_tr), (sweeps, ties, pairs, rows, remap, staged, alt)
     finally:
         for k, v in (("fused_rows", 0), ("xcd_remap", 1), ("staged", 1), ("fused_alternate", 1), ("fused_sweeps", 2),
-                     ("fused_ties", 1)):
+                     ("fused_ties", 1), ("fused_pairs", 1)):
             dev.ising_set_option(k, v)
 
 
