@@ -750,15 +750,16 @@ __global__ __launch_bounds__(1024) void k_sweep_fused2q(FusedArgs a) {
 
 constexpr uint32_t kPairQueueCap = 512;                        // 8 updates x 64 lanes
 constexpr uint32_t kPairQueueSlots = kPairQueueCap + 64u;       // and one write-off slot per lane
-constexpr uint32_t kPairWaveBytes = 4u * kPairQueueSlots * 4u + 64u * 8u * 4u;  // 9 KiB entries, 2 KiB results
+constexpr uint32_t kPairWaveBytes = kPairQueueSlots * 16u + 8u * 64u * 4u;  // 9 KiB entries, 2 KiB results
 
-// Per-wave LDS of the pair's tie queue: task[4][576] = (tied, tied & sel2, Philox row, meta = u | lane
-// << 3 | group << 9) and res[64][8] = the sites of update u of lane l that the queue accepted.  A lane
-// with no tied site writes its entry to its own slot past the queue (512 + lane), so that a push is
-// straight-line code.  The first 4 KiB double as the row staging buffer outside the pushes and the
-// settle.
+// Per-wave LDS of the pair's tie queue: task[576] = (tied, tied & sel2, Philox row, meta = u | lane << 3 |
+// group << 9), one 16-byte entry each, and res[8][64] = the sites of update u of lane l that the queue
+// accepted (update-major, so that neither the settle's scattered writes nor a lane's reads collide on
+// LDS banks).  A lane with no tied site writes its entry to its own slot past the queue (512 + lane), so
+// that a push is straight-line code.  The first 4 KiB double as the row staging buffer outside the pushes
+// and the settle.
 struct PairQueue {
-    uint32_t* task;
+    uint4* task;
     uint32_t* res;
 };
 
@@ -796,10 +797,7 @@ __device__ __forceinline__ void pair_update(RowBits& own, const RowBits& v0, con
     const uint64_t B = __builtin_amdgcn_ballot_w64(tied != 0u);
     const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, 0u));
     const uint32_t pos = tied != 0u ? n + rank : kPairQueueCap + lane;
-    q.task[pos] = tied;
-    q.task[kPairQueueSlots + pos] = sel2 & tied;
-    q.task[2u * kPairQueueSlots + pos] = urow;
-    q.task[3u * kPairQueueSlots + pos] = (uint32_t)U | (lane << 3) | (g << 9);
+    q.task[pos] = make_uint4(tied, sel2 & tied, urow, (uint32_t)U | (lane << 3) | (g << 9));
     n += (uint32_t)__builtin_popcountll(B);
 }
 
@@ -812,13 +810,10 @@ __device__ __forceinline__ void pair_settle(const PairQueue& q, uint32_t n, cons
     for (uint32_t b = 0; b < n; b += 64u) {
         const uint32_t j = b + lane;
         const bool have = j < n;
-        uint32_t tied = 0u, s2 = 0u, row = 0u, meta = 0u;
-        if (have) {
-            tied = q.task[j];
-            s2 = q.task[kPairQueueSlots + j];
-            row = q.task[2u * kPairQueueSlots + j];
-            meta = q.task[3u * kPairQueueSlots + j];
-        }
+        uint4 e = make_uint4(0u, 0u, 0u, 0u);
+        if (have) e = q.task[j];
+        uint32_t tied = e.x;
+        const uint32_t s2 = e.y, row = e.z, meta = e.w;
         const uint32_t u = meta & 7u, src = (meta >> 3) & 63u, g = meta >> 9;
         const uint32_t tu = t + ((u >> 1) & 1u), qu = (u & 1u) ^ 1u;
         uint32_t acc = 0u;
@@ -827,7 +822,7 @@ __device__ __forceinline__ void pair_settle(const PairQueue& q, uint32_t n, cons
             if (!wave_any(tied != 0u)) break;
             compare_planes(acc, tied, s2, philox4x32_10(g, row, tu, 2u * m + qu, key0, key1), th, m);
         }
-        if (have) q.res[8u * src + u] = acc;
+        if (have) q.res[64u * u + src] = acc;
     }
     wave_lds_sync();
 }
@@ -841,7 +836,7 @@ __device__ __forceinline__ void fused2p_strip(const FusedArgs& a, uint32_t strip
     uint32_t* const wl = reinterpret_cast<uint32_t*>(fused_lds) + (tid >> 6) * (kPairWaveBytes / 4u);
     uint4* const stage = reinterpret_cast<uint4*>(wl);
     uint32_t* const xch = reinterpret_cast<uint32_t*>(fused_lds) + (nt >> 6) * (kPairWaveBytes / 4u);
-    const PairQueue q{wl, wl + 4u * kPairQueueSlots};
+    const PairQueue q{reinterpret_cast<uint4*>(wl), wl + 4u * kPairQueueSlots};
     const bool active = tid < G;
     const uint32_t g = active ? tid : G - 1;
     const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
@@ -899,8 +894,8 @@ __device__ __forceinline__ void fused2p_strip(const FusedArgs& a, uint32_t strip
         const bool u2a = s >= 4u && s <= R + 7, u2b = s1 >= 4u && s1 <= R + 7;
         const bool u3a = s >= 8u && s <= R + 9, u3b = s1 >= 8u && s1 <= R + 9;
         const bool u4a = s >= 12u, u4b = s1 >= 12u;
-        reinterpret_cast<uint4*>(q.res)[2u * lane] = make_uint4(0u, 0u, 0u, 0u);
-        reinterpret_cast<uint4*>(q.res)[2u * lane + 1u] = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (uint32_t u = 0; u < 8u; ++u) q.res[64u * u + lane] = 0u;
         uint32_t n = 0u;
         if (u1a) pair_update<OA, 1, 0>(w2, w3, w1, nbL, nbR, a.th, g, vrow(s + 1u), t, k0, k1, q, n, lane);
         if (u2a) pair_update<OA, 0, 1>(w5, w6, w4, nbL, nbR, a.th, g, vrow(s - 2u), t, k0, k1, q, n, lane);
@@ -911,8 +906,9 @@ __device__ __forceinline__ void fused2p_strip(const FusedArgs& a, uint32_t strip
         if (u3b) pair_update<OB, 1, 6>(w7, w8, w6, nbL, nbR, a.th, g, vrow(s - 4u), t + 1u, k0, k1, q, n, lane);
         if (u4b) pair_update<OB, 0, 7>(w10, w11, w9, nbL, nbR, a.th, g, vrow(s - 7u), t + 1u, k0, k1, q, n, lane);
         pair_settle(q, n, a.th, t, k0, k1, lane);
-        const uint4 ra = reinterpret_cast<const uint4*>(q.res)[2u * lane];  // zero for updates not made
-        const uint4 rb = reinterpret_cast<const uint4*>(q.res)[2u * lane + 1u];
+        // zero for the updates the pair does not make
+        const uint4 ra = make_uint4(q.res[lane], q.res[64u + lane], q.res[128u + lane], q.res[192u + lane]);
+        const uint4 rb = make_uint4(q.res[256u + lane], q.res[320u + lane], q.res[384u + lane], q.res[448u + lane]);
         if (OA) { w2.o ^= ra.x; w5.o ^= ra.y; w8.o ^= ra.z; w11.o ^= ra.w; w1.e ^= rb.x; w4.e ^= rb.y; w7.e ^= rb.z; w10.e ^= rb.w; }
         else { w2.e ^= ra.x; w5.e ^= ra.y; w8.e ^= ra.z; w11.e ^= ra.w; w1.o ^= rb.x; w4.o ^= rb.y; w7.o ^= rb.z; w10.o ^= rb.w; }
         if (OBS) {
@@ -922,14 +918,15 @@ __device__ __forceinline__ void fused2p_strip(const FusedArgs& a, uint32_t strip
             if (u4a) tq_count<OA, 3>(w11, w12, w10, nbL, nbR, ct1);
             if (u4b) tq_count<OB, 7>(w10, w11, w9, nbL, nbR, ct1);
         }
+        // walk rows s + 4, s + 5 (fetched a pair ago), the rows the pair finished, and the requests for
+        // s + 6, s + 7 (past the walk's last row the last row again; those rows are never updated).  The
+        // vector-memory counter also counts stores: converting the fetched rows before the stores keeps
+        // their waits from draining the stores just issued.
+        const RowBits n4 = own(rawA), n5 = own(rawB);
         if (u4a) put(vrow(s - 8u), w11);
         if (u4b) put(vrow(s - 7u), w10);
-        // walk rows s + 4, s + 5 (fetched a pair ago) and the requests for s + 6, s + 7
-        RowBits n4 = z, n5 = z;
-        if (s + 4u <= R + 7) n4 = own(rawA);
-        if (s + 5u <= R + 7) n5 = own(rawB);
-        if (s + 6u <= R + 7) fetch(rawA, vrow(s + 6u));
-        if (s + 7u <= R + 7) fetch(rawB, vrow(s + 7u));
+        fetch(rawA, vrow(s + 6u <= R + 7 ? s + 6u : R + 7));
+        fetch(rawB, vrow(s + 7u <= R + 7 ? s + 7u : R + 7));
         w12 = w10; w11 = w9; w10 = w8; w9 = w7; w8 = w6; w7 = w5; w6 = w4; w5 = w3; w4 = w2; w3 = w1; w2 = w0;
         w1 = n4;
         w0 = n5;

@@ -272,14 +272,16 @@ __device__ __forceinline__ void compare_planes(uint32_t& acc, uint32_t& tied, ui
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         const uint32_t k = 4u * m + (uint32_t)w;
-        // threshold bit of every site: bit 31 - k of T_4, flipped on sel2 where T_2 differs (two
-        // instructions with uniform masks; branching on the uniform bits instead measured slower)
+        // the site's threshold bit is bit 31 - k of T_4 (m4), flipped on sel2 where T_2 differs (d); the
+        // uniform masks enter one at a time (a vector instruction reads at most one scalar register):
+        // diff = x ^ m4 ^ (sel2 & d) = x ^ threshold bit.  (Branching on the uniform bits measured slower.)
         const uint32_t m4 = 0u - ((th.t4 >> (31u - k)) & 1u);
         const uint32_t d = 0u - (((th.t2 ^ th.t4) >> (31u - k)) & 1u);
-        const uint32_t tbit = m4 ^ (sel2 & d);
         const uint32_t x = planes[w];
-        acc |= tied & tbit & ~x;
-        tied &= ~(x ^ tbit);
+        // four instructions: the compiler would otherwise fold the masks back into five
+        const uint32_t diff = __builtin_amdgcn_bitop3_b32(x ^ m4, sel2, d, 0x78);  // a ^ (b & c)
+        acc |= __builtin_amdgcn_bitop3_b32(tied, diff, x, 0x40);  // differs with x = 0: threshold bit 1, x < T
+        tied = __builtin_amdgcn_bitop3_b32(tied, diff, 0u, 0x30);  // a & ~b
     }
 }
 
