@@ -322,8 +322,8 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
  *                    2), 0 = autotune (default).
  *   "fused_rows"     rows per workgroup strip of ising_sweep_fused: 0 = automatic, else an even
  *                    number in [2, 256].  The two-sweep pass with paired steps takes any such value
- *                    (its last strip takes the rows left over); the other passes ignore a value that
- *                    does not divide L.
+ *                    (its strips then hold that many rows or two fewer); the other passes ignore a
+ *                    value that does not divide L.
  *   "fused_alternate" 1 = odd strips of ising_sweep_fused walk upwards (default), 0 = all down.
  *   "fused_sweeps"   sweeps per pass of ising_sweep_fused: 2 (default) or 1.
  *   "fused_ties"     fused passes (two sweeps or one): 1 = the updates of a step are independent

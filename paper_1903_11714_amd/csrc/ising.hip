@@ -237,8 +237,19 @@ struct FusedArgs {
     uint32_t nt_store;   // non-temporal stores of the output rows
     uint32_t alternate;  // walk odd strips upwards
     uint32_t spread;     // k_sweep_fused2q: obs is a spread set (each workgroup adds into its line)
-    uint32_t rows_last;  // k_sweep_fused2p: rows of the last strip (even, <= rows; the others have rows)
+    uint32_t tall;       // k_sweep_fused2p: strips of rows + 2 rows (spread evenly among the others)
 };
+
+// Strip l of k_sweep_fused2p (of S = gridDim.x): `tall` of the S strips have rows + 2 rows, the rest
+// rows, spread evenly (the first l strips hold floor(l tall / S) tall ones), so that the strips a compute
+// unit takes together hold nearly the same number of rows.  Returns the strip's first row and sets R.
+__device__ __forceinline__ uint32_t pair_strip_rows(uint32_t l, uint32_t S, uint32_t rows, uint32_t tall,
+                                                    uint32_t& R) {
+    const uint32_t before = (uint32_t)(((uint64_t)l * tall) / S);
+    const uint32_t upto = (uint32_t)(((uint64_t)(l + 1u) * tall) / S);
+    R = rows + 2u * (upto - before);
+    return l * rows + 2u * before;
+}
 
 // Edge bits a thread publishes after step x: bit 0 / 1 = site 0 of the even columns / site 31 of
 // the odd columns of row x + 1, bit 2 / 3 = the same sites of row x.
@@ -817,8 +828,16 @@ __device__ __forceinline__ void pair_settle(const PairQueue& q, uint32_t n, cons
         const uint32_t u = meta & 7u, src = (meta >> 3) & 63u, g = meta >> 9;
         const uint32_t tu = t + ((u >> 1) & 1u), qu = (u & 1u) ^ 1u;
         uint32_t acc = 0u;
+        // blocks 2 and 3 as two independent chains (a queue of a few dozen words almost always needs both;
+        // a block that finds no tied site changes nothing), then one at a time
+        if (wave_any(tied != 0u)) {
+            const Words4 b2 = philox4x32_10(g, row, tu, 4u + qu, key0, key1);
+            const Words4 b3 = philox4x32_10(g, row, tu, 6u + qu, key0, key1);
+            compare_planes(acc, tied, s2, b2, th, 2u);
+            compare_planes(acc, tied, s2, b3, th, 3u);
+        }
 #pragma unroll 1
-        for (uint32_t m = 2; m < th.blocks; ++m) {
+        for (uint32_t m = 4; m < th.blocks; ++m) {
             if (!wave_any(tied != 0u)) break;
             compare_planes(acc, tied, s2, philox4x32_10(g, row, tu, 2u * m + qu, key0, key1), th, m);
         }
@@ -827,9 +846,9 @@ __device__ __forceinline__ void pair_settle(const PairQueue& q, uint32_t n, cons
     wave_lds_sync();
 }
 
-// Strip `strip` holds rows strip * a.rows .. + R - 1 (R = a.rows, or a.rows_last for the last strip).
+// The strip holds rows r0 .. r0 + R - 1 (pair_strip_rows).
 template <bool OBS, bool STAGED, bool UP>
-__device__ __forceinline__ void fused2p_strip(const FusedArgs& a, uint32_t strip, uint32_t R, uint4* fused_lds,
+__device__ __forceinline__ void fused2p_strip(const FusedArgs& a, uint32_t r0_, uint32_t R, uint4* fused_lds,
                                               Counts& ct, Counts& ct1) {
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
     const uint32_t G = a.groups, L = a.L;
@@ -841,7 +860,7 @@ __device__ __forceinline__ void fused2p_strip(const FusedArgs& a, uint32_t strip
     const uint32_t g = active ? tid : G - 1;
     const uint32_t gl = g == 0 ? G - 1 : g - 1, gr = g + 1 == G ? 0 : g + 1;
     const uint32_t lane = tid & 63u;
-    const uint32_t r0 = __builtin_amdgcn_readfirstlane(strip * a.rows);  // uniform: keeps the row arithmetic scalar
+    const uint32_t r0 = __builtin_amdgcn_readfirstlane(r0_);  // uniform: keeps the row arithmetic scalar
     const size_t col = (size_t)(STAGED ? g - lane : g) * 64u;
     // walk row k = 0 .. R + 7: r0 - 4 .. r0 + R + 3 (down) or r0 + R + 3 .. r0 - 4 (up), wrapped onto the
     // torus; callers pass k <= R + 7 for every row they load or store
@@ -939,10 +958,11 @@ template <bool OBS, bool STAGED>
 __global__ __launch_bounds__(512) void k_sweep_fused2p(FusedArgs a) {
     extern __shared__ uint4 fused_lds[];
     const uint32_t strip = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
-    const uint32_t R = strip + 1u == gridDim.x ? a.rows_last : a.rows;
+    uint32_t R;
+    const uint32_t r0 = pair_strip_rows(strip, gridDim.x, a.rows, a.tall, R);
     Counts ct{0u, 0u}, ct1{0u, 0u};
-    if (a.alternate && (strip & 1u)) fused2p_strip<OBS, STAGED, true>(a, strip, R, fused_lds, ct, ct1);
-    else fused2p_strip<OBS, STAGED, false>(a, strip, R, fused_lds, ct, ct1);
+    if (a.alternate && (strip & 1u)) fused2p_strip<OBS, STAGED, true>(a, r0, R, fused_lds, ct, ct1);
+    else fused2p_strip<OBS, STAGED, false>(a, r0, R, fused_lds, ct, ct1);
     const bool active = threadIdx.x < a.groups;
     if (OBS) {
         int64_t* const out = a.spread ? spread_line(a.obs, blockIdx.x) : a.obs;
@@ -2254,17 +2274,27 @@ uint32_t device_cus() {
     return v;
 }
 
-// Rows per strip of the two-sweep pass with paired steps (even, need not divide L: the last strip takes
-// the rest).  Its waves hold up to 168 registers, three per SIMD: the strips are made just tall enough
-// that all of them fit on the device at once (tall strips recompute fewer rows), 8 rows at least.
-uint32_t fused_rows_pairs(int64_t L) {
-    if (g_opt.fused_rows > 0 && g_opt.fused_rows <= L) return (uint32_t)g_opt.fused_rows;
-    const uint64_t waves_per_strip = (uint64_t)(L / 64 + 63) / 64;
-    const uint64_t slots = (uint64_t)device_cus() * 4u * 3u;
-    const uint64_t strips = std::max<uint64_t>(1, slots / waves_per_strip);
-    uint64_t R = ((uint64_t)L + strips - 1) / strips;
-    R += R & 1u;
-    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(R, 8), 128);
+// Strips of the two-sweep pass with paired steps: S strips of R or R + 2 rows (R even), `tall` of them
+// the taller.  Its waves hold up to 168 registers, three per SIMD: by default there are as many strips
+// as the device holds at once (tall strips recompute fewer rows), of 8 to 128 rows; option fused_rows
+// asks for strips of about that many rows.
+struct PairStrips {
+    uint32_t S, R, tall;
+};
+
+PairStrips fused_strips_pairs(int64_t L) {
+    uint64_t S;
+    if (g_opt.fused_rows > 0 && g_opt.fused_rows <= L) {
+        S = ((uint64_t)L + (uint64_t)g_opt.fused_rows - 1) / (uint64_t)g_opt.fused_rows;
+    } else {
+        const uint64_t waves_per_strip = (uint64_t)(L / 64 + 63) / 64;
+        const uint64_t slots = (uint64_t)device_cus() * 4u * 3u;
+        S = std::max<uint64_t>(1, slots / waves_per_strip);
+        S = std::min<uint64_t>(S, (uint64_t)L / 8);                 // 8 rows at least
+        S = std::max<uint64_t>(S, ((uint64_t)L + 127) / 128);       // 128 rows at most
+    }
+    const uint64_t R = 2 * ((uint64_t)L / (2 * S));  // even; L - S R < 2 S
+    return PairStrips{(uint32_t)S, (uint32_t)R, (uint32_t)(((uint64_t)L - S * R) / 2)};
 }
 
 // One pass of the fused kernel: `sweeps` (1 or 2) sweeps t, t + 1 from src to dst; obs: NULL or
@@ -2278,9 +2308,17 @@ int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::T
     a.groups = (uint32_t)(L / 64);
     // paired steps: two sweeps with the ties of two steps settled together, rows of at most 512 groups
     const bool pairs = sweeps == 2 && g_opt.fused_ties != 0 && g_opt.fused_pairs != 0 && a.groups <= 512u;
-    a.rows = pairs ? fused_rows_pairs(L) : fused_rows(L, sweeps);
-    const uint32_t n_strips = (a.L + a.rows - 1u) / a.rows;
-    a.rows_last = a.L - (n_strips - 1u) * a.rows;
+    uint32_t n_strips;
+    if (pairs) {
+        const PairStrips ps = fused_strips_pairs(L);
+        a.rows = ps.R;
+        a.tall = ps.tall;
+        n_strips = ps.S;
+    } else {
+        a.rows = fused_rows(L, sweeps);
+        a.tall = 0;
+        n_strips = a.L / a.rows;
+    }
     a.t = t;
     a.key0 = (uint32_t)seed;
     a.key1 = (uint32_t)(seed >> 32);
