@@ -905,6 +905,15 @@ __device__ __forceinline__ void fused2p_strip(const FusedArgs& a, uint32_t r0_, 
     workgroup_lds_sync();
 #pragma unroll 1
     for (uint32_t s = 0; s < R + 12; s += 2) {
+        // a wave's issue priority falls as it walks (3 in the first quarter of its pairs, 0 in the last).
+        // The instruction arbiter otherwise favours the oldest wave, so the workgroups dispatched last ran
+        // almost twice as long as the first ones and each SIMD ended with one wave alone.
+        switch ((4u * s) / (R + 12u)) {
+            case 0: __builtin_amdgcn_s_setprio(3); break;
+            case 1: __builtin_amdgcn_s_setprio(2); break;
+            case 2: __builtin_amdgcn_s_setprio(1); break;
+            default: __builtin_amdgcn_s_setprio(0); break;
+        }
         const uint32_t sl = ((s >> 1) & 1u) * nt;
         const uint32_t nbL = xch[sl + gl], nbR = xch[sl + gr];
         // step s makes U1 for s <= R + 5, U2 for 4 <= s <= R + 7, U3 for 8 <= s <= R + 9, U4 for 12 <= s
