@@ -222,6 +222,26 @@ def test_fused_largest_full_row_lattice_and_bands_above_it(dev):
         torch.cuda.empty_cache()
 
 
+def test_fused_pairs_at_the_widest_rows_they_take(dev):
+    # The two-sweep pass with two steps per settle up to 512 groups per row: L = 32768 (512 threads per
+    # workgroup, 86 KiB of LDS, 384 strips of 84 and 86 rows) and L = 32704 (511 groups: one idle thread,
+    # rows loaded lane by lane); both equal the in-place two-launch path over two passes
+    for L, n in ((32768, 4), (32704, 4)):
+        _say("fused pairs wide", L, n)
+        s = torch.empty((L, L), dtype=torch.int8, device="cuda")
+        dev.ising_init(s, L, 8)
+        ref = s.clone()
+        tr_ref = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+        dev.ising_sweep(ref, L, BETA_C, n, 8, 21, tr_ref)
+        scratch = torch.zeros_like(s)
+        tr = torch.empty_like(tr_ref)
+        dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", n, 8, 21, tr)
+        assert torch.equal(s, ref), L
+        assert torch.equal(tr, tr_ref), L
+        del s, ref, scratch
+        torch.cuda.empty_cache()
+
+
 def test_fused_strip_height_divides_odd_multiple_of_64(dev):
     # L = 64 * 769: the tallest two-sweep strip that leaves enough waves (128 rows) does not divide L,
     # so the strips must be 64 rows tall; every row of the lattice must still be swept
