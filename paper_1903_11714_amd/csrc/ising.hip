@@ -1116,6 +1116,128 @@ __global__ __launch_bounds__(256, 4) void k_sweep_fused2b(BandArgs a) {
     }
 }
 
+// ---- The paired two-sweep walk (k_sweep_fused2p) in column bands of one wave (k_sweep_fused2b): the band's
+// lanes, its recomputed edge groups and its row I/O are those of the band pass, the walk, the uniforms and
+// the tie queue those of the paired pass; the group-edge words come from the adjacent lanes by lane shifts,
+// once per pair.  A wrong value at a band's edge still spreads by at most four columns over the pass (four
+// colour updates), so the result is the same two sweeps, bit for bit.
+template <bool OBS, bool UP>
+__device__ __forceinline__ void fused2pb_strip(const BandArgs& a, uint32_t band, uint32_t strip, uint32_t* wl,
+                                               uint32_t lane, Counts& ct, Counts& ct1) {
+    const uint32_t G = a.groups, L = a.L, R = a.rows;
+    uint4* const stage = reinterpret_cast<uint4*>(wl);
+    const PairQueue q{reinterpret_cast<uint4*>(wl), wl + 4u * kPairQueueSlots};
+    const uint32_t b0 = band_first(a, band), n_own = band_width(a, band);
+    // b0 + G - 1 + lane < 3G since G >= 64
+    uint32_t g = b0 + G - 1u + lane;
+    g = g >= G ? g - G : g;
+    g = g >= G ? g - G : g;
+    uint32_t gbase = b0 + G - 1u + (lane >> 2);
+    gbase = gbase >= G ? gbase - G : gbase;
+    gbase = gbase >= G ? gbase - G : gbase;
+    const uint32_t r0 = __builtin_amdgcn_readfirstlane(strip * R);  // uniform: keeps the row arithmetic scalar
+    auto vrow = [&](uint32_t k) {
+        const int32_t v = (int32_t)(UP ? r0 + R + 3 - k : r0 + k) - (UP ? 0 : 4);  // in [-4, L + 4)
+        return (uint32_t)(v < 0 ? v + (int32_t)L : v >= (int32_t)L ? v - (int32_t)L : v);
+    };
+    auto fetch = [&](Row& raw, uint32_t r) { load_row_chunks(raw, a.src + (size_t)r * L, gbase, G, lane); };
+    auto own = [&](const Row& raw) {
+        Row row;
+        regroup_to_owner(row, raw, stage, lane);
+        return row_bits(row);
+    };
+    auto put = [&](uint32_t r, const RowBits& b) {
+        Row row;
+        bits_to_row(row, b);
+        store_row_chunks(a.dst + (size_t)r * L, row, stage, lane, gbase, G, n_own, a.nt_store);
+    };
+    constexpr int OA = UP ? 1 : 0, OB = 1 - OA;
+    const uint32_t t = a.t, k0 = a.key0, k1 = a.key1;
+    const RowBits z{0u, 0u};
+    RowBits w12 = z, w11 = z, w10 = z, w9 = z, w8 = z, w7 = z, w6 = z, w5 = z, w4 = z;
+    Row rawA, rawB;
+    fetch(rawA, vrow(0));
+    RowBits w3 = own(rawA);
+    fetch(rawA, vrow(1));
+    RowBits w2 = own(rawA);
+    fetch(rawA, vrow(2));
+    RowBits w1 = own(rawA);
+    fetch(rawA, vrow(3));
+    RowBits w0 = own(rawA);
+    fetch(rawA, vrow(4));
+    fetch(rawB, vrow(5));
+    uint32_t e = pair_edges(w2, w5, w8, w11, w1, w4, w7, w10);
+#pragma unroll 1
+    for (uint32_t s = 0; s < R + 12; s += 2) {
+        switch ((4u * s) / (R + 12u)) {  // issue priority falling along the walk (as in k_sweep_fused2p)
+            case 0: __builtin_amdgcn_s_setprio(3); break;
+            case 1: __builtin_amdgcn_s_setprio(2); break;
+            case 2: __builtin_amdgcn_s_setprio(1); break;
+            default: __builtin_amdgcn_s_setprio(0); break;
+        }
+        const uint32_t nbL = from_left_lane(e), nbR = from_right_lane(e);
+        const uint32_t s1 = s + 1u;
+        const bool u1a = s <= R + 5, u1b = s1 <= R + 5;
+        const bool u2a = s >= 4u && s <= R + 7, u2b = s1 >= 4u && s1 <= R + 7;
+        const bool u3a = s >= 8u && s <= R + 9, u3b = s1 >= 8u && s1 <= R + 9;
+        const bool u4a = s >= 12u, u4b = s1 >= 12u;
+#pragma unroll
+        for (uint32_t u = 0; u < 8u; ++u) q.res[64u * u + lane] = 0u;
+        uint32_t n = 0u;
+        if (u1a) pair_update<OA, 1, 0>(w2, w3, w1, nbL, nbR, a.th, g, vrow(s + 1u), t, k0, k1, q, n, lane);
+        if (u2a) pair_update<OA, 0, 1>(w5, w6, w4, nbL, nbR, a.th, g, vrow(s - 2u), t, k0, k1, q, n, lane);
+        if (u3a) pair_update<OA, 1, 2>(w8, w9, w7, nbL, nbR, a.th, g, vrow(s - 5u), t + 1u, k0, k1, q, n, lane);
+        if (u4a) pair_update<OA, 0, 3>(w11, w12, w10, nbL, nbR, a.th, g, vrow(s - 8u), t + 1u, k0, k1, q, n, lane);
+        if (u1b) pair_update<OB, 1, 4>(w1, w2, w0, nbL, nbR, a.th, g, vrow(s + 2u), t, k0, k1, q, n, lane);
+        if (u2b) pair_update<OB, 0, 5>(w4, w5, w3, nbL, nbR, a.th, g, vrow(s - 1u), t, k0, k1, q, n, lane);
+        if (u3b) pair_update<OB, 1, 6>(w7, w8, w6, nbL, nbR, a.th, g, vrow(s - 4u), t + 1u, k0, k1, q, n, lane);
+        if (u4b) pair_update<OB, 0, 7>(w10, w11, w9, nbL, nbR, a.th, g, vrow(s - 7u), t + 1u, k0, k1, q, n, lane);
+        pair_settle(q, n, a.th, t, k0, k1, lane);
+        const uint4 ra = make_uint4(q.res[lane], q.res[64u + lane], q.res[128u + lane], q.res[192u + lane]);
+        const uint4 rb = make_uint4(q.res[256u + lane], q.res[320u + lane], q.res[384u + lane], q.res[448u + lane]);
+        if (OA) { w2.o ^= ra.x; w5.o ^= ra.y; w8.o ^= ra.z; w11.o ^= ra.w; w1.e ^= rb.x; w4.e ^= rb.y; w7.e ^= rb.z; w10.e ^= rb.w; }
+        else { w2.e ^= ra.x; w5.e ^= ra.y; w8.e ^= ra.z; w11.e ^= ra.w; w1.o ^= rb.x; w4.o ^= rb.y; w7.o ^= rb.z; w10.o ^= rb.w; }
+        if (OBS) {
+            if (s >= 6u && s <= R + 5) tq_count<OA, 1>(w5, w6, w4, nbL, nbR, ct);
+            if (s1 >= 6u && s1 <= R + 5) tq_count<OB, 5>(w4, w5, w3, nbL, nbR, ct);
+            if (u4a) tq_count<OA, 3>(w11, w12, w10, nbL, nbR, ct1);
+            if (u4b) tq_count<OB, 7>(w10, w11, w9, nbL, nbR, ct1);
+        }
+        const RowBits n4 = own(rawA), n5 = own(rawB);
+        if (u4a) put(vrow(s - 8u), w11);
+        if (u4b) put(vrow(s - 7u), w10);
+        fetch(rawA, vrow(s + 6u <= R + 7 ? s + 6u : R + 7));
+        fetch(rawB, vrow(s + 7u <= R + 7 ? s + 7u : R + 7));
+        w12 = w10; w11 = w9; w10 = w8; w9 = w7; w8 = w6; w7 = w5; w6 = w4; w5 = w3; w4 = w2; w3 = w1; w2 = w0;
+        w1 = n4;
+        w0 = n5;
+        e = pair_edges(w2, w5, w8, w11, w1, w4, w7, w10);
+    }
+}
+
+// One wave per (band, strip) unit, numbered as for k_sweep_fused2b; up to 168 registers, three waves per
+// SIMD.
+template <bool OBS>
+__global__ __launch_bounds__(256, 3) void k_sweep_fused2pb(BandArgs a) {
+    extern __shared__ uint4 band_lds[];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t unit = logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * (blockDim.x >> 6) + wave;
+    uint32_t* const wl = reinterpret_cast<uint32_t*>(band_lds) + wave * (kPairWaveBytes / 4u);
+    Counts ct{0u, 0u}, ct1{0u, 0u};
+    const bool live = unit < a.units;  // uniform per wave
+    const uint32_t band = live ? unit % a.bands : 0u, strip = live ? unit / a.bands : 0u;
+    if (live) {
+        if (a.alternate && (strip & 1u)) fused2pb_strip<OBS, true>(a, band, strip, wl, lane, ct, ct1);
+        else fused2pb_strip<OBS, false>(a, band, strip, wl, lane, ct, ct1);
+    }
+    if (OBS) {
+        const bool own = live && lane >= 1u && lane <= band_width(a, band);
+        block_accumulate(a.obs, own ? ct.anti : 0u, own ? ct.neg : 0u, own ? 1u : 0u, 64u * a.rows);
+        __syncthreads();  // block_accumulate's LDS is reused
+        block_accumulate(a.obs + 2, own ? ct1.anti : 0u, own ? ct1.neg : 0u, own ? 1u : 0u, 64u * a.rows);
+    }
+}
+
 // ---- One sweep per pass with the ties of a step settled together: the one-sweep walk with two
 // rows between its updates.  Step s updates the white sites of walk row s + 1 and the black sites
 // of walk row s - 1; neither reads what the other writes, so the two are independent and share
@@ -2418,6 +2540,13 @@ int launch_band_pass(const int8_t* src, int8_t* dst, int64_t L, const ising::Thr
     a.alternate = g_opt.fused_alternate ? 1u : 0u;
     constexpr uint32_t waves = 4;
     const dim3 grid((a.units + waves - 1) / waves), block(64 * waves);
+    if (g_opt.fused_ties != 0 && g_opt.fused_pairs != 0) {
+        // the paired walk: two steps per settle
+        const size_t lds = waves * ising::kPairWaveBytes;
+        if (obs) hipLaunchKernelGGL((ising::k_sweep_fused2pb<true>), grid, block, lds, stream, a);
+        else hipLaunchKernelGGL((ising::k_sweep_fused2pb<false>), grid, block, lds, stream, a);
+        return check_launch("k_sweep_fused2pb");
+    }
     const size_t lds = waves * ising::kTieQueueBytes;
     if (obs) hipLaunchKernelGGL((ising::k_sweep_fused2b<true>), grid, block, lds, stream, a);
     else hipLaunchKernelGGL((ising::k_sweep_fused2b<false>), grid, block, lds, stream, a);

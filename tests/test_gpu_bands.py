@@ -1,5 +1,6 @@
-"""GPU parity of the two-sweep pass in column bands (k_sweep_fused2b: one wave per band and strip,
-the default above L = 65536 and, with option "fused_bands", from L = 4096).
+"""GPU parity of the two-sweep pass in column bands (one wave per band and strip, the default above
+L = 65536 and, with option "fused_bands", from L = 4096): k_sweep_fused2pb (two steps per tie settle, the
+default) and k_sweep_fused2b (one step per settle, option "fused_pairs" = 0).
 
 A band's wave recomputes one group on either side of its own groups and takes its group-edge
 neighbours by a lane shift; every decision uses the site's own uniform, so the lattice and the (M, E)
@@ -53,16 +54,18 @@ def _to_dev(a: np.ndarray):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
+@pytest.mark.parametrize("pairs", [1, 0])
 @pytest.mark.parametrize("L,beta,n,seed,offset,fmt", [
     (4096, BETA_C, 2, 1, 0, "exact"), (4096, 0.3, 4, 2, 7, "exact"), (4096, 0.7, 3, 3, 2**32 - 3, "exact"),
     (4096, BETA_C, 4, 4, 0, "bf16"), (4096, 0.45, 2, 5, 1, "fp16"), (4096, 0.0, 2, 6, 0, "exact"),
     (4096, math.inf, 2, 7, 0, "exact")])
-def test_band_pass_matches_oracle(dev, oracle_lib, L, beta, n, seed, offset, fmt):
-    _say("bands vs oracle", L, beta, n, seed, offset, fmt)
+def test_band_pass_matches_oracle(dev, oracle_lib, L, beta, n, seed, offset, fmt, pairs):
+    # pairs: the band's walk settles two steps' tied words together (1, the default) or one step's (0)
+    _say("bands vs oracle", L, beta, n, seed, offset, fmt, pairs)
     host = inputs.random_lattice(L, seed=L + n + seed)
     s, scratch = _to_dev(host), torch.empty((L, L), dtype=torch.int8, device="cuda")
     trace = torch.empty((n, 2), dtype=torch.int64, device="cuda")
-    with options(dev, fused_bands=1):
+    with options(dev, fused_bands=1, fused_pairs=pairs):
         dev.ising_sweep_fused(s, scratch, L, beta, fmt, n, seed, offset, trace)
     if fmt == "exact":
         ref = oracle_lib.sweep(host, beta, n, seed, offset, trace=True)
@@ -84,14 +87,14 @@ def test_band_pass_equals_two_launch_path_for_every_strip_height(dev, L):
     for R in (2, 4, 8, 16, 32, 64, 128, 256):
         if L % R:
             continue
-        for alternate in (1, 0):
-            _say("bands strip height", L, R, alternate)
+        for alternate, pairs in ((1, 1), (0, 1), (1, 0), (0, 0)):
+            _say("bands strip height", L, R, alternate, pairs)
             s = base.clone()
             tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
-            with options(dev, fused_bands=1, band_rows=R, fused_alternate=alternate):
+            with options(dev, fused_bands=1, band_rows=R, fused_alternate=alternate, fused_pairs=pairs):
                 dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", n, seed, 3, tr)
-            assert torch.equal(s, ref), (L, R, alternate)
-            assert torch.equal(tr, ref_tr), (L, R, alternate)
+            assert torch.equal(s, ref), (L, R, alternate, pairs)
+            assert torch.equal(tr, ref_tr), (L, R, alternate, pairs)
 
 
 def test_band_pair_is_two_sweeps_out_of_place(dev, oracle_lib):
