@@ -104,7 +104,7 @@ FUSED_MAX_L = 65536  # above this the two-sweep pass runs as column bands of one
 KERNEL_NAME = {
     "fused": "k_sweep_fused2p (two sweeps per launch, ties of two steps settled together)",
     "fused_wide": "k_sweep_fused2q (two sweeps per launch, tie queue)",
-    "bands": "k_sweep_fused2b (two sweeps per launch in column bands of one wave, tie queue)",
+    "bands": "k_sweep_fused2pb (two sweeps per launch in column bands of one wave, ties of two steps settled together)",
     "int8": "k_sweep_int8 (one colour per launch)",
     "packed": "k_sweep_packed_q (one colour per launch, tie queue)",
 }
