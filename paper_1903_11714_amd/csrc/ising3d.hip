@@ -48,10 +48,12 @@ __device__ __forceinline__ void compare_planes3(uint32_t& acc, uint32_t& tied, u
         const uint32_t m6 = 0u - ((th.t[2] >> (31u - k)) & 1u);
         const uint32_t d2 = 0u - (((th.t[0] ^ th.t[2]) >> (31u - k)) & 1u);
         const uint32_t d4 = 0u - (((th.t[1] ^ th.t[2]) >> (31u - k)) & 1u);
-        const uint32_t tbit = m6 ^ (s2 & d2) ^ (s4 & d4);
+        // diff = x ^ threshold bit, one uniform mask per instruction (a vector instruction reads at most
+        // one scalar register): five instructions per plane
         const uint32_t x = planes[w];
-        acc |= tied & tbit & ~x;
-        tied &= ~(x ^ tbit);
+        const uint32_t diff = __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_bitop3_b32(x ^ m6, s2, d2, 0x78), s4, d4, 0x78);
+        acc |= __builtin_amdgcn_bitop3_b32(tied, diff, x, 0x40);  // differs with x = 0: threshold bit 1, x < T
+        tied = __builtin_amdgcn_bitop3_b32(tied, diff, 0u, 0x30);  // a & ~b
     }
 }
 
