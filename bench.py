@@ -560,7 +560,8 @@ def ingest_counters(key: str, layout: str, L: int, dirs, traced: str, untraced: 
         entry["hbm_bytes_per_launch"] = round(1024.0 * (entry["fetch_kib_raw"] * entry["fetch_scale"] +
                                                         entry["write_kib_raw"] * entry["write_scale"]))
     entry["alg_bytes_per_launch"] = algorithmic_bytes(layout, L) if alg_bytes is None else alg_bytes
-    entry["source_hash"] = kernel_source_hash()
+    entry["source_hash"] = kernel_source_hash(KERNEL_SOURCES_3D if layout.endswith("3d") or key.startswith("int8_3d")
+                                              else None)
     entry["command"] = command
     try:
         with open(TRAFFIC_FILE) as f:

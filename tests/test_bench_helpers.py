@@ -49,3 +49,8 @@ def test_ingest_counters_scales_by_the_copy_calibration(tmp_path, monkeypatch):
     assert e["hbm_bytes_per_launch"] == 1024 * (1100 * 2 + 2000)
     assert e["source_hash"] == bench.kernel_source_hash()
     assert json.load(open(out))["fused_L16384"]["command"] == "cmd"
+    # the cubic lattice's record is keyed to the hash of its own sources as well, which measured_counters checks
+    e3 = bench.ingest_counters("int8_3d_L1024", "int8", 1024, dirs, "k_sweep_fused2q<true", None, 1 << 28, "cmd",
+                               2.0 * 1024 ** 3)
+    assert e3["source_hash"] == bench.kernel_source_hash(bench.KERNEL_SOURCES_3D)
+    assert bench.measured_traffic("int8_3d", 1024) == e3["hbm_bytes_per_launch"]
