@@ -67,19 +67,29 @@ struct TieQueue3 {
 };
 constexpr uint32_t kTieQueue3Bytes = 5u * 256u * 4u + 64u * 16u;
 
-// The start of decide3 for one word: returns the sites decided by the neighbour count and the first
-// two Philox blocks (to flip at once); tied, s2, s4 = the sites still tied and which of them
-// compare with T_2 / T_4.
-__device__ __forceinline__ uint32_t decide3_head(uint32_t a, const uint32_t (&nb)[6], const Thresholds3& th,
-                                                 uint32_t g, uint32_t r, uint32_t t, uint32_t q, uint32_t key0,
-                                                 uint32_t key1, uint32_t& tied, uint32_t& s2, uint32_t& s4) {
+// Anti-aligned neighbours of each site of a word, bit-sliced: c = b0 + 2 b1 + 4 b2 (0 .. 6), from
+// two full adders of three neighbours each and their sum.
+struct Count3 {
+    uint32_t b0, b1, b2;
+};
+
+__device__ __forceinline__ Count3 neighbour_count3(uint32_t a, const uint32_t (&nb)[6]) {
     uint32_t x[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) x[k] = a ^ nb[k];
     const uint32_t sa = x[0] ^ x[1] ^ x[2], ca = (x[0] & x[1]) | (x[2] & (x[0] ^ x[1]));
     const uint32_t sb = x[3] ^ x[4] ^ x[5], cb = (x[3] & x[4]) | (x[5] & (x[3] ^ x[4]));
-    const uint32_t b0 = sa ^ sb, kk = sa & sb;
-    const uint32_t b1 = ca ^ cb ^ kk, b2 = (ca & cb) | (kk & (ca ^ cb));  // c = b0 + 2 b1 + 4 b2
+    const uint32_t kk = sa & sb;
+    return Count3{sa ^ sb, ca ^ cb ^ kk, (ca & cb) | (kk & (ca ^ cb))};
+}
+
+// The start of decide3 for one word whose neighbour count is c: returns the sites decided by the
+// count and the first two Philox blocks (to flip at once); tied, s2, s4 = the sites still tied and
+// which of them compare with T_2 / T_4.
+__device__ __forceinline__ uint32_t decide3_head(const Count3& c, const Thresholds3& th, uint32_t g, uint32_t r,
+                                                 uint32_t t, uint32_t q, uint32_t key0, uint32_t key1,
+                                                 uint32_t& tied, uint32_t& s2, uint32_t& s4) {
+    const uint32_t b0 = c.b0, b1 = c.b1, b2 = c.b2;
     uint32_t sel2 = b1 & ~b0 & ~b2, sel4 = b0 & ~b1 & ~b2, sel6 = ~(b0 | b1 | b2);
     uint32_t acc = b2 | (b1 & b0);  // c >= 3: s <= 0
     if (th.full[0]) { acc |= sel2; sel2 = 0u; }
@@ -288,13 +298,13 @@ __global__ __launch_bounds__(512) void k_sweep3(Sweep3Args a) {
         const uint32_t nbb[6] = {Ob ? ym.w : ym.z, Ob ? yp.w : yp.z, Ob ? ca.o : ca.e, Ob ? next.o : next.e, sb, hb};
         q.res[lane] = make_uint4(0u, 0u, 0u, 0u);
         uint32_t n = 0u, tied, s2, s4;
-        uint32_t acc = decide3_head(Oa ? ca.o : ca.e, nba, a.th, g, za * L + y, a.t, (uint32_t)Q, a.key0, a.key1,
-                                    tied, s2, s4);
+        uint32_t acc = decide3_head(neighbour_count3(Oa ? ca.o : ca.e, nba), a.th, g, za * L + y, a.t, (uint32_t)Q,
+                                    a.key0, a.key1, tied, s2, s4);
         ca.o ^= Oa ? acc : 0u;  // both fields, with selects: the parity is a runtime value
         ca.e ^= Oa ? 0u : acc;
         tq3_push(q, n, tied, s2, s4, za * L + y, 0u | (lane << 2) | (g << 8));
-        acc = decide3_head(Ob ? cb.o : cb.e, nbb, a.th, g, zb * L + y, a.t, (uint32_t)Q, a.key0, a.key1, tied, s2,
-                           s4);
+        acc = decide3_head(neighbour_count3(Ob ? cb.o : cb.e, nbb), a.th, g, zb * L + y, a.t, (uint32_t)Q, a.key0,
+                           a.key1, tied, s2, s4);
         cb.o ^= Ob ? acc : 0u;
         cb.e ^= Ob ? 0u : acc;
         tq3_push(q, n, tied, s2, s4, zb * L + y, 1u | (lane << 2) | (g << 8));
@@ -613,8 +623,8 @@ __global__ __launch_bounds__(640) void k_sweep3_fusedq(Fused3Args a) {
         const uint32_t hs = P ? shift_next(c.e, re & 1u) : shift_prev(c.o, lo_o >> 31);
         const uint32_t nb[6] = {ymw, ypw, P ? lo.o : lo.e, P ? hi.o : hi.e, side, hs};
         uint32_t tied, s2, s4;
-        const uint32_t acc = mask & decide3_head(P ? c.o : c.e, nb, a.th, g, z * L + y, a.t, colour, a.key0,
-                                                 a.key1, tied, s2, s4);
+        const uint32_t acc = mask & decide3_head(neighbour_count3(P ? c.o : c.e, nb), a.th, g, z * L + y, a.t,
+                                                 colour, a.key0, a.key1, tied, s2, s4);
         c.o ^= P ? acc : 0u;
         c.e ^= P ? 0u : acc;
         tq3_push(q, n, mask & tied, s2, s4, z * L + y, u | (lane << 2) | (g << 8));
@@ -796,8 +806,7 @@ struct Packed3Args {
     uint64_t n_lanes;    // L * G * (L / Rz): lane = ((zs * L + y) * G + g)
     uint32_t t, key0, key1;
     Thresholds3 th;
-    int64_t* obs;
-    int64_t* zero_slot;
+    int64_t* obs;  // OBS: a spread set (zeroed beforehand) that takes (M, E)
     uint32_t xcd_remap;
 };
 
@@ -809,7 +818,6 @@ struct Packed3Args {
 template <int Q, bool OBS>
 __global__ __launch_bounds__(256) void k_sweep3_packed(Packed3Args a) {
     const uint64_t id = (uint64_t)logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * blockDim.x + threadIdx.x;
-    if (a.zero_slot && blockIdx.x == 0 && threadIdx.x == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
     const bool active = id < a.n_lanes;
     Counts cnt{0u, 0u};
     if (active) {
@@ -843,14 +851,16 @@ __global__ __launch_bounds__(256) void k_sweep3_packed(Packed3Args a) {
             zcur = zpn;
         }
     }
-    if (OBS) block_accumulate(a.obs, cnt.anti, cnt.neg, active ? 1u : 0u, 64u * a.Rz, 3u);
+    if (OBS) block_accumulate(spread_line(a.obs, blockIdx.x), cnt.anti, cnt.neg, active ? 1u : 0u, 64u * a.Rz, 3u);
 }
 
 // Half-sweep of colour Q on the packed cubic layout with the ties of four planes settled together:
 // a lane takes planes z .. z + 3 of its column at a time (all colour-Q sites of a half-sweep are
 // independent), draws the first two Philox blocks of each word, queues the words still holding tied
 // sites and settles them with the other lanes'.  Same uniforms and results as k_sweep3_packed.
-// Rz % 4 == 0; lanes past n_lanes shadow the last lane without storing.
+// Rz % 4 == 0; lanes past n_lanes shadow the last lane without storing.  OBS: (M, E) of the lattice
+// as the launch finds it, before its own updates, from the neighbour counts the update forms anyway
+// (k_sweep3_packed counts after its updates instead).
 template <int Q, bool OBS>
 __global__ __launch_bounds__(256) void k_sweep3_packed_q(Packed3Args a) {
     extern __shared__ uint4 packed3_lds[];
@@ -858,10 +868,9 @@ __global__ __launch_bounds__(256) void k_sweep3_packed_q(Packed3Args a) {
     uint4* const mine = packed3_lds + (tid >> 6) * (kTieQueue3Bytes / 16u);
     const TieQueue3 q{reinterpret_cast<uint32_t*>(mine), mine + 5u * 64u};
     const uint64_t raw = (uint64_t)logical_block(blockIdx.x, gridDim.x, a.xcd_remap) * blockDim.x + tid;
-    if (a.zero_slot && blockIdx.x == 0 && tid == 0) { a.zero_slot[0] = 0; a.zero_slot[1] = 0; }
     const bool active = raw < a.n_lanes;
     const uint64_t id = active ? raw : a.n_lanes - 1u;
-    Counts cnt{0u, 0u};
+    uint32_t n1 = 0u, n2 = 0u, neg = 0u;  // OBS: anti-aligned bonds = n1 + 2 n2; -1 spins
     const uint32_t L = a.L, G = a.G, Rz = a.Rz;
     const uint32_t g = (uint32_t)(id % G);
     const uint64_t zy = id / G;
@@ -899,8 +908,18 @@ __global__ __launch_bounds__(256) void k_sweep3_packed_q(Packed3Args a) {
             const uint32_t side = zw[i + 1];
             const uint32_t hs = O ? shift_next(side, ed[i] & 1u) : shift_prev(side, ed[i] >> 31);
             const uint32_t nb[6] = {up[i], dn[i], zw[i], zw[i + 2], side, hs};
+            const Count3 c = neighbour_count3(w[i], nb);
+            if (OBS) {
+                // the lattice as the launch finds it: the anti-aligned neighbours of each colour-Q site
+                // (every bond once), and the spins of both colours
+                n1 += __builtin_popcount(c.b0);
+                n2 += __builtin_popcount(c.b1) + 2u * __builtin_popcount(c.b2);
+                neg += __builtin_popcount(w[i]) + __builtin_popcount(side);
+                // keep the counts here rather than sunk past the Philox blocks with their inputs
+                __asm__ volatile("" : "+v"(n1), "+v"(n2), "+v"(neg));
+            }
             uint32_t tied, s2, s4;
-            w[i] ^= decide3_head(w[i], nb, th, g, z * L + y, a.t, (uint32_t)Q, a.key0, a.key1, tied, s2, s4);
+            w[i] ^= decide3_head(c, th, g, z * L + y, a.t, (uint32_t)Q, a.key0, a.key1, tied, s2, s4);
             tq3_push(q, n, tied, s2, s4, z * L + y, (uint32_t)i | (lane << 2) | (g << 8));
         }
         tq3_settle<Q>(q, n, th, a.t, a.key0, a.key1, lane);
@@ -911,28 +930,21 @@ __global__ __launch_bounds__(256) void k_sweep3_packed_q(Packed3Args a) {
         w[3] ^= rr.w;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const uint32_t z = z0 + k0 + (uint32_t)i;
-            if (active) pq[at(z, y, g)] = w[i];
-            if (OBS) {
-                const bool O = ((Q + y + z) & 1u) != 0;
-                const uint32_t side = zw[i + 1];
-                const uint32_t hs = O ? shift_next(side, ed[i] & 1u) : shift_prev(side, ed[i] >> 31);
-                cnt.anti += __builtin_popcount(w[i] ^ up[i]) + __builtin_popcount(w[i] ^ dn[i]) +
-                            __builtin_popcount(w[i] ^ zw[i]) + __builtin_popcount(w[i] ^ zw[i + 2]) +
-                            __builtin_popcount(w[i] ^ side) + __builtin_popcount(w[i] ^ hs);
-                cnt.neg += __builtin_popcount(w[i]) + __builtin_popcount(side);
-            }
+            if (active) pq[at(z0 + k0 + (uint32_t)i, y, g)] = w[i];
         }
         zprev = zw[4];
         zcur = zw[5];
     }
-    if (OBS) block_accumulate(a.obs, active ? cnt.anti : 0u, active ? cnt.neg : 0u, active ? 1u : 0u, 64u * a.Rz, 3u);
+    // a lane's counts stay below 2^13 (Rz <= 32 words of 32 sites, six bonds each)
+    if (OBS)
+        block_accumulate(spread_line(a.obs, blockIdx.x), active ? n1 + 2u * n2 : 0u, active ? neg : 0u,
+                         active ? 1u : 0u, 64u * a.Rz, 3u);
 }
 
 // (M, E) of a packed cubic lattice: every bond has one black end, so the black sites' anti-aligned
 // neighbour counts cover all 3 L^3 bonds once.
 __global__ __launch_bounds__(256) void k_observables3_packed(const uint32_t* planes, uint32_t L, uint32_t G,
-                                                             uint64_t n_lanes, int64_t* out) {
+                                                             uint64_t n_lanes, int64_t* out, uint32_t spread) {
     const uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = id < n_lanes;
     uint32_t anti = 0, neg = 0;
@@ -954,7 +966,8 @@ __global__ __launch_bounds__(256) void k_observables3_packed(const uint32_t* pla
                __builtin_popcount(b ^ w1(z + 1 == L ? 0 : z + 1, y, g));
         neg = __builtin_popcount(b) + __builtin_popcount(w);
     }
-    block_accumulate(out, anti, neg, active ? 1u : 0u, 64u, 3u);
+    // spread: out is a spread set (a line per workgroup)
+    block_accumulate(spread ? spread_line(out, blockIdx.x) : out, anti, neg, active ? 1u : 0u, 64u, 3u);
 }
 
 }  // namespace ising
@@ -1061,35 +1074,63 @@ uint32_t packed_planes3(int64_t L) {
     return Rz;
 }
 
-int launch_half_sweep3_packed(uint32_t* planes, int64_t L, const ising::Thresholds3& th, uint64_t seed, uint32_t t,
-                              int q, int64_t* obs, int64_t* zero_slot, hipStream_t stream) {
+// The launch shape of a call's packed half-sweeps, read from the options once per call, so that
+// every launch of the call takes the same kernel (the two kernels count (M, E) at different points).
+struct Packed3Plan {
+    uint32_t Rz;
+    bool ties;  // k_sweep3_packed_q: counts the lattice as it finds it
+};
+
+Packed3Plan packed3_plan(int64_t L) {
+    const uint32_t Rz = packed_planes3(L);
+    return Packed3Plan{Rz, ising_host::option("packed_ties") != 0 && Rz % 4u == 0};
+}
+
+using Packed3Kernel = void (*)(ising::Packed3Args);
+
+Packed3Kernel pick_packed3(bool ties, int q, bool obs) {
+    if (ties)
+        return q == 1 ? (obs ? ising::k_sweep3_packed_q<1, true> : ising::k_sweep3_packed_q<1, false>)
+                      : (obs ? ising::k_sweep3_packed_q<0, true> : ising::k_sweep3_packed_q<0, false>);
+    return q == 1 ? (obs ? ising::k_sweep3_packed<1, true> : ising::k_sweep3_packed<1, false>)
+                  : (obs ? ising::k_sweep3_packed<0, true> : ising::k_sweep3_packed<0, false>);
+}
+
+// obs: null, or a zeroed spread set for (M, E) (after the launch's updates for k_sweep3_packed, before
+// them for k_sweep3_packed_q)
+int launch_half_sweep3_packed(uint32_t* planes, int64_t L, const Packed3Plan& plan, const ising::Thresholds3& th,
+                              uint64_t seed, uint32_t t, int q, int64_t* obs, hipStream_t stream) {
     ising::Packed3Args a;
     a.planes = planes;
     a.L = (uint32_t)L;
     a.G = (uint32_t)(L / 64);
-    a.Rz = packed_planes3(L);
+    a.Rz = plan.Rz;
     a.n_lanes = (uint64_t)L * a.G * (uint64_t)(L / a.Rz);
     a.t = t;
     a.key0 = (uint32_t)seed;
     a.key1 = (uint32_t)(seed >> 32);
     a.th = th;
     a.obs = obs;
-    a.zero_slot = zero_slot;
     a.xcd_remap = ising_host::xcd_remap() ? 1u : 0u;
     const dim3 grid((unsigned)((a.n_lanes + 255) / 256)), block(256);
-    if (ising_host::option("packed_ties") && a.Rz % 4u == 0) {
-        const size_t lds = 4u * ising::kTieQueue3Bytes;  // four waves per workgroup
-#define ISING_LAUNCH3PQ(QQ, OO) hipLaunchKernelGGL((ising::k_sweep3_packed_q<QQ, OO>), grid, block, lds, stream, a)
-        if (q == 1) { if (obs) ISING_LAUNCH3PQ(1, true); else ISING_LAUNCH3PQ(1, false); }
-        else { if (obs) ISING_LAUNCH3PQ(0, true); else ISING_LAUNCH3PQ(0, false); }
-#undef ISING_LAUNCH3PQ
-        return ising_host::check_launch("k_sweep3_packed_q");
+    const size_t lds = plan.ties ? 4u * ising::kTieQueue3Bytes : 0u;  // four waves per workgroup
+    const Packed3Kernel kern = pick_packed3(plan.ties, q, obs != nullptr);
+    void* args[] = {&a};
+    const hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(kern), grid, block, args, lds, stream);
+    const char* name = plan.ties ? "k_sweep3_packed_q" : "k_sweep3_packed";
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return ising_host::hip_failed(e, name);
     }
-#define ISING_LAUNCH3P(QQ, OO) hipLaunchKernelGGL((ising::k_sweep3_packed<QQ, OO>), grid, block, 0, stream, a)
-    if (q == 1) { if (obs) ISING_LAUNCH3P(1, true); else ISING_LAUNCH3P(1, false); }
-    else { if (obs) ISING_LAUNCH3P(0, true); else ISING_LAUNCH3P(0, false); }
-#undef ISING_LAUNCH3P
-    return ising_host::check_launch("k_sweep3_packed");
+    return ising_host::check_launch(name);
+}
+
+// (M, E) of a packed cubic lattice added into out: two zeroed int64, or (spread) a zeroed spread set.
+int launch_observables3_packed(const uint32_t* planes, int64_t L, int64_t* out, bool spread, hipStream_t s) {
+    const uint64_t n = (uint64_t)L * (uint64_t)L * (uint64_t)(L / 64);
+    hipLaunchKernelGGL(ising::k_observables3_packed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, planes,
+                       (uint32_t)L, (uint32_t)(L / 64), n, out, spread ? 1u : 0u);
+    return ising_host::check_launch("k_observables3_packed");
 }
 
 uint64_t lanes3(int64_t L) { return (uint64_t)L * (uint64_t)L * (uint64_t)(L / 64); }
@@ -1208,8 +1249,8 @@ int ising3_half_sweep_packed(uint32_t* planes, int64_t L, double beta, uint64_t 
                              void* stream) {
     if (!planes || !valid_L3(L) || !ising_host::valid_beta(beta) || (q != 0 && q != 1) || t >= (uint64_t(1) << 32))
         return ISING_EINVAL;
-    return launch_half_sweep3_packed(planes, L, make_thresholds3(beta), seed, (uint32_t)t, q, nullptr, nullptr,
-                                     (hipStream_t)stream);
+    return launch_half_sweep3_packed(planes, L, packed3_plan(L), make_thresholds3(beta), seed, (uint32_t)t, q,
+                                     nullptr, (hipStream_t)stream);
 }
 
 int ising3_sweep_packed(uint32_t* planes, int64_t L, double beta, int64_t n_sweeps, uint64_t seed,
@@ -1218,27 +1259,44 @@ int ising3_sweep_packed(uint32_t* planes, int64_t L, double beta, int64_t n_swee
         sweep_offset > (uint64_t(1) << 32) || (uint64_t)n_sweeps > (uint64_t(1) << 32) - sweep_offset)
         return ISING_EINVAL;
     const ising::Thresholds3 th = make_thresholds3(beta);
+    const Packed3Plan plan = packed3_plan(L);
     hipStream_t s = (hipStream_t)stream;
-    for (int64_t i = 0; i < n_sweeps; ++i) {
-        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
-        int64_t* slot = trace_ME ? trace_ME + 2 * i : nullptr;
-        int rc = launch_half_sweep3_packed(planes, L, th, seed, t, 1, nullptr, slot, s);
-        if (rc) return rc;
-        rc = launch_half_sweep3_packed(planes, L, th, seed, t, 0, slot, nullptr, s);
+    ising_host::SpreadTrace sp;
+    if (trace_ME && n_sweeps > 0) {
+        const int rc = sp.begin(nullptr, n_sweeps, s);
         if (rc) return rc;
     }
-    return ISING_OK;
+    for (int64_t i = 0; i < n_sweeps; ++i) {
+        const uint32_t t = (uint32_t)(sweep_offset + (uint64_t)i);
+        int64_t* set = nullptr;
+        int rc = ISING_OK;
+        if (plan.ties) {
+            // the first launch of sweep i counts the lattice after sweep i - 1
+            if (trace_ME && i > 0 && (rc = sp.next(trace_ME + 2 * (i - 1), 2, &set))) return rc;
+            if ((rc = launch_half_sweep3_packed(planes, L, plan, th, seed, t, 1, set, s))) return rc;
+            if ((rc = launch_half_sweep3_packed(planes, L, plan, th, seed, t, 0, nullptr, s))) return rc;
+        } else {
+            if (trace_ME && (rc = sp.next(trace_ME + 2 * i, 2, &set))) return rc;
+            if ((rc = launch_half_sweep3_packed(planes, L, plan, th, seed, t, 1, nullptr, s))) return rc;
+            if ((rc = launch_half_sweep3_packed(planes, L, plan, th, seed, t, 0, set, s))) return rc;
+        }
+    }
+    if (plan.ties && trace_ME && n_sweeps > 0) {
+        // the lattice after the last sweep
+        int64_t* set = nullptr;
+        int rc = sp.next(trace_ME + 2 * (n_sweeps - 1), 2, &set);
+        if (rc) return rc;
+        if ((rc = launch_observables3_packed(planes, L, set, true, s))) return rc;
+    }
+    return sp.fold();
 }
 
 int ising3_observables_packed(const uint32_t* planes, int64_t L, int64_t* out_ME, void* stream) {
     if (!planes || !out_ME || !valid_L3(L)) return ISING_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    int rc = ising_host::zero_trace(out_ME, 2, s);
+    const int rc = ising_host::zero_trace(out_ME, 2, s);
     if (rc) return rc;
-    const uint64_t n = lanes3(L);
-    hipLaunchKernelGGL(ising::k_observables3_packed, grid3(n), dim3(256), 0, s, planes, (uint32_t)L,
-                       (uint32_t)(L / 64), n, out_ME);
-    return ising_host::check_launch("k_observables3_packed");
+    return launch_observables3_packed(planes, L, out_ME, false, s);
 }
 
 int ising3_thresholds(double beta, uint64_t out[3]) {

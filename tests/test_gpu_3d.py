@@ -243,6 +243,33 @@ def test_packed3_planes_and_tie_queue_match_oracle(dev, oracle_lib, L, beta, n, 
         dev.ising_set_option("packed_ties", 1)
 
 
+@pytest.mark.parametrize("ties", [1, 0])
+def test_sweeps3_packed_trace_across_folds(dev, oracle_lib, ties):
+    # With the tie queue, the first launch of sweep i + 1 counts (M, E) after sweep i and an
+    # observables pass counts the last sweep's; without it the second launch of each sweep counts.
+    # 70 traced sweeps span a fold of the 64 spread sets; a second call of one sweep continues the
+    # chain, and a call of no sweeps leaves lattice and trace untouched.
+    L, n, seed = 64, 70, 21
+    _say("sweep3_packed across folds", L, n, ties)
+    host = oracle_lib.init3(L, seed)
+    ref = oracle_lib.sweep3(host, BETA_C3, n, seed, 0, trace=True)
+    ref1 = oracle_lib.sweep3(host, BETA_C3, 1, seed, n, trace=True)
+    try:
+        dev.ising_set_option("packed_ties", ties)
+        p = _planes3(L)
+        dev.ising3_init_packed(p, L, seed)
+        tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+        dev.ising3_sweep_packed(p, L, BETA_C3, n, seed, 0, tr)
+        assert np.array_equal(tr.cpu().numpy(), ref)
+        dev.ising3_sweep_packed(p, L, BETA_C3, 0, seed, n, torch.empty((0, 2), dtype=torch.int64, device="cuda"))
+        t1 = torch.full((1, 2), -7, dtype=torch.int64, device="cuda")
+        dev.ising3_sweep_packed(p, L, BETA_C3, 1, seed, n, t1)
+        assert np.array_equal(t1.cpu().numpy(), ref1)
+        assert np.array_equal(_unpacked3(dev, p, L).cpu().numpy(), host)
+    finally:
+        dev.ising_set_option("packed_ties", 1)
+
+
 @pytest.mark.parametrize("L,n", [(256, 3), (1024, 2)])
 def test_packed3_equals_int8(dev, L, n):
     _say("packed3 == int8", L, n)
