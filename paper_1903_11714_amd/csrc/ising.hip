@@ -2343,12 +2343,17 @@ ising::Thresholds make_thresholds(double beta, int fmt = 0) {
 uint32_t groups_of(int64_t L) { return (uint32_t)((L + 63) / 64); }
 
 // rows per lane for the streaming kernels: even, divides L (L % 32 == 0)
+uint32_t device_cus();
+
 uint32_t rows_per_lane(int64_t L) {
     if (g_opt.rows_per_lane > 0 && L % g_opt.rows_per_lane == 0) return (uint32_t)g_opt.rows_per_lane;
     const uint32_t groups = groups_of(L);
-    // tall strips re-read fewer boundary rows; keep at least ~1024 workgroups' worth of lanes
+    // tall strips re-read fewer boundary rows: the tallest up to 32 that keeps two waves per SIMD
+    // (measured against four waves per SIMD: L = 8192 +25% at 8 rows, 16384 +2% at 32, 65536 and up
+    // unchanged at 32; one wave per SIMD ran slower at 8192 and faster by 3% at 16384)
+    const uint64_t min_lanes = (uint64_t)device_cus() * 4u * 2u * 64u;
     uint32_t R = 32;
-    while (R > 2 && ((uint64_t)groups * (uint64_t)(L / R) < 1024ull * 256ull || L % R != 0)) R >>= 1;
+    while (R > 2 && ((uint64_t)groups * (uint64_t)(L / R) < min_lanes || L % R != 0)) R >>= 1;
     return R;
 }
 
@@ -2520,12 +2525,13 @@ bool use_bands(int64_t L) { return L > kFusedMaxL || (g_opt.fused_bands != 0 && 
 // Bands per row: each owns at most 62 groups (its wave has one recomputed group on either side).
 uint32_t band_count(int64_t L) { return (uint32_t)((L / 64 + 61) / 62); }
 
-// Rows per strip of the band pass: even, divides L; the tallest up to 128 that still leaves 8192
-// waves (two rounds of four waves per SIMD), 8 at least.
+// Rows per strip of the band pass: even, divides L; the tallest up to 256 that still leaves 8192
+// waves (two rounds of four waves per SIMD), 8 at least.  At L = 131072, 256 rows ran 1.1% faster
+// than 128 (fewer halo rows recomputed) and 512 rows 4% slower.
 uint32_t band_rows(int64_t L) {
     if (g_opt.band_rows > 0 && L % g_opt.band_rows == 0 && g_opt.band_rows <= L) return (uint32_t)g_opt.band_rows;
     const uint64_t bands = band_count(L);
-    uint32_t R = 128;
+    uint32_t R = 256;
     while (R > 8 && ((uint64_t)(L / R) * bands < 8192ull || L % R != 0)) R >>= 1;
     return R;
 }
@@ -2948,13 +2954,14 @@ int autotune_batch(const ising_replica_t* reps, int64_t n, const BatchBuffers& b
 
 namespace {
 // Rows per lane of the packed half-sweep: a lane's word is 32 sites (a quarter of the int8 lane's
-// 128), so it takes more lanes to fill the chip.  The tallest strip up to 32 rows that leaves 2^19
-// lanes (8 waves per SIMD), 4 rows at least (the tie queue takes four rows at a time).
+// 128), so it takes more lanes to fill the chip.  The tallest strip up to 32 rows that leaves 2^18
+// lanes (4 waves per SIMD), 4 rows at least (the tie queue takes four rows at a time).  At L = 16384,
+// 16 rows ran 1.7% faster than 8 (with the falling issue priority) and 4 rows 3% slower.
 uint32_t packed_rows(int64_t L) {
     if (g_opt.rows_per_lane > 0 && L % g_opt.rows_per_lane == 0) return (uint32_t)g_opt.rows_per_lane;
     const uint64_t groups = groups_of(L);
     uint32_t R = 32;
-    while (R > 4 && (groups * (uint64_t)(L / R) < (1ull << 19) || L % R != 0)) R >>= 1;
+    while (R > 4 && (groups * (uint64_t)(L / R) < (1ull << 18) || L % R != 0)) R >>= 1;
     return R;
 }
 
