@@ -1610,15 +1610,18 @@ __global__ __launch_bounds__(512) void k_sweep_packed_q(PackedArgs a) {
                                       : shift_prev(side, last_site_bit(e[i], left_half));
             const uint32_t x1 = w[i] ^ b[i], x2 = w[i] ^ b[i + 2], x3 = w[i] ^ side, x4 = w[i] ^ hs;
             const uint32_t o12 = x1 | x2, o34 = x3 | x4;
-            const uint32_t ge2 = ((x1 & x2) | (x3 & x4) | (o12 & o34)) & valid;
+            // three-input logic as explicit v_bitop3 (issued at twice the rate of the v_or3_b32 /
+            // v_and_or_b32 the compiler forms; the kernel is bound by issue), one uniform mask each:
+            // ge2 = (x1 & x2) | (x3 & x4) | (o12 & o34), flip = ge2 | (any & f2) | (~any & f4)
+            const uint32_t ge2 = and_or3(o12, o34, and_or3(x3, x4, x1 & x2)) & valid;
             const uint32_t any = o12 | o34;
-            const uint32_t flip = ge2 | (any & a.th.f2 & valid) | (~any & a.th.f4 & valid);
-            const uint32_t sel2 = any & ~flip & valid;
+            const uint32_t flip = __builtin_amdgcn_bitop3_b32(any, a.th.f4, and_or3(any, a.th.f2, ge2), 0xAE) & valid;
+            const uint32_t sel2 = __builtin_amdgcn_bitop3_b32(any, flip, 0u, 0x30) & valid;  // a & ~b
             uint32_t acc = flip, tied = ~flip & valid;
 #pragma unroll
             for (uint32_t m = 0; m < 2; ++m) {
                 if (!wave_any(tied != 0u)) break;
-                compare_planes(acc, tied, sel2,
+                compare_planes<true>(acc, tied, sel2,
                                philox4x32_10<2, UROW ? 3 : 1>(g, r + (uint32_t)i, a.t, 2u * m + (uint32_t)Q, a.key0, a.key1),
                                a.th, m);
             }

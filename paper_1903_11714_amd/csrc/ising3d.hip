@@ -38,10 +38,14 @@ struct Thresholds3 {
 };
 
 // The four bit planes of one Philox block against T_2 / T_4 / T_6: the threshold bit is bit
-// 31 - k of T_6, flipped on s2 where T_2 differs from it and on s4 where T_4 does.
+// 31 - k of T_6, flipped on s2 where T_2 differs from it and on s4 where T_4 does.  OR3: the accepted
+// sites of each two planes enter acc through one three-input v_bitop3 (as compare_planes<true>; the
+// packed sweep, bound by issue, takes it).
+template <bool OR3 = false>
 __device__ __forceinline__ void compare_planes3(uint32_t& acc, uint32_t& tied, uint32_t s2, uint32_t s4,
                                                 const Words4& blk, const Thresholds3& th, uint32_t m) {
     const uint32_t planes[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
+    uint32_t won[4];
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         const uint32_t k = 4u * m + (uint32_t)w;
@@ -52,8 +56,13 @@ __device__ __forceinline__ void compare_planes3(uint32_t& acc, uint32_t& tied, u
         // one scalar register): five instructions per plane
         const uint32_t x = planes[w];
         const uint32_t diff = __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_bitop3_b32(x ^ m6, s2, d2, 0x78), s4, d4, 0x78);
-        acc |= __builtin_amdgcn_bitop3_b32(tied, diff, x, 0x40);  // differs with x = 0: threshold bit 1, x < T
+        won[w] = __builtin_amdgcn_bitop3_b32(tied, diff, x, 0x40);  // differs with x = 0: threshold bit 1, x < T
+        if (!OR3) acc |= won[w];
         tied = __builtin_amdgcn_bitop3_b32(tied, diff, 0u, 0x30);  // a & ~b
+    }
+    if (OR3) {
+        acc = __builtin_amdgcn_bitop3_b32(acc, won[0], won[1], 0xFE);  // a | b | c
+        acc = __builtin_amdgcn_bitop3_b32(acc, won[2], won[3], 0xFE);
     }
 }
 
@@ -86,6 +95,7 @@ __device__ __forceinline__ Count3 neighbour_count3(uint32_t a, const uint32_t (&
 // The start of decide3 for one word whose neighbour count is c: returns the sites decided by the
 // count and the first two Philox blocks (to flip at once); tied, s2, s4 = the sites still tied and
 // which of them compare with T_2 / T_4.
+template <bool OR3 = false>
 __device__ __forceinline__ uint32_t decide3_head(const Count3& c, const Thresholds3& th, uint32_t g, uint32_t r,
                                                  uint32_t t, uint32_t q, uint32_t key0, uint32_t key1,
                                                  uint32_t& tied, uint32_t& s2, uint32_t& s4) {
@@ -99,7 +109,7 @@ __device__ __forceinline__ uint32_t decide3_head(const Count3& c, const Threshol
 #pragma unroll
     for (uint32_t m = 0; m < 2; ++m) {
         if (!wave_any(tied != 0u)) break;
-        compare_planes3(acc, tied, sel2, sel4, philox4x32_10(g, r, t, 2u * m + q, key0, key1), th, m);
+        compare_planes3<OR3>(acc, tied, sel2, sel4, philox4x32_10(g, r, t, 2u * m + q, key0, key1), th, m);
     }
     s2 = sel2;
     s4 = sel4;
@@ -919,7 +929,7 @@ __global__ __launch_bounds__(256) void k_sweep3_packed_q(Packed3Args a) {
                 __asm__ volatile("" : "+v"(n1), "+v"(n2), "+v"(neg));
             }
             uint32_t tied, s2, s4;
-            w[i] ^= decide3_head(c, th, g, z * L + y, a.t, (uint32_t)Q, a.key0, a.key1, tied, s2, s4);
+            w[i] ^= decide3_head<true>(c, th, g, z * L + y, a.t, (uint32_t)Q, a.key0, a.key1, tied, s2, s4);
             tq3_push(q, n, tied, s2, s4, z * L + y, (uint32_t)i | (lane << 2) | (g << 8));
         }
         tq3_settle<Q>(q, n, th, a.t, a.key0, a.key1, lane);
