@@ -54,3 +54,18 @@ def test_ingest_counters_scales_by_the_copy_calibration(tmp_path, monkeypatch):
                                2.0 * 1024 ** 3)
     assert e3["source_hash"] == bench.kernel_source_hash(bench.KERNEL_SOURCES_3D)
     assert bench.measured_traffic("int8_3d", 1024) == e3["hbm_bytes_per_launch"]
+
+
+def test_fused_passes_cover_every_sweep_and_end_in_the_first_buffer():
+    # the two-sweep and one-sweep passes alternate between two buffers, so they must come in an even
+    # number for the chain to end where it started; an odd count makes its first sweep in place
+    assert bench.fused_passes(0) == (0, 0, 0)
+    assert bench.fused_passes(1) == (0, 0, 1)
+    assert bench.fused_passes(2) == (0, 2, 0)
+    assert bench.fused_passes(4) == (2, 0, 0)
+    assert bench.fused_passes(7) == (2, 2, 1)
+    for n in range(64):
+        pairs, singles, in_place = bench.fused_passes(n)
+        assert 2 * pairs + singles + in_place == n
+        assert (pairs + singles) % 2 == 0 and pairs % 2 == 0 and in_place == n % 2
+        assert singles in (0, 2)
