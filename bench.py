@@ -99,23 +99,19 @@ def alu_roofline(layout: str, L: int, avg_launch_ms: float):
             "valu_insts_per_launch": c["valu_insts_per_launch"]}
 
 
-FUSED_MAX_L = 65536  # above this the two-sweep pass runs as column bands of one wave each
+BANDS_ABOVE_L = 16384  # above this the two-sweep pass runs as column bands of one wave each
 
 KERNEL_NAME = {
     "fused": "k_sweep_fused2p (two sweeps per launch, ties of two steps settled together)",
-    "fused_wide": "k_sweep_fused2q (two sweeps per launch, tie queue)",
     "bands": "k_sweep_fused2pb (two sweeps per launch in column bands of one wave, ties of two steps settled together)",
     "int8": "k_sweep_int8 (one colour per launch)",
     "packed": "k_sweep_packed_q (one colour per launch, tie queue)",
 }
 
 
-FUSED_PAIRS_MAX_L = 32768  # up to here the two-sweep pass settles the ties of two steps together
-
-
 def kernel_name(layout: str, L: int) -> str:
-    if layout == "fused" and L > FUSED_PAIRS_MAX_L:
-        return KERNEL_NAME["bands" if L > FUSED_MAX_L else "fused_wide"]
+    if layout == "fused" and L > BANDS_ABOVE_L:
+        return KERNEL_NAME["bands"]
     return KERNEL_NAME[layout]
 
 

@@ -94,11 +94,12 @@ int ising_sweep_fmt(int8_t* spins, int64_t L, double beta, int fmt, int64_t n_sw
  * On return `spins` holds the lattice after n_sweeps sweeps, bit-identical to ising_sweep_fmt
  * with the same arguments, and so is trace_ME.  Passes alternate spins -> scratch -> spins, an
  * even number of them; an odd count runs its first sweep in place.  Option "fused_sweeps" sets
- * the sweeps per pass (2 by default, 1).  Up to L = 65536 a pass gives each row to one workgroup
- * (one thread per 64-column group); up to L = 32768 the two-sweep pass spaces its four updates three
- * rows apart, so that two consecutive steps are independent and their still-tied words are settled
- * together (option "fused_pairs"); above L = 65536 the two-sweep pass runs in column bands of one wave each
- * (62 own groups and one recomputed group on either side), and the one-sweep pass is not available
+ * the sweeps per pass (2 by default, 1).  Up to L = 16384 a pass gives each row to one workgroup
+ * (one thread per 64-column group), and the two-sweep pass spaces its four updates three rows apart,
+ * so that two consecutive steps are independent and their still-tied words are settled together
+ * (option "fused_pairs"); above L = 16384 the two-sweep pass runs in column bands of one wave each
+ * (62 own groups and one recomputed group on either side; option "fused_bands" moves the switch).
+ * The one-sweep pass needs a whole row per workgroup: above L = 65536 it is not available
  * (fused_sweeps = 1 then sweeps in place as ising_sweep_fmt).  When L % 64 != 0 every sweep runs in
  * place as in ising_sweep_fmt (scratch unused).  Returns ISING_EINVAL for the checks of
  * ising_sweep_fmt, for a null, misaligned or overlapping scratch. */
@@ -124,7 +125,7 @@ int ising_sweep_fused_step(const int8_t* src, int8_t* dst, int64_t L, double bet
 
 /* Two sweeps, t and t + 1 (t + 1 < 2^32), in one pass out of place: dst = src after both (same
  * buffers and conventions as ising_sweep_fused_step).  out_ME: NULL or device int64[4] receiving
- * (M, E) after sweep t, then after sweep t + 1.  Above L = 65536 the pass runs in column bands;
+ * (M, E) after sweep t, then after sweep t + 1.  Above L = 16384 the pass runs in column bands;
  * when L % 64 != 0: a device copy, then the four half-sweeps on dst. */
 int ising_sweep_fused_pair(const int8_t* src, int8_t* dst, int64_t L, double beta, int fmt, uint64_t seed,
                            uint64_t t, int64_t* out_ME, void* stream);
@@ -325,6 +326,12 @@ int ising_moments(const int64_t* trace_ME, int64_t n, int64_t n_sites, double* o
  *                    (its strips then hold that many rows or two fewer); the other passes ignore a
  *                    value that does not divide L.
  *   "fused_alternate" 1 = odd strips of ising_sweep_fused walk upwards (default), 0 = all down.
+ *   "fused_bands"    two-sweep passes in column bands of one wave: 0 = above L = 16384 (default),
+ *                    1 = from L = 4096, 2 = only above L = 65536 (rows wherever a whole row fits
+ *                    one workgroup: up to 512 groups with paired steps, else one step per settle).
+ *   "band_rows"      rows per strip of the band pass: 0 = automatic (a power of two in [8, 256]
+ *                    chosen from the waves each SIMD would run), else a power of two in [2, 1024]
+ *                    (ignored for lattices it does not divide).
  *   "fused_sweeps"   sweeps per pass of ising_sweep_fused: 2 (default) or 1.
  *   "fused_ties"     fused passes (two sweeps or one): 1 = the updates of a step are independent
  *                    and the words still tied after two Philox blocks are settled together

@@ -2237,7 +2237,7 @@ struct Options {
     std::atomic<int64_t> fused_sweeps = 2;     // fused sweep: sweeps per pass over the lattice (1 or 2)
     std::atomic<int64_t> fused_ties = 1;       // two-sweep pass: settle the ties of a step's four updates together
     std::atomic<int64_t> fused_pairs = 1;      // two-sweep pass, rows of at most 512 groups: ties of two steps together
-    std::atomic<int64_t> fused_bands = 0;      // two-sweep pass in column bands of one wave: 0 = above L = 65536, 1 = always
+    std::atomic<int64_t> fused_bands = 0;      // two-sweep pass in column bands of one wave: 0 = above L = 16384, 1 = from 4096, 2 = above 65536
     std::atomic<int64_t> band_rows = 0;        // rows per strip of the band pass; 0 = choose from L
     std::atomic<int64_t> packed_ties = 1;      // packed half-sweep: settle the ties of four rows together
     std::atomic<int64_t> ties3 = 1;            // 3-D int8 half-sweep: two planes per exchange, ties settled together
@@ -2521,22 +2521,39 @@ int launch_fused_sweep(const int8_t* src, int8_t* dst, int64_t L, const ising::T
     return check_launch("k_sweep_fused");
 }
 
-// The two-sweep pass runs in column bands (k_sweep_fused2b) above kFusedMaxL, and with option
-// "fused_bands" from L = 4096 (a band's 64 lanes then take 64 distinct groups).
-bool use_bands(int64_t L) { return L > kFusedMaxL || (g_opt.fused_bands != 0 && L >= 4096); }
+// The two-sweep pass runs in column bands above kBandsAboveL by default (above kFusedMaxL always).
+// Between the two the row kernels were measured 6-75% slower than the bands (at L = 20480 ... 65536),
+// and at L = 16384 14% faster.  Option "fused_bands": 1 = bands from L = 4096 (a band's 64 lanes then
+// take 64 distinct groups), 2 = rows wherever a whole row fits a workgroup.
+constexpr int64_t kBandsAboveL = 16384;
+bool use_bands(int64_t L) {
+    if (L > kFusedMaxL) return true;
+    if (g_opt.fused_bands == 1) return L >= 4096;
+    return g_opt.fused_bands == 0 && L > kBandsAboveL;
+}
 
 // Bands per row: each owns at most 62 groups (its wave has one recomputed group on either side).
 uint32_t band_count(int64_t L) { return (uint32_t)((L / 64 + 61) / 62); }
 
-// Rows per strip of the band pass: even, divides L; the tallest up to 256 that still leaves 8192
-// waves (two rounds of four waves per SIMD), 8 at least.  At L = 131072, 256 rows ran 1.1% faster
-// than 128 (fewer halo rows recomputed) and 512 rows 4% slower.
+// Rows per strip of the band pass: the power of two in [8, 256] dividing L whose launch costs least
+// under a count of the waves each SIMD runs.  A strip of R rows costs R + 10 rows of work (the
+// recomputed halo rows of the two sweeps); a launch of W waves puts ceil(W / SIMDs) of them on the
+// busiest SIMD, and a SIMD that holds a single wave has no other wave to cover its latency and runs
+// it at about half speed.  The smallest cost picked the fastest of 8 ... 256 rows, or one within
+// 0.7% of it, at every L measured (16384 ... 65536 and 131072: 32 rows at 16384, 64 or 128 between,
+// 256 at 131072).
 uint32_t band_rows(int64_t L) {
     if (g_opt.band_rows > 0 && L % g_opt.band_rows == 0 && g_opt.band_rows <= L) return (uint32_t)g_opt.band_rows;
-    const uint64_t bands = band_count(L);
-    uint32_t R = 256;
-    while (R > 8 && ((uint64_t)(L / R) * bands < 8192ull || L % R != 0)) R >>= 1;
-    return R;
+    const uint64_t bands = band_count(L), simds = (uint64_t)device_cus() * 4u;
+    uint32_t best = 8;
+    uint64_t best_cost = UINT64_MAX;
+    for (uint32_t R = 8; R <= 256 && R <= L; R <<= 1) {
+        if (L % R != 0) continue;
+        const uint64_t waves = bands * (uint64_t)(L / R), per_simd = (waves + simds - 1) / simds;
+        const uint64_t cost = (per_simd == 1 ? 2u : per_simd) * (R + 10u);
+        if (cost < best_cost) best = R, best_cost = cost;  // ties keep the shorter strip
+    }
+    return best;
 }
 
 // One two-sweep pass in column bands: sweeps t, t + 1 from src to dst; obs: NULL or 4 int64, zeroed
@@ -3518,7 +3535,7 @@ int ising_set_option(const char* name, int64_t value) {
         if (value != 0 && value != 1) return ISING_EINVAL;
         g_opt.ties3 = value;
     } else if (n == "fused_bands") {
-        if (value != 0 && value != 1) return ISING_EINVAL;
+        if (value < 0 || value > 2) return ISING_EINVAL;
         g_opt.fused_bands = value;
     } else if (n == "band_rows") {
         if (value != 0 && (value < 2 || value > 1024 || (value & (value - 1)) != 0)) return ISING_EINVAL;

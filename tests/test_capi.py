@@ -139,7 +139,7 @@ def test_options_round_trip(lib):
                             ("staged", [0, 1], [-1]), ("nt_store", [0, 1], [5]),
                             ("fused_rows", [0, 2, 6, 16, 22, 256], [1, 3, 258, 512, -4]), ("fused_alternate", [0, 1], [2]), ("fused_sweeps", [1, 2], [0, 3]),
                             ("fused_ties", [0, 1], [2, -1]), ("fused_pairs", [0, 1], [2, -1]), ("packed_ties", [0, 1], [2]), ("ties3", [0, 1], [2]),
-                            ("fused_bands", [0, 1], [2, -1]), ("band_rows", [0, 2, 128, 1024], [1, 6, 2048, -8]),
+                            ("fused_bands", [0, 1, 2], [3, -1]), ("band_rows", [0, 2, 128, 1024], [1, 6, 2048, -8]),
                             ("planes3", [0, 2, 32, 256], [1, 3, 512]),
                             ("batch_threads", [0, 256, 512, 1024], [128, 2048, -1]),
                             ("batch_slab_sites", [0, -1, 1024, 65536, 262144], [512, 3000, 524288, -2]),

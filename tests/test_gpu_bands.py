@@ -1,5 +1,5 @@
 """GPU parity of the two-sweep pass in column bands (one wave per band and strip, the default above
-L = 65536 and, with option "fused_bands", from L = 4096): k_sweep_fused2pb (two steps per tie settle, the
+L = 16384 and, with option "fused_bands", from L = 4096): k_sweep_fused2pb (two steps per tie settle, the
 default) and k_sweep_fused2b (one step per settle, option "fused_pairs" = 0).
 
 A band's wave recomputes one group on either side of its own groups and takes its group-edge

@@ -4,9 +4,9 @@ The fused pass reads one buffer and writes the other; every decision uses the si
 so the lattice and the (M, E) trace must equal the oracle's two half-sweeps bit for bit.  Cases:
 one workgroup thread per 64-column group with threads past the last group idle (L = 64, 192,
 320), whole waves staged through LDS (L = 4096, 8192), the full 16384^2 benchmark lattice, the
-largest full-row lattice (65536^2, 1024 threads per workgroup) and the column-band pass above it;
-the two-sweep pass with two steps' ties settled together (rows of up to 512 groups, the default
-there) and with one step's.
+largest full-row lattice (65536^2, 1024 threads per workgroup, rows forced by option) and the
+column-band pass, the default above L = 16384; the two-sweep pass with two steps' ties settled
+together (rows of up to 512 groups, the default there) and with one step's.
 """
 import math
 import sys
@@ -202,44 +202,53 @@ def test_fused_full_size_16384_crops_and_trace(dev, oracle_lib):
     assert torch.equal(trace, tr2)
 
 
+def _fused_equals_two_launch_path(dev, L, n, seed, offset, bands_opt):
+    s = torch.empty((L, L), dtype=torch.int8, device="cuda")
+    dev.ising_init(s, L, seed)
+    ref = s.clone()
+    tr_ref = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    dev.ising_sweep(ref, L, BETA_C, n, seed, offset, tr_ref)
+    scratch = torch.zeros_like(s)
+    tr = torch.empty_like(tr_ref)
+    old = dev.ising_get_option("fused_bands")
+    dev.ising_set_option("fused_bands", bands_opt)
+    try:
+        dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", n, seed, offset, tr)
+    finally:
+        dev.ising_set_option("fused_bands", old)
+    assert torch.equal(s, ref), (L, bands_opt)
+    assert torch.equal(tr, tr_ref), (L, bands_opt)
+    del s, ref, scratch
+    torch.cuda.empty_cache()
+
+
 def test_fused_largest_full_row_lattice_and_bands_above_it(dev):
-    # L = 65536: 1024 threads per workgroup, 72 KiB of LDS.  L = 65600 (1025 groups): above the
-    # full-row limit, the two-sweep pass runs in column bands (17 bands of 60 or 61 groups, strips of
-    # 64 rows); both equal the in-place two-launch path
-    for L, n in ((65536, 2), (65600, 2)):
-        _say("fused large", L, n)
-        s = torch.empty((L, L), dtype=torch.int8, device="cuda")
-        dev.ising_init(s, L, 5)
-        ref = s.clone()
-        tr_ref = torch.empty((n, 2), dtype=torch.int64, device="cuda")
-        dev.ising_sweep(ref, L, BETA_C, n, 5, 9, tr_ref)
-        scratch = torch.zeros_like(s)
-        tr = torch.empty_like(tr_ref)
-        dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", n, 5, 9, tr)
-        assert torch.equal(s, ref), L
-        assert torch.equal(tr, tr_ref), L
-        del s, ref, scratch
-        torch.cuda.empty_cache()
+    # L = 65536 with rows kept whole (option fused_bands = 2): 1024 threads per workgroup, 72 KiB of
+    # LDS.  L = 65600 (1025 groups): above the full-row limit the two-sweep pass runs in column bands
+    # whatever the option (17 bands of 60 or 61 groups, strips of 64 rows).  Both equal the in-place
+    # two-launch path.
+    for L, n, opt in ((65536, 2, 2), (65600, 2, 2), (65600, 2, 0)):
+        _say("fused large", L, n, opt)
+        _fused_equals_two_launch_path(dev, L, n, 5, 9, opt)
 
 
 def test_fused_pairs_at_the_widest_rows_they_take(dev):
-    # The two-sweep pass with two steps per settle up to 512 groups per row: L = 32768 (512 threads per
-    # workgroup, 86 KiB of LDS, 384 strips of 84 and 86 rows) and L = 32704 (511 groups: one idle thread,
-    # rows loaded lane by lane); both equal the in-place two-launch path over two passes
+    # The two-sweep pass with two steps per settle up to 512 groups per row, kept as rows (option
+    # fused_bands = 2): L = 32768 (512 threads per workgroup, 86 KiB of LDS, 384 strips of 84 and 86
+    # rows) and L = 32704 (511 groups: one idle thread, rows loaded lane by lane); both equal the
+    # in-place two-launch path over two passes
     for L, n in ((32768, 4), (32704, 4)):
         _say("fused pairs wide", L, n)
-        s = torch.empty((L, L), dtype=torch.int8, device="cuda")
-        dev.ising_init(s, L, 8)
-        ref = s.clone()
-        tr_ref = torch.empty((n, 2), dtype=torch.int64, device="cuda")
-        dev.ising_sweep(ref, L, BETA_C, n, 8, 21, tr_ref)
-        scratch = torch.zeros_like(s)
-        tr = torch.empty_like(tr_ref)
-        dev.ising_sweep_fused(s, scratch, L, BETA_C, "exact", n, 8, 21, tr)
-        assert torch.equal(s, ref), L
-        assert torch.equal(tr, tr_ref), L
-        del s, ref, scratch
-        torch.cuda.empty_cache()
+        _fused_equals_two_launch_path(dev, L, n, 8, 21, 2)
+
+
+def test_fused_default_bands_above_16384(dev):
+    # Above L = 16384 the two-sweep pass runs in column bands by default, with strip heights chosen
+    # from the waves per SIMD: L = 16448 (257 groups: 5 bands of 51 or 52), 24576 (7 bands of 54 or
+    # 55), 32768 (9 bands of 56 or 57), 49152 (13 bands of 59 or 60, 128-row strips); two passes each
+    for L, n in ((16448, 4), (24576, 4), (32768, 4), (49152, 4)):
+        _say("fused default bands", L, n)
+        _fused_equals_two_launch_path(dev, L, n, 13, 7, 0)
 
 
 def test_fused_strip_height_divides_odd_multiple_of_64(dev):
