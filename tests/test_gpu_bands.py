@@ -6,7 +6,8 @@ A band's wave recomputes one group on either side of its own groups and takes it
 neighbours by a lane shift; every decision uses the site's own uniform, so the lattice and the (M, E)
 trace must equal the oracle's half-sweeps bit for bit: against the oracle on full 4096^2 lattices
 (two bands of 32 groups, both wrapping round the seam), against the two-launch path for every strip
-height, for bands of unequal width (L = 4160: 65 groups) and at 16384^2.
+height, for bands of unequal width (L = 4160: 65 groups), at 16384^2, and as the default pass at
+L = 20480 and 24576 against both the two-launch path and the full-row pass.
 """
 import contextlib
 import math
@@ -127,4 +128,33 @@ def test_band_pass_full_size_16384(dev):
     assert torch.equal(base, ref)
     assert torch.equal(tr, ref_tr)
     del base, ref, scratch
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("L,n,seed", [(20480, 5, 3), (24576, 4, 8)])
+def test_default_band_pass_between_16384_and_65536(dev, L, n, seed):
+    """Above L = 16384 the default two-sweep pass runs in column bands (20480: 6 bands of 53-54 groups;
+    24576: 7 bands); it must equal both the two-launch path and the full-row pass (option
+    "fused_bands" = 2), lattice and trace, over an odd and an even sweep count."""
+    base = torch.empty((L, L), dtype=torch.int8, device="cuda")
+    dev.ising_init(base, L, seed)
+    ref = base.clone()
+    ref_tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    _say("default bands", L, n, seed, "two-launch reference")
+    dev.ising_sweep(ref, L, BETA_C, n, seed, 7, ref_tr)
+    scratch = torch.empty_like(base)
+    rows = base.clone()
+    tr = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    _say("default bands", L, n, seed, "band pass")
+    with options(dev, fused_bands=0):
+        dev.ising_sweep_fused(base, scratch, L, BETA_C, "exact", n, seed, 7, tr)
+    assert torch.equal(base, ref)
+    assert torch.equal(tr, ref_tr)
+    tr.zero_()
+    _say("default bands", L, n, seed, "full-row pass")
+    with options(dev, fused_bands=2):
+        dev.ising_sweep_fused(rows, scratch, L, BETA_C, "exact", n, seed, 7, tr)
+    assert torch.equal(rows, ref)
+    assert torch.equal(tr, ref_tr)
+    del base, ref, scratch, rows
     torch.cuda.empty_cache()
